@@ -1,0 +1,297 @@
+/*
+ * plasma.c -- grid sampling, plasma state and thermal synchrotron
+ * coefficients (oracle).  TEST INFRASTRUCTURE ONLY (see oracle.h).
+ *
+ * Paper sections 2.5 (Sampling) and 2.6 (Coefficients):
+ *  - primitives rho, p, normal-frame u~, B^a are interpolated (nearest cell
+ *    or trilinear within a block) and everything else derives from them;
+ *  - b^alpha = u_beta (*F)^{beta alpha}: b^t = B^i u_i, b^i = (B^i + b^t u^i)/u^t;
+ *    B = (b.b)^1/2, sigma = B^2/rho, beta^-1 = B^2/(2p);
+ *  - n_e = rho/(mu m_p) (1 + 1/(n_e/n_i))^-1;
+ *  - T_i/T_e = (R_high + beta^-2 R_low)/(1 + beta^-2),
+ *    T_e = (mu m_p p/(k_B rho)) (n_e/n_i + 1)/(n_e/n_i + T_i/T_e);
+ *  - sigma > sigma_max is vacuum (used for every simulation image);
+ *  - the frame is rotated so that the U coefficients vanish.
+ *
+ * Readings (formulas and conventions the paper does not print):
+ *  - cells are cell-centred; trilinear weights use the 8 nearest centres in
+ *    the block, with corner indices clamped to the block (constant within
+ *    half a cell of a block face); a point belongs to the block whose
+ *    half-open box [x0,x1) x [y0,y1) x [z0,z1) holds it; outside all blocks,
+ *    or rho <= 0, is vacuum;
+ *  - code units: p_unit = rho_unit c^2, B_gauss = B_code c sqrt(4 pi rho_unit);
+ *  - thermal fitting formulas (the paper cites Marszewski et al. 2021, not
+ *    reproduced in it): the Dexter (2016) / Shcherbakov (2008) thermal set
+ *    written out in thermal_coeffs() below, with alpha_A = j_A / B_nu
+ *    (Kirchhoff).  Physical values are parity-unpinned;
+ *  - invariants j/nu^2, alpha*nu, rho*nu at the fluid-frame frequency
+ *    nu_fl = n (-k.u);
+ *  - tetrad: e0 = u, e3 = (k - omega u)/omega with omega = -k.u,
+ *    e2 along b projected orthogonal to e3, e1^a = [a b c d] u_b e2_c e3_d
+ *    (sqrt(-g) = 1 in CKS); Q > 0 along e1 (perpendicular to the field).
+ */
+#include <math.h>
+#include <string.h>
+#include "oracle.h"
+
+#define C_LIGHT 2.99792458e10
+#define G_NEWTON 6.67430e-8
+#define M_SUN 1.98841e33
+#define M_ELECTRON 9.1093837015e-28
+#define M_PROTON 1.67262192369e-24
+#define Q_ELECTRON 4.80320471e-10
+#define H_PLANCK 6.62607015e-27
+#define K_BOLTZMANN 1.380649e-16
+
+int or_grid_sample(const or_grid *gr, int interp, const double x[3], double prim[8])
+{
+    int b, found = -1, m;
+    for (b = 0; b < gr->n_blocks; ++b) {
+        const double *bd = gr->bounds + 6 * b;
+        if (x[0] >= bd[0] && x[0] < bd[1] && x[1] >= bd[2] && x[1] < bd[3]
+            && x[2] >= bd[4] && x[2] < bd[5]) { found = b; break; }
+    }
+    if (found < 0) return -1;
+    {
+        const double *bd = gr->bounds + 6 * found;
+        int nn[3] = {gr->bnx, gr->bny, gr->bnz};
+        double w[3];
+        int i0[3], d;
+        const double *base = gr->prims + (size_t)found * gr->bnx * gr->bny * gr->bnz * 8;
+        for (d = 0; d < 3; ++d) {
+            double dx = (bd[2 * d + 1] - bd[2 * d]) / nn[d];
+            if (interp) {
+                double u = (x[d] - bd[2 * d]) / dx - 0.5;
+                double fl = floor(u);
+                i0[d] = (int)fl;
+                w[d] = u - fl;
+                if (i0[d] < 0) { i0[d] = 0; w[d] = 0.0; }
+                if (i0[d] > nn[d] - 2) { i0[d] = nn[d] - 2; w[d] = 1.0; }
+                if (nn[d] == 1) { i0[d] = 0; w[d] = 0.0; }
+            } else {
+                int ii = (int)floor((x[d] - bd[2 * d]) / dx);
+                if (ii < 0) ii = 0;
+                if (ii > nn[d] - 1) ii = nn[d] - 1;
+                i0[d] = ii;
+                w[d] = 0.0;
+            }
+        }
+        for (m = 0; m < 8; ++m) prim[m] = 0.0;
+        {
+            int di, dj, dk;
+            for (dk = 0; dk < 2; ++dk)
+                for (dj = 0; dj < 2; ++dj)
+                    for (di = 0; di < 2; ++di) {
+                        double wt = (di ? w[0] : 1.0 - w[0]) * (dj ? w[1] : 1.0 - w[1])
+                                  * (dk ? w[2] : 1.0 - w[2]);
+                        int ii = i0[0] + di, jj = i0[1] + dj, kk = i0[2] + dk;
+                        const double *cell;
+                        if (wt == 0.0) continue;
+                        cell = base + (((size_t)kk * gr->bny + jj) * gr->bnx + ii) * 8;
+                        for (m = 0; m < 8; ++m) prim[m] += wt * cell[m];
+                    }
+        }
+    }
+    return found;
+}
+
+/* e^x K_n(x) = int_0^inf exp(-x (cosh t - 1)) cosh(n t) dt by the trapezoid
+   rule, which converges exponentially for this analytic integrand: the step
+   min(1/16, 1/(4 sqrt(x))) keeps the discretisation error far below double
+   precision also when the integrand narrows to width ~ x^-1/2; summed until
+   the integrand is below e^-50 of its scale. */
+double or_bessel_k_scaled(int n, double x)
+{
+    const double hq = fmin(1.0 / 16.0, 0.25 / sqrt(x));
+    double sum = 0.5, t;
+    int i;
+    for (i = 1;; ++i) {
+        double term;
+        t = i * hq;
+        term = exp(-x * (cosh(t) - 1.0)) * cosh(n * t);
+        sum += term;
+        if (x * (cosh(t) - 1.0) - n * t > 50.0 && t > 1.0) break;
+    }
+    return sum * hq;
+}
+
+/* Thermal synchrotron coefficients in the fluid frame (CGS), Dexter (2016)
+   emissivity fits with x = nu/nu_c, nu_c = 3/2 nu_B sin(theta) Theta_e^2,
+   nu_B = e B/(2 pi m_e c); Faraday rotativities after Shcherbakov (2008)
+   with X = Theta_e (sqrt(2) sin(theta) 1e3 nu_B/nu)^(1/2).
+   out = jI, jQ, jV, aI, aQ, aV, rQ, rV. */
+void or_thermal_coeffs(double ne, double thetae, double B, double nu,
+                       double cos_theta, int polarized, double out[8])
+{
+    double sin_theta, nuB, nuc, x, E, pre, jI, jQ = 0, jV = 0, Bnu;
+    int m;
+    for (m = 0; m < 8; ++m) out[m] = 0.0;
+    if (cos_theta > 1.0) cos_theta = 1.0;
+    if (cos_theta < -1.0) cos_theta = -1.0;
+    sin_theta = sqrt(1.0 - cos_theta * cos_theta);
+    if (!(ne > 0.0) || !(thetae > 0.0) || !(B > 0.0) || !(sin_theta > 0.0)) return;
+    nuB = Q_ELECTRON * B / (2.0 * M_PI * M_ELECTRON * C_LIGHT);
+    nuc = 1.5 * nuB * sin_theta * thetae * thetae;
+    x = nu / nuc;
+    E = exp(-1.8899 * pow(x, 1.0 / 3.0));
+    pre = ne * Q_ELECTRON * Q_ELECTRON * nu / (2.0 * sqrt(3.0) * C_LIGHT * thetae * thetae);
+    jI = pre * 2.5651 * (1.0 + 1.92 * pow(x, -1.0 / 3.0) + 0.9977 * pow(x, -2.0 / 3.0)) * E;
+    Bnu = 2.0 * H_PLANCK * nu * nu * nu / (C_LIGHT * C_LIGHT)
+        / expm1(H_PLANCK * nu / (thetae * M_ELECTRON * C_LIGHT * C_LIGHT));
+    out[0] = jI;
+    out[3] = jI / Bnu;
+    if (!polarized) return;
+    jQ = pre * 2.5651 * (1.0 + 0.932 * pow(x, -1.0 / 3.0) + 0.4998 * pow(x, -2.0 / 3.0)) * E;
+    jV = 2.0 * ne * Q_ELECTRON * Q_ELECTRON * nu * (cos_theta / sin_theta)
+       / (3.0 * sqrt(3.0) * C_LIGHT * thetae * thetae * thetae)
+       * (1.8138 / x + 3.423 * pow(x, -2.0 / 3.0) + 0.02955 * pow(x, -0.5)
+          + 2.0377 * pow(x, -1.0 / 3.0)) * E;
+    out[1] = jQ;
+    out[2] = jV;
+    out[4] = jQ / Bnu;
+    out[5] = jV / Bnu;
+    {
+        double Xr = thetae * sqrt(sqrt(2.0) * sin_theta * 1.0e3 * nuB / nu);
+        double k0 = or_bessel_k_scaled(0, 1.0 / thetae);
+        double k1 = or_bessel_k_scaled(1, 1.0 / thetae);
+        double k2 = or_bessel_k_scaled(2, 1.0 / thetae);
+        double ism = pow(Xr, -0.5);
+        double f0 = 2.011 * exp(-19.78 * pow(Xr, -0.5175))
+                  - cos(39.89 * ism) * exp(-70.16 * pow(Xr, -0.6))
+                  - 0.011 * exp(-1.69 * ism);
+        double fm = f0 + (0.011 * exp(-1.69 * ism) - 0.003135 * pow(Xr, 4.0 / 3.0))
+                  * 0.5 * (1.0 + tanh(10.0 * log(0.6648 * ism)));
+        double gX = 1.0 - 0.11 * log(1.0 + 0.035 * Xr);
+        double base = ne * Q_ELECTRON * Q_ELECTRON / (M_ELECTRON * C_LIGHT);
+        out[6] = base * nuB * nuB * sin_theta * sin_theta / (nu * nu * nu) * fm
+               * (k1 / k2 + 6.0 * thetae);
+        out[7] = 2.0 * base * nuB / (nu * nu) * (k0 / k2) * cos_theta * gX;
+    }
+}
+
+static double dot4(const double g[16], const double a[4], const double b[4])
+{
+    double s = 0.0;
+    int i, j;
+    for (i = 0; i < 4; ++i)
+        for (j = 0; j < 4; ++j) s += g[4 * i + j] * a[i] * b[j];
+    return s;
+}
+
+static void lower4(const double g[16], const double a[4], double al[4])
+{
+    int i, j;
+    for (i = 0; i < 4; ++i) {
+        al[i] = 0.0;
+        for (j = 0; j < 4; ++j) al[i] += g[4 * i + j] * a[j];
+    }
+}
+
+static int perm_sign(int a, int b, int c, int d)
+{
+    int p[4] = {a, b, c, d}, s = 1, i, j;
+    for (i = 0; i < 4; ++i)
+        for (j = i + 1; j < 4; ++j) {
+            if (p[i] == p[j]) return 0;
+            if (p[i] > p[j]) s = -s;
+        }
+    return s;
+}
+
+/* Orthonormal tetrad for observer u and photon momentum k (covariant), with
+   e2 along vector w projected into the screen; e1 completes the right-handed
+   screen basis.  e[4][4] contravariant. */
+void or_tetrad(const double g[16], const double gi[16], const double u[4],
+               const double kcov[4], const double w[4], double e[4][4])
+{
+    double ku[4], omega = 0.0, ul[4], e2l[4], e3l[4], t[4], nrm, we3, wu;
+    const double zhat[4] = {0, 0, 0, 1}, xhat[4] = {0, 1, 0, 0};
+    int al, be, ga, de, attempt;
+    for (al = 0; al < 4; ++al) {
+        ku[al] = 0.0;
+        for (be = 0; be < 4; ++be) ku[al] += gi[4 * al + be] * kcov[be];
+        omega -= kcov[al] * u[al];
+    }
+    for (al = 0; al < 4; ++al) {
+        e[0][al] = u[al];
+        e[3][al] = (ku[al] - omega * u[al]) / omega;
+    }
+    for (attempt = 0; attempt < 3; ++attempt) {
+        const double *v = attempt == 0 ? w : (attempt == 1 ? zhat : xhat);
+        double vn = sqrt(fabs(dot4(g, v, v)));
+        wu = dot4(g, v, u);
+        we3 = dot4(g, v, e[3]);
+        for (al = 0; al < 4; ++al) t[al] = v[al] + wu * u[al] - we3 * e[3][al];
+        nrm = sqrt(fabs(dot4(g, t, t)));
+        if (vn > 0.0 && nrm > 1e-10 * vn) break;
+    }
+    for (al = 0; al < 4; ++al) e[2][al] = t[al] / nrm;
+    lower4(g, u, ul);
+    lower4(g, e[2], e2l);
+    lower4(g, e[3], e3l);
+    for (al = 0; al < 4; ++al) {
+        double s = 0.0;
+        for (be = 0; be < 4; ++be)
+            for (ga = 0; ga < 4; ++ga)
+                for (de = 0; de < 4; ++de) {
+                    int sg = perm_sign(al, be, ga, de);
+                    if (sg) s += sg * ul[be] * e2l[ga] * e3l[de];
+                }
+        e[1][al] = s;
+    }
+}
+
+void or_sample_point(const or_spacetime *st, const or_grid *gr, const or_plasma *pl,
+                     const double y[8], double n_norm, double out[30])
+{
+    double g[16], gi[16], prim[8], u[4], ul[4], b[4], bl[4], ku[4];
+    double q = 0.0, gam, alpha, beta[3], bt, b2, rho, p, sigma, binv, ne, tr, thetae;
+    double Bg, omega, nu_fl, kb, cth, co[8], e[4][4];
+    int i, j;
+    memset(out, 0, 30 * sizeof(double));
+    if (or_grid_sample(gr, pl->interp, y + 1, prim) < 0) return;
+    rho = prim[0];
+    p = prim[1];
+    if (!(rho > 0.0)) return;
+    or_metric(st->a, st->flat, y, g, gi);
+    /* fluid velocity from normal-frame components */
+    for (i = 0; i < 3; ++i)
+        for (j = 0; j < 3; ++j) q += g[4 * (1 + i) + 1 + j] * prim[2 + i] * prim[2 + j];
+    gam = sqrt(1.0 + q);
+    alpha = 1.0 / sqrt(-gi[0]);
+    for (i = 0; i < 3; ++i) beta[i] = -gi[1 + i] / gi[0];
+    u[0] = gam / alpha;
+    for (i = 0; i < 3; ++i) u[1 + i] = prim[2 + i] - gam * beta[i] / alpha;
+    lower4(g, u, ul);
+    /* magnetic 4-vector */
+    bt = prim[5] * ul[1] + prim[6] * ul[2] + prim[7] * ul[3];
+    b[0] = bt;
+    for (i = 0; i < 3; ++i) b[1 + i] = (prim[5 + i] + bt * u[1 + i]) / u[0];
+    b2 = dot4(g, b, b);
+    sigma = b2 / rho;
+    out[29] = sigma;
+    if (sigma > pl->sigma_max) return;
+    binv = b2 / (2.0 * p);
+    ne = rho * gr->rho_unit / (pl->mu * M_PROTON) / (1.0 + 1.0 / pl->ne_ni);
+    tr = (pl->r_high + binv * binv * pl->r_low) / (1.0 + binv * binv);
+    thetae = pl->mu * M_PROTON / M_ELECTRON * (p / rho) * (pl->ne_ni + 1.0) / (pl->ne_ni + tr);
+    Bg = sqrt(b2) * C_LIGHT * sqrt(4.0 * M_PI * gr->rho_unit);
+    omega = 0.0;
+    kb = 0.0;
+    for (i = 0; i < 4; ++i) { omega -= y[4 + i] * u[i]; kb += y[4 + i] * b[i]; }
+    nu_fl = n_norm * omega;
+    cth = (b2 > 0.0) ? kb / (omega * sqrt(b2)) : 0.0;
+    or_thermal_coeffs(ne, thetae, Bg, nu_fl, cth, pl->polarized, co);
+    for (i = 0; i < 3; ++i) out[i] = co[i] / (nu_fl * nu_fl);
+    for (i = 3; i < 8; ++i) out[i] = co[i] * nu_fl;
+    out[8] = ne; out[9] = thetae; out[10] = Bg; out[11] = nu_fl;
+    for (i = 0; i < 4; ++i) {
+        ku[i] = 0.0;
+        for (j = 0; j < 4; ++j) ku[i] += gi[4 * i + j] * y[4 + j];
+    }
+    lower4(g, b, bl);
+    or_tetrad(g, gi, u, y + 4, b, e);
+    for (i = 0; i < 4; ++i)
+        for (j = 0; j < 4; ++j) out[12 + 4 * i + j] = e[i][j];
+    out[28] = 1.0;
+}
