@@ -1,0 +1,210 @@
+/*
+ * blgpu.h -- C ABI of the MI355X (gfx950) implementation of the Blacklight
+ * ray-tracing hot path (C. J. White 2022, "Blacklight: A General-Relativistic
+ * Ray-Tracing and Analysis Tool", arXiv:2203.15963).
+ *
+ * For every camera pixel the library integrates a null geodesic of the Kerr
+ * metric in Cartesian Kerr-Schild coordinates with adaptive Dormand-Prince
+ * RK5(4) steps (paper section 2.2), samples GRMHD-like cell data on the ray
+ * (section 2.4), evaluates thermal synchrotron coefficients (section 2.5) and
+ * integrates the unpolarized (section 2.3) or polarized (section 2.4,
+ * Strang-split coordinate/plasma terms) transfer equation from source to
+ * camera.  The camera is the plane-parallel camera of section 2.1.
+ *
+ * Conventions
+ *  - Units: lengths, times and the affine parameter in M (G = c = 1, M = 1);
+ *    plasma and radiation in CGS.  Images hold I_nu, Q_nu, U_nu, V_nu in
+ *    erg s^-1 cm^-2 sr^-1 Hz^-1.
+ *  - Ownership: the caller owns every buffer it passes; the library never
+ *    frees caller memory.  Pointers documented "device" must be device
+ *    memory of the context's GPU; "host" pointers are read during the call
+ *    only.  A bl_grid borrows the caller's device primitive array, which must
+ *    stay alive and unchanged while the grid is used.
+ *  - Asynchrony: every call that launches work enqueues it on the context's
+ *    stream and returns; the caller synchronises the stream before reading
+ *    outputs.  Calls on one context must not overlap in time from several
+ *    host threads.
+ *  - Errors: calls return a bl_status and never abort or throw across the
+ *    ABI; bl_last_error() holds a message for the last non-OK status.  Per-ray
+ *    numerical outcomes go to the status auxiliary map, not to the return code.
+ *  - Layout: images are row-major [stokes][j][i] with i the horizontal pixel
+ *    index (offset a along H) and j the vertical one (offset b along V).
+ */
+#ifndef BLGPU_H
+#define BLGPU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BLGPU_ABI_VERSION 1
+
+typedef enum {
+    BL_OK = 0,
+    BL_E_INVALID_ARG = -1,   /* a pointer, size or parameter is invalid       */
+    BL_E_DEVICE = -2,        /* a HIP runtime call failed                      */
+    BL_E_OOM = -3,           /* device memory for the workspace is exhausted   */
+    BL_E_UNSUPPORTED = -4    /* a valid request this version does not support  */
+} bl_status;
+
+/* Auxiliary maps, each [N][N] doubles, in this order (paper section 4.5:
+   elapsed time, proper length, affine parameter, optical depth and
+   integrated emissivity; plus step counts, status and sample counts). */
+#define BL_NAUX 10
+enum {
+    BL_AUX_DT = 0,       /* t_pixel - t_end (Kerr-Schild t)                     */
+    BL_AUX_S = 1,        /* proper length sum of |h| (g_pq k^p k^q)^1/2        */
+    BL_AUX_LAMBDA = 2,   /* affine length sum of |h|                           */
+    BL_AUX_TAU = 3,      /* sum alpha_I dlambda over plasma samples            */
+    BL_AUX_IJ = 4,       /* nu^3 sum j_I dlambda (unabsorbed I_nu)             */
+    BL_AUX_NACC = 5,     /* accepted DP steps                                  */
+    BL_AUX_NREJ = 6,     /* rejected DP steps                                  */
+    BL_AUX_STATUS = 7,   /* bl_ray_status                                      */
+    BL_AUX_NSAMP = 8,    /* plasma samples used by the transfer                */
+    BL_AUX_NREC = 9      /* transfer records of the ray (pieces + vacuum steps) */
+};
+
+typedef enum {
+    BL_RAY_ESCAPED = 1,      /* r crossed the camera radius from below         */
+    BL_RAY_CAPTURED = 2,     /* r fell below r_in                              */
+    BL_RAY_MAXSTEPS = 3,     /* accepted + rejected trials reached max_steps   */
+    BL_RAY_UNDERFLOW = 4,    /* |h| < 1e-14 (1 + |lambda|)                     */
+    BL_RAY_NONFINITE = 5     /* a NaN or Inf appeared in the state or error    */
+} bl_ray_status;
+
+typedef struct bl_context bl_context;   /* one device + one HIP stream */
+typedef struct bl_grid bl_grid;         /* device-resident fluid data  */
+
+/* Plane-parallel camera, paper section 2.1. */
+typedef struct {
+    double r, theta, phi;     /* camera centre in spherical Kerr-Schild       */
+    double u_normal[3];       /* u^p: normal-frame velocity (spherical KS)    */
+    double k_cov[3];          /* k_i: received momentum, spherical KS, any norm */
+    double width;             /* w: full width of the image plane (M)         */
+    int32_t n;                /* N: pixels per side (1 .. 16384)              */
+    int32_t freq_mode;        /* 0: nu at infinity (-n k_t = nu);
+                                 1: nu at the camera (-n k.u = nu)            */
+    double psi;               /* rotation of the camera about its axis        */
+    double nu_hz;             /* observing frequency (Hz)                     */
+} bl_camera;
+
+typedef struct {
+    double a;                 /* spin a/M, |a| < 1                            */
+    double mass_msun;         /* M in solar masses: sets the CGS length GM/c^2 */
+    double r_in;              /* inner termination radius (M)                 */
+    int32_t flat;             /* 1: Minkowski metric on the same coordinates  */
+    int32_t pad;
+} bl_spacetime;
+
+/* Dormand-Prince RK5(4)7M, paper section 2.2 and its Table of coefficients. */
+typedef struct {
+    double f_abs, f_rel;      /* error tolerances of the step norm            */
+    double ds_max;            /* proper-length limit of a transfer piece (M);
+                                 0 disables subdivision                       */
+    double h0_frac;           /* first trial step = -h0_frac * r_pixel (0.1: the
+                                 first error estimate then lies well above
+                                 rounding noise)                              */
+    int64_t max_steps;        /* cap on accepted + rejected trials per ray    */
+    int32_t record_cap;       /* step records kept per ray in the fast path
+                                 (0 = 512); longer rays take a slower path    */
+    int32_t pad;
+} bl_integrator;
+
+/* Block-structured fluid data (paper section 2.4): n_blocks logically
+   Cartesian blocks of bnx*bny*bnz cells; cell values are cell-centred. */
+typedef struct {
+    int32_t n_blocks, bnx, bny, bnz;  /* every bn* >= 2                       */
+    const double *bounds;     /* host [n_blocks][6] = x0,x1,y0,y1,z0,z1; the
+                                 blocks must tile the bounding box without
+                                 overlap and be aligned to a common grid of
+                                 the smallest block size                      */
+    const void *prims;        /* device [n_blocks][bnz][bny][bnx][8]:
+                                 rho, p, u~x, u~y, u~z, Bx, By, Bz in code
+                                 units (u~ = CKS normal-frame velocity)       */
+    int32_t dtype;            /* 0: float64, 1: float32 (mixed precision)     */
+    int32_t pad;
+    double rho_unit;          /* g cm^-3 per code density unit; p is in units
+                                 of rho_unit c^2 and B of c sqrt(4 pi rho_unit) */
+} bl_grid_desc;
+
+/* Plasma model, paper section 2.5 (thermal electrons, R_high/R_low). */
+typedef struct {
+    double mu, ne_ni;         /* molecular weight, n_e/n_i                    */
+    double r_high, r_low;     /* T_i/T_e prescription                         */
+    double sigma_max;         /* sigma above this is vacuum                   */
+    int32_t polarized;        /* 0: I only (eq. unpolarized); 1: I,Q,U,V      */
+    int32_t interp;           /* 0: nearest cell; 1: trilinear within a block */
+} bl_plasma;
+
+typedef struct {
+    int32_t precision;        /* 0: FP64 throughout; 1: FP64 geodesics with
+                                 FP32 coefficients and transfer               */
+    int32_t step_model;       /* 0: the plain step-size controller            */
+} bl_mode;
+
+/* ABI version of the loaded library (BLGPU_ABI_VERSION). */
+int bl_abi_version(void);
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+   (a hipStream_t; NULL = the null stream).  *out receives the handle. */
+bl_status bl_create(int device, void *hip_stream, bl_context **out);
+void bl_destroy(bl_context *ctx);
+/* Message of the last non-OK status on this context ("" if none). */
+const char *bl_last_error(const bl_context *ctx);
+
+/* Describe device-resident cell data for sampling; copies the block table
+   (host) and builds the block lookup table on the device.  The primitive
+   array is borrowed, not copied. */
+bl_status bl_grid_create(bl_context *ctx, const bl_grid_desc *desc, bl_grid **out);
+void bl_grid_destroy(bl_grid *grid);
+
+/* Initial pixel states (paper section 2.1): state_out device [N*N][8] =
+   x^alpha (t,x,y,z), k_alpha (t,x,y,z) with pixel index i + N j;
+   norm_out device [N*N] = n, the frequency normalisation. */
+bl_status bl_camera_rays(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
+                         double *state_out, double *norm_out);
+
+/* Geodesics only (paper section 2.2): state_out device [N*N][8] final
+   states; aux_out device [BL_NAUX][N*N] with the geodesic maps (dt, s,
+   lambda, n_acc, n_rej, status) filled and the transfer maps zero. */
+bl_status bl_trace_geodesics(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
+                             const bl_integrator *integ, double *state_out, double *aux_out);
+
+/* Full image (paper sections 2.1-2.5): image_out device [4][N][N] doubles
+   (I, Q, U, V; Q, U, V zero when unpolarized); aux_out device
+   [BL_NAUX][N][N].  Q > 0 means polarization along the vertical V, U > 0
+   along the direction 45 degrees from V towards -H. */
+bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
+                    const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
+                    const bl_mode *mode, double *image_out, double *aux_out);
+
+/* Per-sample evaluation for checking (paper sections 2.2, 2.4, 2.5): for
+   states device [n][8] and norms device [n], writes out device [n][64]:
+   [0..7]   geodesic right-hand side dy/dlambda,
+   [8..23]  G^a_d = Gamma^a_cd k^c (row-major a, d),
+   [24..31] jI, jQ, jV, aI, aQ, aV, rQ, rV (invariants j/nu^2, alpha*nu),
+   [32..35] n_e, Theta_e, B (gauss), nu in the fluid frame,
+   [36..51] tetrad e0..e3 (contravariant),
+   [52]     1 for emitting plasma, 0 for vacuum, [53] sigma, [54..63] 0. */
+#define BL_NSAMPLE_OUT 64
+bl_status bl_eval_samples(bl_context *ctx, const bl_spacetime *st, const bl_grid *grid,
+                          const bl_plasma *plasma, int64_t n, const double *states,
+                          const double *norms, double *out);
+
+/* Kernel timing with HIP events recorded around every launch on the context's
+   stream (tracing aid; off by default).  Kernel classes: */
+#define BL_NKERNEL 4
+enum { BL_K_SETUP = 0, BL_K_GEODESIC = 1, BL_K_TRANSFER = 2, BL_K_OVERFLOW = 3 };
+bl_status bl_profile_enable(bl_context *ctx, int enable);
+/* Synchronises the stream, then writes the summed durations (ms) and launch
+   counts per kernel class since the last read into host arrays
+   ms_out[BL_NKERNEL] and launches_out[BL_NKERNEL], and clears them. */
+bl_status bl_profile_read(bl_context *ctx, double *ms_out, int64_t *launches_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLGPU_H */

@@ -20,10 +20,10 @@
 
 #include <stdint.h>
 
-#define OR_NAUX 9
+#define OR_NAUX 10
 /* auxiliary map order */
 enum { OR_AUX_DT = 0, OR_AUX_S, OR_AUX_LAMBDA, OR_AUX_TAU, OR_AUX_IJ,
-       OR_AUX_NACC, OR_AUX_NREJ, OR_AUX_STATUS, OR_AUX_NSAMP };
+       OR_AUX_NACC, OR_AUX_NREJ, OR_AUX_STATUS, OR_AUX_NSAMP, OR_AUX_NREC };
 
 /* per-ray termination status */
 enum { OR_RUNNING = 0, OR_ESCAPED = 1, OR_CAPTURED = 2, OR_MAXSTEPS = 3,

@@ -13,8 +13,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
-NAUX = 9
-AUX_NAMES = ["dt", "s", "lambda", "tau", "I_j", "n_acc", "n_rej", "status", "n_samp"]
+NAUX = 10
+AUX_NAMES = ["dt", "s", "lambda", "tau", "I_j", "n_acc", "n_rej", "status", "n_samp", "n_rec"]
 ESCAPED, CAPTURED, MAXSTEPS, UNDERFLOW, NONFINITE = 1, 2, 3, 4, 5
 
 
@@ -120,7 +120,7 @@ def spacetime(d):
 def integrator(d):
     g = Integrator()
     g.f_abs, g.f_rel = d.get("f_abs", 1e-8), d.get("f_rel", 1e-8)
-    g.ds_max, g.h0_frac = d.get("ds_max", 0.0), d.get("h0_frac", 0.01)
+    g.ds_max, g.h0_frac = d.get("ds_max", 0.0), d.get("h0_frac", 0.1)
     g.max_steps = int(d.get("max_steps", 100000))
     return g
 

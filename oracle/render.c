@@ -33,7 +33,7 @@
  *    I_nu = nu^3 I;
  *  - auxiliary: dt = t_pix - t_end, s = sum ds, lambda = sum |h| over the
  *    whole ray, tau = sum alpha_I dl_phys, I_j = nu^3 sum j_I dl_phys over
- *    plasma records.
+ *    plasma records; the number of records (pieces and vacuum steps).
  */
 #include <math.h>
 #include <pthread.h>
@@ -117,8 +117,11 @@ static record *make_records(const or_spacetime *st, const or_integrator *in,
         double f0[8], f1[8];
         if (inb) {
             double ds = fabs(h) * or_ds_dlambda(st->a, st->flat, ym);
-            if (in->ds_max > 0.0) nsub = (int64_t)ceil(ds / in->ds_max);
-            if (nsub < 1) nsub = 1;
+            if (in->ds_max > 0.0) {
+                /* at most 2^24 pieces per step; a non-finite length gives one */
+                double q = ceil(ds / in->ds_max);
+                nsub = (q >= 1.0) ? (int64_t)fmin(q, 16777216.0) : 1;
+            }
             if (nsub > 1) {
                 or_geodesic_rhs(st->a, st->flat, y0, f0);
                 or_geodesic_rhs(st->a, st->flat, y1, f1);
@@ -283,6 +286,7 @@ static void render_one(const or_camera *cam, const or_spacetime *st, const or_in
     aux[OR_AUX_NREJ] = (double)ray.n_rej;
     aux[OR_AUX_STATUS] = (double)ray.status;
     aux[OR_AUX_NSAMP] = (double)n_samp;
+    aux[OR_AUX_NREC] = (double)n_rec;
     free(rec);
     or_ray_free(&ray);
 }

@@ -15,7 +15,12 @@
  *  - accept iff eps <= 1; new h = h * min(10, max(0.2, 0.9 eps^-1/5)),
  *    factor 10 when eps == 0; after a rejection h = h * max(0.2, 0.9 eps^-1/5)
  *    and the next accepted step may not grow h;
- *  - first trial step h0 = -h0_frac * r_pix;
+ *  - every step-size factor is rounded to a multiple of 1/4096, and the
+ *    first trial step is h0 = -h0_frac * r_pix with r_pix rounded to a
+ *    multiple of 2^-10: the error estimate is a sum with heavy cancellation,
+ *    so its last bits are noise, and the rounding keeps that noise out of
+ *    the step sequence (the sequence is then reproducible across compilers
+ *    and hardware except where a factor sits on a rounding boundary);
  *  - stop with STEP_UNDERFLOW when |h| < 1e-14 (1 + |lambda|), MAXSTEPS when
  *    accepted + rejected trials reach max_steps, NONFINITE on a NaN/Inf state;
  *  - termination is tested on accepted steps: r_prev < r_cam <= r_new
@@ -121,7 +126,7 @@ int or_trace(const or_camera *cam, const or_spacetime *st, const or_integrator *
     ray->status = OR_RUNNING;
     ray->s = 0.0;
     r_prev = or_ks_radius(a, y[1], y[2], y[3]);
-    h = -in->h0_frac * r_prev;
+    h = -in->h0_frac * (rint(r_prev * 1024.0) / 1024.0);
     or_geodesic_rhs(a, flat, y, k[0]);
 
     while (ray->status == OR_RUNNING) {
@@ -149,12 +154,17 @@ int or_trace(const or_camera *cam, const or_spacetime *st, const or_integrator *
             err[m] = h * se;
             ym[m] = y[m] + 0.5 * h * sm;
         }
-        for (m = 0; m < 8; ++m) {
-            double sc = in->f_abs + in->f_rel * fmax(fabs(y[m]), fabs(y5[m]));
-            double e = fabs(err[m]) / sc;
-            if (!(e <= eps)) eps = e;   /* NaN propagates */
+        {
+            int bad = 0;
+            for (m = 0; m < 8; ++m) {
+                double sc = in->f_abs + in->f_rel * fmax(fabs(y[m]), fabs(y5[m]));
+                /* an exactly zero error is no error, also at zero tolerance */
+                double e = (err[m] == 0.0) ? 0.0 : fabs(err[m]) / sc;
+                if (isnan(e)) bad = 1;
+                else if (e > eps) eps = e;
+            }
+            if (bad || !finite8(y5)) { ray->status = OR_NONFINITE; break; }
         }
-        if (!isfinite(eps) || !finite8(y5)) { ray->status = OR_NONFINITE; break; }
         if (eps <= 1.0) {
             double fac, r_new;
             push_step(ray, y, ym, y5, h);
@@ -162,6 +172,7 @@ int or_trace(const or_camera *cam, const or_spacetime *st, const or_integrator *
             lambda += h;
             ray->s += fabs(h) * or_ds_dlambda(a, flat, ym);
             fac = (eps == 0.0) ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * pow(eps, -0.2)));
+            fac = rint(fac * 4096.0) / 4096.0;
             if (no_grow) fac = fmin(fac, 1.0);
             no_grow = 0;
             memcpy(y, y5, sizeof(y));
@@ -173,7 +184,7 @@ int or_trace(const or_camera *cam, const or_spacetime *st, const or_integrator *
             h *= fac;
         } else {
             ray->n_rej++;
-            h *= fmax(0.2, 0.9 * pow(eps, -0.2));
+            h *= rint(fmax(0.2, 0.9 * pow(eps, -0.2)) * 4096.0) / 4096.0;
             no_grow = 1;
         }
     }

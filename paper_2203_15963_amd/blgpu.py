@@ -1,0 +1,272 @@
+"""ctypes binding of libblgpu (include/blgpu.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Device buffers are torch tensors on the context's GPU; the library
+enqueues on the torch stream given at context creation.  The binding refuses
+to work without the built library (there is no fallback path).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libblgpu.so")
+ABI_VERSION = 1
+NAUX = 10
+NKERNEL = 4
+KERNEL_NAMES = ["setup", "geodesic", "transfer", "overflow"]
+NSAMPLE_OUT = 64
+AUX_NAMES = ["dt", "s", "lambda", "tau", "I_j", "n_acc", "n_rej", "status", "n_samp", "n_rec"]
+STATUS = {"OK": 0, "E_INVALID_ARG": -1, "E_DEVICE": -2, "E_OOM": -3, "E_UNSUPPORTED": -4}
+_STATUS_NAME = {v: k for k, v in STATUS.items()}
+
+
+class bl_camera(C.Structure):
+    _fields_ = [("r", C.c_double), ("theta", C.c_double), ("phi", C.c_double),
+                ("u_normal", C.c_double * 3), ("k_cov", C.c_double * 3),
+                ("width", C.c_double), ("n", C.c_int32), ("freq_mode", C.c_int32),
+                ("psi", C.c_double), ("nu_hz", C.c_double)]
+
+
+class bl_spacetime(C.Structure):
+    _fields_ = [("a", C.c_double), ("mass_msun", C.c_double), ("r_in", C.c_double),
+                ("flat", C.c_int32), ("pad", C.c_int32)]
+
+
+class bl_integrator(C.Structure):
+    _fields_ = [("f_abs", C.c_double), ("f_rel", C.c_double), ("ds_max", C.c_double),
+                ("h0_frac", C.c_double), ("max_steps", C.c_int64), ("record_cap", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class bl_grid_desc(C.Structure):
+    _fields_ = [("n_blocks", C.c_int32), ("bnx", C.c_int32), ("bny", C.c_int32), ("bnz", C.c_int32),
+                ("bounds", C.POINTER(C.c_double)), ("prims", C.c_void_p), ("dtype", C.c_int32),
+                ("pad", C.c_int32), ("rho_unit", C.c_double)]
+
+
+class bl_plasma(C.Structure):
+    _fields_ = [("mu", C.c_double), ("ne_ni", C.c_double), ("r_high", C.c_double),
+                ("r_low", C.c_double), ("sigma_max", C.c_double), ("polarized", C.c_int32),
+                ("interp", C.c_int32)]
+
+
+class bl_mode(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("step_model", C.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libblgpu.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_2203_15963_amd/build.py "
+                           "(or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.bl_abi_version.restype = C.c_int
+    L.bl_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+    L.bl_create.restype = C.c_int
+    L.bl_destroy.argtypes = [vp]
+    L.bl_last_error.argtypes = [vp]
+    L.bl_last_error.restype = C.c_char_p
+    L.bl_grid_create.argtypes = [vp, C.POINTER(bl_grid_desc), C.POINTER(vp)]
+    L.bl_grid_create.restype = C.c_int
+    L.bl_grid_destroy.argtypes = [vp]
+    L.bl_camera_rays.argtypes = [vp, C.POINTER(bl_camera), C.POINTER(bl_spacetime), vp, vp]
+    L.bl_camera_rays.restype = C.c_int
+    L.bl_trace_geodesics.argtypes = [vp, C.POINTER(bl_camera), C.POINTER(bl_spacetime),
+                                     C.POINTER(bl_integrator), vp, vp]
+    L.bl_trace_geodesics.restype = C.c_int
+    L.bl_render.argtypes = [vp, C.POINTER(bl_camera), C.POINTER(bl_spacetime), C.POINTER(bl_integrator),
+                            vp, C.POINTER(bl_plasma), C.POINTER(bl_mode), vp, vp]
+    L.bl_render.restype = C.c_int
+    L.bl_eval_samples.argtypes = [vp, C.POINTER(bl_spacetime), vp, C.POINTER(bl_plasma), i64, vp, vp, vp]
+    L.bl_eval_samples.restype = C.c_int
+    L.bl_profile_enable.argtypes = [vp, C.c_int]
+    L.bl_profile_enable.restype = C.c_int
+    L.bl_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.bl_profile_read.restype = C.c_int
+    if L.bl_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"libblgpu ABI {L.bl_abi_version()} != binding ABI {ABI_VERSION}")
+    _lib = L
+    return L
+
+
+# ------------------------------------------------------------ parameters
+def camera(d):
+    c = bl_camera()
+    c.r, c.theta, c.phi = d["r"], d["theta"], d.get("phi", 0.0)
+    for k in range(3):
+        c.u_normal[k] = d.get("u_normal", (0.0, 0.0, 0.0))[k]
+        c.k_cov[k] = d.get("k_cov", (1.0, 0.0, 0.0))[k]
+    c.width, c.n = d["width"], int(d["n"])
+    c.freq_mode = int(d.get("freq_mode", 0))
+    c.psi, c.nu_hz = d.get("psi", 0.0), d.get("nu_hz", 230e9)
+    return c
+
+
+def spacetime(d):
+    s = bl_spacetime()
+    s.a, s.mass_msun, s.r_in = d["a"], d.get("mass_msun", 4.152e6), d["r_in"]
+    s.flat = int(d.get("flat", 0))
+    return s
+
+
+def integrator(d):
+    g = bl_integrator()
+    g.f_abs, g.f_rel = d.get("f_abs", 1e-8), d.get("f_rel", 1e-8)
+    g.ds_max, g.h0_frac = d.get("ds_max", 0.0), d.get("h0_frac", 0.1)
+    g.max_steps = int(d.get("max_steps", 100000))
+    g.record_cap = int(d.get("record_cap", 0))
+    return g
+
+
+def plasma(d):
+    p = bl_plasma()
+    p.mu, p.ne_ni = d.get("mu", 0.5), d.get("ne_ni", 1.0)
+    p.r_high, p.r_low = d.get("r_high", 20.0), d.get("r_low", 1.0)
+    p.sigma_max = d.get("sigma_max", 1.0)
+    p.polarized, p.interp = int(d.get("polarized", 0)), int(d.get("interp", 1))
+    return p
+
+
+def mode(precision=0, step_model=0):
+    m = bl_mode()
+    m.precision, m.step_model = int(precision), int(step_model)
+    return m
+
+
+class BlError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS_NAME.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Grid:
+    """Device-resident fluid data; keeps the primitive tensor alive."""
+
+    def __init__(self, ctx, bounds, prims, rho_unit):
+        import torch
+        self.ctx = ctx
+        self.bounds = np.ascontiguousarray(bounds, dtype=np.float64)
+        if not isinstance(prims, torch.Tensor):
+            prims = torch.from_numpy(np.ascontiguousarray(prims))
+        self.prims = prims.to(ctx.device).contiguous()
+        nb, bnz, bny, bnx, nv = self.prims.shape
+        if nv != 8 or self.bounds.shape != (nb, 6):
+            raise ValueError("prims must be [nb, bnz, bny, bnx, 8] and bounds [nb, 6]")
+        d = bl_grid_desc()
+        d.n_blocks, d.bnx, d.bny, d.bnz = nb, bnx, bny, bnz
+        d.bounds = self.bounds.ctypes.data_as(C.POINTER(C.c_double))
+        d.prims = C.c_void_p(self.prims.data_ptr())
+        d.dtype = 0 if self.prims.dtype == torch.float64 else 1
+        d.rho_unit = rho_unit
+        h = C.c_void_p()
+        ctx._check(load().bl_grid_create(ctx.handle, C.byref(d), C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            load().bl_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """A library context on one GPU, enqueuing on a torch stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = C.c_void_p()
+        st = load().bl_create(int(device), C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != 0:
+            raise BlError(st, "bl_create failed")
+        self.handle = h
+
+    def _check(self, st):
+        if st != 0:
+            raise BlError(st, load().bl_last_error(self.handle).decode())
+
+    def close(self):
+        if self.handle:
+            load().bl_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def grid(self, g):
+        """Grid from a dict(bounds, prims, rho_unit) (numpy or torch prims)."""
+        return Grid(self, g["bounds"], g["prims"], g["rho_unit"])
+
+    def _empty(self, *shape):
+        import torch
+        return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+    def camera_rays(self, cam, st, out=None):
+        n = int(cam["n"])
+        state = self._empty(n * n, 8) if out is None else out[0]
+        norm = self._empty(n * n) if out is None else out[1]
+        c, s = camera(cam), spacetime(st)
+        self._check(load().bl_camera_rays(self.handle, C.byref(c), C.byref(s), _ptr(state), _ptr(norm)))
+        return state, norm
+
+    def trace_geodesics(self, cam, st, integ):
+        n = int(cam["n"])
+        state, aux = self._empty(n * n, 8), self._empty(NAUX, n, n)
+        c, s, g = camera(cam), spacetime(st), integrator(integ)
+        self._check(load().bl_trace_geodesics(self.handle, C.byref(c), C.byref(s), C.byref(g),
+                                              _ptr(state), _ptr(aux)))
+        return state, aux
+
+    def render(self, cam, st, integ, grid, pl, precision=0, image=None, aux=None):
+        n = int(cam["n"])
+        image = self._empty(4, n, n) if image is None else image
+        aux = self._empty(NAUX, n, n) if aux is None else aux
+        c, s, g, p, m = camera(cam), spacetime(st), integrator(integ), plasma(pl), mode(precision)
+        self._check(load().bl_render(self.handle, C.byref(c), C.byref(s), C.byref(g), grid.handle,
+                                     C.byref(p), C.byref(m), _ptr(image), _ptr(aux)))
+        return image, aux
+
+    def profile_enable(self, on=True):
+        self._check(load().bl_profile_enable(self.handle, int(bool(on))))
+
+    def profile_read(self):
+        """{kernel class: (total ms, launches)} since the last read."""
+        ms = (C.c_double * NKERNEL)()
+        nl = (C.c_int64 * NKERNEL)()
+        self._check(load().bl_profile_read(self.handle, ms, nl))
+        return {KERNEL_NAMES[k]: (ms[k], nl[k]) for k in range(NKERNEL)}
+
+    def eval_samples(self, st, grid, pl, states, norms):
+        import torch
+        states = torch.as_tensor(states, dtype=torch.float64, device=self.device).contiguous()
+        norms = torch.as_tensor(norms, dtype=torch.float64, device=self.device).contiguous()
+        n = states.shape[0]
+        out = self._empty(n, NSAMPLE_OUT)
+        s, p = spacetime(st), plasma(pl)
+        self._check(load().bl_eval_samples(self.handle, C.byref(s), grid.handle, C.byref(p), n,
+                                           _ptr(states), _ptr(norms), _ptr(out)))
+        return out

@@ -1,0 +1,169 @@
+// bl_geodesic.hpp -- adaptive Dormand-Prince RK5(4)7M integration of one
+// ray per lane (paper section 2.2 and its coefficient table).
+//
+// The error of a trial step is eps = max_m |y5_m - y4_m| / (f_abs + f_rel
+// max(|y_init_m|, |y5_m|)) over the eight variables (x^mu, k_mu); eps > 1
+// rejects.  y5 - y4 is formed as h sum_i (b5_i - b4_i) k_i (no cancellation
+// of two nearly equal states).  The Shampine midpoint of the step,
+// y_mid = y0 + (h/2) sum_i bm_i k_i (the printed midpoint row sums to one), is
+// stored with the step for the transfer.  Controller: after an accepted step
+// h *= min(10, max(0.2, 0.9 eps^-1/5)) (10 for eps = 0), not growing right
+// after a rejection; after a rejection h *= max(0.2, 0.9 eps^-1/5).  Every
+// factor is rounded to a multiple of 1/4096 and the first step h0 =
+// -h0_frac r_pix uses r_pix rounded to a multiple of 2^-10: the last bits of
+// the error estimate (a sum with heavy cancellation) are rounding noise, and
+// the rounding keeps them out of the step sequence.
+// Integration runs at negative lambda from the camera and stops on an
+// accepted step with r_prev < r_cam <= r_new or r_new < r_in.
+#pragma once
+
+#include "bl_kerr.hpp"
+
+namespace bl {
+
+// Tableau (paper, Table "tab:dp").
+constexpr double A21 = 1.0 / 5.0;
+constexpr double A31 = 3.0 / 40.0, A32 = 9.0 / 40.0;
+constexpr double A41 = 44.0 / 45.0, A42 = -56.0 / 15.0, A43 = 32.0 / 9.0;
+constexpr double A51 = 19372.0 / 6561.0, A52 = -25360.0 / 2187.0, A53 = 64448.0 / 6561.0,
+                 A54 = -212.0 / 729.0;
+constexpr double A61 = 9017.0 / 3168.0, A62 = -355.0 / 33.0, A63 = 46732.0 / 5247.0, A64 = 49.0 / 176.0,
+                 A65 = -5103.0 / 18656.0;
+constexpr double B1 = 35.0 / 384.0, B3 = 500.0 / 1113.0, B4 = 125.0 / 192.0, B5 = -2187.0 / 6784.0,
+                 B6 = 11.0 / 84.0;
+constexpr double E1 = B1 - 5179.0 / 57600.0, E3 = B3 - 7571.0 / 16695.0, E4 = B4 - 393.0 / 640.0,
+                 E5 = B5 - (-92097.0 / 339200.0), E6 = B6 - 187.0 / 2100.0, E7 = 0.0 - 1.0 / 40.0;
+constexpr double M1 = 6025192743.0 / 30085553152.0, M3 = 51252292925.0 / 65400821598.0,
+                 M4 = -2691868925.0 / 45128329728.0, M5 = 187940372067.0 / 1594534317056.0,
+                 M6 = -1776094331.0 / 19743644256.0, M7 = 11237099.0 / 235043384.0;
+
+struct TraceOut {
+    int status;
+    int n_acc, n_rej;
+    double lambda, s, dt;
+};
+
+// Trace one ray from its pixel state y (x^mu, k_x, k_y, k_z; k_t = kt held
+// fixed).  Step records (16 doubles each, see below) go to rec[0..cap); the
+// final state goes to record n_acc.  A ray needing more than cap records
+// stops with status kRayOverflow.  Without WREC nothing is stored.
+//   record: [0..3] x^mu of y0, [4..6] k_a of y0, [7] h,
+//           [8..11] x^mu of y_mid, [12..14] k_a of y_mid, [15] ds of the step
+template <bool WREC>
+__device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], double kt, double *rec, int cap,
+                                          TraceOut &o) {
+    const double a = P.a;
+    const int flat = P.flat;
+    double k1[7], k2[7], k3[7], k4[7], k5[7], k6[7], k7[7], ys[7];
+    double t_pix = y[0];
+    geo_rhs(a, flat, y, kt, k1);
+    double r_prev = ks_r(a, y[1], y[2], y[3]);
+    double h = -P.h0_frac * (rint(r_prev * 1024.0) / 1024.0);
+    double lambda = 0.0, s = 0.0;
+    int nacc = 0, nrej = 0, status = kRunning;
+    bool no_grow = false;
+    while (status == kRunning) {
+        if ((long long)nacc + nrej >= P.max_steps) { status = kMaxSteps; break; }
+        if (fabs(h) < 1e-14 * (1.0 + fabs(lambda))) { status = kUnderflow; break; }
+#pragma unroll
+        for (int m = 0; m < 7; ++m) ys[m] = y[m] + h * (A21 * k1[m]);
+        geo_rhs(a, flat, ys, kt, k2);
+#pragma unroll
+        for (int m = 0; m < 7; ++m) ys[m] = y[m] + h * (A31 * k1[m] + A32 * k2[m]);
+        geo_rhs(a, flat, ys, kt, k3);
+#pragma unroll
+        for (int m = 0; m < 7; ++m) ys[m] = y[m] + h * (A41 * k1[m] + A42 * k2[m] + A43 * k3[m]);
+        geo_rhs(a, flat, ys, kt, k4);
+#pragma unroll
+        for (int m = 0; m < 7; ++m) ys[m] = y[m] + h * (A51 * k1[m] + A52 * k2[m] + A53 * k3[m] + A54 * k4[m]);
+        geo_rhs(a, flat, ys, kt, k5);
+#pragma unroll
+        for (int m = 0; m < 7; ++m)
+            ys[m] = y[m] + h * (A61 * k1[m] + A62 * k2[m] + A63 * k3[m] + A64 * k4[m] + A65 * k5[m]);
+        geo_rhs(a, flat, ys, kt, k6);
+        double y5[7];
+#pragma unroll
+        for (int m = 0; m < 7; ++m) y5[m] = y[m] + h * (B1 * k1[m] + B3 * k3[m] + B4 * k4[m] + B5 * k5[m] + B6 * k6[m]);
+        geo_rhs(a, flat, y5, kt, k7);
+        // error norm over (t, x, y, z, k_t, k_x, k_y, k_z); the k_t error is 0
+        double eps = 0.0;
+        bool bad = false;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            double err, y0m, y5m;
+            if (m < 4) {
+                err = h * (E1 * k1[m] + E3 * k3[m] + E4 * k4[m] + E5 * k5[m] + E6 * k6[m] + E7 * k7[m]);
+                y0m = y[m];
+                y5m = y5[m];
+            } else if (m == 4) {
+                err = 0.0;
+                y0m = kt;
+                y5m = kt;
+            } else {
+                int q = m - 1;
+                err = h * (E1 * k1[q] + E3 * k3[q] + E4 * k4[q] + E5 * k5[q] + E6 * k6[q] + E7 * k7[q]);
+                y0m = y[q];
+                y5m = y5[q];
+            }
+            double sc = P.f_abs + P.f_rel * fmax(fabs(y0m), fabs(y5m));
+            double e = (err == 0.0) ? 0.0 : fabs(err) / sc;
+            if (isnan(e)) bad = true;
+            else if (e > eps) eps = e;
+        }
+        bool fin = true;
+#pragma unroll
+        for (int m = 0; m < 7; ++m) fin = fin && isfinite(y5[m]);
+        if (bad || !fin) { status = kNonfinite; break; }
+        if (eps <= 1.0) {
+            if (WREC && nacc + 2 > cap) { status = kRayOverflow; break; }
+            double ym[7];
+#pragma unroll
+            for (int m = 0; m < 7; ++m)
+                ym[m] = y[m] + 0.5 * h * (M1 * k1[m] + M3 * k3[m] + M4 * k4[m] + M5 * k5[m] + M6 * k6[m] + M7 * k7[m]);
+            double ds = fabs(h) * ds_dlambda(a, flat, ym, kt);
+            if (WREC) {
+                double *r = rec + (long long)nacc * kRecDoubles;
+#pragma unroll
+                for (int m = 0; m < 7; ++m) r[m] = y[m];
+                r[7] = h;
+#pragma unroll
+                for (int m = 0; m < 7; ++m) r[8 + m] = ym[m];
+                r[15] = ds;
+            }
+            ++nacc;
+            lambda += h;
+            s += ds;
+            double fac = (eps == 0.0) ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * pow(eps, -0.2)));
+            fac = rint(fac * 4096.0) / 4096.0;
+            if (no_grow) fac = fmin(fac, 1.0);
+            no_grow = false;
+#pragma unroll
+            for (int m = 0; m < 7; ++m) {
+                y[m] = y5[m];
+                k1[m] = k7[m];
+            }
+            double r_new = ks_r(a, y[1], y[2], y[3]);
+            if (r_new < P.r_in) status = kCaptured;
+            else if (r_prev < P.r_cam && r_new >= P.r_cam) status = kEscaped;
+            r_prev = r_new;
+            h *= fac;
+        } else {
+            ++nrej;
+            h *= rint(fmax(0.2, 0.9 * pow(eps, -0.2)) * 4096.0) / 4096.0;
+            no_grow = true;
+        }
+    }
+    if (WREC && status != kRayOverflow) {
+        double *r = rec + (long long)nacc * kRecDoubles;
+#pragma unroll
+        for (int m = 0; m < 7; ++m) r[m] = y[m];
+    }
+    o.status = status;
+    o.n_acc = nacc;
+    o.n_rej = nrej;
+    o.lambda = fabs(lambda);
+    o.s = s;
+    o.dt = t_pix - y[0];
+}
+
+}  // namespace bl

@@ -1,0 +1,376 @@
+// bl_transfer.hpp -- source-to-camera radiative transfer along one traced ray
+// (one ray per lane).
+//
+// Paper section 2.2 (last paragraph): each accepted geodesic step is
+// represented by its fourth-order midpoint; a step longer than the proper
+// length limit is cut into pieces using the quartic through y0, y1, f0, f1 and
+// y_mid.  Section 2.3: unpolarized segments use the exact solution with
+// Delta tau_max = 100.  Section 2.4: polarized transfer Strang-splits every
+// segment into coordinate transport of the coherency tensor N (half, whole
+// plasma step in the fluid tetrad, half), merging adjacent transport halves
+// into one explicit-midpoint step (the paper's predictor-corrector table),
+// with the exact constant-coefficient Stokes solution for the plasma part.
+//
+// Sampling rule: a step is sampled against the grid when its chords y0-y_mid
+// or y_mid-y1 meet the grid's bounding box; it is then cut into
+// n = ceil(ds/ds_max) pieces of equal lambda whose samples are the quartic at
+// the piece centres (y_mid when n = 1).  Other steps are single vacuum
+// records.  Polarized transfer starts at the first plasma record from the
+// source; the merged transport between two records uses the previous sample
+// as predictor point and the boundary between the records as corrector point;
+// the last record is followed by a half-length transport to the pixel.
+#pragma once
+
+#include "bl_plasma.hpp"
+
+namespace bl {
+
+// ------------------------------------------------------ coherency tensor
+// Hermitian N = R + i I with R symmetric (10 entries) and I antisymmetric (6).
+__host__ __device__ constexpr int sidx(int a, int b) {
+    return a <= b ? (a == 0 ? b : (a == 1 ? 3 + b : (a == 2 ? 5 + b : 9))) : sidx(b, a);
+}
+__host__ __device__ constexpr int aidx(int a, int b) {   // a < b
+    return a == 0 ? b - 1 : (a == 1 ? 1 + b : 5);
+}
+
+struct Coh {
+    double r[10], i[6];
+};
+
+__device__ __forceinline__ double Rget(const Coh &N, int a, int b) { return N.r[sidx(a, b)]; }
+__device__ __forceinline__ double Iget(const Coh &N, int a, int b) {
+    return a == b ? 0.0 : (a < b ? N.i[aidx(a, b)] : -N.i[aidx(b, a)]);
+}
+
+// dN^ab/dlambda = -(G^a_d N^db + G^b_d N^ad), the parallel transport of N.
+__device__ __forceinline__ void transport_rhs(const double G[16], const Coh &N, Coh &dN) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a; b < 4; ++b) {
+            double s = 0.0;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) s += G[4 * a + d] * Rget(N, d, b) + G[4 * b + d] * Rget(N, a, d);
+            dN.r[sidx(a, b)] = -s;
+        }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a + 1; b < 4; ++b) {
+            double s = 0.0;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) s += G[4 * a + d] * Iget(N, d, b) + G[4 * b + d] * Iget(N, a, d);
+            dN.i[aidx(a, b)] = -s;
+        }
+}
+
+// One explicit-midpoint transport step of length dl: predictor with the
+// connection at ya, corrector at yb (states x^mu, k_mu).
+__device__ __forceinline__ void transport_step(double a, int flat, const double ya[8], const double yb[8],
+                                               double dl, Coh &N) {
+    double G[16];
+    Coh d, h;
+    conn_k(a, flat, ya, ya + 4, G);
+    transport_rhs(G, N, d);
+#pragma unroll
+    for (int m = 0; m < 10; ++m) h.r[m] = N.r[m] + 0.5 * dl * d.r[m];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) h.i[m] = N.i[m] + 0.5 * dl * d.i[m];
+    conn_k(a, flat, yb, yb + 4, G);
+    transport_rhs(G, h, d);
+#pragma unroll
+    for (int m = 0; m < 10; ++m) N.r[m] += dl * d.r[m];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) N.i[m] += dl * d.i[m];
+}
+
+// Stokes parameters of N in the screen vectors e1, e2 (contravariant) of a
+// tetrad: I = N11 + N22, Q = N11 - N22, U = 2 Re N12, V = -2 Im N12.
+__device__ __forceinline__ void coh_to_stokes(const KS &k, const double e1[4], const double e2[4], const Coh &N,
+                                              double S[4]) {
+    double p[4], q[4];
+    lower(k, e1, p);
+    lower(k, e2, q);
+    double n11 = 0.0, n22 = 0.0, n12r = 0.0, n12i = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            double R = Rget(N, a, b);
+            n11 += p[a] * p[b] * R;
+            n22 += q[a] * q[b] * R;
+            n12r += p[a] * q[b] * R;
+            n12i += p[a] * q[b] * Iget(N, a, b);
+        }
+    S[0] = n11 + n22;
+    S[1] = n11 - n22;
+    S[2] = 2.0 * n12r;
+    S[3] = -2.0 * n12i;
+}
+
+// N = 1/2 [(I+Q) e1 e1 + (I-Q) e2 e2 + (U - iV) e1 e2 + (U + iV) e2 e1]
+__device__ __forceinline__ void stokes_to_coh(const double e1[4], const double e2[4], const double S[4], Coh &N) {
+    double n11 = 0.5 * (S[0] + S[1]), n22 = 0.5 * (S[0] - S[1]), n12r = 0.5 * S[2], n12i = -0.5 * S[3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a; b < 4; ++b)
+            N.r[sidx(a, b)] = n11 * e1[a] * e1[b] + n22 * e2[a] * e2[b] + n12r * (e1[a] * e2[b] + e2[a] * e1[b]);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a + 1; b < 4; ++b) N.i[aidx(a, b)] = n12i * (e1[a] * e2[b] - e2[a] * e1[b]);
+}
+
+// Exact solution of dS/ds = J - M S over length s for thermal coefficients
+// (J = B_nu M e_I, so the fixed point is S_eq = (j_I/alpha_I) e_I):
+//   S(s) = S_eq + e^{-alpha_I s} e^{-s K'} (S0 - S_eq),
+// where K' is the traceless part of M with eigenvalues +-L1, +-i L2,
+// L1^2, L2^2 = sqrt(((a^2 - r^2)/2)^2 + (a.r)^2) +- (a^2 - r^2)/2, and
+// e^{-sK'} = [cosh(sL1) P1 + cos(sL2) P2] - K' [sinh(sL1)/L1 P1 + sin(sL2)/L2 P2]
+// with projectors P1 = (K'^2 + L2^2)/(L1^2 + L2^2), P2 = (L1^2 - K'^2)/(L1^2 + L2^2).
+// If alpha_I s >= 100 the result is S_eq.  c = jI, jQ, jV, aI, aQ, aV, rQ, rV.
+__device__ __forceinline__ void kprime(const double c[8], const double v[4], double w[4]) {
+    w[0] = c[4] * v[1] + c[5] * v[3];
+    w[1] = c[4] * v[0] + c[7] * v[2];
+    w[2] = -c[7] * v[1] + c[6] * v[3];
+    w[3] = c[5] * v[0] - c[6] * v[2];
+}
+
+__device__ __forceinline__ void stokes_step(const double c[8], double s, double S[4]) {
+    double aI = c[3];
+    double Seq = aI > 0.0 ? c[0] / aI : 0.0;
+    if (aI * s >= 100.0) {
+        S[0] = Seq;
+        S[1] = S[2] = S[3] = 0.0;
+        return;
+    }
+    double v[4] = {S[0] - Seq, S[1], S[2], S[3]};
+    double w1[4], w2[4], w3[4];
+    kprime(c, v, w1);
+    kprime(c, w1, w2);
+    kprime(c, w2, w3);
+    double al2 = c[4] * c[4] + c[5] * c[5];
+    double rh2 = c[6] * c[6] + c[7] * c[7];
+    double ar = c[4] * c[6] + c[5] * c[7];
+    double dif = 0.5 * (al2 - rh2);
+    double rt = sqrt(dif * dif + ar * ar);
+    double L1s, L2s;
+    if (dif >= 0.0) {
+        L1s = rt + dif;
+        L2s = L1s > 0.0 ? ar * ar / L1s : 0.0;
+    } else {
+        L2s = rt - dif;
+        L1s = L2s > 0.0 ? ar * ar / L2s : 0.0;
+    }
+    double Th = L1s + L2s;
+    double E = exp(-aI * s);
+    double out[4];
+    if (!(Th > 1e-12 * (al2 + rh2))) {
+        // K' (nearly) nilpotent: K'^4 ~ 0, the cubic Taylor polynomial is exact
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            out[m] = E * (v[m] - s * w1[m] + 0.5 * s * s * w2[m] - (s * s * s / 6.0) * w3[m]);
+    } else {
+        double L1 = sqrt(L1s), L2 = sqrt(L2s);
+        double ch = E * cosh(s * L1);
+        double sh = E * (L1 > 0.0 ? sinh(s * L1) / L1 : s);
+        double co = E * cos(s * L2);
+        double sn = E * (L2 > 0.0 ? sin(s * L2) / L2 : s);
+        double iT = 1.0 / Th;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            out[m] = (ch * (w2[m] + L2s * v[m]) + co * (L1s * v[m] - w2[m])
+                      - sh * (w3[m] + L2s * w1[m]) - sn * (L1s * w1[m] - w3[m])) * iT;
+    }
+    S[0] = Seq + out[0];
+    S[1] = out[1];
+    S[2] = out[2];
+    S[3] = out[3];
+}
+
+// unpolarized segment, eq. (unpolarized)
+__device__ __forceinline__ double unpol_segment(double I, double j, double al, double dl) {
+    if (al > 0.0) {
+        double dtau = al * dl;
+        if (dtau < 100.0) return exp(-dtau) * (I + expm1(dtau) * j / al);
+        return j / al;
+    }
+    return I + j * dl;
+}
+
+struct TransferOut {
+    double S[4];
+    double tau, Ij;
+    int nsamp, nrec;
+};
+
+struct TransferParams {
+    double ds_max;
+    double L;          // GM/c^2 in cm
+};
+
+// Transfer along the records of one ray (n_acc steps + final state).
+template <bool POL>
+__device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
+                                             const TransferParams &tp, const double *rec, int n_acc, double kt,
+                                             double n_norm, const double upix[4], const double Hv[4],
+                                             TransferOut &o) {
+    const double a = P.a;
+    const int flat = P.flat;
+    double I = 0.0, tau = 0.0, Ij = 0.0;
+    int nsamp = 0, nrec = 0;
+    Coh N;
+#pragma unroll
+    for (int m = 0; m < 10; ++m) N.r[m] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) N.i[m] = 0.0;
+    bool started = false;
+    double pys[8], pyb[8], pdl = 0.0;
+    double lscale = tp.L / n_norm;
+    // state on the source side of the current step
+    double y1[8];
+    {
+        const double *r = rec + (long long)n_acc * kRecDoubles;
+        y1[0] = r[0]; y1[1] = r[1]; y1[2] = r[2]; y1[3] = r[3];
+        y1[4] = kt; y1[5] = r[4]; y1[6] = r[5]; y1[7] = r[6];
+    }
+    double f1[7];
+    bool have_f1 = false;
+    for (int st = n_acc - 1; st >= 0; --st) {
+        const double *r = rec + (long long)st * kRecDoubles;
+        double y0[8], ym[8];
+        y0[0] = r[0]; y0[1] = r[1]; y0[2] = r[2]; y0[3] = r[3];
+        y0[4] = kt; y0[5] = r[4]; y0[6] = r[5]; y0[7] = r[6];
+        double h = r[7];
+        ym[0] = r[8]; ym[1] = r[9]; ym[2] = r[10]; ym[3] = r[11];
+        ym[4] = kt; ym[5] = r[12]; ym[6] = r[13]; ym[7] = r[14];
+        double ds = r[15];
+        bool inb = chord_meets_box(g.bb, y0, ym) || chord_meets_box(g.bb, ym, y1);
+        int nsub = 1;
+        if (inb && tp.ds_max > 0.0) {
+            // at most 2^24 pieces per step; a non-finite length gives one piece
+            double q = ceil(ds / tp.ds_max);
+            nsub = (q >= 1.0) ? (int)fmin(q, 16777216.0) : 1;
+        }
+        // quartic coefficients (only when the step is cut into pieces)
+        double c1[7], c2[7], c3[7], c4[7], f0[7];
+        bool have_f0 = false;
+        if (nsub > 1) {
+            double y07[7] = {y0[0], y0[1], y0[2], y0[3], y0[5], y0[6], y0[7]};
+            double y17[7] = {y1[0], y1[1], y1[2], y1[3], y1[5], y1[6], y1[7]};
+            geo_rhs(a, flat, y07, kt, f0);
+            have_f0 = true;
+            if (!have_f1) geo_rhs(a, flat, y17, kt, f1);
+#pragma unroll
+            for (int m = 0; m < 7; ++m) {
+                int q = m < 4 ? m : m + 1;
+                double A = y1[q] - y0[q] - h * f0[m];
+                double B = h * (f1[m] - f0[m]);
+                double C = 16.0 * (ym[q] - y0[q]) - 8.0 * h * f0[m];
+                c1[m] = h * f0[m];
+                c2[m] = -5.0 * A + B + C;
+                c3[m] = 14.0 * A - 3.0 * B - 2.0 * C;
+                c4[m] = -8.0 * A + 2.0 * B + C;
+            }
+        }
+        double dl = fabs(h) / (double)nsub;
+        nrec += nsub;
+        for (int p = nsub - 1; p >= 0; --p) {
+            double ys[8], yb[8];
+            if (nsub == 1) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) ys[m] = ym[m];
+            } else {
+                double th = ((double)p + 0.5) / (double)nsub;
+#pragma unroll
+                for (int m = 0; m < 7; ++m) {
+                    int q = m < 4 ? m : m + 1;
+                    ys[q] = y0[q] + th * (c1[m] + th * (c2[m] + th * (c3[m] + th * c4[m])));
+                }
+                ys[4] = kt;
+            }
+            if (p == 0) {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) yb[m] = y0[m];
+            } else {
+                double th = (double)p / (double)nsub;
+#pragma unroll
+                for (int m = 0; m < 7; ++m) {
+                    int q = m < 4 ? m : m + 1;
+                    yb[q] = y0[q] + th * (c1[m] + th * (c2[m] + th * (c3[m] + th * c4[m])));
+                }
+                yb[4] = kt;
+            }
+            Sample smp;
+            smp.plasma = false;
+            if (inb) sample_point(a, flat, g, pp, ys, n_norm, smp);
+            double dlp = lscale * dl;
+            if (!POL) {
+                if (smp.plasma) {
+                    ++nsamp;
+                    I = unpol_segment(I, smp.c[0], smp.c[3], dlp);
+                    tau += smp.c[3] * dlp;
+                    Ij += smp.c[0] * dlp;
+                }
+            } else {
+                if (!started && !smp.plasma) continue;
+                if (started) transport_step(a, flat, pys, pyb, 0.5 * (pdl + dl), N);
+                started = true;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    pys[m] = ys[m];
+                    pyb[m] = yb[m];
+                }
+                pdl = dl;
+                if (smp.plasma) {
+                    ++nsamp;
+                    tau += smp.c[3] * dlp;
+                    Ij += smp.c[0] * dlp;
+                    bool any = false;
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) any = any || (smp.c[m] != 0.0);
+                    if (any) {
+                        KS k = ks_point(a, flat, ys[1], ys[2], ys[3]);
+                        double e[4][4];
+                        tetrad(k, smp.u, ys + 4, smp.b, e);
+                        double S[4];
+                        coh_to_stokes(k, e[1], e[2], N, S);
+                        stokes_step(smp.c, dlp, S);
+                        stokes_to_coh(e[1], e[2], S, N);
+                    }
+                }
+            }
+        }
+        // this step's y0 is the next (camera-side) step's y1
+#pragma unroll
+        for (int m = 0; m < 8; ++m) y1[m] = y0[m];
+        if (have_f0) {
+#pragma unroll
+            for (int m = 0; m < 7; ++m) f1[m] = f0[m];
+        }
+        have_f1 = have_f0;
+    }
+    o.tau = tau;
+    o.Ij = Ij;
+    o.nsamp = nsamp;
+    o.nrec = nrec;
+    if (!POL) {
+        o.S[0] = I;
+        o.S[1] = o.S[2] = o.S[3] = 0.0;
+    } else {
+        o.S[0] = o.S[1] = o.S[2] = o.S[3] = 0.0;
+        if (started) {
+            // y1 now holds the pixel state
+            transport_step(a, flat, pys, y1, 0.5 * pdl, N);
+            KS k = ks_point(a, flat, y1[1], y1[2], y1[3]);
+            double mH[4] = {-Hv[0], -Hv[1], -Hv[2], -Hv[3]};
+            double e[4][4];
+            tetrad(k, upix, y1 + 4, mH, e);
+            coh_to_stokes(k, e[1], e[2], N, o.S);
+        }
+    }
+}
+
+}  // namespace bl

@@ -1,0 +1,783 @@
+// blgpu.hip -- kernels and C ABI of libblgpu (declarations in include/blgpu.h).
+//
+// Work layout: one ray per lane.  For an image the pixels are processed in
+// chunks; per chunk one kernel integrates the geodesics and writes 128-byte
+// step records (one cache line each, per-ray contiguous so the backward walk
+// of the transfer reads whole lines), then a second kernel walks each ray's
+// records from source to camera.  Rays that need more records than the
+// per-ray slot holds are queued and finished by a single-wave kernel that
+// traces and transfers them one by one with a private record buffer sized
+// for max_steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/blgpu.h"
+#include "bl_transfer.hpp"
+#include "bl_geodesic.hpp"
+
+using namespace bl;
+
+// ============================================================ camera frame
+// Camera frame of the paper's section 2.1 (single lane, once per image):
+// centre from spherical KS, covariant k_a = (J^-1)^i_a k_i, k_t from the null
+// condition (future directed), camera-frame metric g_a'b' and g^a'b', K from
+// k_a - (u_a/u_t) k_t normalised by g^a'b', v from U = z (y on the polar
+// axis) by Gram-Schmidt, h = D^-1/2 [abc] v_b' K_c', rotation by psi, and the
+// return to coordinate components A^t = u^t A^t' - (u_a/u_t) A^a',
+// A^a = A^a' + u^a A^t'.
+__global__ void k_camera_frame(CamParams cp, double a, int flat, Frame *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    Frame fr;
+    double st = sin(cp.theta), ct = cos(cp.theta), sp = sin(cp.phi), cph = cos(cp.phi);
+    double r = cp.r;
+    fr.xc[0] = 0.0;
+    fr.xc[1] = st * (r * cph - a * sp);
+    fr.xc[2] = st * (r * sp + a * cph);
+    fr.xc[3] = r * ct;
+    double J[3][3] = {{st * cph, ct * (r * cph - a * sp), st * (-r * sp - a * cph)},
+                      {st * sp, ct * (r * sp + a * cph), st * (r * cph - a * sp)},
+                      {ct, -r * st, 0.0}};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) fr.ut[i] = J[i][0] * cp.u_normal[0] + J[i][1] * cp.u_normal[1] + J[i][2] * cp.u_normal[2];
+    // covariant spatial k: solve J^T k = k_sph
+    double kl[4];
+    if (st != 0.0) {
+        double M[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) M[i][j] = J[j][i];
+        double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                     M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+        for (int c = 0; c < 3; ++c) {
+            double T[3][3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) T[i][j] = (j == c) ? cp.k_cov[i] : M[i][j];
+            kl[1 + c] = (T[0][0] * (T[1][1] * T[2][2] - T[1][2] * T[2][1]) - T[0][1] * (T[1][0] * T[2][2] - T[1][2] * T[2][0]) +
+                         T[0][2] * (T[1][0] * T[2][1] - T[1][1] * T[2][0])) / det;
+        }
+    } else {
+        double w0 = J[0][1], w1 = J[1][1], ww = w0 * w0 + w1 * w1;
+        kl[3] = cp.k_cov[0] / J[2][0];
+        kl[1] = ww > 0.0 ? cp.k_cov[1] * w0 / ww : 0.0;
+        kl[2] = ww > 0.0 ? cp.k_cov[1] * w1 / ww : 0.0;
+    }
+    KS k = ks_point(a, flat, fr.xc[1], fr.xc[2], fr.xc[3]);
+    double g[4][4], gi[4][4];
+    double ll[4] = {1.0, k.l[0], k.l[1], k.l[2]}, lu[4] = {-1.0, k.l[0], k.l[1], k.l[2]};
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double eta = (i == j) ? (i == 0 ? -1.0 : 1.0) : 0.0;
+            g[i][j] = eta + k.f * ll[i] * ll[j];
+            gi[i][j] = eta - k.f * lu[i] * lu[j];
+        }
+    velocity_from_normal(k, fr.ut, fr.u);
+    double ul[4];
+    lower(k, fr.u, ul);
+    double A = gi[0][0], B = gi[0][1] * kl[1] + gi[0][2] * kl[2] + gi[0][3] * kl[3], C = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) C += gi[1 + i][1 + j] * kl[1 + i] * kl[1 + j];
+    kl[0] = (-B + sqrt(B * B - A * C)) / A;
+    double gp[3][3], gpi[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            gp[i][j] = g[1 + i][1 + j] - ul[1 + i] / ul[0] * g[0][1 + j] - ul[1 + j] / ul[0] * g[0][1 + i] +
+                       ul[1 + i] * ul[1 + j] * g[0][0] / (ul[0] * ul[0]);
+            gpi[i][j] = gi[1 + i][1 + j] + fr.u[1 + i] * fr.u[1 + j];
+        }
+    double Kl[3], Ku[3], Kt = 0.0, nrm = 0.0;
+    for (int i = 0; i < 3; ++i) Kl[i] = kl[1 + i] - ul[1 + i] / ul[0] * kl[0];
+    for (int i = 0; i < 4; ++i) Kt -= fr.u[i] * kl[i];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) nrm += gpi[i][j] * Kl[i] * Kl[j];
+    nrm = 1.0 / sqrt(nrm);
+    for (int i = 0; i < 3; ++i) Kl[i] *= nrm;
+    Kt *= nrm;
+    for (int i = 0; i < 3; ++i) Ku[i] = gpi[i][0] * Kl[0] + gpi[i][1] * Kl[1] + gpi[i][2] * Kl[2];
+    double U[3] = {0.0, 0.0, 1.0};
+    if (fr.xc[1] == 0.0 && fr.xc[2] == 0.0) {
+        U[1] = 1.0;
+        U[2] = 0.0;
+    }
+    double UK = U[0] * Kl[0] + U[1] * Kl[1] + U[2] * Kl[2];
+    double vu[3], vl[3];
+    for (int i = 0; i < 3; ++i) vu[i] = U[i] - UK * Ku[i];
+    for (int i = 0; i < 3; ++i) vl[i] = gp[i][0] * vu[0] + gp[i][1] * vu[1] + gp[i][2] * vu[2];
+    nrm = 1.0 / sqrt(vl[0] * vu[0] + vl[1] * vu[1] + vl[2] * vu[2]);
+    for (int i = 0; i < 3; ++i) {
+        vu[i] *= nrm;
+        vl[i] *= nrm;
+    }
+    double D = gp[0][0] * (gp[1][1] * gp[2][2] - gp[1][2] * gp[2][1]) - gp[0][1] * (gp[1][0] * gp[2][2] - gp[1][2] * gp[2][0]) +
+               gp[0][2] * (gp[1][0] * gp[2][1] - gp[1][1] * gp[2][0]);
+    double isd = 1.0 / sqrt(D);
+    double hu[3] = {(vl[1] * Kl[2] - vl[2] * Kl[1]) * isd, (vl[2] * Kl[0] - vl[0] * Kl[2]) * isd,
+                    (vl[0] * Kl[1] - vl[1] * Kl[0]) * isd};
+    double cps = cos(cp.psi), sps = sin(cp.psi);
+    double Hp[3], Vp[3];
+    for (int i = 0; i < 3; ++i) {
+        Hp[i] = hu[i] * cps - vu[i] * sps;
+        Vp[i] = vu[i] * cps + hu[i] * sps;
+    }
+    fr.K[0] = fr.u[0] * Kt;
+    fr.H[0] = 0.0;
+    fr.V[0] = 0.0;
+    for (int b = 0; b < 3; ++b) {
+        fr.K[0] -= ul[1 + b] / ul[0] * Ku[b];
+        fr.H[0] -= ul[1 + b] / ul[0] * Hp[b];
+        fr.V[0] -= ul[1 + b] / ul[0] * Vp[b];
+    }
+    for (int i = 0; i < 3; ++i) {
+        fr.K[1 + i] = Ku[i] + fr.u[1 + i] * Kt;
+        fr.H[1 + i] = Hp[i];
+        fr.V[1 + i] = Vp[i];
+    }
+    fr.pad = 0.0;
+    *out = fr;
+}
+
+__global__ void k_camera_rays(CamParams cp, double a, int flat, const Frame *__restrict__ frp,
+                              double *__restrict__ state_out, double *__restrict__ norm_out) {
+    long long NN = (long long)cp.n * cp.n;
+    long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pix >= NN) return;
+    Frame fr = *frp;
+    double y[8], n;
+    camera_pixel(fr, cp, a, flat, (int)(pix % cp.n), (int)(pix / cp.n), y, n);
+    for (int m = 0; m < 8; ++m) state_out[pix * 8 + m] = y[m];
+    norm_out[pix] = n;
+}
+
+__global__ void k_fill_int(int *p, int v, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ============================================================ geodesics
+// One lane per ray of the chunk [start, start + count).  With WREC the step
+// records are written into the lane's slot; rays that outgrow the slot are
+// queued on ovf_list.
+template <bool WREC>
+__global__ void __launch_bounds__(64) k_geodesic(GeoParams P, CamParams cp, const Frame *__restrict__ frp,
+                                                 long long start, int count, double *__restrict__ rec,
+                                                 double *__restrict__ meta, int *__restrict__ nacc_out,
+                                                 int *__restrict__ ovf_count, int *__restrict__ ovf_list,
+                                                 double *__restrict__ aux, double *__restrict__ state_out) {
+    int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= count) return;
+    long long pix = start + slot;
+    long long NN = (long long)cp.n * cp.n;
+    const Frame &fr = *frp;
+    double y8[8], n;
+    camera_pixel(fr, cp, P.a, P.flat, (int)(pix % cp.n), (int)(pix / cp.n), y8, n);
+    double y[7] = {y8[0], y8[1], y8[2], y8[3], y8[5], y8[6], y8[7]};
+    double kt = y8[4];
+    TraceOut o;
+    trace_ray<WREC>(P, y, kt, WREC ? rec + (long long)slot * P.cap * kRecDoubles : nullptr, P.cap, o);
+    if (WREC) {
+        meta[2 * slot] = kt;
+        meta[2 * slot + 1] = n;
+        if (o.status == kRayOverflow) {
+            nacc_out[slot] = -1;
+            int idx = atomicAdd(ovf_count, 1);
+            ovf_list[idx] = (int)pix;
+            return;
+        }
+        nacc_out[slot] = o.n_acc;
+    }
+    aux[BL_AUX_DT * NN + pix] = o.dt;
+    aux[BL_AUX_S * NN + pix] = o.s;
+    aux[BL_AUX_LAMBDA * NN + pix] = o.lambda;
+    aux[BL_AUX_NACC * NN + pix] = (double)o.n_acc;
+    aux[BL_AUX_NREJ * NN + pix] = (double)o.n_rej;
+    aux[BL_AUX_STATUS * NN + pix] = (double)o.status;
+    if (!WREC) {
+        aux[BL_AUX_TAU * NN + pix] = 0.0;
+        aux[BL_AUX_IJ * NN + pix] = 0.0;
+        aux[BL_AUX_NSAMP * NN + pix] = 0.0;
+        aux[BL_AUX_NREC * NN + pix] = 0.0;
+        if (state_out) {
+            state_out[pix * 8 + 0] = y[0];
+            state_out[pix * 8 + 1] = y[1];
+            state_out[pix * 8 + 2] = y[2];
+            state_out[pix * 8 + 3] = y[3];
+            state_out[pix * 8 + 4] = kt;
+            state_out[pix * 8 + 5] = y[4];
+            state_out[pix * 8 + 6] = y[5];
+            state_out[pix * 8 + 7] = y[6];
+        }
+    }
+}
+
+__device__ __forceinline__ void write_pixel(const TransferOut &t, double nu3, long long NN, long long pix,
+                                            double *image, double *aux) {
+    for (int q = 0; q < 4; ++q) image[q * NN + pix] = nu3 * t.S[q];
+    aux[BL_AUX_TAU * NN + pix] = t.tau;
+    aux[BL_AUX_IJ * NN + pix] = nu3 * t.Ij;
+    aux[BL_AUX_NSAMP * NN + pix] = (double)t.nsamp;
+    aux[BL_AUX_NREC * NN + pix] = (double)t.nrec;
+}
+
+__device__ __forceinline__ void pixel_observer(const Frame &fr, const GeoParams &P, const double *rec0, double upix[4]) {
+    KS k = ks_point(P.a, P.flat, rec0[1], rec0[2], rec0[3]);
+    velocity_from_normal(k, fr.ut, upix);
+}
+
+template <bool POL>
+__global__ void __launch_bounds__(64) k_transfer(GeoParams P, CamParams cp, DevGrid g, PlasmaParams pp,
+                                                 TransferParams tp, const Frame *__restrict__ frp, long long start,
+                                                 int count, const double *__restrict__ rec,
+                                                 const double *__restrict__ meta, const int *__restrict__ nacc,
+                                                 double *__restrict__ image, double *__restrict__ aux) {
+    int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= count) return;
+    int na = nacc[slot];
+    if (na < 0) return;   // finished by the overflow kernel
+    long long pix = start + slot;
+    long long NN = (long long)cp.n * cp.n;
+    const Frame &fr = *frp;
+    const double *r = rec + (long long)slot * P.cap * kRecDoubles;
+    double upix[4];
+    pixel_observer(fr, P, r, upix);
+    TransferOut t;
+    transfer_ray<POL>(P, g, pp, tp, r, na, meta[2 * slot], meta[2 * slot + 1], upix, fr.H, t);
+    write_pixel(t, cp.nu * cp.nu * cp.nu, NN, pix, image, aux);
+}
+
+// Rays queued by k_geodesic: one wave, each lane traces and transfers its
+// rays in turn with a private buffer of big_cap records.
+template <bool POL>
+__global__ void __launch_bounds__(64) k_overflow(GeoParams P, CamParams cp, DevGrid g, PlasmaParams pp,
+                                                 TransferParams tp, const Frame *__restrict__ frp,
+                                                 const int *__restrict__ ovf_count, const int *__restrict__ ovf_list,
+                                                 double *__restrict__ big_rec, int big_cap,
+                                                 double *__restrict__ image, double *__restrict__ aux) {
+    int lane = threadIdx.x;
+    int total = *ovf_count;
+    long long NN = (long long)cp.n * cp.n;
+    const Frame &fr = *frp;
+    double *r = big_rec + (long long)lane * big_cap * kRecDoubles;
+    GeoParams Q = P;
+    Q.cap = big_cap;
+    for (int idx = lane; idx < total; idx += blockDim.x) {
+        long long pix = ovf_list[idx];
+        double y8[8], n;
+        camera_pixel(fr, cp, P.a, P.flat, (int)(pix % cp.n), (int)(pix / cp.n), y8, n);
+        double y[7] = {y8[0], y8[1], y8[2], y8[3], y8[5], y8[6], y8[7]};
+        double kt = y8[4];
+        TraceOut o;
+        trace_ray<true>(Q, y, kt, r, big_cap, o);
+        aux[BL_AUX_DT * NN + pix] = o.dt;
+        aux[BL_AUX_S * NN + pix] = o.s;
+        aux[BL_AUX_LAMBDA * NN + pix] = o.lambda;
+        aux[BL_AUX_NACC * NN + pix] = (double)o.n_acc;
+        aux[BL_AUX_NREJ * NN + pix] = (double)o.n_rej;
+        aux[BL_AUX_STATUS * NN + pix] = (double)o.status;
+        double upix[4];
+        pixel_observer(fr, P, r, upix);
+        TransferOut t;
+        transfer_ray<POL>(P, g, pp, tp, r, o.n_acc, kt, n, upix, fr.H, t);
+        write_pixel(t, cp.nu * cp.nu * cp.nu, NN, pix, image, aux);
+    }
+}
+
+// ============================================================ per-sample check
+__global__ void k_eval_samples(double a, int flat, DevGrid g, PlasmaParams pp, long long n,
+                               const double *__restrict__ states, const double *__restrict__ norms,
+                               double *__restrict__ out) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double y[8];
+    for (int m = 0; m < 8; ++m) y[m] = states[i * 8 + m];
+    double *o = out + i * BL_NSAMPLE_OUT;
+    for (int m = 0; m < BL_NSAMPLE_OUT; ++m) o[m] = 0.0;
+    double y7[7] = {y[0], y[1], y[2], y[3], y[5], y[6], y[7]}, dy[7];
+    geo_rhs(a, flat, y7, y[4], dy);
+    o[0] = dy[0]; o[1] = dy[1]; o[2] = dy[2]; o[3] = dy[3];
+    o[4] = 0.0; o[5] = dy[4]; o[6] = dy[5]; o[7] = dy[6];
+    double G[16];
+    conn_k(a, flat, y, y + 4, G);
+    for (int m = 0; m < 16; ++m) o[8 + m] = G[m];
+    Sample s;
+    sample_point(a, flat, g, pp, y, norms[i], s);
+    o[53] = s.sigma;
+    if (!s.plasma) return;
+    for (int m = 0; m < 8; ++m) o[24 + m] = s.c[m];
+    o[32] = s.ne; o[33] = s.th; o[34] = s.B; o[35] = s.nu_fl;
+    KS k = ks_point(a, flat, y[1], y[2], y[3]);
+    double e[4][4];
+    tetrad(k, s.u, y + 4, s.b, e);
+    for (int q = 0; q < 4; ++q)
+        for (int m = 0; m < 4; ++m) o[36 + 4 * q + m] = e[q][m];
+    o[52] = 1.0;
+}
+
+// ============================================================ host side
+struct bl_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    Frame *d_frame = nullptr;
+    double *d_rec = nullptr;
+    size_t rec_bytes = 0;
+    double *d_meta = nullptr;
+    int *d_nacc = nullptr;
+    size_t slot_cap = 0;
+    int *d_ovf_count = nullptr;
+    int *d_ovf_list = nullptr;
+    size_t ovf_cap = 0;
+    double *d_big = nullptr;
+    size_t big_bytes = 0;
+    size_t ws_limit = (size_t)8 << 30;   // bytes of step records per chunk
+    bool prof = false;
+    struct Timed {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Timed> timed;
+};
+
+struct bl_grid {
+    bl_context *ctx = nullptr;
+    DevGrid g{};
+    double *d_bmeta = nullptr;
+    int *d_table = nullptr;
+};
+
+namespace {
+
+bl_status fail(bl_context *ctx, bl_status s, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? BL_E_OOM : BL_E_DEVICE,                   \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                        \
+    } while (0)
+
+bl_status check_camera(bl_context *ctx, const bl_camera *cam) {
+    if (!cam) return fail(ctx, BL_E_INVALID_ARG, "camera is NULL");
+    if (cam->n < 1 || cam->n > 16384) return fail(ctx, BL_E_INVALID_ARG, "camera n must be in 1..16384");
+    if (!(cam->width > 0.0) || !(cam->r > 0.0) || !(cam->nu_hz > 0.0))
+        return fail(ctx, BL_E_INVALID_ARG, "camera width, r and nu_hz must be positive");
+    if (cam->freq_mode != 0 && cam->freq_mode != 1) return fail(ctx, BL_E_INVALID_ARG, "freq_mode must be 0 or 1");
+    return BL_OK;
+}
+
+bl_status check_spacetime(bl_context *ctx, const bl_spacetime *st) {
+    if (!st) return fail(ctx, BL_E_INVALID_ARG, "spacetime is NULL");
+    if (!(std::fabs(st->a) < 1.0)) return fail(ctx, BL_E_INVALID_ARG, "spin must satisfy |a| < 1");
+    if (!(st->mass_msun > 0.0)) return fail(ctx, BL_E_INVALID_ARG, "mass_msun must be positive");
+    if (!(st->r_in >= 0.0)) return fail(ctx, BL_E_INVALID_ARG, "r_in must be >= 0");
+    return BL_OK;
+}
+
+bl_status check_integrator(bl_context *ctx, const bl_integrator *in) {
+    if (!in) return fail(ctx, BL_E_INVALID_ARG, "integrator is NULL");
+    if (!(in->f_abs >= 0.0) || !(in->f_rel >= 0.0) || !(in->ds_max >= 0.0) || !(in->h0_frac > 0.0))
+        return fail(ctx, BL_E_INVALID_ARG, "tolerances and ds_max must be >= 0, h0_frac > 0");
+    if (in->max_steps < 1 || in->max_steps > (int64_t)1 << 30)
+        return fail(ctx, BL_E_INVALID_ARG, "max_steps must be in 1..2^30");
+    if (in->record_cap < 0 || in->record_cap == 1) return fail(ctx, BL_E_INVALID_ARG, "record_cap must be 0 or >= 2");
+    return BL_OK;
+}
+
+CamParams cam_params(const bl_camera *c) {
+    CamParams p;
+    p.r = c->r;
+    p.theta = c->theta;
+    p.phi = c->phi;
+    for (int i = 0; i < 3; ++i) {
+        p.u_normal[i] = c->u_normal[i];
+        p.k_cov[i] = c->k_cov[i];
+    }
+    p.width = c->width;
+    p.psi = c->psi;
+    p.nu = c->nu_hz;
+    p.n = c->n;
+    p.freq_mode = c->freq_mode;
+    return p;
+}
+
+GeoParams geo_params(const bl_camera *c, const bl_spacetime *st, const bl_integrator *in) {
+    GeoParams P;
+    P.a = st->a;
+    P.r_in = st->r_in;
+    P.r_cam = c->r;
+    P.f_abs = in ? in->f_abs : 1e-8;
+    P.f_rel = in ? in->f_rel : 1e-8;
+    P.h0_frac = in ? in->h0_frac : 0.01;
+    P.max_steps = in ? in->max_steps : 100000;
+    P.flat = st->flat ? 1 : 0;
+    P.cap = (in && in->record_cap > 0) ? in->record_cap : 512;
+    P.n = c->n;
+    P.pad = 0;
+    return P;
+}
+
+template <typename T>
+bl_status ensure(bl_context *ctx, T **p, size_t &have, size_t need_bytes) {
+    if (have >= need_bytes && *p) return BL_OK;
+    if (*p) {
+        HIPCHK(ctx, hipFree(*p));
+        *p = nullptr;
+        have = 0;
+    }
+    HIPCHK(ctx, hipMalloc((void **)p, need_bytes));
+    have = need_bytes;
+    return BL_OK;
+}
+
+// Event pair around one launch when timing is on.
+struct TimedLaunch {
+    bl_context *ctx;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(bl_context *c, int k) : ctx(c), kind(k) {
+        if (!ctx->prof) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            a = b = nullptr;
+            return;
+        }
+        (void)hipEventRecord(a, ctx->stream);
+    }
+    ~TimedLaunch() {
+        if (!a) return;
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->timed.push_back({kind, a, b});
+    }
+};
+
+bl_status launch_frame(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st) {
+    if (!ctx->d_frame) HIPCHK(ctx, hipMalloc((void **)&ctx->d_frame, sizeof(Frame)));
+    {
+        TimedLaunch tl(ctx, BL_K_SETUP);
+        hipLaunchKernelGGL(k_camera_frame, dim3(1), dim3(64), 0, ctx->stream, cam_params(cam), st->a,
+                           st->flat ? 1 : 0, ctx->d_frame);
+    }
+    HIPCHK(ctx, hipGetLastError());
+    return BL_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+int bl_abi_version(void) { return BLGPU_ABI_VERSION; }
+
+bl_status bl_create(int device, void *hip_stream, bl_context **out) {
+    if (!out) return BL_E_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return BL_E_DEVICE;
+    bl_context *ctx = new (std::nothrow) bl_context();
+    if (!ctx) return BL_E_OOM;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete ctx;
+        return BL_E_DEVICE;
+    }
+    *out = ctx;
+    return BL_OK;
+}
+
+void bl_destroy(bl_context *ctx) {
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    for (auto &t : ctx->timed) {
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+    }
+    hipFree(ctx->d_frame);
+    hipFree(ctx->d_rec);
+    hipFree(ctx->d_meta);
+    hipFree(ctx->d_nacc);
+    hipFree(ctx->d_ovf_count);
+    hipFree(ctx->d_ovf_list);
+    hipFree(ctx->d_big);
+    delete ctx;
+}
+
+const char *bl_last_error(const bl_context *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+bl_status bl_grid_create(bl_context *ctx, const bl_grid_desc *d, bl_grid **out) {
+    if (!ctx || !d || !out) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (d->n_blocks < 1 || d->bnx < 2 || d->bny < 2 || d->bnz < 2)
+        return fail(ctx, BL_E_INVALID_ARG, "need n_blocks >= 1 and at least 2 cells per block axis");
+    if (!d->bounds || !d->prims) return fail(ctx, BL_E_INVALID_ARG, "bounds and prims must be non-NULL");
+    if (d->dtype != 0 && d->dtype != 1) return fail(ctx, BL_E_INVALID_ARG, "dtype must be 0 (f64) or 1 (f32)");
+    if (!(d->rho_unit > 0.0)) return fail(ctx, BL_E_INVALID_ARG, "rho_unit must be positive");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    int nb = d->n_blocks;
+    DevGrid g{};
+    double bb[6] = {1e300, -1e300, 1e300, -1e300, 1e300, -1e300};
+    double tb[3] = {1e300, 1e300, 1e300};
+    for (int b = 0; b < nb; ++b)
+        for (int c = 0; c < 3; ++c) {
+            double lo = d->bounds[6 * b + 2 * c], hi = d->bounds[6 * b + 2 * c + 1];
+            if (!(hi > lo)) return fail(ctx, BL_E_INVALID_ARG, "block bounds must satisfy x1 > x0");
+            bb[2 * c] = std::min(bb[2 * c], lo);
+            bb[2 * c + 1] = std::max(bb[2 * c + 1], hi);
+            tb[c] = std::min(tb[c], hi - lo);
+        }
+    long long tn[3];
+    for (int c = 0; c < 3; ++c) {
+        double q = (bb[2 * c + 1] - bb[2 * c]) / tb[c];
+        tn[c] = std::llround(q);
+        if (std::fabs(q - (double)tn[c]) > 1e-9 * q || tn[c] < 1)
+            return fail(ctx, BL_E_UNSUPPORTED, "blocks are not aligned to a lattice of the smallest block size");
+    }
+    if (tn[0] * tn[1] * tn[2] > (1LL << 24)) return fail(ctx, BL_E_UNSUPPORTED, "block lattice larger than 2^24 cells");
+    std::vector<int> table((size_t)(tn[0] * tn[1] * tn[2]), -1);
+    std::vector<double> bmeta((size_t)nb * 6);
+    int nn[3] = {d->bnx, d->bny, d->bnz};
+    for (int b = 0; b < nb; ++b) {
+        long long lo[3], hi[3];
+        for (int c = 0; c < 3; ++c) {
+            double x0 = d->bounds[6 * b + 2 * c], x1 = d->bounds[6 * b + 2 * c + 1];
+            double ql = (x0 - bb[2 * c]) / tb[c], qh = (x1 - bb[2 * c]) / tb[c];
+            lo[c] = std::llround(ql);
+            hi[c] = std::llround(qh);
+            if (std::fabs(ql - lo[c]) > 1e-9 * (1.0 + ql) || std::fabs(qh - hi[c]) > 1e-9 * (1.0 + qh))
+                return fail(ctx, BL_E_UNSUPPORTED, "block not aligned to the block lattice");
+            bmeta[6 * b + c] = x0;
+            bmeta[6 * b + 3 + c] = (x1 - x0) / nn[c];
+        }
+        for (long long k = lo[2]; k < hi[2]; ++k)
+            for (long long j = lo[1]; j < hi[1]; ++j)
+                for (long long i = lo[0]; i < hi[0]; ++i) {
+                    int &t = table[(size_t)((k * tn[1] + j) * tn[0] + i)];
+                    if (t >= 0) return fail(ctx, BL_E_INVALID_ARG, "blocks overlap");
+                    t = b;
+                }
+    }
+    bl_grid *gr = new (std::nothrow) bl_grid();
+    if (!gr) return fail(ctx, BL_E_OOM, "host allocation failed");
+    gr->ctx = ctx;
+    hipError_t e1 = hipMalloc((void **)&gr->d_bmeta, bmeta.size() * sizeof(double));
+    hipError_t e2 = hipMalloc((void **)&gr->d_table, table.size() * sizeof(int));
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        hipFree(gr->d_bmeta);
+        hipFree(gr->d_table);
+        delete gr;
+        return fail(ctx, BL_E_OOM, "device allocation of the block tables failed");
+    }
+    HIPCHK(ctx, hipMemcpy(gr->d_bmeta, bmeta.data(), bmeta.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(gr->d_table, table.data(), table.size() * sizeof(int), hipMemcpyHostToDevice));
+    g.prims = d->prims;
+    g.bmeta = gr->d_bmeta;
+    g.table = gr->d_table;
+    for (int c = 0; c < 6; ++c) g.bb[c] = bb[c];
+    for (int c = 0; c < 3; ++c) {
+        g.t0[c] = bb[2 * c];
+        g.tb[c] = tb[c];
+        g.tn[c] = (int)tn[c];
+    }
+    g.nb = nb;
+    g.bnx = d->bnx;
+    g.bny = d->bny;
+    g.bnz = d->bnz;
+    g.dtype = d->dtype;
+    g.rho_unit = d->rho_unit;
+    gr->g = g;
+    *out = gr;
+    return BL_OK;
+}
+
+void bl_grid_destroy(bl_grid *gr) {
+    if (!gr) return;
+    if (gr->ctx) hipSetDevice(gr->ctx->device);
+    hipFree(gr->d_bmeta);
+    hipFree(gr->d_table);
+    delete gr;
+}
+
+bl_status bl_camera_rays(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st, double *state_out,
+                         double *norm_out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    bl_status s;
+    if ((s = check_camera(ctx, cam)) != BL_OK || (s = check_spacetime(ctx, st)) != BL_OK) return s;
+    if (!state_out || !norm_out) return fail(ctx, BL_E_INVALID_ARG, "output pointers must be non-NULL");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if ((s = launch_frame(ctx, cam, st)) != BL_OK) return s;
+    long long NN = (long long)cam->n * cam->n;
+    hipLaunchKernelGGL(k_camera_rays, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, ctx->stream, cam_params(cam),
+                       st->a, st->flat ? 1 : 0, ctx->d_frame, state_out, norm_out);
+    HIPCHK(ctx, hipGetLastError());
+    return BL_OK;
+}
+
+bl_status bl_trace_geodesics(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
+                             const bl_integrator *integ, double *state_out, double *aux_out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    bl_status s;
+    if ((s = check_camera(ctx, cam)) != BL_OK || (s = check_spacetime(ctx, st)) != BL_OK ||
+        (s = check_integrator(ctx, integ)) != BL_OK)
+        return s;
+    if (!state_out || !aux_out) return fail(ctx, BL_E_INVALID_ARG, "output pointers must be non-NULL");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if ((s = launch_frame(ctx, cam, st)) != BL_OK) return s;
+    long long NN = (long long)cam->n * cam->n;
+    GeoParams P = geo_params(cam, st, integ);
+    const long long chunk = 1 << 20;
+    for (long long start = 0; start < NN; start += chunk) {
+        int count = (int)std::min(chunk, NN - start);
+        TimedLaunch tl(ctx, BL_K_GEODESIC);
+        hipLaunchKernelGGL(k_geodesic<false>, dim3((count + 63) / 64), dim3(64), 0, ctx->stream, P, cam_params(cam),
+                           ctx->d_frame, start, count, nullptr, nullptr, nullptr, nullptr, nullptr, aux_out,
+                           state_out);
+        HIPCHK(ctx, hipGetLastError());
+    }
+    return BL_OK;
+}
+
+bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st, const bl_integrator *integ,
+                    const bl_grid *grid, const bl_plasma *plasma, const bl_mode *mode, double *image_out,
+                    double *aux_out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    bl_status s;
+    if ((s = check_camera(ctx, cam)) != BL_OK || (s = check_spacetime(ctx, st)) != BL_OK ||
+        (s = check_integrator(ctx, integ)) != BL_OK)
+        return s;
+    if (!grid || !plasma || !image_out || !aux_out) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
+    if (mode && (mode->precision != 0 || mode->step_model != 0))
+        return fail(ctx, BL_E_UNSUPPORTED, "only precision 0 and step_model 0 are available");
+    if (grid->g.dtype != 0) return fail(ctx, BL_E_UNSUPPORTED, "float32 grids need precision 1");
+    if (!(plasma->mu > 0.0) || !(plasma->ne_ni > 0.0) || !(plasma->sigma_max >= 0.0))
+        return fail(ctx, BL_E_INVALID_ARG, "plasma mu, ne_ni must be positive and sigma_max >= 0");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if ((s = launch_frame(ctx, cam, st)) != BL_OK) return s;
+    long long NN = (long long)cam->n * cam->n;
+    GeoParams P = geo_params(cam, st, integ);
+    size_t rec_per_ray = (size_t)P.cap * kRecDoubles * sizeof(double);
+    long long chunk = (long long)(ctx->ws_limit / rec_per_ray);
+    chunk = std::max(64LL, chunk - chunk % 64);
+    chunk = std::min(chunk, (NN + 63) / 64 * 64);
+    if ((s = ensure(ctx, &ctx->d_rec, ctx->rec_bytes, (size_t)chunk * rec_per_ray)) != BL_OK) return s;
+    size_t have_meta = ctx->slot_cap * 2 * sizeof(double), have_nacc = ctx->slot_cap * sizeof(int);
+    if ((s = ensure(ctx, &ctx->d_meta, have_meta, (size_t)chunk * 2 * sizeof(double))) != BL_OK) return s;
+    if ((s = ensure(ctx, &ctx->d_nacc, have_nacc, (size_t)chunk * sizeof(int))) != BL_OK) return s;
+    ctx->slot_cap = std::min(have_meta / (2 * sizeof(double)), have_nacc / sizeof(int));
+    size_t one = sizeof(int);
+    size_t have_cnt = ctx->d_ovf_count ? one : 0;
+    if ((s = ensure(ctx, &ctx->d_ovf_count, have_cnt, one)) != BL_OK) return s;
+    if ((s = ensure(ctx, &ctx->d_ovf_list, ctx->ovf_cap, (size_t)NN * sizeof(int))) != BL_OK) return s;
+    int big_cap = (int)std::min<long long>(P.max_steps + 1, 1LL << 30);
+    if ((s = ensure(ctx, &ctx->d_big, ctx->big_bytes, (size_t)64 * big_cap * kRecDoubles * sizeof(double))) != BL_OK)
+        return s;
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, ctx->d_ovf_count, 0, 1);
+    HIPCHK(ctx, hipGetLastError());
+    PlasmaParams pp;
+    pp.mu = plasma->mu;
+    pp.ne_ni = plasma->ne_ni;
+    pp.r_high = plasma->r_high;
+    pp.r_low = plasma->r_low;
+    pp.sigma_max = plasma->sigma_max;
+    pp.mass_msun = st->mass_msun;
+    pp.polarized = plasma->polarized ? 1 : 0;
+    pp.interp = plasma->interp ? 1 : 0;
+    TransferParams tp;
+    tp.ds_max = integ->ds_max;
+    tp.L = kG * st->mass_msun * kMsun / (kC * kC);
+    CamParams cp = cam_params(cam);
+    for (long long start = 0; start < NN; start += chunk) {
+        int count = (int)std::min(chunk, NN - start);
+        dim3 grd((count + 63) / 64), blk(64);
+        {
+            TimedLaunch tl(ctx, BL_K_GEODESIC);
+            hipLaunchKernelGGL(k_geodesic<true>, grd, blk, 0, ctx->stream, P, cp, ctx->d_frame, start, count,
+                               ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_ovf_count, ctx->d_ovf_list, aux_out,
+                               nullptr);
+        }
+        HIPCHK(ctx, hipGetLastError());
+        {
+            TimedLaunch tl(ctx, BL_K_TRANSFER);
+            if (pp.polarized)
+                hipLaunchKernelGGL(k_transfer<true>, grd, blk, 0, ctx->stream, P, cp, grid->g, pp, tp, ctx->d_frame,
+                                   start, count, ctx->d_rec, ctx->d_meta, ctx->d_nacc, image_out, aux_out);
+            else
+                hipLaunchKernelGGL(k_transfer<false>, grd, blk, 0, ctx->stream, P, cp, grid->g, pp, tp, ctx->d_frame,
+                                   start, count, ctx->d_rec, ctx->d_meta, ctx->d_nacc, image_out, aux_out);
+        }
+        HIPCHK(ctx, hipGetLastError());
+    }
+    {
+        TimedLaunch tl(ctx, BL_K_OVERFLOW);
+        if (pp.polarized)
+            hipLaunchKernelGGL(k_overflow<true>, dim3(1), dim3(64), 0, ctx->stream, P, cp, grid->g, pp, tp,
+                               ctx->d_frame, ctx->d_ovf_count, ctx->d_ovf_list, ctx->d_big, big_cap, image_out, aux_out);
+        else
+            hipLaunchKernelGGL(k_overflow<false>, dim3(1), dim3(64), 0, ctx->stream, P, cp, grid->g, pp, tp,
+                               ctx->d_frame, ctx->d_ovf_count, ctx->d_ovf_list, ctx->d_big, big_cap, image_out, aux_out);
+    }
+    HIPCHK(ctx, hipGetLastError());
+    return BL_OK;
+}
+
+bl_status bl_eval_samples(bl_context *ctx, const bl_spacetime *st, const bl_grid *grid, const bl_plasma *plasma,
+                          int64_t n, const double *states, const double *norms, double *out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    bl_status s;
+    if ((s = check_spacetime(ctx, st)) != BL_OK) return s;
+    if (!grid || !plasma || !states || !norms || !out || n < 0) return fail(ctx, BL_E_INVALID_ARG, "invalid argument");
+    if (grid->g.dtype != 0) return fail(ctx, BL_E_UNSUPPORTED, "float32 grids need precision 1");
+    if (n == 0) return BL_OK;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    PlasmaParams pp;
+    pp.mu = plasma->mu;
+    pp.ne_ni = plasma->ne_ni;
+    pp.r_high = plasma->r_high;
+    pp.r_low = plasma->r_low;
+    pp.sigma_max = plasma->sigma_max;
+    pp.mass_msun = st->mass_msun;
+    pp.polarized = plasma->polarized ? 1 : 0;
+    pp.interp = plasma->interp ? 1 : 0;
+    hipLaunchKernelGGL(k_eval_samples, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, ctx->stream, st->a,
+                       st->flat ? 1 : 0, grid->g, pp, (long long)n, states, norms, out);
+    HIPCHK(ctx, hipGetLastError());
+    return BL_OK;
+}
+
+bl_status bl_profile_enable(bl_context *ctx, int enable) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    ctx->prof = enable != 0;
+    return BL_OK;
+}
+
+bl_status bl_profile_read(bl_context *ctx, double *ms_out, int64_t *launches_out) {
+    if (!ctx || !ms_out || !launches_out) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < BL_NKERNEL; ++k) {
+        ms_out[k] = 0.0;
+        launches_out[k] = 0;
+    }
+    bl_status s = BL_OK;
+    for (auto &t : ctx->timed) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess) s = fail(ctx, BL_E_DEVICE, "hipEventElapsedTime failed");
+        if (t.kind >= 0 && t.kind < BL_NKERNEL) {
+            ms_out[t.kind] += ms;
+            launches_out[t.kind] += 1;
+        }
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    ctx->timed.clear();
+    return s;
+}
+
+}  // extern "C"

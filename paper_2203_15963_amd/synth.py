@@ -176,7 +176,7 @@ def workload(name, n=None):
     cam = dict(r=100.0, theta=th * deg, phi=0.0, u_normal=(0.0, 0.0, 0.0), k_cov=(1.0, 0.0, 0.0),
                width=30.0, n=N, freq_mode=0, psi=0.0, nu_hz=230e9)
     st = dict(a=a, mass_msun=4.152e6, r_in=1.01 * r_horizon(a), flat=0)
-    integ = dict(f_abs=1e-8, f_rel=1e-8, ds_max=ds_max, h0_frac=0.01, max_steps=100000)
+    integ = dict(f_abs=1e-8, f_rel=1e-8, ds_max=ds_max, h0_frac=0.1, max_steps=100000)
     pl = dict(mu=0.5, ne_ni=1.0, r_high=20.0, r_low=1.0, sigma_max=1.0, polarized=polz, interp=1)
     return dict(camera=cam, spacetime=st, integrator=integ, plasma=pl, grid_args=grid_args)
 

@@ -1,0 +1,72 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(no GPU needed: nothing is computed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "blgpu.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bl_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2203_15963_amd import blgpu
+    if not os.path.exists(blgpu.LIB_PATH):
+        from paper_2203_15963_amd import build
+        build.build()
+    return ctypes.CDLL(blgpu.LIB_PATH)
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for n in ["bl_abi_version", "bl_create", "bl_destroy", "bl_last_error", "bl_grid_create",
+              "bl_grid_destroy", "bl_camera_rays", "bl_trace_geodesics", "bl_render", "bl_eval_samples",
+              "bl_profile_enable", "bl_profile_read"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_abi_version(lib):
+    from paper_2203_15963_amd import blgpu
+    lib.bl_abi_version.restype = ctypes.c_int
+    assert lib.bl_abi_version() == blgpu.ABI_VERSION
+
+
+def test_struct_layouts_match_header():
+    """The binding's ctypes structs have the sizes the header's C structs have
+    (checked by compiling the header with the host compiler)."""
+    import subprocess
+    import tempfile
+    from paper_2203_15963_amd import blgpu
+    src = '#include <stdio.h>\n#include "blgpu.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu",' \
+          'sizeof(bl_camera),sizeof(bl_spacetime),sizeof(bl_integrator),sizeof(bl_grid_desc),' \
+          'sizeof(bl_plasma),sizeof(bl_mode));return 0;}\n'
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "t")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        sizes = [int(v) for v in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
+    mine = [ctypes.sizeof(s) for s in (blgpu.bl_camera, blgpu.bl_spacetime, blgpu.bl_integrator,
+                                       blgpu.bl_grid_desc, blgpu.bl_plasma, blgpu.bl_mode)]
+    assert sizes == mine
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2203_15963_amd import blgpu
+    monkeypatch.setattr(blgpu, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(blgpu, "_lib", None)
+    with pytest.raises(RuntimeError):
+        blgpu.load()
