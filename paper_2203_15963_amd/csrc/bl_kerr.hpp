@@ -111,16 +111,13 @@ __device__ __forceinline__ void geo_rhs(double a, int flat, const double *y, dou
     dy[1] = y[4] - flk * k.l[0];
     dy[2] = y[5] - flk * k.l[1];
     dy[3] = y[6] - flk * k.l[2];
-    if (flat) {
-        dy[4] = dy[5] = dy[6] = 0.0;
-        return;
-    }
+    // (no early return for the flat case: it keeps dy out of private memory)
     KSDeriv d;
     ks_deriv(a, flat, y[1], y[2], y[3], k, d);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         double dlk = d.dl[c][0] * y[4] + d.dl[c][1] * y[5] + d.dl[c][2] * y[6];
-        dy[4 + c] = 0.5 * d.df[c] * lk * lk + flk * dlk;
+        dy[4 + c] = flat ? 0.0 : 0.5 * d.df[c] * lk * lk + flk * dlk;
     }
 }
 
@@ -196,6 +193,62 @@ __device__ __forceinline__ void conn_k(double a, int flat, const double x[4], co
         G[2 * 4 + dd] = C[2][dd] - k.f * lu[2] * lc;
         G[3 * 4 + dd] = C[3][dd] - k.f * lu[3] * lc;
     }
+}
+
+// The same connection, one column d of G at a time, from scalars prepared
+// once per point (keeps the 4x4 temporaries of conn_k out of the registers
+// when G is applied immediately).
+struct ConnGeom {
+    double f, q, Df;
+    double l4[4], lu[4], Dl[4], W[4], df4[4];
+    double dl[3][3];
+};
+
+__device__ __forceinline__ void conn_geom(double a, int flat, const double x[4], const double kc[4], ConnGeom &c) {
+    KS k = ks_point(a, flat, x[1], x[2], x[3]);
+    KSDeriv d;
+    ks_deriv(a, flat, x[1], x[2], x[3], k, d);
+    double ku[4];
+    raise(k, kc, ku);
+    c.f = k.f;
+    c.q = l_dot_up(k, ku);
+    c.l4[0] = 1.0;
+    c.lu[0] = -1.0;
+    c.Dl[0] = 0.0;
+    c.W[0] = 0.0;
+    c.df4[0] = 0.0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        c.l4[1 + b] = k.l[b];
+        c.lu[1 + b] = k.l[b];
+        c.df4[1 + b] = d.df[b];
+        c.Dl[1 + b] = d.dl[0][b] * ku[1] + d.dl[1][b] * ku[2] + d.dl[2][b] * ku[3];
+        c.W[1 + b] = d.dl[b][0] * ku[1] + d.dl[b][1] * ku[2] + d.dl[b][2] * ku[3];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) c.dl[b][e] = d.dl[b][e];
+    }
+    c.Df = d.df[0] * ku[1] + d.df[1] * ku[2] + d.df[2] * ku[3];
+}
+
+// column dd of G^a_d (see conn_k)
+__device__ __forceinline__ void conn_col(const ConnGeom &c, int dd, double Gc[4]) {
+    double C[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        double T1 = c.Df * c.l4[e] * c.l4[dd] + c.f * (c.Dl[e] * c.l4[dd] + c.l4[e] * c.Dl[dd]);
+        double T2ed = (dd == 0) ? 0.0
+                                : c.q * (c.df4[dd] * c.l4[e] + c.f * (e == 0 ? 0.0 : c.dl[dd - 1][e - 1])) +
+                                      c.f * c.l4[e] * c.W[dd];
+        double T2de = (e == 0) ? 0.0
+                               : c.q * (c.df4[e] * c.l4[dd] + c.f * (dd == 0 ? 0.0 : c.dl[e - 1][dd - 1])) +
+                                     c.f * c.l4[dd] * c.W[e];
+        C[e] = 0.5 * (T1 + T2ed - T2de);
+    }
+    double lc = c.lu[0] * C[0] + c.lu[1] * C[1] + c.lu[2] * C[2] + c.lu[3] * C[3];
+    Gc[0] = -C[0] - c.f * c.lu[0] * lc;
+    Gc[1] = C[1] - c.f * c.lu[1] * lc;
+    Gc[2] = C[2] - c.f * c.lu[2] * lc;
+    Gc[3] = C[3] - c.f * c.lu[3] * lc;
 }
 
 // 4-velocity from CKS normal-frame components ut at point k:

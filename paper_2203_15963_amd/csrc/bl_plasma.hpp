@@ -118,9 +118,10 @@ __device__ __forceinline__ void bessel_ratios(double x, double &r0, double &r1) 
         double I0 = 1.0, S0 = 0.0, A = 1.0, S1 = 1.0;   // k = 0 terms (H_0 = 0, H_1 = 1)
 #pragma unroll
         for (int kk = 1; kk < 16; ++kk) {
-            double k = (double)kk;
-            t0 *= y / (k * k);
-            t1 *= y / (k * (k + 1.0));
+            // 1/k^2, 1/(k(k+1)), 1/k, 1/(k+1) fold to constants after unrolling
+            const double k = (double)kk;
+            t0 *= y * (1.0 / (k * k));
+            t1 *= y * (1.0 / (k * (k + 1.0)));
             H += 1.0 / k;
             double Hn = H + 1.0 / (k + 1.0);
             I0 += t0;
@@ -188,10 +189,12 @@ __device__ __forceinline__ void thermal_coeffs(double ne, double th, double B, d
     double Xr = th * sqrt(sqrt(2.0) * sth * 1.0e3 * nuB / nu);
     double r0, r1;
     bessel_ratios(1.0 / th, r0, r1);
-    double ism = 1.0 / sqrt(Xr);
+    // powers of X through one logarithm: X^-1/2, X^-0.5175, X^-0.6, X^4/3
+    double lX = log(Xr);
+    double ism = exp(-0.5 * lX);
     double e169 = 0.011 * exp(-1.69 * ism);
-    double f0 = 2.011 * exp(-19.78 * pow(Xr, -0.5175)) - cos(39.89 * ism) * exp(-70.16 * pow(Xr, -0.6)) - e169;
-    double fm = f0 + (e169 - 0.003135 * pow(Xr, 4.0 / 3.0)) * 0.5 * (1.0 + tanh(10.0 * log(0.6648 * ism)));
+    double f0 = 2.011 * exp(-19.78 * exp(-0.5175 * lX)) - cos(39.89 * ism) * exp(-70.16 * exp(-0.6 * lX)) - e169;
+    double fm = f0 + (e169 - 0.003135 * exp((4.0 / 3.0) * lX)) * 0.5 * (1.0 + tanh(10.0 * (log(0.6648) - 0.5 * lX)));
     double gX = 1.0 - 0.11 * log1p(0.035 * Xr);
     double base = ne * e2 / (kMe * kC);
     out[6] = base * nuB * nuB * sth * sth / (nu * nu * nu) * fm * (r1 + 6.0 * th);

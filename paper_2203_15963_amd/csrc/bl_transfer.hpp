@@ -27,9 +27,10 @@ namespace bl {
 
 // ------------------------------------------------------ coherency tensor
 // Hermitian N = R + i I with R symmetric (10 entries) and I antisymmetric (6).
-__host__ __device__ constexpr int sidx(int a, int b) {
-    return a <= b ? (a == 0 ? b : (a == 1 ? 3 + b : (a == 2 ? 5 + b : 9))) : sidx(b, a);
+__host__ __device__ constexpr int sidx_ord(int a, int b) {   // a <= b
+    return a == 0 ? b : (a == 1 ? 3 + b : (a == 2 ? 5 + b : 9));
 }
+__host__ __device__ constexpr int sidx(int a, int b) { return a <= b ? sidx_ord(a, b) : sidx_ord(b, a); }
 __host__ __device__ constexpr int aidx(int a, int b) {   // a < b
     return a == 0 ? b - 1 : (a == 1 ? 1 + b : 5);
 }
@@ -65,20 +66,42 @@ __device__ __forceinline__ void transport_rhs(const double G[16], const Coh &N, 
         }
 }
 
+// dN = F(N) with the connection applied one column of G at a time.
+__device__ __forceinline__ void transport_apply(const ConnGeom &c, const Coh &N, Coh &dN) {
+#pragma unroll
+    for (int m = 0; m < 10; ++m) dN.r[m] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) dN.i[m] = 0.0;
+#pragma unroll
+    for (int dd = 0; dd < 4; ++dd) {
+        double Gc[4];
+        conn_col(c, dd, Gc);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = a; b < 4; ++b) dN.r[sidx(a, b)] -= Gc[a] * Rget(N, dd, b) + Gc[b] * Rget(N, a, dd);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = a + 1; b < 4; ++b) dN.i[aidx(a, b)] -= Gc[a] * Iget(N, dd, b) + Gc[b] * Iget(N, a, dd);
+    }
+}
+
 // One explicit-midpoint transport step of length dl: predictor with the
 // connection at ya, corrector at yb (states x^mu, k_mu).
 __device__ __forceinline__ void transport_step(double a, int flat, const double ya[8], const double yb[8],
                                                double dl, Coh &N) {
-    double G[16];
+    if (flat) return;   // the connection vanishes
+    ConnGeom c;
     Coh d, h;
-    conn_k(a, flat, ya, ya + 4, G);
-    transport_rhs(G, N, d);
+    conn_geom(a, flat, ya, ya + 4, c);
+    transport_apply(c, N, d);
 #pragma unroll
     for (int m = 0; m < 10; ++m) h.r[m] = N.r[m] + 0.5 * dl * d.r[m];
 #pragma unroll
     for (int m = 0; m < 6; ++m) h.i[m] = N.i[m] + 0.5 * dl * d.i[m];
-    conn_k(a, flat, yb, yb + 4, G);
-    transport_rhs(G, h, d);
+    conn_geom(a, flat, yb, yb + 4, c);
+    transport_apply(c, h, d);
 #pragma unroll
     for (int m = 0; m < 10; ++m) N.r[m] += dl * d.r[m];
 #pragma unroll
@@ -211,12 +234,18 @@ struct TransferParams {
     double L;          // GM/c^2 in cm
 };
 
-// Transfer along the records of one ray (n_acc steps + final state).
+// Transfer along the records of one ray (n_acc steps + final state).  The
+// quartic of the step being cut into pieces lives in LDS (35 doubles per lane,
+// lane-interleaved) and is read back for every piece through an offset the
+// compiler cannot hoist, so it does not occupy registers across the piece
+// loop.  Requires blockDim.x == 64.
 template <bool POL>
 __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
                                              const TransferParams &tp, const double *rec, int n_acc, double kt,
                                              double n_norm, const double upix[4], const double Hv[4],
                                              TransferOut &o) {
+    __shared__ double s_q[35 * 64];
+    const int lane = threadIdx.x;
     const double a = P.a;
     const int flat = P.flat;
     double I = 0.0, tau = 0.0, Ij = 0.0;
@@ -229,23 +258,17 @@ __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &
     bool started = false;
     double pys[8], pyb[8], pdl = 0.0;
     double lscale = tp.L / n_norm;
-    // state on the source side of the current step
-    double y1[8];
-    {
-        const double *r = rec + (long long)n_acc * kRecDoubles;
-        y1[0] = r[0]; y1[1] = r[1]; y1[2] = r[2]; y1[3] = r[3];
-        y1[4] = kt; y1[5] = r[4]; y1[6] = r[5]; y1[7] = r[6];
-    }
-    double f1[7];
-    bool have_f1 = false;
     for (int st = n_acc - 1; st >= 0; --st) {
         const double *r = rec + (long long)st * kRecDoubles;
-        double y0[8], ym[8];
+        const double *r1 = r + kRecDoubles;   // next record: this step's end state
+        double y0[8], ym[8], y1[8];
         y0[0] = r[0]; y0[1] = r[1]; y0[2] = r[2]; y0[3] = r[3];
         y0[4] = kt; y0[5] = r[4]; y0[6] = r[5]; y0[7] = r[6];
-        double h = r[7];
         ym[0] = r[8]; ym[1] = r[9]; ym[2] = r[10]; ym[3] = r[11];
         ym[4] = kt; ym[5] = r[12]; ym[6] = r[13]; ym[7] = r[14];
+        y1[0] = r1[0]; y1[1] = r1[1]; y1[2] = r1[2]; y1[3] = r1[3];
+        y1[4] = kt; y1[5] = r1[4]; y1[6] = r1[5]; y1[7] = r1[6];
+        double h = r[7];
         double ds = r[15];
         bool inb = chord_meets_box(g.bb, y0, ym) || chord_meets_box(g.bb, ym, y1);
         int nsub = 1;
@@ -254,55 +277,64 @@ __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &
             double q = ceil(ds / tp.ds_max);
             nsub = (q >= 1.0) ? (int)fmin(q, 16777216.0) : 1;
         }
-        // quartic coefficients (only when the step is cut into pieces)
-        double c1[7], c2[7], c3[7], c4[7], f0[7];
-        bool have_f0 = false;
+        // y0 and the quartic coefficients go to LDS
+#pragma unroll
+        for (int m = 0; m < 7; ++m) s_q[m * 64 + lane] = y0[m < 4 ? m : m + 1];
         if (nsub > 1) {
             double y07[7] = {y0[0], y0[1], y0[2], y0[3], y0[5], y0[6], y0[7]};
             double y17[7] = {y1[0], y1[1], y1[2], y1[3], y1[5], y1[6], y1[7]};
+            double f0[7], f1[7];
             geo_rhs(a, flat, y07, kt, f0);
-            have_f0 = true;
-            if (!have_f1) geo_rhs(a, flat, y17, kt, f1);
+            geo_rhs(a, flat, y17, kt, f1);
 #pragma unroll
             for (int m = 0; m < 7; ++m) {
                 int q = m < 4 ? m : m + 1;
                 double A = y1[q] - y0[q] - h * f0[m];
                 double B = h * (f1[m] - f0[m]);
                 double C = 16.0 * (ym[q] - y0[q]) - 8.0 * h * f0[m];
-                c1[m] = h * f0[m];
-                c2[m] = -5.0 * A + B + C;
-                c3[m] = 14.0 * A - 3.0 * B - 2.0 * C;
-                c4[m] = -8.0 * A + 2.0 * B + C;
+                s_q[(7 + m) * 64 + lane] = h * f0[m];
+                s_q[(14 + m) * 64 + lane] = -5.0 * A + B + C;
+                s_q[(21 + m) * 64 + lane] = 14.0 * A - 3.0 * B - 2.0 * C;
+                s_q[(28 + m) * 64 + lane] = -8.0 * A + 2.0 * B + C;
             }
         }
         double dl = fabs(h) / (double)nsub;
         nrec += nsub;
         for (int p = nsub - 1; p >= 0; --p) {
+            int off = lane;
+            asm volatile("" : "+v"(off));   // keep the LDS reads inside the loop
             double ys[8], yb[8];
             if (nsub == 1) {
-#pragma unroll
-                for (int m = 0; m < 8; ++m) ys[m] = ym[m];
+                const double *rr = rec + (long long)st * kRecDoubles;
+                ys[0] = rr[8]; ys[1] = rr[9]; ys[2] = rr[10]; ys[3] = rr[11];
+                ys[5] = rr[12]; ys[6] = rr[13]; ys[7] = rr[14];
             } else {
                 double th = ((double)p + 0.5) / (double)nsub;
 #pragma unroll
                 for (int m = 0; m < 7; ++m) {
                     int q = m < 4 ? m : m + 1;
-                    ys[q] = y0[q] + th * (c1[m] + th * (c2[m] + th * (c3[m] + th * c4[m])));
+                    ys[q] = s_q[m * 64 + off] +
+                            th * (s_q[(7 + m) * 64 + off] +
+                                  th * (s_q[(14 + m) * 64 + off] +
+                                        th * (s_q[(21 + m) * 64 + off] + th * s_q[(28 + m) * 64 + off])));
                 }
-                ys[4] = kt;
             }
+            ys[4] = kt;
             if (p == 0) {
 #pragma unroll
-                for (int m = 0; m < 8; ++m) yb[m] = y0[m];
+                for (int m = 0; m < 7; ++m) yb[m < 4 ? m : m + 1] = s_q[m * 64 + off];
             } else {
                 double th = (double)p / (double)nsub;
 #pragma unroll
                 for (int m = 0; m < 7; ++m) {
                     int q = m < 4 ? m : m + 1;
-                    yb[q] = y0[q] + th * (c1[m] + th * (c2[m] + th * (c3[m] + th * c4[m])));
+                    yb[q] = s_q[m * 64 + off] +
+                            th * (s_q[(7 + m) * 64 + off] +
+                                  th * (s_q[(14 + m) * 64 + off] +
+                                        th * (s_q[(21 + m) * 64 + off] + th * s_q[(28 + m) * 64 + off])));
                 }
-                yb[4] = kt;
             }
+            yb[4] = kt;
             Sample smp;
             smp.plasma = false;
             if (inb) sample_point(a, flat, g, pp, ys, n_norm, smp);
@@ -343,14 +375,6 @@ __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &
                 }
             }
         }
-        // this step's y0 is the next (camera-side) step's y1
-#pragma unroll
-        for (int m = 0; m < 8; ++m) y1[m] = y0[m];
-        if (have_f0) {
-#pragma unroll
-            for (int m = 0; m < 7; ++m) f1[m] = f0[m];
-        }
-        have_f1 = have_f0;
     }
     o.tau = tau;
     o.Ij = Ij;
@@ -362,12 +386,14 @@ __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &
     } else {
         o.S[0] = o.S[1] = o.S[2] = o.S[3] = 0.0;
         if (started) {
-            // y1 now holds the pixel state
-            transport_step(a, flat, pys, y1, 0.5 * pdl, N);
-            KS k = ks_point(a, flat, y1[1], y1[2], y1[3]);
+            double y0[8];
+            y0[0] = rec[0]; y0[1] = rec[1]; y0[2] = rec[2]; y0[3] = rec[3];
+            y0[4] = kt; y0[5] = rec[4]; y0[6] = rec[5]; y0[7] = rec[6];
+            transport_step(a, flat, pys, y0, 0.5 * pdl, N);
+            KS k = ks_point(a, flat, y0[1], y0[2], y0[3]);
             double mH[4] = {-Hv[0], -Hv[1], -Hv[2], -Hv[3]};
             double e[4][4];
-            tetrad(k, upix, y1 + 4, mH, e);
+            tetrad(k, upix, y0 + 4, mH, e);
             coh_to_stokes(k, e[1], e[2], N, o.S);
         }
     }
