@@ -234,11 +234,202 @@ struct TransferParams {
     double L;          // GM/c^2 in cm
 };
 
-// Transfer along the records of one ray (n_acc steps + final state).  The
-// quartic of the step being cut into pieces lives in LDS (35 doubles per lane,
-// lane-interleaved) and is read back for every piece through an offset the
-// compiler cannot hoist, so it does not occupy registers across the piece
-// loop.  Requires blockDim.x == 64.
+// Per-lane state of the source-to-camera walk over one ray's records.  The
+// walk is a state machine so that a persistent wave can interleave rays:
+// begin_ray -> (next_step -> piece*)* -> finish_ray.  The quartic of the step
+// being cut into pieces lives in LDS (35 doubles per lane, lane-interleaved)
+// and is read back for every piece through an offset the compiler cannot
+// hoist, so it does not occupy registers across pieces.  blockDim.x == 64.
+struct RayWalk {
+    const double *rec;   // the ray's records
+    double kt, n_norm, lscale;
+    int st;              // next step to open (counting down), -1: all opened
+    int p;               // next piece of the open step (counting down), -1: none
+    int nsub;
+    bool inb, started;
+    double dl, pdl;
+    double I, tau, Ij;
+    int nsamp, nrec;
+    double pys[7], pyb[7];   // previous record: sample and boundary (x^mu, k_a)
+    Coh N;
+};
+
+__device__ __forceinline__ void begin_ray(RayWalk &w, const double *rec, int n_acc, double kt, double n_norm,
+                                          double L) {
+    w.rec = rec;
+    w.kt = kt;
+    w.n_norm = n_norm;
+    w.lscale = L / n_norm;
+    w.st = n_acc - 1;
+    w.p = -1;
+    w.nsub = 0;
+    w.inb = false;
+    w.started = false;
+    w.dl = w.pdl = 0.0;
+    w.I = w.tau = w.Ij = 0.0;
+    w.nsamp = w.nrec = 0;
+#pragma unroll
+    for (int m = 0; m < 10; ++m) w.N.r[m] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) w.N.i[m] = 0.0;
+}
+
+__device__ __forceinline__ void load_state7(const double *r, double y[7]) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) y[m] = r[m];
+}
+
+// Open step w.st: sampling decision, number of pieces, quartic into LDS.
+__device__ __forceinline__ void next_step(RayWalk &w, const GeoParams &P, const DevGrid &g,
+                                          const TransferParams &tp, double *s_q, int lane) {
+    const double *r = w.rec + (long long)w.st * kRecDoubles;
+    double y0[7], ym[7], y1[7];
+    load_state7(r, y0);
+    load_state7(r + 8, ym);
+    load_state7(r + kRecDoubles, y1);
+    double h = r[7], ds = r[15];
+    // chords use the spatial components 1..3 of (t, x, y, z, ...)
+    w.inb = chord_meets_box(g.bb, y0, ym) || chord_meets_box(g.bb, ym, y1);
+    int nsub = 1;
+    if (w.inb && tp.ds_max > 0.0) {
+        // at most 2^24 pieces per step; a non-finite length gives one piece
+        double q = ceil(ds / tp.ds_max);
+        nsub = (q >= 1.0) ? (int)fmin(q, 16777216.0) : 1;
+    }
+#pragma unroll
+    for (int m = 0; m < 7; ++m) s_q[m * 64 + lane] = y0[m];
+    if (nsub > 1) {
+        double f0[7], f1[7];
+        geo_rhs(P.a, P.flat, y0, w.kt, f0);
+        geo_rhs(P.a, P.flat, y1, w.kt, f1);
+#pragma unroll
+        for (int m = 0; m < 7; ++m) {
+            double A = y1[m] - y0[m] - h * f0[m];
+            double B = h * (f1[m] - f0[m]);
+            double C = 16.0 * (ym[m] - y0[m]) - 8.0 * h * f0[m];
+            s_q[(7 + m) * 64 + lane] = h * f0[m];
+            s_q[(14 + m) * 64 + lane] = -5.0 * A + B + C;
+            s_q[(21 + m) * 64 + lane] = 14.0 * A - 3.0 * B - 2.0 * C;
+            s_q[(28 + m) * 64 + lane] = -8.0 * A + 2.0 * B + C;
+        }
+    }
+    w.nsub = nsub;
+    w.dl = fabs(h) / (double)nsub;
+    w.nrec += nsub;
+    w.p = nsub - 1;
+    --w.st;
+}
+
+__device__ __forceinline__ void quartic_at(const double *s_q, int off, double th, double y[8], double kt) {
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+        int q = m < 4 ? m : m + 1;
+        y[q] = s_q[m * 64 + off] +
+               th * (s_q[(7 + m) * 64 + off] +
+                     th * (s_q[(14 + m) * 64 + off] + th * (s_q[(21 + m) * 64 + off] + th * s_q[(28 + m) * 64 + off])));
+    }
+    y[4] = kt;
+}
+
+// Process piece w.p of the open step.
+template <bool POL>
+__device__ __forceinline__ void piece(RayWalk &w, const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
+                                      const double *s_q, int lane) {
+    const double a = P.a;
+    const int flat = P.flat;
+    int off = lane;
+    asm volatile("" : "+v"(off));   // keep the LDS reads here
+    const int p = w.p;
+    double ys[8], yb[8];
+    if (w.nsub == 1) {
+        const double *rr = w.rec + (long long)(w.st + 1) * kRecDoubles + 8;
+        ys[0] = rr[0]; ys[1] = rr[1]; ys[2] = rr[2]; ys[3] = rr[3];
+        ys[5] = rr[4]; ys[6] = rr[5]; ys[7] = rr[6];
+        ys[4] = w.kt;
+    } else {
+        quartic_at(s_q, off, ((double)p + 0.5) / (double)w.nsub, ys, w.kt);
+    }
+    if (p == 0) {
+#pragma unroll
+        for (int m = 0; m < 7; ++m) yb[m < 4 ? m : m + 1] = s_q[m * 64 + off];
+        yb[4] = w.kt;
+    } else {
+        quartic_at(s_q, off, (double)p / (double)w.nsub, yb, w.kt);
+    }
+    w.p = p - 1;
+    Sample smp;
+    smp.plasma = false;
+    if (w.inb) sample_point(a, flat, g, pp, ys, w.n_norm, smp);
+    double dlp = w.lscale * w.dl;
+    if (!POL) {
+        if (smp.plasma) {
+            ++w.nsamp;
+            w.I = unpol_segment(w.I, smp.c[0], smp.c[3], dlp);
+            w.tau += smp.c[3] * dlp;
+            w.Ij += smp.c[0] * dlp;
+        }
+        return;
+    }
+    if (!w.started && !smp.plasma) return;
+    if (w.started) {
+        double ya[8] = {w.pys[0], w.pys[1], w.pys[2], w.pys[3], w.kt, w.pys[4], w.pys[5], w.pys[6]};
+        double yc[8] = {w.pyb[0], w.pyb[1], w.pyb[2], w.pyb[3], w.kt, w.pyb[4], w.pyb[5], w.pyb[6]};
+        transport_step(a, flat, ya, yc, 0.5 * (w.pdl + w.dl), w.N);
+    }
+    w.started = true;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+        w.pys[m] = ys[m < 4 ? m : m + 1];
+        w.pyb[m] = yb[m < 4 ? m : m + 1];
+    }
+    w.pdl = w.dl;
+    if (smp.plasma) {
+        ++w.nsamp;
+        w.tau += smp.c[3] * dlp;
+        w.Ij += smp.c[0] * dlp;
+        bool any = false;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) any = any || (smp.c[m] != 0.0);
+        if (any) {
+            KS k = ks_point(a, flat, ys[1], ys[2], ys[3]);
+            double e[4][4];
+            tetrad(k, smp.u, ys + 4, smp.b, e);
+            double S[4];
+            coh_to_stokes(k, e[1], e[2], w.N, S);
+            stokes_step(smp.c, dlp, S);
+            stokes_to_coh(e[1], e[2], S, w.N);
+        }
+    }
+}
+
+// Close the ray at the pixel: final half transport, camera Stokes basis.
+template <bool POL>
+__device__ __forceinline__ void finish_ray(RayWalk &w, const GeoParams &P, const double upix[4], const double Hv[4],
+                                           TransferOut &o) {
+    o.tau = w.tau;
+    o.Ij = w.Ij;
+    o.nsamp = w.nsamp;
+    o.nrec = w.nrec;
+    o.S[0] = o.S[1] = o.S[2] = o.S[3] = 0.0;
+    if (!POL) {
+        o.S[0] = w.I;
+        return;
+    }
+    if (!w.started) return;
+    const double *rec = w.rec;
+    double y0[8];
+    y0[0] = rec[0]; y0[1] = rec[1]; y0[2] = rec[2]; y0[3] = rec[3];
+    y0[4] = w.kt; y0[5] = rec[4]; y0[6] = rec[5]; y0[7] = rec[6];
+    double ya[8] = {w.pys[0], w.pys[1], w.pys[2], w.pys[3], w.kt, w.pys[4], w.pys[5], w.pys[6]};
+    transport_step(P.a, P.flat, ya, y0, 0.5 * w.pdl, w.N);
+    KS k = ks_point(P.a, P.flat, y0[1], y0[2], y0[3]);
+    double mH[4] = {-Hv[0], -Hv[1], -Hv[2], -Hv[3]};
+    double e[4][4];
+    tetrad(k, upix, y0 + 4, mH, e);
+    coh_to_stokes(k, e[1], e[2], w.N, o.S);
+}
+
+// Whole ray by one lane (used where rays are not interleaved).
 template <bool POL>
 __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
                                              const TransferParams &tp, const double *rec, int n_acc, double kt,
@@ -246,157 +437,13 @@ __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &
                                              TransferOut &o) {
     __shared__ double s_q[35 * 64];
     const int lane = threadIdx.x;
-    const double a = P.a;
-    const int flat = P.flat;
-    double I = 0.0, tau = 0.0, Ij = 0.0;
-    int nsamp = 0, nrec = 0;
-    Coh N;
-#pragma unroll
-    for (int m = 0; m < 10; ++m) N.r[m] = 0.0;
-#pragma unroll
-    for (int m = 0; m < 6; ++m) N.i[m] = 0.0;
-    bool started = false;
-    double pys[8], pyb[8], pdl = 0.0;
-    double lscale = tp.L / n_norm;
-    for (int st = n_acc - 1; st >= 0; --st) {
-        const double *r = rec + (long long)st * kRecDoubles;
-        const double *r1 = r + kRecDoubles;   // next record: this step's end state
-        double y0[8], ym[8], y1[8];
-        y0[0] = r[0]; y0[1] = r[1]; y0[2] = r[2]; y0[3] = r[3];
-        y0[4] = kt; y0[5] = r[4]; y0[6] = r[5]; y0[7] = r[6];
-        ym[0] = r[8]; ym[1] = r[9]; ym[2] = r[10]; ym[3] = r[11];
-        ym[4] = kt; ym[5] = r[12]; ym[6] = r[13]; ym[7] = r[14];
-        y1[0] = r1[0]; y1[1] = r1[1]; y1[2] = r1[2]; y1[3] = r1[3];
-        y1[4] = kt; y1[5] = r1[4]; y1[6] = r1[5]; y1[7] = r1[6];
-        double h = r[7];
-        double ds = r[15];
-        bool inb = chord_meets_box(g.bb, y0, ym) || chord_meets_box(g.bb, ym, y1);
-        int nsub = 1;
-        if (inb && tp.ds_max > 0.0) {
-            // at most 2^24 pieces per step; a non-finite length gives one piece
-            double q = ceil(ds / tp.ds_max);
-            nsub = (q >= 1.0) ? (int)fmin(q, 16777216.0) : 1;
-        }
-        // y0 and the quartic coefficients go to LDS
-#pragma unroll
-        for (int m = 0; m < 7; ++m) s_q[m * 64 + lane] = y0[m < 4 ? m : m + 1];
-        if (nsub > 1) {
-            double y07[7] = {y0[0], y0[1], y0[2], y0[3], y0[5], y0[6], y0[7]};
-            double y17[7] = {y1[0], y1[1], y1[2], y1[3], y1[5], y1[6], y1[7]};
-            double f0[7], f1[7];
-            geo_rhs(a, flat, y07, kt, f0);
-            geo_rhs(a, flat, y17, kt, f1);
-#pragma unroll
-            for (int m = 0; m < 7; ++m) {
-                int q = m < 4 ? m : m + 1;
-                double A = y1[q] - y0[q] - h * f0[m];
-                double B = h * (f1[m] - f0[m]);
-                double C = 16.0 * (ym[q] - y0[q]) - 8.0 * h * f0[m];
-                s_q[(7 + m) * 64 + lane] = h * f0[m];
-                s_q[(14 + m) * 64 + lane] = -5.0 * A + B + C;
-                s_q[(21 + m) * 64 + lane] = 14.0 * A - 3.0 * B - 2.0 * C;
-                s_q[(28 + m) * 64 + lane] = -8.0 * A + 2.0 * B + C;
-            }
-        }
-        double dl = fabs(h) / (double)nsub;
-        nrec += nsub;
-        for (int p = nsub - 1; p >= 0; --p) {
-            int off = lane;
-            asm volatile("" : "+v"(off));   // keep the LDS reads inside the loop
-            double ys[8], yb[8];
-            if (nsub == 1) {
-                const double *rr = rec + (long long)st * kRecDoubles;
-                ys[0] = rr[8]; ys[1] = rr[9]; ys[2] = rr[10]; ys[3] = rr[11];
-                ys[5] = rr[12]; ys[6] = rr[13]; ys[7] = rr[14];
-            } else {
-                double th = ((double)p + 0.5) / (double)nsub;
-#pragma unroll
-                for (int m = 0; m < 7; ++m) {
-                    int q = m < 4 ? m : m + 1;
-                    ys[q] = s_q[m * 64 + off] +
-                            th * (s_q[(7 + m) * 64 + off] +
-                                  th * (s_q[(14 + m) * 64 + off] +
-                                        th * (s_q[(21 + m) * 64 + off] + th * s_q[(28 + m) * 64 + off])));
-                }
-            }
-            ys[4] = kt;
-            if (p == 0) {
-#pragma unroll
-                for (int m = 0; m < 7; ++m) yb[m < 4 ? m : m + 1] = s_q[m * 64 + off];
-            } else {
-                double th = (double)p / (double)nsub;
-#pragma unroll
-                for (int m = 0; m < 7; ++m) {
-                    int q = m < 4 ? m : m + 1;
-                    yb[q] = s_q[m * 64 + off] +
-                            th * (s_q[(7 + m) * 64 + off] +
-                                  th * (s_q[(14 + m) * 64 + off] +
-                                        th * (s_q[(21 + m) * 64 + off] + th * s_q[(28 + m) * 64 + off])));
-                }
-            }
-            yb[4] = kt;
-            Sample smp;
-            smp.plasma = false;
-            if (inb) sample_point(a, flat, g, pp, ys, n_norm, smp);
-            double dlp = lscale * dl;
-            if (!POL) {
-                if (smp.plasma) {
-                    ++nsamp;
-                    I = unpol_segment(I, smp.c[0], smp.c[3], dlp);
-                    tau += smp.c[3] * dlp;
-                    Ij += smp.c[0] * dlp;
-                }
-            } else {
-                if (!started && !smp.plasma) continue;
-                if (started) transport_step(a, flat, pys, pyb, 0.5 * (pdl + dl), N);
-                started = true;
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    pys[m] = ys[m];
-                    pyb[m] = yb[m];
-                }
-                pdl = dl;
-                if (smp.plasma) {
-                    ++nsamp;
-                    tau += smp.c[3] * dlp;
-                    Ij += smp.c[0] * dlp;
-                    bool any = false;
-#pragma unroll
-                    for (int m = 0; m < 8; ++m) any = any || (smp.c[m] != 0.0);
-                    if (any) {
-                        KS k = ks_point(a, flat, ys[1], ys[2], ys[3]);
-                        double e[4][4];
-                        tetrad(k, smp.u, ys + 4, smp.b, e);
-                        double S[4];
-                        coh_to_stokes(k, e[1], e[2], N, S);
-                        stokes_step(smp.c, dlp, S);
-                        stokes_to_coh(e[1], e[2], S, N);
-                    }
-                }
-            }
-        }
+    RayWalk w;
+    begin_ray(w, rec, n_acc, kt, n_norm, tp.L);
+    while (w.st >= 0 || w.p >= 0) {
+        if (w.p < 0) next_step(w, P, g, tp, s_q, lane);
+        piece<POL>(w, P, g, pp, s_q, lane);
     }
-    o.tau = tau;
-    o.Ij = Ij;
-    o.nsamp = nsamp;
-    o.nrec = nrec;
-    if (!POL) {
-        o.S[0] = I;
-        o.S[1] = o.S[2] = o.S[3] = 0.0;
-    } else {
-        o.S[0] = o.S[1] = o.S[2] = o.S[3] = 0.0;
-        if (started) {
-            double y0[8];
-            y0[0] = rec[0]; y0[1] = rec[1]; y0[2] = rec[2]; y0[3] = rec[3];
-            y0[4] = kt; y0[5] = rec[4]; y0[6] = rec[5]; y0[7] = rec[6];
-            transport_step(a, flat, pys, y0, 0.5 * pdl, N);
-            KS k = ks_point(a, flat, y0[1], y0[2], y0[3]);
-            double mH[4] = {-Hv[0], -Hv[1], -Hv[2], -Hv[3]};
-            double e[4][4];
-            tetrad(k, upix, y0 + 4, mH, e);
-            coh_to_stokes(k, e[1], e[2], N, o.S);
-        }
-    }
+    finish_ray<POL>(w, P, upix, Hv, o);
 }
 
 }  // namespace bl

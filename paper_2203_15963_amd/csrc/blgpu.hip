@@ -228,25 +228,62 @@ __device__ __forceinline__ void pixel_observer(const Frame &fr, const GeoParams 
     velocity_from_normal(k, fr.ut, upix);
 }
 
+// Persistent transfer: each wave keeps its 64 lanes busy by giving a lane
+// that finished its ray the next ray of the chunk (one atomic per wave for all
+// lanes that need one), so the per-piece work always runs on full waves even
+// though rays hold from tens to thousands of pieces.  Every lane leaves the
+// loop once the queue is exhausted and its ray is written.
 template <bool POL>
 __global__ void __launch_bounds__(64) k_transfer(GeoParams P, CamParams cp, DevGrid g, PlasmaParams pp,
                                                  TransferParams tp, const Frame *__restrict__ frp, long long start,
                                                  int count, const double *__restrict__ rec,
                                                  const double *__restrict__ meta, const int *__restrict__ nacc,
-                                                 double *__restrict__ image, double *__restrict__ aux) {
-    int slot = blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= count) return;
-    int na = nacc[slot];
-    if (na < 0) return;   // finished by the overflow kernel
-    long long pix = start + slot;
-    long long NN = (long long)cp.n * cp.n;
-    const Frame &fr = *frp;
-    const double *r = rec + (long long)slot * P.cap * kRecDoubles;
-    double upix[4];
-    pixel_observer(fr, P, r, upix);
-    TransferOut t;
-    transfer_ray<POL>(P, g, pp, tp, r, na, meta[2 * slot], meta[2 * slot + 1], upix, fr.H, t);
-    write_pixel(t, cp.nu * cp.nu * cp.nu, NN, pix, image, aux);
+                                                 int *__restrict__ queue, double *__restrict__ image,
+                                                 double *__restrict__ aux) {
+    __shared__ double s_q[35 * 64];
+    const int lane = threadIdx.x;
+    const long long NN = (long long)cp.n * cp.n;
+    const double nu3 = cp.nu * cp.nu * cp.nu;
+    RayWalk w;
+    int slot = -1;
+    bool done = false;
+    for (;;) {
+        unsigned long long need = __ballot(slot < 0 && !done);
+        if (need) {
+            int leader = __ffsll((long long)need) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(queue, __popcll(need));
+            base = __shfl(base, leader);
+            if (slot < 0 && !done) {
+                int id = base + __popcll(need & ((1ull << lane) - 1ull));
+                if (id >= count) {
+                    done = true;
+                } else {
+                    int na = nacc[id];
+                    if (na >= 0) {   // negative: finished by the overflow kernel
+                        slot = id;
+                        begin_ray(w, rec + (long long)id * P.cap * kRecDoubles, na, meta[2 * id], meta[2 * id + 1],
+                                  tp.L);
+                    }
+                }
+            }
+        }
+        if (__ballot(slot >= 0 || !done) == 0) break;
+        if (slot >= 0 && w.p < 0) {
+            if (w.st < 0) {
+                const Frame &fr = *frp;
+                double upix[4];
+                pixel_observer(fr, P, w.rec, upix);
+                TransferOut t;
+                finish_ray<POL>(w, P, upix, fr.H, t);
+                write_pixel(t, nu3, NN, start + slot, image, aux);
+                slot = -1;
+            } else {
+                next_step(w, P, g, tp, s_q, lane);
+            }
+        }
+        if (slot >= 0) piece<POL>(w, P, g, pp, s_q, lane);
+    }
 }
 
 // Rays queued by k_geodesic: one wave, each lane traces and transfers its
@@ -334,6 +371,9 @@ struct bl_context {
     double *d_big = nullptr;
     size_t big_bytes = 0;
     size_t ws_limit = (size_t)8 << 30;   // bytes of step records per chunk
+    int *d_queue = nullptr;              // per-chunk work counters of the persistent kernels
+    size_t queue_bytes = 0;
+    int waves_tr[2] = {0, 0};            // resident waves of k_transfer<unpolarized / polarized>
     bool prof = false;
     struct Timed {
         int kind;
@@ -457,6 +497,18 @@ struct TimedLaunch {
     }
 };
 
+// Number of waves of each persistent kernel that fit on the device at once.
+bl_status persistent_waves(bl_context *ctx) {
+    if (ctx->waves_tr[0] > 0) return BL_OK;
+    int cus = 0, b0 = 0, b1 = 0;
+    HIPCHK(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_transfer<false>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_transfer<true>, 64, 0));
+    ctx->waves_tr[0] = std::max(1, b0) * cus;
+    ctx->waves_tr[1] = std::max(1, b1) * cus;
+    return BL_OK;
+}
+
 bl_status launch_frame(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st) {
     if (!ctx->d_frame) HIPCHK(ctx, hipMalloc((void **)&ctx->d_frame, sizeof(Frame)));
     {
@@ -507,6 +559,7 @@ void bl_destroy(bl_context *ctx) {
     hipFree(ctx->d_ovf_count);
     hipFree(ctx->d_ovf_list);
     hipFree(ctx->d_big);
+    hipFree(ctx->d_queue);
     delete ctx;
 }
 
@@ -693,7 +746,14 @@ bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *s
     tp.ds_max = integ->ds_max;
     tp.L = kG * st->mass_msun * kMsun / (kC * kC);
     CamParams cp = cam_params(cam);
-    for (long long start = 0; start < NN; start += chunk) {
+    long long nchunk = (NN + chunk - 1) / chunk;
+    if ((s = ensure(ctx, &ctx->d_queue, ctx->queue_bytes, (size_t)nchunk * 2 * sizeof(int))) != BL_OK) return s;
+    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((2 * nchunk + 63) / 64)), dim3(64), 0, ctx->stream, ctx->d_queue, 0,
+                       (int)(2 * nchunk));
+    HIPCHK(ctx, hipGetLastError());
+    if ((s = persistent_waves(ctx)) != BL_OK) return s;
+    long long ichunk = 0;
+    for (long long start = 0; start < NN; start += chunk, ++ichunk) {
         int count = (int)std::min(chunk, NN - start);
         dim3 grd((count + 63) / 64), blk(64);
         {
@@ -705,12 +765,15 @@ bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *s
         HIPCHK(ctx, hipGetLastError());
         {
             TimedLaunch tl(ctx, BL_K_TRANSFER);
+            int *q = ctx->d_queue + 2 * ichunk;
             if (pp.polarized)
-                hipLaunchKernelGGL(k_transfer<true>, grd, blk, 0, ctx->stream, P, cp, grid->g, pp, tp, ctx->d_frame,
-                                   start, count, ctx->d_rec, ctx->d_meta, ctx->d_nacc, image_out, aux_out);
+                hipLaunchKernelGGL(k_transfer<true>, dim3(std::min<int>(grd.x, ctx->waves_tr[1])), blk, 0, ctx->stream,
+                                   P, cp, grid->g, pp, tp, ctx->d_frame, start, count, ctx->d_rec, ctx->d_meta,
+                                   ctx->d_nacc, q, image_out, aux_out);
             else
-                hipLaunchKernelGGL(k_transfer<false>, grd, blk, 0, ctx->stream, P, cp, grid->g, pp, tp, ctx->d_frame,
-                                   start, count, ctx->d_rec, ctx->d_meta, ctx->d_nacc, image_out, aux_out);
+                hipLaunchKernelGGL(k_transfer<false>, dim3(std::min<int>(grd.x, ctx->waves_tr[0])), blk, 0,
+                                   ctx->stream, P, cp, grid->g, pp, tp, ctx->d_frame, start, count, ctx->d_rec,
+                                   ctx->d_meta, ctx->d_nacc, q, image_out, aux_out);
         }
         HIPCHK(ctx, hipGetLastError());
     }
