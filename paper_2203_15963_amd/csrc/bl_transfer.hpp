@@ -35,46 +35,31 @@ __host__ __device__ constexpr int aidx(int a, int b) {   // a < b
     return a == 0 ? b - 1 : (a == 1 ? 1 + b : 5);
 }
 
+template <typename R>
 struct Coh {
-    double r[10], i[6];
+    R r[10], i[6];
 };
 
-__device__ __forceinline__ double Rget(const Coh &N, int a, int b) { return N.r[sidx(a, b)]; }
-__device__ __forceinline__ double Iget(const Coh &N, int a, int b) {
-    return a == b ? 0.0 : (a < b ? N.i[aidx(a, b)] : -N.i[aidx(b, a)]);
+template <typename R>
+__device__ __forceinline__ R Rget(const Coh<R> &N, int a, int b) {
+    return N.r[sidx(a, b)];
+}
+template <typename R>
+__device__ __forceinline__ R Iget(const Coh<R> &N, int a, int b) {
+    return a == b ? R(0) : (a < b ? N.i[aidx(a, b)] : -N.i[aidx(b, a)]);
 }
 
-// dN^ab/dlambda = -(G^a_d N^db + G^b_d N^ad), the parallel transport of N.
-__device__ __forceinline__ void transport_rhs(const double G[16], const Coh &N, Coh &dN) {
+// dN^ab/dlambda = -(G^a_d N^db + G^b_d N^ad), the parallel transport of N,
+// with the connection applied one column of G at a time.
+template <typename R>
+__device__ __forceinline__ void transport_apply(const ConnGeom<R> &c, const Coh<R> &N, Coh<R> &dN) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int m = 0; m < 10; ++m) dN.r[m] = R(0);
 #pragma unroll
-        for (int b = a; b < 4; ++b) {
-            double s = 0.0;
-#pragma unroll
-            for (int d = 0; d < 4; ++d) s += G[4 * a + d] * Rget(N, d, b) + G[4 * b + d] * Rget(N, a, d);
-            dN.r[sidx(a, b)] = -s;
-        }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = a + 1; b < 4; ++b) {
-            double s = 0.0;
-#pragma unroll
-            for (int d = 0; d < 4; ++d) s += G[4 * a + d] * Iget(N, d, b) + G[4 * b + d] * Iget(N, a, d);
-            dN.i[aidx(a, b)] = -s;
-        }
-}
-
-// dN = F(N) with the connection applied one column of G at a time.
-__device__ __forceinline__ void transport_apply(const ConnGeom &c, const Coh &N, Coh &dN) {
-#pragma unroll
-    for (int m = 0; m < 10; ++m) dN.r[m] = 0.0;
-#pragma unroll
-    for (int m = 0; m < 6; ++m) dN.i[m] = 0.0;
+    for (int m = 0; m < 6; ++m) dN.i[m] = R(0);
 #pragma unroll
     for (int dd = 0; dd < 4; ++dd) {
-        double Gc[4];
+        R Gc[4];
         conn_col(c, dd, Gc);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -89,17 +74,17 @@ __device__ __forceinline__ void transport_apply(const ConnGeom &c, const Coh &N,
 
 // One explicit-midpoint transport step of length dl: predictor with the
 // connection at ya, corrector at yb (states x^mu, k_mu).
-__device__ __forceinline__ void transport_step(double a, int flat, const double ya[8], const double yb[8],
-                                               double dl, Coh &N) {
+template <typename R>
+__device__ __forceinline__ void transport_step(R a, int flat, const R ya[8], const R yb[8], R dl, Coh<R> &N) {
     if (flat) return;   // the connection vanishes
-    ConnGeom c;
-    Coh d, h;
+    ConnGeom<R> c;
+    Coh<R> d, h;
     conn_geom(a, flat, ya, ya + 4, c);
     transport_apply(c, N, d);
 #pragma unroll
-    for (int m = 0; m < 10; ++m) h.r[m] = N.r[m] + 0.5 * dl * d.r[m];
+    for (int m = 0; m < 10; ++m) h.r[m] = N.r[m] + R(0.5) * dl * d.r[m];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) h.i[m] = N.i[m] + 0.5 * dl * d.i[m];
+    for (int m = 0; m < 6; ++m) h.i[m] = N.i[m] + R(0.5) * dl * d.i[m];
     conn_geom(a, flat, yb, yb + 4, c);
     transport_apply(c, h, d);
 #pragma unroll
@@ -110,31 +95,33 @@ __device__ __forceinline__ void transport_step(double a, int flat, const double 
 
 // Stokes parameters of N in the screen vectors e1, e2 (contravariant) of a
 // tetrad: I = N11 + N22, Q = N11 - N22, U = 2 Re N12, V = -2 Im N12.
-__device__ __forceinline__ void coh_to_stokes(const KS &k, const double e1[4], const double e2[4], const Coh &N,
-                                              double S[4]) {
-    double p[4], q[4];
+template <typename R>
+__device__ __forceinline__ void coh_to_stokes(const KS<R> &k, const R e1[4], const R e2[4], const Coh<R> &N,
+                                              R S[4]) {
+    R p[4], q[4];
     lower(k, e1, p);
     lower(k, e2, q);
-    double n11 = 0.0, n22 = 0.0, n12r = 0.0, n12i = 0.0;
+    R n11 = R(0), n22 = R(0), n12r = R(0), n12i = R(0);
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            double R = Rget(N, a, b);
-            n11 += p[a] * p[b] * R;
-            n22 += q[a] * q[b] * R;
-            n12r += p[a] * q[b] * R;
+            R Rv = Rget(N, a, b);
+            n11 += p[a] * p[b] * Rv;
+            n22 += q[a] * q[b] * Rv;
+            n12r += p[a] * q[b] * Rv;
             n12i += p[a] * q[b] * Iget(N, a, b);
         }
     S[0] = n11 + n22;
     S[1] = n11 - n22;
-    S[2] = 2.0 * n12r;
-    S[3] = -2.0 * n12i;
+    S[2] = R(2) * n12r;
+    S[3] = R(-2) * n12i;
 }
 
 // N = 1/2 [(I+Q) e1 e1 + (I-Q) e2 e2 + (U - iV) e1 e2 + (U + iV) e2 e1]
-__device__ __forceinline__ void stokes_to_coh(const double e1[4], const double e2[4], const double S[4], Coh &N) {
-    double n11 = 0.5 * (S[0] + S[1]), n22 = 0.5 * (S[0] - S[1]), n12r = 0.5 * S[2], n12i = -0.5 * S[3];
+template <typename R>
+__device__ __forceinline__ void stokes_to_coh(const R e1[4], const R e2[4], const R S[4], Coh<R> &N) {
+    R n11 = R(0.5) * (S[0] + S[1]), n22 = R(0.5) * (S[0] - S[1]), n12r = R(0.5) * S[2], n12i = R(-0.5) * S[3];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -146,81 +133,141 @@ __device__ __forceinline__ void stokes_to_coh(const double e1[4], const double e
         for (int b = a + 1; b < 4; ++b) N.i[aidx(a, b)] = n12i * (e1[a] * e2[b] - e2[a] * e1[b]);
 }
 
-// Exact solution of dS/ds = J - M S over length s for thermal coefficients
-// (J = B_nu M e_I, so the fixed point is S_eq = (j_I/alpha_I) e_I):
-//   S(s) = S_eq + e^{-alpha_I s} e^{-s K'} (S0 - S_eq),
-// where K' is the traceless part of M with eigenvalues +-L1, +-i L2,
-// L1^2, L2^2 = sqrt(((a^2 - r^2)/2)^2 + (a.r)^2) +- (a^2 - r^2)/2, and
-// e^{-sK'} = [cosh(sL1) P1 + cos(sL2) P2] - K' [sinh(sL1)/L1 P1 + sin(sL2)/L2 P2]
-// with projectors P1 = (K'^2 + L2^2)/(L1^2 + L2^2), P2 = (L1^2 - K'^2)/(L1^2 + L2^2).
-// If alpha_I s >= 100 the result is S_eq.  c = jI, jQ, jV, aI, aQ, aV, rQ, rV.
-__device__ __forceinline__ void kprime(const double c[8], const double v[4], double w[4]) {
+// Exact solution of dS/ds = J - M S over unit length (the coefficients carry
+// the segment length) for thermal coefficients, where Kirchhoff's law gives
+// J = B_nu M e_I (B_nu = j_I/alpha_I):
+//   S = e^{-M} S0 + B_nu (1 - e^{-M}) e_I,   M = alpha_I + K',
+// K' the traceless part of M, whose square has eigenvalues p = L1^2 >= 0 and
+// q = -L2^2 <= 0 with L1^2, L2^2 = sqrt(((a^2 - r^2)/2)^2 + (a.r)^2) +- (a^2 - r^2)/2.
+// Any f(K') = F_e(K'^2) + K' F_o(K'^2) with F_e, F_o the even and odd parts
+// of f as functions of the squared eigenvalue, and on the two-point spectrum
+// F(K'^2) = F(x0) + F[p,q] (K'^2 - x0) for either x0 in {p, q}, F[p,q] the
+// divided difference.  For f = e^{-mu} the parts are C(x) = cosh sqrt(x) and
+// -Sh(x) = -sinh sqrt(x)/sqrt(x), both entire in x.  The propagator acts on
+// S0 in the form based at q; the source acts on e_I in the form based at p,
+// since K'^2 e_I - p e_I = (X^2/((a^2+r^2)/2 + sqrt(...)), 0, -X, 0) with
+// X = aQ rV - aV rQ is small exactly where e_I lies near the p eigenspace:
+//   src = (1 - e^{-a} cosh L1) e_I - e^{-a} C[p,q] u + e^{-a} Sh(p) K' e_I
+//         + e^{-a} Sh[p,q] K' u,   u = K'^2 e_I - p e_I.
+// Nothing cancels when the step is optically thin and B_nu dwarfs S0:
+// 1 - e^{-a} cosh L1 = -(expm1(L1 - a) + expm1(-L1 - a))/2 with a >= L1, and
+// when p - q <= 1 (so |p|, |q| <= 1) the divided differences are summed from
+// the Taylor series of C and Sh instead of differenced.  If alpha_I >= 100 the
+// result is B_nu e_I.  c = jI, jQ, jV, aI, aQ, aV, rQ, rV.
+template <typename R>
+__device__ __forceinline__ void kprime(const R c[8], const R v[4], R w[4]) {
     w[0] = c[4] * v[1] + c[5] * v[3];
     w[1] = c[4] * v[0] + c[7] * v[2];
     w[2] = -c[7] * v[1] + c[6] * v[3];
     w[3] = c[5] * v[0] - c[6] * v[2];
 }
 
-__device__ __forceinline__ void stokes_step(const double c[8], double s, double S[4]) {
-    double aI = c[3];
-    double Seq = aI > 0.0 ? c[0] / aI : 0.0;
-    if (aI * s >= 100.0) {
-        S[0] = Seq;
-        S[1] = S[2] = S[3] = 0.0;
-        return;
-    }
-    double v[4] = {S[0] - Seq, S[1], S[2], S[3]};
-    double w1[4], w2[4], w3[4];
-    kprime(c, v, w1);
-    kprime(c, w1, w2);
-    kprime(c, w2, w3);
-    double al2 = c[4] * c[4] + c[5] * c[5];
-    double rh2 = c[6] * c[6] + c[7] * c[7];
-    double ar = c[4] * c[6] + c[5] * c[7];
-    double dif = 0.5 * (al2 - rh2);
-    double rt = sqrt(dif * dif + ar * ar);
-    double L1s, L2s;
-    if (dif >= 0.0) {
-        L1s = rt + dif;
-        L2s = L1s > 0.0 ? ar * ar / L1s : 0.0;
-    } else {
-        L2s = rt - dif;
-        L1s = L2s > 0.0 ? ar * ar / L2s : 0.0;
-    }
-    double Th = L1s + L2s;
-    double E = exp(-aI * s);
-    double out[4];
-    if (!(Th > 1e-12 * (al2 + rh2))) {
-        // K' (nearly) nilpotent: K'^4 ~ 0, the cubic Taylor polynomial is exact
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-            out[m] = E * (v[m] - s * w1[m] + 0.5 * s * s * w2[m] - (s * s * s / 6.0) * w3[m]);
-    } else {
-        double L1 = sqrt(L1s), L2 = sqrt(L2s);
-        double ch = E * cosh(s * L1);
-        double sh = E * (L1 > 0.0 ? sinh(s * L1) / L1 : s);
-        double co = E * cos(s * L2);
-        double sn = E * (L2 > 0.0 ? sin(s * L2) / L2 : s);
-        double iT = 1.0 / Th;
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-            out[m] = (ch * (w2[m] + L2s * v[m]) + co * (L1s * v[m] - w2[m])
-                      - sh * (w3[m] + L2s * w1[m]) - sn * (L1s * w1[m] - w3[m])) * iT;
-    }
-    S[0] = Seq + out[0];
-    S[1] = out[1];
-    S[2] = out[2];
-    S[3] = out[3];
+__device__ __forceinline__ void sincos_r(double x, double &s, double &c) { sincos(x, &s, &c); }
+__device__ __forceinline__ void sincos_r(float x, float &s, float &c) { sincosf(x, &s, &c); }
+
+constexpr double inv_factorial(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= (double)i;
+    return 1.0 / f;
 }
 
-// unpolarized segment, eq. (unpolarized)
-__device__ __forceinline__ double unpol_segment(double I, double j, double al, double dl) {
-    if (al > 0.0) {
-        double dtau = al * dl;
-        if (dtau < 100.0) return exp(-dtau) * (I + expm1(dtau) * j / al);
-        return j / al;
+// Sh(x) = sum_k x^k / (2k+1)! for |x| <= 1
+template <typename R>
+__device__ __forceinline__ R sh_series(R x) {
+    constexpr int K = sizeof(R) == 8 ? 9 : 5;
+    R s = R(0);
+#pragma unroll
+    for (int k = K; k >= 1; --k) s = (s + R(inv_factorial(2 * k + 1))) * x;
+    return s + R(1);
+}
+
+// C[p,q] and Sh[p,q] from the series: sum_{k>=1} h_{k-1}(p,q) / (2k)! and
+// / (2k+1)!, h_m the complete homogeneous polynomial of degree m.
+template <typename R>
+__device__ __forceinline__ void dd_series(R p, R q, R &dc, R &ds) {
+    constexpr int K = sizeof(R) == 8 ? 10 : 6;
+    R h = R(1), qk = R(1);
+    dc = R(0);
+    ds = R(0);
+#pragma unroll
+    for (int k = 1; k <= K; ++k) {
+        dc += h * R(inv_factorial(2 * k));
+        ds += h * R(inv_factorial(2 * k + 1));
+        qk *= q;
+        h = p * h + qk;                               // h_k = p h_{k-1} + q^k
     }
-    return I + j * dl;
+}
+
+template <typename R>
+__device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
+    const R aI = c[3];
+    const R Bnu = aI > R(0) ? c[0] / aI : R(0);
+    if (aI >= R(100)) {
+        S[0] = Bnu;
+        S[1] = S[2] = S[3] = R(0);
+        return;
+    }
+    R w1[4], w2[4], w3[4];
+    kprime(c, S, w1);
+    kprime(c, w1, w2);
+    kprime(c, w2, w3);
+    const R al2 = c[4] * c[4] + c[5] * c[5];
+    const R rh2 = c[6] * c[6] + c[7] * c[7];
+    const R ar = c[4] * c[6] + c[5] * c[7];
+    const R dif = R(0.5) * (al2 - rh2);
+    const R rt = sqrt(dif * dif + ar * ar);
+    R L1s, L2s;
+    if (dif >= R(0)) {
+        L1s = rt + dif;
+        L2s = L1s > R(0) ? ar * ar / L1s : R(0);
+    } else {
+        L2s = rt - dif;
+        L1s = L2s > R(0) ? ar * ar / L2s : R(0);
+    }
+    const R Th = L1s + L2s;
+    const R E = exp(-aI);
+    const R L1 = sqrt(L1s), L2 = sqrt(L2s);
+    const R ep = exp(L1 - aI), em = exp(-L1 - aI);   // e^{-aI} e^{+-L1}
+    R sn, cs;
+    sincos_r(L2, sn, cs);
+    const R shq = L2s <= R(1) ? sh_series(-L2s) : sn / L2;
+    const R shp = L1s <= R(1) ? E * sh_series(L1s) : R(0.5) * (ep - em) / L1;   // e^{-aI} Sh(p)
+    R dc, ds;   // e^{-aI} C[p,q], e^{-aI} Sh[p,q]
+    if (Th <= R(1)) {
+        dd_series(L1s, -L2s, dc, ds);
+        dc *= E;
+        ds *= E;
+    } else {
+        const R iT = R(1) / Th;
+        dc = (R(0.5) * (ep + em) - E * cs) * iT;
+        ds = (shp - E * shq) * iT;
+    }
+    const R ec = E * cs, es = E * shq;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+        S[m] = ec * S[m] + dc * (w2[m] + L2s * S[m]) - es * w1[m] - ds * (w3[m] + L2s * w1[m]);
+    if (Bnu > R(0)) {
+        const R X = c[4] * c[7] - c[5] * c[6];
+        const R den = R(0.5) * (al2 + rh2) + rt;
+        const R u0 = den > R(0) ? X * X / den : R(0);
+        // K' e_I = (0, aQ, 0, aV);  K' u for u = (u0, 0, -X, 0)
+        const R ku1 = c[4] * u0 - c[7] * X, ku3 = c[5] * u0 + c[6] * X;
+        const R fp = R(-0.5) * (expm1(L1 - aI) + expm1(-L1 - aI));   // 1 - e^{-aI} cosh L1
+        S[0] += Bnu * (fp - dc * u0);
+        S[1] += Bnu * (shp * c[4] + ds * ku1);
+        S[2] += Bnu * (dc * X);
+        S[3] += Bnu * (shp * c[5] + ds * ku3);
+    }
+}
+
+// unpolarized segment, eq. (unpolarized), with j and alpha carrying the length
+template <typename R>
+__device__ __forceinline__ R unpol_segment(R I, R j, R dtau) {
+    if (dtau > R(0)) {
+        if (dtau < R(100)) return exp(-dtau) * (I + expm1(dtau) * j / dtau);
+        return j / dtau;
+    }
+    return I + j;
 }
 
 struct TransferOut {
@@ -232,46 +279,70 @@ struct TransferOut {
 struct TransferParams {
     double ds_max;
     double L;          // GM/c^2 in cm
+    double nu_cam;     // observing frequency
 };
 
 // Per-lane state of the source-to-camera walk over one ray's records.  The
 // walk is a state machine so that a persistent wave can interleave rays:
-// begin_ray -> (next_step -> piece*)* -> finish_ray.  The quartic of the step
-// being cut into pieces lives in LDS (35 doubles per lane, lane-interleaved)
-// and is read back for every piece through an offset the compiler cannot
-// hoist, so it does not occupy registers across pieces.  blockDim.x == 64.
+// begin_ray -> (next_step -> piece*)* -> finish_ray.  Positions and the
+// quartic are FP64; R is the type of the coefficients, frames, transport and
+// Stokes state.  Intensities are carried in camera units (nu^3 times the
+// invariant), with the segment length folded into the coefficients:
+//   emission  j' = j_nu L dl (nu_cam/n)^3 / omega^2,
+//   depths    a' = alpha_nu L dl omega,  r' = rho_nu L dl omega,
+// which equal nu_cam^3 j/nu^2 dlambda_phys and alpha nu dlambda_phys with
+// dlambda_phys = L dl/n, nu = n omega.  The quartic of the step being cut into
+// pieces lives in LDS (35 doubles per lane, lane-interleaved) and is read back
+// for every piece through an offset the compiler cannot hoist, so it does not
+// occupy registers across pieces.  blockDim.x == 64.
+template <typename R>
 struct RayWalk {
     const double *rec;   // the ray's records
-    double kt, n_norm, lscale;
+    double kt, n_norm;
+    double L;            // GM/c^2 in cm
+    double lj;           // L (nu_cam/n)^3
     int st;              // next step to open (counting down), -1: all opened
     int p;               // next piece of the open step (counting down), -1: none
     int nsub;
     bool inb, started;
     double dl, pdl;
-    double I, tau, Ij;
+    R I, tau, Ij;
+    R tau_c, Ij_c;       // compensation terms of the two sums
     int nsamp, nrec;
-    double pys[7], pyb[7];   // previous record: sample and boundary (x^mu, k_a)
-    Coh N;
+    R pys[7], pyb[7];    // previous record: sample and boundary (x^mu, k_a)
+    Coh<R> N;
 };
 
-__device__ __forceinline__ void begin_ray(RayWalk &w, const double *rec, int n_acc, double kt, double n_norm,
-                                          double L) {
+template <typename R>
+__device__ __forceinline__ void begin_ray(RayWalk<R> &w, const double *rec, int n_acc, double kt, double n_norm,
+                                          const TransferParams &tp) {
     w.rec = rec;
     w.kt = kt;
     w.n_norm = n_norm;
-    w.lscale = L / n_norm;
+    double q = tp.nu_cam / n_norm;
+    w.L = tp.L;
+    w.lj = tp.L * q * q * q;
     w.st = n_acc - 1;
     w.p = -1;
     w.nsub = 0;
     w.inb = false;
     w.started = false;
     w.dl = w.pdl = 0.0;
-    w.I = w.tau = w.Ij = 0.0;
+    w.I = w.tau = w.Ij = w.tau_c = w.Ij_c = R(0);
     w.nsamp = w.nrec = 0;
 #pragma unroll
-    for (int m = 0; m < 10; ++m) w.N.r[m] = 0.0;
+    for (int m = 0; m < 10; ++m) w.N.r[m] = R(0);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) w.N.i[m] = 0.0;
+    for (int m = 0; m < 6; ++m) w.N.i[m] = R(0);
+}
+
+// Kahan-compensated s += x
+template <typename R>
+__device__ __forceinline__ void csum(R &s, R &c, R x) {
+    R y = x - c;
+    R t = s + y;
+    c = (t - s) - y;
+    s = t;
 }
 
 __device__ __forceinline__ void load_state7(const double *r, double y[7]) {
@@ -280,7 +351,8 @@ __device__ __forceinline__ void load_state7(const double *r, double y[7]) {
 }
 
 // Open step w.st: sampling decision, number of pieces, quartic into LDS.
-__device__ __forceinline__ void next_step(RayWalk &w, const GeoParams &P, const DevGrid &g,
+template <typename R>
+__device__ __forceinline__ void next_step(RayWalk<R> &w, const GeoParams &P, const DevGrid &g,
                                           const TransferParams &tp, double *s_q, int lane) {
     const double *r = w.rec + (long long)w.st * kRecDoubles;
     double y0[7], ym[7], y1[7];
@@ -331,11 +403,16 @@ __device__ __forceinline__ void quartic_at(const double *s_q, int off, double th
     y[4] = kt;
 }
 
+template <typename R>
+__device__ __forceinline__ void to_state_r(const R p7[7], R kt, R y[8]) {
+    y[0] = p7[0]; y[1] = p7[1]; y[2] = p7[2]; y[3] = p7[3];
+    y[4] = kt; y[5] = p7[4]; y[6] = p7[5]; y[7] = p7[6];
+}
+
 // Process piece w.p of the open step.
-template <bool POL>
-__device__ __forceinline__ void piece(RayWalk &w, const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
+template <bool POL, typename R>
+__device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
                                       const double *s_q, int lane) {
-    const double a = P.a;
     const int flat = P.flat;
     int off = lane;
     asm volatile("" : "+v"(off));   // keep the LDS reads here
@@ -357,93 +434,110 @@ __device__ __forceinline__ void piece(RayWalk &w, const GeoParams &P, const DevG
         quartic_at(s_q, off, (double)p / (double)w.nsub, yb, w.kt);
     }
     w.p = p - 1;
-    Sample smp;
+    Sample<R> smp;
     smp.plasma = false;
-    if (w.inb) sample_point(a, flat, g, pp, ys, w.n_norm, smp);
-    double dlp = w.lscale * w.dl;
+    if (w.inb) sample_point<R>(P.a, flat, g, pp, ys, w.n_norm, smp);
+    R c[8];
+    if (smp.plasma) {
+        R lt = (R)(w.L * w.dl) * smp.omega;
+        R ljw = (R)(w.lj * w.dl) / (smp.omega * smp.omega);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) c[m] = smp.co[m] * ljw;
+#pragma unroll
+        for (int m = 3; m < 8; ++m) c[m] = smp.co[m] * lt;
+    }
     if (!POL) {
         if (smp.plasma) {
             ++w.nsamp;
-            w.I = unpol_segment(w.I, smp.c[0], smp.c[3], dlp);
-            w.tau += smp.c[3] * dlp;
-            w.Ij += smp.c[0] * dlp;
+            w.I = unpol_segment<R>(w.I, c[0], c[3]);
+            csum(w.tau, w.tau_c, c[3]);
+            csum(w.Ij, w.Ij_c, c[0]);
         }
         return;
     }
     if (!w.started && !smp.plasma) return;
+    const R ktr = (R)w.kt;
+    const R ar = (R)P.a;
     if (w.started) {
-        double ya[8] = {w.pys[0], w.pys[1], w.pys[2], w.pys[3], w.kt, w.pys[4], w.pys[5], w.pys[6]};
-        double yc[8] = {w.pyb[0], w.pyb[1], w.pyb[2], w.pyb[3], w.kt, w.pyb[4], w.pyb[5], w.pyb[6]};
-        transport_step(a, flat, ya, yc, 0.5 * (w.pdl + w.dl), w.N);
+        R ya[8], yc[8];
+        to_state_r(w.pys, ktr, ya);
+        to_state_r(w.pyb, ktr, yc);
+        transport_step<R>(ar, flat, ya, yc, (R)(0.5 * (w.pdl + w.dl)), w.N);
     }
     w.started = true;
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
-        w.pys[m] = ys[m < 4 ? m : m + 1];
-        w.pyb[m] = yb[m < 4 ? m : m + 1];
+        w.pys[m] = (R)ys[m < 4 ? m : m + 1];
+        w.pyb[m] = (R)yb[m < 4 ? m : m + 1];
     }
     w.pdl = w.dl;
     if (smp.plasma) {
         ++w.nsamp;
-        w.tau += smp.c[3] * dlp;
-        w.Ij += smp.c[0] * dlp;
+        csum(w.tau, w.tau_c, c[3]);
+        csum(w.Ij, w.Ij_c, c[0]);
         bool any = false;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) any = any || (smp.c[m] != 0.0);
+        for (int m = 0; m < 8; ++m) any = any || (c[m] != R(0));
         if (any) {
-            KS k = ks_point(a, flat, ys[1], ys[2], ys[3]);
-            double e[4][4];
-            tetrad(k, smp.u, ys + 4, smp.b, e);
-            double S[4];
+            KS<R> k = ks_point<R>(ar, flat, (R)ys[1], (R)ys[2], (R)ys[3]);
+            R kc[4] = {(R)ys[4], (R)ys[5], (R)ys[6], (R)ys[7]};
+            R e[4][4];
+            tetrad(k, smp.u, kc, smp.b, e);
+            R S[4];
             coh_to_stokes(k, e[1], e[2], w.N, S);
-            stokes_step(smp.c, dlp, S);
+            stokes_step(c, S);
             stokes_to_coh(e[1], e[2], S, w.N);
         }
     }
 }
 
 // Close the ray at the pixel: final half transport, camera Stokes basis.
-template <bool POL>
-__device__ __forceinline__ void finish_ray(RayWalk &w, const GeoParams &P, const double upix[4], const double Hv[4],
-                                           TransferOut &o) {
-    o.tau = w.tau;
-    o.Ij = w.Ij;
+template <bool POL, typename R>
+__device__ __forceinline__ void finish_ray(RayWalk<R> &w, const GeoParams &P, const double upix[4],
+                                           const double Hv[4], TransferOut &o) {
+    o.tau = (double)w.tau;
+    o.Ij = (double)w.Ij;
     o.nsamp = w.nsamp;
     o.nrec = w.nrec;
     o.S[0] = o.S[1] = o.S[2] = o.S[3] = 0.0;
     if (!POL) {
-        o.S[0] = w.I;
+        o.S[0] = (double)w.I;
         return;
     }
     if (!w.started) return;
     const double *rec = w.rec;
-    double y0[8];
-    y0[0] = rec[0]; y0[1] = rec[1]; y0[2] = rec[2]; y0[3] = rec[3];
-    y0[4] = w.kt; y0[5] = rec[4]; y0[6] = rec[5]; y0[7] = rec[6];
-    double ya[8] = {w.pys[0], w.pys[1], w.pys[2], w.pys[3], w.kt, w.pys[4], w.pys[5], w.pys[6]};
-    transport_step(P.a, P.flat, ya, y0, 0.5 * w.pdl, w.N);
-    KS k = ks_point(P.a, P.flat, y0[1], y0[2], y0[3]);
-    double mH[4] = {-Hv[0], -Hv[1], -Hv[2], -Hv[3]};
-    double e[4][4];
-    tetrad(k, upix, y0 + 4, mH, e);
-    coh_to_stokes(k, e[1], e[2], w.N, o.S);
+    const R ktr = (R)w.kt, ar = (R)P.a;
+    R y0[8];
+    y0[0] = (R)rec[0]; y0[1] = (R)rec[1]; y0[2] = (R)rec[2]; y0[3] = (R)rec[3];
+    y0[4] = ktr; y0[5] = (R)rec[4]; y0[6] = (R)rec[5]; y0[7] = (R)rec[6];
+    R ya[8];
+    to_state_r(w.pys, ktr, ya);
+    transport_step<R>(ar, P.flat, ya, y0, (R)(0.5 * w.pdl), w.N);
+    KS<R> k = ks_point<R>(ar, P.flat, y0[1], y0[2], y0[3]);
+    R mH[4] = {(R)-Hv[0], (R)-Hv[1], (R)-Hv[2], (R)-Hv[3]};
+    R up[4] = {(R)upix[0], (R)upix[1], (R)upix[2], (R)upix[3]};
+    R e[4][4];
+    tetrad(k, up, y0 + 4, mH, e);
+    R S[4];
+    coh_to_stokes(k, e[1], e[2], w.N, S);
+    for (int m = 0; m < 4; ++m) o.S[m] = (double)S[m];
 }
 
 // Whole ray by one lane (used where rays are not interleaved).
-template <bool POL>
+template <bool POL, typename R>
 __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
                                              const TransferParams &tp, const double *rec, int n_acc, double kt,
                                              double n_norm, const double upix[4], const double Hv[4],
                                              TransferOut &o) {
     __shared__ double s_q[35 * 64];
     const int lane = threadIdx.x;
-    RayWalk w;
-    begin_ray(w, rec, n_acc, kt, n_norm, tp.L);
+    RayWalk<R> w;
+    begin_ray(w, rec, n_acc, kt, n_norm, tp);
     while (w.st >= 0 || w.p >= 0) {
         if (w.p < 0) next_step(w, P, g, tp, s_q, lane);
-        piece<POL>(w, P, g, pp, s_q, lane);
+        piece<POL, R>(w, P, g, pp, s_q, lane);
     }
-    finish_ray<POL>(w, P, upix, Hv, o);
+    finish_ray<POL, R>(w, P, upix, Hv, o);
 }
 
 }  // namespace bl

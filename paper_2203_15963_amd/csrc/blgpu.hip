@@ -67,7 +67,7 @@ __global__ void k_camera_frame(CamParams cp, double a, int flat, Frame *out) {
         kl[1] = ww > 0.0 ? cp.k_cov[1] * w0 / ww : 0.0;
         kl[2] = ww > 0.0 ? cp.k_cov[1] * w1 / ww : 0.0;
     }
-    KS k = ks_point(a, flat, fr.xc[1], fr.xc[2], fr.xc[3]);
+    auto k = ks_point(a, flat, fr.xc[1], fr.xc[2], fr.xc[3]);
     double g[4][4], gi[4][4];
     double ll[4] = {1.0, k.l[0], k.l[1], k.l[2]}, lu[4] = {-1.0, k.l[0], k.l[1], k.l[2]};
     for (int i = 0; i < 4; ++i)
@@ -214,17 +214,18 @@ __global__ void __launch_bounds__(64) k_geodesic(GeoParams P, CamParams cp, cons
     }
 }
 
-__device__ __forceinline__ void write_pixel(const TransferOut &t, double nu3, long long NN, long long pix,
-                                            double *image, double *aux) {
-    for (int q = 0; q < 4; ++q) image[q * NN + pix] = nu3 * t.S[q];
+// Transfer results are already in camera units (I_nu = nu^3 I).
+__device__ __forceinline__ void write_pixel(const TransferOut &t, long long NN, long long pix, double *image,
+                                            double *aux) {
+    for (int q = 0; q < 4; ++q) image[q * NN + pix] = t.S[q];
     aux[BL_AUX_TAU * NN + pix] = t.tau;
-    aux[BL_AUX_IJ * NN + pix] = nu3 * t.Ij;
+    aux[BL_AUX_IJ * NN + pix] = t.Ij;
     aux[BL_AUX_NSAMP * NN + pix] = (double)t.nsamp;
     aux[BL_AUX_NREC * NN + pix] = (double)t.nrec;
 }
 
 __device__ __forceinline__ void pixel_observer(const Frame &fr, const GeoParams &P, const double *rec0, double upix[4]) {
-    KS k = ks_point(P.a, P.flat, rec0[1], rec0[2], rec0[3]);
+    auto k = ks_point(P.a, P.flat, rec0[1], rec0[2], rec0[3]);
     velocity_from_normal(k, fr.ut, upix);
 }
 
@@ -233,7 +234,7 @@ __device__ __forceinline__ void pixel_observer(const Frame &fr, const GeoParams 
 // lanes that need one), so the per-piece work always runs on full waves even
 // though rays hold from tens to thousands of pieces.  Every lane leaves the
 // loop once the queue is exhausted and its ray is written.
-template <bool POL>
+template <bool POL, typename R>
 __global__ void __launch_bounds__(64) k_transfer(GeoParams P, CamParams cp, DevGrid g, PlasmaParams pp,
                                                  TransferParams tp, const Frame *__restrict__ frp, long long start,
                                                  int count, const double *__restrict__ rec,
@@ -243,8 +244,7 @@ __global__ void __launch_bounds__(64) k_transfer(GeoParams P, CamParams cp, DevG
     __shared__ double s_q[35 * 64];
     const int lane = threadIdx.x;
     const long long NN = (long long)cp.n * cp.n;
-    const double nu3 = cp.nu * cp.nu * cp.nu;
-    RayWalk w;
+    RayWalk<R> w;
     int slot = -1;
     bool done = false;
     for (;;) {
@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(64) k_transfer(GeoParams P, CamParams cp, DevG
                     if (na >= 0) {   // negative: finished by the overflow kernel
                         slot = id;
                         begin_ray(w, rec + (long long)id * P.cap * kRecDoubles, na, meta[2 * id], meta[2 * id + 1],
-                                  tp.L);
+                                  tp);
                     }
                 }
             }
@@ -275,20 +275,20 @@ __global__ void __launch_bounds__(64) k_transfer(GeoParams P, CamParams cp, DevG
                 double upix[4];
                 pixel_observer(fr, P, w.rec, upix);
                 TransferOut t;
-                finish_ray<POL>(w, P, upix, fr.H, t);
-                write_pixel(t, nu3, NN, start + slot, image, aux);
+                finish_ray<POL, R>(w, P, upix, fr.H, t);
+                write_pixel(t, NN, start + slot, image, aux);
                 slot = -1;
             } else {
                 next_step(w, P, g, tp, s_q, lane);
             }
         }
-        if (slot >= 0) piece<POL>(w, P, g, pp, s_q, lane);
+        if (slot >= 0) piece<POL, R>(w, P, g, pp, s_q, lane);
     }
 }
 
 // Rays queued by k_geodesic: one wave, each lane traces and transfers its
 // rays in turn with a private buffer of big_cap records.
-template <bool POL>
+template <bool POL, typename R>
 __global__ void __launch_bounds__(64) k_overflow(GeoParams P, CamParams cp, DevGrid g, PlasmaParams pp,
                                                  TransferParams tp, const Frame *__restrict__ frp,
                                                  const int *__restrict__ ovf_count, const int *__restrict__ ovf_list,
@@ -318,8 +318,8 @@ __global__ void __launch_bounds__(64) k_overflow(GeoParams P, CamParams cp, DevG
         double upix[4];
         pixel_observer(fr, P, r, upix);
         TransferOut t;
-        transfer_ray<POL>(P, g, pp, tp, r, o.n_acc, kt, n, upix, fr.H, t);
-        write_pixel(t, cp.nu * cp.nu * cp.nu, NN, pix, image, aux);
+        transfer_ray<POL, R>(P, g, pp, tp, r, o.n_acc, kt, n, upix, fr.H, t);
+        write_pixel(t, NN, pix, image, aux);
     }
 }
 
@@ -340,13 +340,15 @@ __global__ void k_eval_samples(double a, int flat, DevGrid g, PlasmaParams pp, l
     double G[16];
     conn_k(a, flat, y, y + 4, G);
     for (int m = 0; m < 16; ++m) o[8 + m] = G[m];
-    Sample s;
-    sample_point(a, flat, g, pp, y, norms[i], s);
+    Sample<double> s;
+    sample_point<double>(a, flat, g, pp, y, norms[i], s);
     o[53] = s.sigma;
     if (!s.plasma) return;
-    for (int m = 0; m < 8; ++m) o[24 + m] = s.c[m];
+    // invariants: j/nu^2, alpha nu, rho nu at the fluid-frame frequency
+    for (int m = 0; m < 3; ++m) o[24 + m] = s.co[m] / (s.nu_fl * s.nu_fl);
+    for (int m = 3; m < 8; ++m) o[24 + m] = s.co[m] * s.nu_fl;
     o[32] = s.ne; o[33] = s.th; o[34] = s.B; o[35] = s.nu_fl;
-    KS k = ks_point(a, flat, y[1], y[2], y[3]);
+    auto k = ks_point(a, flat, y[1], y[2], y[3]);
     double e[4][4];
     tetrad(k, s.u, y + 4, s.b, e);
     for (int q = 0; q < 4; ++q)
@@ -373,7 +375,7 @@ struct bl_context {
     size_t ws_limit = (size_t)8 << 30;   // bytes of step records per chunk
     int *d_queue = nullptr;              // per-chunk work counters of the persistent kernels
     size_t queue_bytes = 0;
-    int waves_tr[2] = {0, 0};            // resident waves of k_transfer<unpolarized / polarized>
+    int waves_tr[4] = {0, 0, 0, 0};      // resident waves of k_transfer<pol, R>: [2 pol + (R == float)]
     bool prof = false;
     struct Timed {
         int kind;
@@ -500,12 +502,13 @@ struct TimedLaunch {
 // Number of waves of each persistent kernel that fit on the device at once.
 bl_status persistent_waves(bl_context *ctx) {
     if (ctx->waves_tr[0] > 0) return BL_OK;
-    int cus = 0, b0 = 0, b1 = 0;
+    int cus = 0, b[4] = {0, 0, 0, 0};
     HIPCHK(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b0, k_transfer<false>, 64, 0));
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_transfer<true>, 64, 0));
-    ctx->waves_tr[0] = std::max(1, b0) * cus;
-    ctx->waves_tr[1] = std::max(1, b1) * cus;
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[0], k_transfer<false, double>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[1], k_transfer<false, float>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[2], k_transfer<true, double>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[3], k_transfer<true, float>, 64, 0));
+    for (int k = 0; k < 4; ++k) ctx->waves_tr[k] = std::max(1, b[k]) * cus;
     return BL_OK;
 }
 
@@ -546,20 +549,20 @@ bl_status bl_create(int device, void *hip_stream, bl_context **out) {
 
 void bl_destroy(bl_context *ctx) {
     if (!ctx) return;
-    hipSetDevice(ctx->device);
-    hipStreamSynchronize(ctx->stream);
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
     for (auto &t : ctx->timed) {
-        hipEventDestroy(t.a);
-        hipEventDestroy(t.b);
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
     }
-    hipFree(ctx->d_frame);
-    hipFree(ctx->d_rec);
-    hipFree(ctx->d_meta);
-    hipFree(ctx->d_nacc);
-    hipFree(ctx->d_ovf_count);
-    hipFree(ctx->d_ovf_list);
-    hipFree(ctx->d_big);
-    hipFree(ctx->d_queue);
+    (void)hipFree(ctx->d_frame);
+    (void)hipFree(ctx->d_rec);
+    (void)hipFree(ctx->d_meta);
+    (void)hipFree(ctx->d_nacc);
+    (void)hipFree(ctx->d_ovf_count);
+    (void)hipFree(ctx->d_ovf_list);
+    (void)hipFree(ctx->d_big);
+    (void)hipFree(ctx->d_queue);
     delete ctx;
 }
 
@@ -623,8 +626,8 @@ bl_status bl_grid_create(bl_context *ctx, const bl_grid_desc *d, bl_grid **out) 
     hipError_t e1 = hipMalloc((void **)&gr->d_bmeta, bmeta.size() * sizeof(double));
     hipError_t e2 = hipMalloc((void **)&gr->d_table, table.size() * sizeof(int));
     if (e1 != hipSuccess || e2 != hipSuccess) {
-        hipFree(gr->d_bmeta);
-        hipFree(gr->d_table);
+        (void)hipFree(gr->d_bmeta);
+        (void)hipFree(gr->d_table);
         delete gr;
         return fail(ctx, BL_E_OOM, "device allocation of the block tables failed");
     }
@@ -653,8 +656,8 @@ bl_status bl_grid_create(bl_context *ctx, const bl_grid_desc *d, bl_grid **out) 
 void bl_grid_destroy(bl_grid *gr) {
     if (!gr) return;
     if (gr->ctx) hipSetDevice(gr->ctx->device);
-    hipFree(gr->d_bmeta);
-    hipFree(gr->d_table);
+    (void)hipFree(gr->d_bmeta);
+    (void)hipFree(gr->d_table);
     delete gr;
 }
 
@@ -706,9 +709,11 @@ bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *s
         (s = check_integrator(ctx, integ)) != BL_OK)
         return s;
     if (!grid || !plasma || !image_out || !aux_out) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
-    if (mode && (mode->precision != 0 || mode->step_model != 0))
-        return fail(ctx, BL_E_UNSUPPORTED, "only precision 0 and step_model 0 are available");
-    if (grid->g.dtype != 0) return fail(ctx, BL_E_UNSUPPORTED, "float32 grids need precision 1");
+    if (mode && (mode->precision < 0 || mode->precision > 1))
+        return fail(ctx, BL_E_INVALID_ARG, "precision must be 0 (FP64) or 1 (mixed)");
+    if (mode && mode->step_model != 0) return fail(ctx, BL_E_UNSUPPORTED, "only step_model 0 is available");
+    const bool mixed = mode && mode->precision == 1;
+    if (grid->g.dtype != 0 && !mixed) return fail(ctx, BL_E_UNSUPPORTED, "float32 grids need precision 1");
     if (!(plasma->mu > 0.0) || !(plasma->ne_ni > 0.0) || !(plasma->sigma_max >= 0.0))
         return fail(ctx, BL_E_INVALID_ARG, "plasma mu, ne_ni must be positive and sigma_max >= 0");
     HIPCHK(ctx, hipSetDevice(ctx->device));
@@ -745,6 +750,7 @@ bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *s
     TransferParams tp;
     tp.ds_max = integ->ds_max;
     tp.L = kG * st->mass_msun * kMsun / (kC * kC);
+    tp.nu_cam = cam->nu_hz;
     CamParams cp = cam_params(cam);
     long long nchunk = (NN + chunk - 1) / chunk;
     if ((s = ensure(ctx, &ctx->d_queue, ctx->queue_bytes, (size_t)nchunk * 2 * sizeof(int))) != BL_OK) return s;
@@ -766,24 +772,40 @@ bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *s
         {
             TimedLaunch tl(ctx, BL_K_TRANSFER);
             int *q = ctx->d_queue + 2 * ichunk;
-            if (pp.polarized)
-                hipLaunchKernelGGL(k_transfer<true>, dim3(std::min<int>(grd.x, ctx->waves_tr[1])), blk, 0, ctx->stream,
-                                   P, cp, grid->g, pp, tp, ctx->d_frame, start, count, ctx->d_rec, ctx->d_meta,
-                                   ctx->d_nacc, q, image_out, aux_out);
+            int kidx = 2 * pp.polarized + (mixed ? 1 : 0);
+            dim3 pg(std::min<int>(grd.x, ctx->waves_tr[kidx]));
+            if (pp.polarized && mixed)
+                hipLaunchKernelGGL((k_transfer<true, float>), pg, blk, 0, ctx->stream, P, cp, grid->g, pp, tp,
+                                   ctx->d_frame, start, count, ctx->d_rec, ctx->d_meta, ctx->d_nacc, q, image_out,
+                                   aux_out);
+            else if (pp.polarized)
+                hipLaunchKernelGGL((k_transfer<true, double>), pg, blk, 0, ctx->stream, P, cp, grid->g, pp, tp,
+                                   ctx->d_frame, start, count, ctx->d_rec, ctx->d_meta, ctx->d_nacc, q, image_out,
+                                   aux_out);
+            else if (mixed)
+                hipLaunchKernelGGL((k_transfer<false, float>), pg, blk, 0, ctx->stream, P, cp, grid->g, pp, tp,
+                                   ctx->d_frame, start, count, ctx->d_rec, ctx->d_meta, ctx->d_nacc, q, image_out,
+                                   aux_out);
             else
-                hipLaunchKernelGGL(k_transfer<false>, dim3(std::min<int>(grd.x, ctx->waves_tr[0])), blk, 0,
-                                   ctx->stream, P, cp, grid->g, pp, tp, ctx->d_frame, start, count, ctx->d_rec,
-                                   ctx->d_meta, ctx->d_nacc, q, image_out, aux_out);
+                hipLaunchKernelGGL((k_transfer<false, double>), pg, blk, 0, ctx->stream, P, cp, grid->g, pp, tp,
+                                   ctx->d_frame, start, count, ctx->d_rec, ctx->d_meta, ctx->d_nacc, q, image_out,
+                                   aux_out);
         }
         HIPCHK(ctx, hipGetLastError());
     }
     {
         TimedLaunch tl(ctx, BL_K_OVERFLOW);
-        if (pp.polarized)
-            hipLaunchKernelGGL(k_overflow<true>, dim3(1), dim3(64), 0, ctx->stream, P, cp, grid->g, pp, tp,
+        if (pp.polarized && mixed)
+            hipLaunchKernelGGL((k_overflow<true, float>), dim3(1), dim3(64), 0, ctx->stream, P, cp, grid->g, pp, tp,
+                               ctx->d_frame, ctx->d_ovf_count, ctx->d_ovf_list, ctx->d_big, big_cap, image_out, aux_out);
+        else if (pp.polarized)
+            hipLaunchKernelGGL((k_overflow<true, double>), dim3(1), dim3(64), 0, ctx->stream, P, cp, grid->g, pp, tp,
+                               ctx->d_frame, ctx->d_ovf_count, ctx->d_ovf_list, ctx->d_big, big_cap, image_out, aux_out);
+        else if (mixed)
+            hipLaunchKernelGGL((k_overflow<false, float>), dim3(1), dim3(64), 0, ctx->stream, P, cp, grid->g, pp, tp,
                                ctx->d_frame, ctx->d_ovf_count, ctx->d_ovf_list, ctx->d_big, big_cap, image_out, aux_out);
         else
-            hipLaunchKernelGGL(k_overflow<false>, dim3(1), dim3(64), 0, ctx->stream, P, cp, grid->g, pp, tp,
+            hipLaunchKernelGGL((k_overflow<false, double>), dim3(1), dim3(64), 0, ctx->stream, P, cp, grid->g, pp, tp,
                                ctx->d_frame, ctx->d_ovf_count, ctx->d_ovf_list, ctx->d_big, big_cap, image_out, aux_out);
     }
     HIPCHK(ctx, hipGetLastError());

@@ -84,8 +84,12 @@ def _compare_render(ctx, oracle, w, pixels=None, precision=0, tol=TOL_FP64, max_
         for q in (0, 1, 2):
             assert np.abs(aux[q] - ao[q])[match].max() <= 1e-9 * (1 + np.abs(ao[q]).max())
         assert np.array_equal(aux[7][match], ao[7][match])
-        assert np.array_equal(aux[8][match], ao[8][match])
         assert np.array_equal(aux[9][match], ao[9][match])
+        if precision == 0:
+            assert np.array_equal(aux[8][match], ao[8][match])
+        else:
+            # the sigma cut is taken in FP32: a sample right at sigma_max may flip
+            assert np.abs(aux[8] - ao[8])[match].sum() <= 1e-3 * ao[8].sum() + 2
         for q in (3, 4):
             d = np.abs(aux[q] - ao[q])[match]
             assert d.max() <= tol * (1e-30 + np.abs(ao[q]).max())
@@ -250,3 +254,44 @@ def test_deterministic(ctx):
     a2, x2 = ctx.render(w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"])
     torch.cuda.synchronize()
     assert torch.equal(a1, a2) and torch.equal(x1, x2)
+
+
+# ------------------------------------------------------------ mixed precision
+TOL_MIXED = 1e-4
+
+
+def test_render_mixed_unpolarized(ctx, oracle):
+    _compare_render(ctx, oracle, _wl("c1_64_unpol", 16), precision=1, tol=TOL_MIXED)
+
+
+def test_render_mixed_polarized_smr(ctx, oracle):
+    _compare_render(ctx, oracle, _wl("c3_1024_smr", 12), precision=1, tol=TOL_MIXED)
+
+
+def test_render_mixed_fp32_grid(ctx, oracle):
+    """Grid stored in FP32 (half the bytes): compare with the oracle run on the
+    same float-rounded cell values."""
+    w = _wl("c2_256_pol", 12)
+    g = _grid(w)
+    g32 = dict(g, prims=g["prims"].astype(np.float32))
+    g64r = dict(g, prims=g32["prims"].astype(np.float64))
+    n = 12
+    gg = ctx.grid(g32)
+    img, aux = ctx.render(w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"], precision=1)
+    torch.cuda.synchronize()
+    img, aux = img.cpu().numpy(), aux.cpu().numpy()
+    io, ao = oracle.render(w["camera"], w["spacetime"], w["integrator"], g64r, w["plasma"])
+    match = (ao[5] == aux[5]) & (ao[6] == aux[6])
+    ep, e = epix(img, io, match)
+    _say("mixed fp32 grid E_pix", ep, "matched", int(match.sum()))
+    assert ep <= TOL_MIXED and match.sum() >= 0.98 * n * n
+
+
+def test_full_size_sampled_mixed(ctx, oracle):
+    """The benchmark configuration (1024^2 SMR polarized, mixed precision)
+    against the FP64 oracle on sampled pixels."""
+    w = _wl("c3_1024_smr", 1024)
+    rng = np.random.default_rng(12)
+    pix = rng.choice(1024 * 1024, size=48, replace=False)
+    pix = np.concatenate([pix, [0, 1023, 1024 * 512 + 512, 1024 * 1024 - 1]])
+    _compare_render(ctx, oracle, w, pixels=pix, precision=1, tol=TOL_MIXED)
