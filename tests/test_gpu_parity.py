@@ -64,11 +64,18 @@ def epix(img_g, img_o, counts_match):
     return e[counts_match].max() if counts_match.any() else 0.0, e
 
 
-def _compare_render(ctx, oracle, w, pixels=None, precision=0, tol=TOL_FP64, max_mismatch=0.02):
+def _compare_render(ctx, oracle, w, pixels=None, precision=0, tol=TOL_FP64, max_mismatch=0.02, grid_f32=False):
     g = _grid(w)
     n = int(w["camera"]["n"])
-    _say("render", w["camera"]["n"], w["plasma"]["polarized"], w["grid_args"].get("kind"))
-    gg = ctx.grid(g)
+    _say("render", w["camera"]["n"], w["plasma"]["polarized"], w["grid_args"].get("kind"), "precision", precision,
+         "f32 grid" if grid_f32 else "")
+    if grid_f32:
+        # the device holds the float-rounded cells; the oracle reads the same values
+        g32 = dict(g, prims=g["prims"].astype(np.float32))
+        gg = ctx.grid(g32)
+        g = dict(g, prims=g32["prims"].astype(np.float64))
+    else:
+        gg = ctx.grid(g)
     img, aux = ctx.render(w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"], precision=precision)
     torch.cuda.synchronize()
     img, aux = img.cpu().numpy(), aux.cpu().numpy()
@@ -288,10 +295,17 @@ def test_render_mixed_fp32_grid(ctx, oracle):
 
 
 def test_full_size_sampled_mixed(ctx, oracle):
-    """The benchmark configuration (1024^2 SMR polarized, mixed precision)
-    against the FP64 oracle on sampled pixels."""
+    """The benchmark configuration (1024^2 SMR polarized, mixed precision, FP32
+    grid) against the FP64 oracle on sampled pixels."""
     w = _wl("c3_1024_smr", 1024)
     rng = np.random.default_rng(12)
     pix = rng.choice(1024 * 1024, size=48, replace=False)
     pix = np.concatenate([pix, [0, 1023, 1024 * 512 + 512, 1024 * 1024 - 1]])
+    _compare_render(ctx, oracle, w, pixels=pix, precision=1, tol=TOL_MIXED, grid_f32=True)
+
+
+def test_full_size_sampled_mixed_f64_grid(ctx, oracle):
+    w = _wl("c3_1024_smr", 1024)
+    rng = np.random.default_rng(13)
+    pix = rng.choice(1024 * 1024, size=32, replace=False)
     _compare_render(ctx, oracle, w, pixels=pix, precision=1, tol=TOL_MIXED)
