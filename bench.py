@@ -88,6 +88,102 @@ def cpu_baseline(w, grid, budget_s=15.0, seed=0):
             "sample": f"{done} random pixels of the same {n}x{n} image (seed {seed}), {t_used:.1f} s"}
 
 
+def roofline(precision, dom, kern, units):
+    model = OPS_PER_UNIT[precision][dom]
+    nl = max(1.0, kern[dom]["launches_per_step"])
+    ops = {t: sum(c * units[u] for u, c in model[t].items()) / nl for t in ("F64", "F32")}
+    t_min = ops["F64"] / (FP64_PEAK_TFLOPS * 1e12) + ops["F32"] / (FP32_PEAK_TFLOPS * 1e12)
+    per_launch = ops["F64"] + ops["F32"]
+    peak = per_launch / t_min / 1e12
+    achieved = per_launch / (kern[dom]["avg_launch_ms"] / 1e3) / 1e12
+    tr = TRAFFIC.get((precision, dom))
+    traffic = tr["bytes"] if tr is not None and tr["src"] == source_hash() else None
+    return {"bound": "alu", "kernel": "k_" + dom, "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic, "traffic_unit": "bytes/launch",
+            "ops_per_launch": {"f64": ops["F64"], "f32": ops["F32"]},
+            "peak_note": f"combined bound t >= F64/{FP64_PEAK_TFLOPS} + F32/{FP32_PEAK_TFLOPS} TFLOP/s",
+            "units_per_step": units}
+
+
+def kernel_table(prof, steps):
+    return {name: {"ms_per_step": tot / steps, "launches_per_step": nl / steps,
+                   "avg_launch_ms": (tot / nl) if nl else 0.0} for name, (tot, nl) in prof.items()}
+
+
+def run_batch(args):
+    """64 images of uneven size, frequency, inclination and spin on one grid:
+    one batched render per step (autotuned schedule) against one bl_render
+    per image with the same schedule."""
+    import numpy as np
+    import torch
+    from paper_2203_15963_amd import blgpu, synth
+
+    bw = synth.batch_workload()
+    grid_f32 = args.precision == 1 and not args.grid_f64
+    grid = synth.make_grid(bw["grid_args"], dtype=np.float32 if grid_f32 else np.float64)
+    ctx = blgpu.Context(0)
+    gg = ctx.grid(grid)
+    imgs = bw["images"]
+    rays = sum(int(c["n"]) ** 2 for c, _ in imgs)
+    outs = [(torch.empty(4, c["n"], c["n"], dtype=torch.float64, device="cuda"),
+             torch.empty(blgpu.NAUX, c["n"], c["n"], dtype=torch.float64, device="cuda")) for c, _ in imgs]
+    log(f"{len(imgs)} images, {rays} rays")
+    tuning = ctx.get_tuning()
+    tune_ms = None
+    if not args.no_autotune:
+        tuning, tune_ms = ctx.autotune(imgs, bw["integrator"], gg, bw["plasma"], precision=args.precision,
+                                       max_trials=args.tune_trials, outputs=outs)
+        log("autotuned", tuning, f"{tune_ms:.1f} ms")
+
+    def batched():
+        ctx.render_batch(imgs, bw["integrator"], gg, bw["plasma"], precision=args.precision, outputs=outs)
+
+    def per_image():
+        for (cam, st), (im, ax) in zip(imgs, outs):
+            ctx.render(cam, st, bw["integrator"], gg, bw["plasma"], precision=args.precision, image=im, aux=ax)
+
+    res = {}
+    for name, fn in (("per_image", per_image), ("batched", batched)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        ctx.profile_read()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = ctx.profile_read()
+        ctx.profile_enable(False)
+        res[name] = ((t1 - t0) * 1e3 / args.steps, kernel_table(prof, args.steps))
+        log(name, f"{res[name][0]:.2f} ms per batch")
+    ms, kern = res["batched"]
+    units = {"trial": 0.0, "acc": 0.0, "samp": 0.0, "rec": 0.0, "ray": float(rays)}
+    for _, ax in outs:
+        x = ax.cpu().numpy()
+        units["trial"] += float(x[5].sum() + x[6].sum())
+        units["acc"] += float(x[5].sum())
+        units["samp"] += float(x[8].sum())
+        units["rec"] += float(x[9].sum())
+    dom = max(("geodesic", "transfer"), key=lambda k: kern[k]["ms_per_step"])
+    out = {
+        "metric": "rays/sec of a 64-image batch (geodesic+polarized transfer), one batched launch sequence",
+        "value": rays / (ms / 1e3), "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == 0 else "f64+f32", "data": "synthetic",
+        "config": {"workload": f"c4_batch64: {len(imgs)} images of 64^2 to 512^2 pixels ({rays} rays), "
+                               "86-690 GHz, inclinations 17-90 deg, spins 0-0.98, shared 128^3 grid, polarized",
+                   "precision": args.precision, "grid_dtype": "f32" if grid_f32 else "f64", "pixels": rays},
+        "per_image_launches": {"ms_per_step": res["per_image"][0], "value": rays / (res["per_image"][0] / 1e3)},
+        "batch_speedup": res["per_image"][0] / ms,
+        "tuning": tuning, "autotune_ms": tune_ms,
+        "kernels": kern,
+        "roofline": roofline(args.precision, dom, kern, units),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +197,10 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the image size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-autotune", action="store_true", help="batched workload: keep the default schedule")
+    ap.add_argument("--autotune", action="store_true", help="single image: autotune the schedule first (untimed)")
+    ap.add_argument("--tuning", default=None, help="schedule as JSON, e.g. '{\"tile_w\": 8, \"tile_h\": 8}'")
+    ap.add_argument("--tune-trials", type=int, default=14)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -109,6 +209,9 @@ def main():
               "(pixels are independent; see the design notes for how the image would shard)",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload.startswith("c4"):
+        run_batch(args)
+        return
 
     import numpy as np
     import torch
@@ -124,6 +227,14 @@ def main():
     img = torch.empty(4, n, n, dtype=torch.float64, device="cuda")
     aux = torch.empty(blgpu.NAUX, n, n, dtype=torch.float64, device="cuda")
     log("grid resident:", grid["prims"].nbytes / 1e6, "MB;", len(grid["bounds"]), "blocks")
+
+    if args.tuning:
+        ctx.set_tuning(json.loads(args.tuning))
+    tune_ms = None
+    if args.autotune:
+        _, tune_ms = ctx.autotune([(w["camera"], w["spacetime"])], w["integrator"], gg, w["plasma"],
+                                  precision=args.precision, max_trials=args.tune_trials, outputs=[(img, aux)])
+        log("autotuned", ctx.get_tuning(), f"{tune_ms:.1f} ms")
 
     def step():
         ctx.render(w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"], precision=args.precision,
@@ -152,26 +263,10 @@ def main():
     units = {"trial": float(a[5].sum() + a[6].sum()), "acc": float(a[5].sum()), "samp": float(a[8].sum()),
              "rec": float(a[9].sum()), "ray": float(rays)}
     pol = bool(w["plasma"]["polarized"])
-    kern = {}
-    for name, (tot, nl) in prof.items():
-        kern[name] = {"ms_per_step": tot / args.steps, "launches_per_step": nl / args.steps,
-                      "avg_launch_ms": (tot / nl) if nl else 0.0}
+    kern = kernel_table(prof, args.steps)
     # dominant kernel: largest share of the step
     dom = max(("geodesic", "transfer"), key=lambda k: kern[k]["ms_per_step"])
-    model = OPS_PER_UNIT[args.precision][dom]
-    nl = max(1.0, kern[dom]["launches_per_step"])
-    ops = {t: sum(c * units[u] for u, c in model[t].items()) / nl for t in ("F64", "F32")}
-    t_min = ops["F64"] / (FP64_PEAK_TFLOPS * 1e12) + ops["F32"] / (FP32_PEAK_TFLOPS * 1e12)
-    per_launch = ops["F64"] + ops["F32"]
-    peak = per_launch / t_min / 1e12
-    achieved = per_launch / (kern[dom]["avg_launch_ms"] / 1e3) / 1e12
-    tr = TRAFFIC.get((args.precision, dom))
-    traffic = tr["bytes"] if tr is not None and tr["src"] == source_hash() else None
-    roof = {"bound": "alu", "kernel": "k_" + dom, "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic, "traffic_unit": "bytes/launch",
-            "ops_per_launch": {"f64": ops["F64"], "f32": ops["F32"]},
-            "peak_note": f"combined bound t >= F64/{FP64_PEAK_TFLOPS} + F32/{FP32_PEAK_TFLOPS} TFLOP/s",
-            "units_per_step": units}
+    roof = roofline(args.precision, dom, kern, units)
     out = {
         "metric": "rays/sec at 1024² (geodesic+polarized transfer) at ≤1e-4 rel. error vs FP64 oracle",
         "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -182,6 +277,7 @@ def main():
                                f"{'polarized' if pol else 'unpolarized'}, {len(grid['bounds'])} blocks of "
                                f"{grid['prims'].shape[1]}^3 cells, f_abs=f_rel={w['integrator']['f_abs']}",
                    "precision": args.precision, "grid_dtype": "f32" if grid_f32 else "f64", "pixels": rays},
+        "tuning": ctx.get_tuning(),
         "kernels": kern,
         "roofline": roof,
     }

@@ -180,6 +180,63 @@ bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *s
                     const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
                     const bl_mode *mode, double *image_out, double *aux_out);
 
+/* Schedule of a render (how the work is laid out on the GPU; results do not
+   depend on it).  bl_render and bl_render_batch use the context's tuning
+   (bl_set_tuning; defaults below) unless bl_render_batch is given one. */
+typedef struct {
+    int32_t tile_w, tile_h;   /* pixels that share a wave: a tile_w x tile_h
+                                 tile with tile_w * tile_h = 64 (default
+                                 16 x 4); 0, 0 = plain row-major order        */
+    int32_t transfer_waves_per_cu; /* resident waves of the persistent transfer
+                                 kernel per compute unit; 0 = as many as fit
+                                 (default)                                    */
+    int32_t refill_min;       /* a transfer wave takes new rays once this many
+                                 of its lanes are idle (1..64; default 1)     */
+    int64_t chunk_rays;       /* rays traced per geodesic/transfer launch pair
+                                 (multiple of 64; 0 = as many as the step-
+                                 record workspace holds, the default: 32 GiB
+                                 or a quarter of the free device memory at
+                                 bl_create, whichever is less)                */
+    int32_t order;            /* 0: images in the given order; 1: largest
+                                 first                                        */
+    int32_t reserved;         /* must be 0                                    */
+} bl_tuning;
+
+bl_status bl_set_tuning(bl_context *ctx, const bl_tuning *tuning);
+bl_status bl_get_tuning(const bl_context *ctx, bl_tuning *tuning_out);
+
+/* One image of a batch: camera, spacetime (spin, mass and r_in may differ per
+   image; `flat` too) and device outputs as for bl_render. */
+typedef struct {
+    bl_camera cam;
+    bl_spacetime st;
+    double *image_out;        /* device [4][N][N]                             */
+    double *aux_out;          /* device [BL_NAUX][N][N]                       */
+} bl_image_desc;
+
+/* Many images of uneven size, frequency, inclination and spin over one grid
+   (the batched form of the paper's section 2 pipeline): all rays of all
+   images are dealt to the same geodesic and persistent transfer launches
+   (in chunks of tuning.chunk_rays), so small images do not leave the GPU
+   idle.  Each image's results equal those of bl_render for that image.
+   images: host [n_images]; tuning: host or NULL (the context's).  Total ray
+   count below 2^31. */
+bl_status bl_render_batch(bl_context *ctx, int32_t n_images, const bl_image_desc *images,
+                          const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
+                          const bl_mode *mode, const bl_tuning *tuning);
+
+/* Autotuner: times bl_render_batch of the given images (which it renders,
+   into their outputs, several times) under a coordinate search over tile
+   shape, transfer waves per CU, refill threshold, chunk size and image
+   order, starting from the context's tuning, with at most max_trials timed
+   renders.  Writes the fastest tuning and its time (ms per batch, from HIP
+   events on the context's stream) to host best_out / best_ms_out (either
+   may be NULL) and installs it as the context's tuning.  Synchronises the
+   stream. */
+bl_status bl_autotune(bl_context *ctx, int32_t n_images, const bl_image_desc *images,
+                      const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
+                      const bl_mode *mode, int32_t max_trials, bl_tuning *best_out, double *best_ms_out);
+
 /* Per-sample evaluation for checking (paper sections 2.2, 2.4, 2.5): for
    states device [n][8] and norms device [n], writes out device [n][64]:
    [0..7]   geodesic right-hand side dy/dlambda,

@@ -56,6 +56,31 @@ class bl_mode(C.Structure):
     _fields_ = [("precision", C.c_int32), ("step_model", C.c_int32)]
 
 
+class bl_tuning(C.Structure):
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("transfer_waves_per_cu", C.c_int32),
+                ("refill_min", C.c_int32), ("chunk_rays", C.c_int64), ("order", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class bl_image_desc(C.Structure):
+    _fields_ = [("cam", bl_camera), ("st", bl_spacetime), ("image_out", C.c_void_p), ("aux_out", C.c_void_p)]
+
+
+TUNING_FIELDS = ["tile_w", "tile_h", "transfer_waves_per_cu", "refill_min", "chunk_rays", "order"]
+
+
+def tuning(d):
+    t = bl_tuning()
+    for k in TUNING_FIELDS:
+        setattr(t, k, int(d.get(k, {"refill_min": 1}.get(k, 0))))
+    t.reserved = 0
+    return t
+
+
+def tuning_dict(t):
+    return {k: int(getattr(t, k)) for k in TUNING_FIELDS}
+
+
 _lib = None
 
 
@@ -86,6 +111,17 @@ def load():
     L.bl_render.argtypes = [vp, C.POINTER(bl_camera), C.POINTER(bl_spacetime), C.POINTER(bl_integrator),
                             vp, C.POINTER(bl_plasma), C.POINTER(bl_mode), vp, vp]
     L.bl_render.restype = C.c_int
+    L.bl_render_batch.argtypes = [vp, i32, C.POINTER(bl_image_desc), C.POINTER(bl_integrator), vp,
+                                  C.POINTER(bl_plasma), C.POINTER(bl_mode), C.POINTER(bl_tuning)]
+    L.bl_render_batch.restype = C.c_int
+    L.bl_set_tuning.argtypes = [vp, C.POINTER(bl_tuning)]
+    L.bl_set_tuning.restype = C.c_int
+    L.bl_get_tuning.argtypes = [vp, C.POINTER(bl_tuning)]
+    L.bl_get_tuning.restype = C.c_int
+    L.bl_autotune.argtypes = [vp, i32, C.POINTER(bl_image_desc), C.POINTER(bl_integrator), vp,
+                              C.POINTER(bl_plasma), C.POINTER(bl_mode), i32, C.POINTER(bl_tuning),
+                              C.POINTER(C.c_double)]
+    L.bl_autotune.restype = C.c_int
     L.bl_eval_samples.argtypes = [vp, C.POINTER(bl_spacetime), vp, C.POINTER(bl_plasma), i64, vp, vp, vp]
     L.bl_eval_samples.restype = C.c_int
     L.bl_profile_enable.argtypes = [vp, C.c_int]
@@ -249,6 +285,54 @@ class Context:
         self._check(load().bl_render(self.handle, C.byref(c), C.byref(s), C.byref(g), grid.handle,
                                      C.byref(p), C.byref(m), _ptr(image), _ptr(aux)))
         return image, aux
+
+    def _batch_descs(self, images, outputs):
+        """images: list of (camera dict, spacetime dict); outputs: list of
+        (image, aux) tensors or None to allocate."""
+        n = len(images)
+        descs = (bl_image_desc * n)()
+        outs = []
+        for k, (cam, st) in enumerate(images):
+            nn = int(cam["n"])
+            if outputs is None:
+                im, ax = self._empty(4, nn, nn), self._empty(NAUX, nn, nn)
+            else:
+                im, ax = outputs[k]
+            descs[k].cam = camera(cam)
+            descs[k].st = spacetime(st)
+            descs[k].image_out = C.c_void_p(im.data_ptr())
+            descs[k].aux_out = C.c_void_p(ax.data_ptr())
+            outs.append((im, ax))
+        return descs, outs
+
+    def render_batch(self, images, integ, grid, pl, precision=0, tuning_=None, outputs=None):
+        """Render many images in one batched launch sequence; returns a list
+        of (image, aux) tensors in the order given."""
+        descs, outs = self._batch_descs(images, outputs)
+        g, p, m = integrator(integ), plasma(pl), mode(precision)
+        t = C.byref(tuning(tuning_)) if tuning_ is not None else None
+        self._check(load().bl_render_batch(self.handle, len(images), descs, C.byref(g), grid.handle, C.byref(p),
+                                           C.byref(m), t))
+        return outs
+
+    def set_tuning(self, d):
+        t = tuning(d)
+        self._check(load().bl_set_tuning(self.handle, C.byref(t)))
+
+    def get_tuning(self):
+        t = bl_tuning()
+        self._check(load().bl_get_tuning(self.handle, C.byref(t)))
+        return tuning_dict(t)
+
+    def autotune(self, images, integ, grid, pl, precision=0, max_trials=16, outputs=None):
+        """Run the library's autotuner on this batch; returns (tuning dict,
+        ms per batch) and installs the tuning on the context."""
+        descs, outs = self._batch_descs(images, outputs)
+        g, p, m = integrator(integ), plasma(pl), mode(precision)
+        best, ms = bl_tuning(), C.c_double()
+        self._check(load().bl_autotune(self.handle, len(images), descs, C.byref(g), grid.handle, C.byref(p),
+                                       C.byref(m), int(max_trials), C.byref(best), C.byref(ms)))
+        return tuning_dict(best), ms.value
 
     def profile_enable(self, on=True):
         self._check(load().bl_profile_enable(self.handle, int(bool(on))))

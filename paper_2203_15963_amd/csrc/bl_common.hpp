@@ -70,4 +70,57 @@ struct PlasmaParams {
     int polarized, interp;
 };
 
+// One image of a render (a batch of one for bl_render): the camera frame
+// (filled on the device), camera and spacetime parameters, where its results
+// go, and the first global ray id it owns.
+struct ImgDev {
+    Frame fr;
+    CamParams cp;
+    double a, r_in;
+    double L;            // GM/c^2 in cm
+    double *image;       // [4][n][n]
+    double *aux;         // [naux][n][n]
+    long long ray0;      // first global ray id
+    long long nray;      // ray ids owned: n^2, or whole pixel tiles
+    int flat, pad;
+};
+
+// The images of one render and how ray ids map to pixels.  Ray ids of an image
+// are dealt out tile by tile: a tile of tw x th pixels (tw th = 64, so one
+// wave traces one tile of neighbouring pixels), tiles in row-major order over
+// the image, pixels row-major within the tile; ids of pixels past the image
+// edge are skipped.  tw = 0 means plain row-major pixel order.
+struct Batch {
+    ImgDev *imgs;
+    const long long *ray0;   // [n_img] copy of imgs[k].ray0 for the search
+    int n_img, tw, th, pad;
+};
+
+__device__ __forceinline__ int find_image(const Batch &B, long long gid) {
+    int lo = 0, hi = B.n_img - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (B.ray0[mid] <= gid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Pixel (i, j) of ray id rl (counted from the image's first id); false for
+// the ids of tile pixels that lie outside the image.
+__device__ __forceinline__ bool ray_pixel(const Batch &B, int n, long long rl, int &i, int &j) {
+    if (B.tw <= 0) {
+        i = (int)(rl % n);
+        j = (int)(rl / n);
+        return rl < (long long)n * n;
+    }
+    const int tsz = B.tw * B.th;
+    const int ntx = (n + B.tw - 1) / B.tw;
+    const long long tile = rl / tsz;
+    const int o = (int)(rl - tile * tsz);
+    i = (int)(tile % ntx) * B.tw + o % B.tw;
+    j = (int)(tile / ntx) * B.th + o / B.tw;
+    return i < n && j < n;
+}
+
 }  // namespace bl

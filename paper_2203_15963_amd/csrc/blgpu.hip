@@ -31,9 +31,14 @@ using namespace bl;
 // k_a - (u_a/u_t) k_t normalised by g^a'b', v from U = z (y on the polar
 // axis) by Gram-Schmidt, h = D^-1/2 [abc] v_b' K_c', rotation by psi, and the
 // return to coordinate components A^t = u^t A^t' - (u_a/u_t) A^a',
-// A^a = A^a' + u^a A^t'.
-__global__ void k_camera_frame(CamParams cp, double a, int flat, Frame *out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// A^a = A^a' + u^a A^t'.  One block per image, the frame of image b is
+// written into B.imgs[b].fr.
+__global__ void k_camera_frame(Batch bt) {
+    if (threadIdx.x != 0 || (int)blockIdx.x >= bt.n_img) return;
+    ImgDev &im = bt.imgs[blockIdx.x];
+    const CamParams cp = im.cp;
+    const double a = im.a;
+    const int flat = im.flat;
     Frame fr;
     double st = sin(cp.theta), ct = cos(cp.theta), sp = sin(cp.phi), cph = cos(cp.phi);
     double r = cp.r;
@@ -138,17 +143,18 @@ __global__ void k_camera_frame(CamParams cp, double a, int flat, Frame *out) {
         fr.V[1 + i] = Vp[i];
     }
     fr.pad = 0.0;
-    *out = fr;
+    im.fr = fr;
 }
 
-__global__ void k_camera_rays(CamParams cp, double a, int flat, const Frame *__restrict__ frp,
-                              double *__restrict__ state_out, double *__restrict__ norm_out) {
+__global__ void k_camera_rays(const ImgDev *__restrict__ imp, double *__restrict__ state_out,
+                              double *__restrict__ norm_out) {
+    const ImgDev &im = *imp;
+    const CamParams &cp = im.cp;
     long long NN = (long long)cp.n * cp.n;
     long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= NN) return;
-    Frame fr = *frp;
     double y[8], n;
-    camera_pixel(fr, cp, a, flat, (int)(pix % cp.n), (int)(pix / cp.n), y, n);
+    camera_pixel(im.fr, cp, im.a, im.flat, (int)(pix % cp.n), (int)(pix / cp.n), y, n);
     for (int m = 0; m < 8; ++m) state_out[pix * 8 + m] = y[m];
     norm_out[pix] = n;
 }
@@ -159,33 +165,55 @@ __global__ void k_fill_int(int *p, int v, int n) {
 }
 
 // ============================================================ geodesics
-// One lane per ray of the chunk [start, start + count).  With WREC the step
+// Per-image parameters of a lane: in a batch they are read from the image's
+// descriptor, for a single image the kernel arguments already hold them.
+template <bool BATCH>
+__device__ __forceinline__ GeoParams lane_params(const GeoParams &P, const ImgDev &im) {
+    if (!BATCH) return P;
+    GeoParams Q = P;
+    Q.a = im.a;
+    Q.r_in = im.r_in;
+    Q.r_cam = im.cp.r;
+    Q.flat = im.flat;
+    Q.n = im.cp.n;
+    return Q;
+}
+
+// One lane per ray id of the chunk [start, start + count).  With WREC the step
 // records are written into the lane's slot; rays that outgrow the slot are
-// queued on ovf_list.
-template <bool WREC>
-__global__ void __launch_bounds__(64) k_geodesic(GeoParams P, CamParams cp, const Frame *__restrict__ frp,
-                                                 long long start, int count, double *__restrict__ rec,
-                                                 double *__restrict__ meta, int *__restrict__ nacc_out,
-                                                 int *__restrict__ ovf_count, int *__restrict__ ovf_list,
-                                                 double *__restrict__ aux, double *__restrict__ state_out) {
+// queued on ovf_list; ids of tile pixels outside their image get nacc = -2.
+template <bool WREC, bool BATCH>
+__global__ void __launch_bounds__(64) k_geodesic(GeoParams P, Batch B, long long start, int count,
+                                                 double *__restrict__ rec, double *__restrict__ meta,
+                                                 int *__restrict__ nacc_out, int *__restrict__ ovf_count,
+                                                 int *__restrict__ ovf_list, double *__restrict__ state_out) {
     int slot = blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= count) return;
-    long long pix = start + slot;
-    long long NN = (long long)cp.n * cp.n;
-    const Frame &fr = *frp;
+    const long long gid = start + slot;
+    const int img = BATCH ? find_image(B, gid) : 0;
+    const ImgDev &im = B.imgs[img];
+    int pi, pj;
+    if (!ray_pixel(B, im.cp.n, gid - (BATCH ? B.ray0[img] : 0), pi, pj)) {
+        if (WREC) nacc_out[slot] = -2;
+        return;
+    }
+    const GeoParams Q = lane_params<BATCH>(P, im);
+    const long long NN = (long long)im.cp.n * im.cp.n;
+    const long long pix = (long long)pj * im.cp.n + pi;
+    double *aux = im.aux;
     double y8[8], n;
-    camera_pixel(fr, cp, P.a, P.flat, (int)(pix % cp.n), (int)(pix / cp.n), y8, n);
+    camera_pixel(im.fr, im.cp, Q.a, Q.flat, pi, pj, y8, n);
     double y[7] = {y8[0], y8[1], y8[2], y8[3], y8[5], y8[6], y8[7]};
     double kt = y8[4];
     TraceOut o;
-    trace_ray<WREC>(P, y, kt, WREC ? rec + (long long)slot * P.cap * kRecDoubles : nullptr, P.cap, o);
+    trace_ray<WREC>(Q, y, kt, WREC ? rec + (long long)slot * Q.cap * kRecDoubles : nullptr, Q.cap, o);
     if (WREC) {
         meta[2 * slot] = kt;
         meta[2 * slot + 1] = n;
         if (o.status == kRayOverflow) {
             nacc_out[slot] = -1;
             int idx = atomicAdd(ovf_count, 1);
-            ovf_list[idx] = (int)pix;
+            ovf_list[idx] = (int)gid;
             return;
         }
         nacc_out[slot] = o.n_acc;
@@ -232,24 +260,24 @@ __device__ __forceinline__ void pixel_observer(const Frame &fr, const GeoParams 
 // Persistent transfer: each wave keeps its 64 lanes busy by giving a lane
 // that finished its ray the next ray of the chunk (one atomic per wave for all
 // lanes that need one), so the per-piece work always runs on full waves even
-// though rays hold from tens to thousands of pieces.  Every lane leaves the
-// loop once the queue is exhausted and its ray is written.
-template <bool POL, typename R>
-__global__ void __launch_bounds__(64) k_transfer(GeoParams P, CamParams cp, DevGrid g, PlasmaParams pp,
-                                                 TransferParams tp, const Frame *__restrict__ frp, long long start,
-                                                 int count, const double *__restrict__ rec,
-                                                 const double *__restrict__ meta, const int *__restrict__ nacc,
-                                                 int *__restrict__ queue, double *__restrict__ image,
-                                                 double *__restrict__ aux) {
+// though rays hold from tens to thousands of pieces.  A wave takes new rays
+// once at least refill_min lanes are idle, or when none holds a ray.  Every
+// lane leaves the loop once the queue is exhausted and its ray is written.
+template <bool POL, typename R, bool BATCH>
+__global__ void __launch_bounds__(64) k_transfer(GeoParams P, Batch B, DevGrid g, PlasmaParams pp, TransferParams tp,
+                                                 long long start, int count, int refill_min,
+                                                 const double *__restrict__ rec, const double *__restrict__ meta,
+                                                 const int *__restrict__ nacc, int *__restrict__ queue) {
     __shared__ double s_q[35 * 64];
     const int lane = threadIdx.x;
-    const long long NN = (long long)cp.n * cp.n;
     RayWalk<R> w;
-    int slot = -1;
+    int slot = -1, img = 0;
+    double a_l = P.a;
+    int flat_l = P.flat;
     bool done = false;
     for (;;) {
         unsigned long long need = __ballot(slot < 0 && !done);
-        if (need) {
+        if (need && (__popcll(need) >= refill_min || __ballot(slot >= 0) == 0)) {
             int leader = __ffsll((long long)need) - 1;
             int base = 0;
             if (lane == leader) base = atomicAdd(queue, __popcll(need));
@@ -260,51 +288,73 @@ __global__ void __launch_bounds__(64) k_transfer(GeoParams P, CamParams cp, DevG
                     done = true;
                 } else {
                     int na = nacc[id];
-                    if (na >= 0) {   // negative: finished by the overflow kernel
+                    if (na >= 0) {   // -1: finished by the overflow kernel, -2: no pixel
                         slot = id;
+                        TransferParams tl = tp;
+                        if (BATCH) {
+                            img = find_image(B, start + id);
+                            const ImgDev &im = B.imgs[img];
+                            a_l = im.a;
+                            flat_l = im.flat;
+                            tl.L = im.L;
+                            tl.nu_cam = im.cp.nu;
+                        }
                         begin_ray(w, rec + (long long)id * P.cap * kRecDoubles, na, meta[2 * id], meta[2 * id + 1],
-                                  tp);
+                                  tl);
                     }
                 }
             }
         }
         if (__ballot(slot >= 0 || !done) == 0) break;
+        GeoParams Pl = P;
+        if (BATCH) {
+            Pl.a = a_l;
+            Pl.flat = flat_l;
+        }
         if (slot >= 0 && w.p < 0) {
             if (w.st < 0) {
-                const Frame &fr = *frp;
+                const ImgDev &im = B.imgs[img];
+                const long long gid = start + slot;
+                int pi = 0, pj = 0;
+                ray_pixel(B, im.cp.n, gid - (BATCH ? B.ray0[img] : 0), pi, pj);
                 double upix[4];
-                pixel_observer(fr, P, w.rec, upix);
+                pixel_observer(im.fr, Pl, w.rec, upix);
                 TransferOut t;
-                finish_ray<POL, R>(w, P, upix, fr.H, t);
-                write_pixel(t, NN, start + slot, image, aux);
+                finish_ray<POL, R>(w, Pl, upix, im.fr.H, t);
+                write_pixel(t, (long long)im.cp.n * im.cp.n, (long long)pj * im.cp.n + pi, im.image, im.aux);
                 slot = -1;
             } else {
-                next_step(w, P, g, tp, s_q, lane);
+                next_step(w, Pl, g, tp, s_q, lane);
             }
         }
-        if (slot >= 0) piece<POL, R>(w, P, g, pp, s_q, lane);
+        if (slot >= 0) piece<POL, R>(w, Pl, g, pp, s_q, lane);
     }
 }
 
 // Rays queued by k_geodesic: one wave, each lane traces and transfers its
 // rays in turn with a private buffer of big_cap records.
 template <bool POL, typename R>
-__global__ void __launch_bounds__(64) k_overflow(GeoParams P, CamParams cp, DevGrid g, PlasmaParams pp,
-                                                 TransferParams tp, const Frame *__restrict__ frp,
+__global__ void __launch_bounds__(64) k_overflow(GeoParams P, Batch B, DevGrid g, PlasmaParams pp, TransferParams tp,
                                                  const int *__restrict__ ovf_count, const int *__restrict__ ovf_list,
-                                                 double *__restrict__ big_rec, int big_cap,
-                                                 double *__restrict__ image, double *__restrict__ aux) {
+                                                 double *__restrict__ big_rec, int big_cap) {
     int lane = threadIdx.x;
     int total = *ovf_count;
-    long long NN = (long long)cp.n * cp.n;
-    const Frame &fr = *frp;
     double *r = big_rec + (long long)lane * big_cap * kRecDoubles;
-    GeoParams Q = P;
-    Q.cap = big_cap;
     for (int idx = lane; idx < total; idx += blockDim.x) {
-        long long pix = ovf_list[idx];
+        const long long gid = ovf_list[idx];
+        const int img = find_image(B, gid);
+        const ImgDev &im = B.imgs[img];
+        int pi, pj;
+        ray_pixel(B, im.cp.n, gid - B.ray0[img], pi, pj);
+        GeoParams Q = lane_params<true>(P, im);
+        Q.cap = big_cap;
+        TransferParams tl = tp;
+        tl.L = im.L;
+        tl.nu_cam = im.cp.nu;
+        const long long NN = (long long)im.cp.n * im.cp.n, pix = (long long)pj * im.cp.n + pi;
+        double *aux = im.aux;
         double y8[8], n;
-        camera_pixel(fr, cp, P.a, P.flat, (int)(pix % cp.n), (int)(pix / cp.n), y8, n);
+        camera_pixel(im.fr, im.cp, Q.a, Q.flat, pi, pj, y8, n);
         double y[7] = {y8[0], y8[1], y8[2], y8[3], y8[5], y8[6], y8[7]};
         double kt = y8[4];
         TraceOut o;
@@ -316,10 +366,10 @@ __global__ void __launch_bounds__(64) k_overflow(GeoParams P, CamParams cp, DevG
         aux[BL_AUX_NREJ * NN + pix] = (double)o.n_rej;
         aux[BL_AUX_STATUS * NN + pix] = (double)o.status;
         double upix[4];
-        pixel_observer(fr, P, r, upix);
+        pixel_observer(im.fr, Q, r, upix);
         TransferOut t;
-        transfer_ray<POL, R>(P, g, pp, tp, r, o.n_acc, kt, n, upix, fr.H, t);
-        write_pixel(t, NN, pix, image, aux);
+        transfer_ray<POL, R>(Q, g, pp, tl, r, o.n_acc, kt, n, upix, im.fr.H, t);
+        write_pixel(t, NN, pix, im.image, aux);
     }
 }
 
@@ -361,7 +411,16 @@ struct bl_context {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
-    Frame *d_frame = nullptr;
+    // image descriptors of the current render; the host copies stay alive
+    // until the upload that read them has completed (upload_done)
+    ImgDev *d_imgs = nullptr;
+    size_t imgs_bytes = 0;
+    long long *d_ray0 = nullptr;
+    size_t ray0_bytes = 0;
+    std::vector<ImgDev> h_imgs;
+    std::vector<long long> h_ray0;
+    hipEvent_t upload_done = nullptr;
+    bl_tuning tuning = {16, 4, 0, 1, 0, 0, 0};
     double *d_rec = nullptr;
     size_t rec_bytes = 0;
     double *d_meta = nullptr;
@@ -372,10 +431,12 @@ struct bl_context {
     size_t ovf_cap = 0;
     double *d_big = nullptr;
     size_t big_bytes = 0;
-    size_t ws_limit = (size_t)8 << 30;   // bytes of step records per chunk
+    size_t ws_limit = (size_t)32 << 30;  // bytes of step records per chunk (set at creation)
     int *d_queue = nullptr;              // per-chunk work counters of the persistent kernels
     size_t queue_bytes = 0;
-    int waves_tr[4] = {0, 0, 0, 0};      // resident waves of k_transfer<pol, R>: [2 pol + (R == float)]
+    int cus = 0;
+    int blocks_tr[8] = {0};              // resident waves per CU of k_transfer<pol, R, batch>:
+                                         // [4 batch + 2 pol + (R == float)]
     bool prof = false;
     struct Timed {
         int kind;
@@ -474,7 +535,13 @@ bl_status ensure(bl_context *ctx, T **p, size_t &have, size_t need_bytes) {
         *p = nullptr;
         have = 0;
     }
-    HIPCHK(ctx, hipMalloc((void **)p, need_bytes));
+    hipError_t e = hipMalloc((void **)p, need_bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();   // do not leave the failure for the next launch check
+        *p = nullptr;
+        return fail(ctx, e == hipErrorOutOfMemory ? BL_E_OOM : BL_E_DEVICE,
+                    std::string("hipMalloc of ") + std::to_string(need_bytes) + " bytes: " + hipGetErrorString(e));
+    }
     have = need_bytes;
     return BL_OK;
 }
@@ -499,28 +566,247 @@ struct TimedLaunch {
     }
 };
 
-// Number of waves of each persistent kernel that fit on the device at once.
+// Waves per CU of each persistent transfer kernel that fit at once.
 bl_status persistent_waves(bl_context *ctx) {
-    if (ctx->waves_tr[0] > 0) return BL_OK;
-    int cus = 0, b[4] = {0, 0, 0, 0};
+    if (ctx->cus > 0) return BL_OK;
+    int cus = 0, b[8] = {0};
     HIPCHK(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[0], k_transfer<false, double>, 64, 0));
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[1], k_transfer<false, float>, 64, 0));
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[2], k_transfer<true, double>, 64, 0));
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[3], k_transfer<true, float>, 64, 0));
-    for (int k = 0; k < 4; ++k) ctx->waves_tr[k] = std::max(1, b[k]) * cus;
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[0], k_transfer<false, double, false>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[1], k_transfer<false, float, false>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[2], k_transfer<true, double, false>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[3], k_transfer<true, float, false>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[4], k_transfer<false, double, true>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[5], k_transfer<false, float, true>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[6], k_transfer<true, double, true>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[7], k_transfer<true, float, true>, 64, 0));
+    for (int k = 0; k < 8; ++k) ctx->blocks_tr[k] = std::max(1, b[k]);
+    ctx->cus = std::max(1, cus);
     return BL_OK;
 }
 
-bl_status launch_frame(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st) {
-    if (!ctx->d_frame) HIPCHK(ctx, hipMalloc((void **)&ctx->d_frame, sizeof(Frame)));
+bl_status check_tuning(bl_context *ctx, const bl_tuning *t) {
+    if (!t) return fail(ctx, BL_E_INVALID_ARG, "tuning is NULL");
+    bool rowmajor = t->tile_w == 0 && t->tile_h == 0;
+    if (!rowmajor && !(t->tile_w > 0 && t->tile_h > 0 && t->tile_w * t->tile_h == 64))
+        return fail(ctx, BL_E_INVALID_ARG, "tile_w * tile_h must be 64 (or both 0)");
+    if (t->transfer_waves_per_cu < 0 || t->transfer_waves_per_cu > 64)
+        return fail(ctx, BL_E_INVALID_ARG, "transfer_waves_per_cu must be in 0..64");
+    if (t->refill_min < 1 || t->refill_min > 64) return fail(ctx, BL_E_INVALID_ARG, "refill_min must be in 1..64");
+    if (t->chunk_rays < 0 || t->chunk_rays % 64 != 0 || t->chunk_rays > (1LL << 30))
+        return fail(ctx, BL_E_INVALID_ARG, "chunk_rays must be a multiple of 64 in 0..2^30");
+    if (t->order != 0 && t->order != 1) return fail(ctx, BL_E_INVALID_ARG, "order must be 0 or 1");
+    if (t->reserved != 0) return fail(ctx, BL_E_INVALID_ARG, "reserved must be 0");
+    return BL_OK;
+}
+
+// Ray ids owned by an image of side n under the tuning's pixel order.
+long long image_rays(int n, const bl_tuning &t) {
+    if (t.tile_w <= 0) return (long long)n * n;
+    long long ntx = (n + t.tile_w - 1) / t.tile_w, nty = (n + t.tile_h - 1) / t.tile_h;
+    return ntx * nty * 64;
+}
+
+// Build and upload the image table (in placement order: given, or largest
+// first) and launch the camera-frame kernel.  Returns the batch view and the
+// total ray-id count.
+bl_status upload_images(bl_context *ctx, int n, const bl_camera *const *cams, const bl_spacetime *const *sts,
+                        double *const *images, double *const *auxs, const bl_tuning &t, Batch &B,
+                        long long &total) {
+    std::vector<int> perm(n);
+    for (int k = 0; k < n; ++k) perm[k] = k;
+    if (t.order == 1)
+        std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return cams[x]->n > cams[y]->n; });
+    if (ctx->upload_done) HIPCHK(ctx, hipEventSynchronize(ctx->upload_done));
+    else HIPCHK(ctx, hipEventCreateWithFlags(&ctx->upload_done, hipEventDisableTiming));
+    ctx->h_imgs.assign(n, ImgDev{});
+    ctx->h_ray0.assign(n, 0);
+    long long r = 0;
+    for (int q = 0; q < n; ++q) {
+        const int k = perm[q];
+        ImgDev &im = ctx->h_imgs[q];
+        im.cp = cam_params(cams[k]);
+        im.a = sts[k]->a;
+        im.r_in = sts[k]->r_in;
+        im.flat = sts[k]->flat ? 1 : 0;
+        im.L = kG * sts[k]->mass_msun * kMsun / (kC * kC);
+        im.image = images[k];
+        im.aux = auxs[k];
+        im.ray0 = r;
+        im.nray = image_rays(cams[k]->n, t);
+        ctx->h_ray0[q] = r;
+        r += im.nray;
+    }
+    if (r >= (1LL << 31)) return fail(ctx, BL_E_UNSUPPORTED, "more than 2^31 - 1 ray ids in one render");
+    bl_status s;
+    if ((s = ensure(ctx, &ctx->d_imgs, ctx->imgs_bytes, (size_t)n * sizeof(ImgDev))) != BL_OK) return s;
+    if ((s = ensure(ctx, &ctx->d_ray0, ctx->ray0_bytes, (size_t)n * sizeof(long long))) != BL_OK) return s;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_imgs, ctx->h_imgs.data(), (size_t)n * sizeof(ImgDev), hipMemcpyHostToDevice,
+                               ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_ray0, ctx->h_ray0.data(), (size_t)n * sizeof(long long),
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
+    B.imgs = ctx->d_imgs;
+    B.ray0 = ctx->d_ray0;
+    B.n_img = n;
+    B.tw = t.tile_w;
+    B.th = t.tile_h;
+    B.pad = 0;
     {
         TimedLaunch tl(ctx, BL_K_SETUP);
-        hipLaunchKernelGGL(k_camera_frame, dim3(1), dim3(64), 0, ctx->stream, cam_params(cam), st->a,
-                           st->flat ? 1 : 0, ctx->d_frame);
+        hipLaunchKernelGGL(k_camera_frame, dim3((unsigned)n), dim3(64), 0, ctx->stream, B);
+    }
+    HIPCHK(ctx, hipGetLastError());
+    total = r;
+    return BL_OK;
+}
+
+bl_status upload_one(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st, double *image, double *aux,
+                     const bl_tuning &t, Batch &B, long long &total) {
+    return upload_images(ctx, 1, &cam, &st, &image, &aux, t, B, total);
+}
+
+template <bool POL, typename R, bool BATCH>
+void launch_transfer(bl_context *ctx, dim3 grd, const GeoParams &P, const Batch &B, const DevGrid &g,
+                     const PlasmaParams &pp, const TransferParams &tp, long long start, int count, int refill,
+                     int *q) {
+    hipLaunchKernelGGL((k_transfer<POL, R, BATCH>), grd, dim3(64), 0, ctx->stream, P, B, g, pp, tp, start, count,
+                       refill, ctx->d_rec, ctx->d_meta, ctx->d_nacc, q);
+}
+
+template <bool POL, typename R>
+void launch_overflow(bl_context *ctx, const GeoParams &P, const Batch &B, const DevGrid &g, const PlasmaParams &pp,
+                     const TransferParams &tp, int big_cap) {
+    hipLaunchKernelGGL((k_overflow<POL, R>), dim3(1), dim3(64), 0, ctx->stream, P, B, g, pp, tp, ctx->d_ovf_count,
+                       ctx->d_ovf_list, ctx->d_big, big_cap);
+}
+
+// The render of n images (a batch of one for bl_render).  With batch = false
+// there is one image and the kernels take its parameters as wave-uniform
+// values.
+bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, const bl_spacetime *const *sts,
+                        double *const *images, double *const *auxs, const bl_integrator *integ, const bl_grid *grid,
+                        const bl_plasma *plasma, const bl_mode *mode, const bl_tuning &t, bool batch) {
+    bl_status s;
+    if ((s = check_integrator(ctx, integ)) != BL_OK || (s = check_tuning(ctx, &t)) != BL_OK) return s;
+    for (int k = 0; k < n; ++k) {
+        if ((s = check_camera(ctx, cams[k])) != BL_OK || (s = check_spacetime(ctx, sts[k])) != BL_OK) return s;
+        if (!images[k] || !auxs[k]) return fail(ctx, BL_E_INVALID_ARG, "image and aux outputs must be non-NULL");
+    }
+    if (!grid || !plasma) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
+    if (mode && (mode->precision < 0 || mode->precision > 1))
+        return fail(ctx, BL_E_INVALID_ARG, "precision must be 0 (FP64) or 1 (mixed)");
+    if (mode && mode->step_model != 0) return fail(ctx, BL_E_UNSUPPORTED, "only step_model 0 is available");
+    const bool mixed = mode && mode->precision == 1;
+    if (grid->g.dtype != 0 && !mixed) return fail(ctx, BL_E_UNSUPPORTED, "float32 grids need precision 1");
+    if (!(plasma->mu > 0.0) || !(plasma->ne_ni > 0.0) || !(plasma->sigma_max >= 0.0))
+        return fail(ctx, BL_E_INVALID_ARG, "plasma mu, ne_ni must be positive and sigma_max >= 0");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if ((s = persistent_waves(ctx)) != BL_OK) return s;
+    Batch B;
+    long long total = 0;
+    if ((s = upload_images(ctx, n, cams, sts, images, auxs, t, B, total)) != BL_OK) return s;
+    GeoParams P = geo_params(cams[0], sts[0], integ);
+    size_t rec_per_ray = (size_t)P.cap * kRecDoubles * sizeof(double);
+    long long chunk = t.chunk_rays > 0 ? t.chunk_rays : (long long)(ctx->ws_limit / rec_per_ray);
+    chunk = std::max(64LL, chunk - chunk % 64);
+    chunk = std::min(chunk, (total + 63) / 64 * 64);
+    if ((s = ensure(ctx, &ctx->d_rec, ctx->rec_bytes, (size_t)chunk * rec_per_ray)) != BL_OK) return s;
+    size_t have_meta = ctx->slot_cap * 2 * sizeof(double), have_nacc = ctx->slot_cap * sizeof(int);
+    if ((s = ensure(ctx, &ctx->d_meta, have_meta, (size_t)chunk * 2 * sizeof(double))) != BL_OK) return s;
+    if ((s = ensure(ctx, &ctx->d_nacc, have_nacc, (size_t)chunk * sizeof(int))) != BL_OK) return s;
+    ctx->slot_cap = std::min(have_meta / (2 * sizeof(double)), have_nacc / sizeof(int));
+    size_t one = sizeof(int);
+    size_t have_cnt = ctx->d_ovf_count ? one : 0;
+    if ((s = ensure(ctx, &ctx->d_ovf_count, have_cnt, one)) != BL_OK) return s;
+    if ((s = ensure(ctx, &ctx->d_ovf_list, ctx->ovf_cap, (size_t)total * sizeof(int))) != BL_OK) return s;
+    int big_cap = (int)std::min<long long>(P.max_steps + 1, 1LL << 30);
+    if ((s = ensure(ctx, &ctx->d_big, ctx->big_bytes, (size_t)64 * big_cap * kRecDoubles * sizeof(double))) != BL_OK)
+        return s;
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, ctx->d_ovf_count, 0, 1);
+    HIPCHK(ctx, hipGetLastError());
+    PlasmaParams pp;
+    pp.mu = plasma->mu;
+    pp.ne_ni = plasma->ne_ni;
+    pp.r_high = plasma->r_high;
+    pp.r_low = plasma->r_low;
+    pp.sigma_max = plasma->sigma_max;
+    pp.mass_msun = sts[0]->mass_msun;
+    pp.polarized = plasma->polarized ? 1 : 0;
+    pp.interp = plasma->interp ? 1 : 0;
+    TransferParams tp;
+    tp.ds_max = integ->ds_max;
+    tp.L = kG * sts[0]->mass_msun * kMsun / (kC * kC);
+    tp.nu_cam = cams[0]->nu_hz;
+    long long nchunk = (total + chunk - 1) / chunk;
+    if ((s = ensure(ctx, &ctx->d_queue, ctx->queue_bytes, (size_t)nchunk * 2 * sizeof(int))) != BL_OK) return s;
+    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((2 * nchunk + 63) / 64)), dim3(64), 0, ctx->stream, ctx->d_queue, 0,
+                       (int)(2 * nchunk));
+    HIPCHK(ctx, hipGetLastError());
+    const int kidx = 4 * (batch ? 1 : 0) + 2 * pp.polarized + (mixed ? 1 : 0);
+    int per_cu = ctx->blocks_tr[kidx];
+    if (t.transfer_waves_per_cu > 0) per_cu = std::min(per_cu, t.transfer_waves_per_cu);
+    const int resident = per_cu * ctx->cus;
+    long long ichunk = 0;
+    for (long long start = 0; start < total; start += chunk, ++ichunk) {
+        int count = (int)std::min(chunk, total - start);
+        dim3 grd((count + 63) / 64), blk(64);
+        {
+            TimedLaunch tl(ctx, BL_K_GEODESIC);
+            if (batch)
+                hipLaunchKernelGGL((k_geodesic<true, true>), grd, blk, 0, ctx->stream, P, B, start, count, ctx->d_rec,
+                                   ctx->d_meta, ctx->d_nacc, ctx->d_ovf_count, ctx->d_ovf_list, nullptr);
+            else
+                hipLaunchKernelGGL((k_geodesic<true, false>), grd, blk, 0, ctx->stream, P, B, start, count,
+                                   ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_ovf_count, ctx->d_ovf_list, nullptr);
+        }
+        HIPCHK(ctx, hipGetLastError());
+        {
+            TimedLaunch tl(ctx, BL_K_TRANSFER);
+            int *q = ctx->d_queue + 2 * ichunk;
+            dim3 pg(std::min<int>(grd.x, resident));
+            switch (kidx) {
+            case 0: launch_transfer<false, double, false>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
+            case 1: launch_transfer<false, float, false>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
+            case 2: launch_transfer<true, double, false>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
+            case 3: launch_transfer<true, float, false>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
+            case 4: launch_transfer<false, double, true>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
+            case 5: launch_transfer<false, float, true>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
+            case 6: launch_transfer<true, double, true>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
+            default: launch_transfer<true, float, true>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
+            }
+        }
+        HIPCHK(ctx, hipGetLastError());
+    }
+    {
+        TimedLaunch tl(ctx, BL_K_OVERFLOW);
+        switch (kidx & 3) {
+        case 0: launch_overflow<false, double>(ctx, P, B, grid->g, pp, tp, big_cap); break;
+        case 1: launch_overflow<false, float>(ctx, P, B, grid->g, pp, tp, big_cap); break;
+        case 2: launch_overflow<true, double>(ctx, P, B, grid->g, pp, tp, big_cap); break;
+        default: launch_overflow<true, float>(ctx, P, B, grid->g, pp, tp, big_cap); break;
+        }
     }
     HIPCHK(ctx, hipGetLastError());
     return BL_OK;
+}
+
+bl_status render_batch_impl(bl_context *ctx, int32_t n_images, const bl_image_desc *images,
+                            const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
+                            const bl_mode *mode, const bl_tuning &t) {
+    if (n_images < 1 || !images) return fail(ctx, BL_E_INVALID_ARG, "need n_images >= 1 and an image array");
+    std::vector<const bl_camera *> cams(n_images);
+    std::vector<const bl_spacetime *> sts(n_images);
+    std::vector<double *> ims(n_images), auxs(n_images);
+    for (int k = 0; k < n_images; ++k) {
+        cams[k] = &images[k].cam;
+        sts[k] = &images[k].st;
+        ims[k] = images[k].image_out;
+        auxs[k] = images[k].aux_out;
+        if (images[k].st.mass_msun != images[0].st.mass_msun)
+            return fail(ctx, BL_E_UNSUPPORTED, "all images of a batch must share mass_msun");
+    }
+    return render_images(ctx, n_images, cams.data(), sts.data(), ims.data(), auxs.data(), integ, grid, plasma, mode, t,
+                         true);
 }
 
 }  // namespace
@@ -543,6 +829,10 @@ bl_status bl_create(int device, void *hip_stream, bl_context **out) {
         delete ctx;
         return BL_E_DEVICE;
     }
+    // step-record workspace per chunk: 32 GiB, at most a quarter of free memory
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
+        ctx->ws_limit = std::max<size_t>((size_t)64 << 20, std::min(ctx->ws_limit, free_b / 4));
     *out = ctx;
     return BL_OK;
 }
@@ -555,7 +845,9 @@ void bl_destroy(bl_context *ctx) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
     }
-    (void)hipFree(ctx->d_frame);
+    (void)hipFree(ctx->d_imgs);
+    (void)hipFree(ctx->d_ray0);
+    if (ctx->upload_done) (void)hipEventDestroy(ctx->upload_done);
     (void)hipFree(ctx->d_rec);
     (void)hipFree(ctx->d_meta);
     (void)hipFree(ctx->d_nacc);
@@ -655,7 +947,7 @@ bl_status bl_grid_create(bl_context *ctx, const bl_grid_desc *d, bl_grid **out) 
 
 void bl_grid_destroy(bl_grid *gr) {
     if (!gr) return;
-    if (gr->ctx) hipSetDevice(gr->ctx->device);
+    if (gr->ctx) (void)hipSetDevice(gr->ctx->device);
     (void)hipFree(gr->d_bmeta);
     (void)hipFree(gr->d_table);
     delete gr;
@@ -668,10 +960,14 @@ bl_status bl_camera_rays(bl_context *ctx, const bl_camera *cam, const bl_spaceti
     if ((s = check_camera(ctx, cam)) != BL_OK || (s = check_spacetime(ctx, st)) != BL_OK) return s;
     if (!state_out || !norm_out) return fail(ctx, BL_E_INVALID_ARG, "output pointers must be non-NULL");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    if ((s = launch_frame(ctx, cam, st)) != BL_OK) return s;
+    bl_tuning t = ctx->tuning;
+    t.tile_w = t.tile_h = 0;
+    Batch B;
+    long long total = 0;
+    if ((s = upload_one(ctx, cam, st, nullptr, nullptr, t, B, total)) != BL_OK) return s;
     long long NN = (long long)cam->n * cam->n;
-    hipLaunchKernelGGL(k_camera_rays, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, ctx->stream, cam_params(cam),
-                       st->a, st->flat ? 1 : 0, ctx->d_frame, state_out, norm_out);
+    hipLaunchKernelGGL(k_camera_rays, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, ctx->stream, ctx->d_imgs,
+                       state_out, norm_out);
     HIPCHK(ctx, hipGetLastError());
     return BL_OK;
 }
@@ -685,16 +981,18 @@ bl_status bl_trace_geodesics(bl_context *ctx, const bl_camera *cam, const bl_spa
         return s;
     if (!state_out || !aux_out) return fail(ctx, BL_E_INVALID_ARG, "output pointers must be non-NULL");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    if ((s = launch_frame(ctx, cam, st)) != BL_OK) return s;
-    long long NN = (long long)cam->n * cam->n;
+    bl_tuning t = ctx->tuning;
+    t.tile_w = t.tile_h = 0;
+    Batch B;
+    long long total = 0;
+    if ((s = upload_one(ctx, cam, st, nullptr, aux_out, t, B, total)) != BL_OK) return s;
     GeoParams P = geo_params(cam, st, integ);
     const long long chunk = 1 << 20;
-    for (long long start = 0; start < NN; start += chunk) {
-        int count = (int)std::min(chunk, NN - start);
+    for (long long start = 0; start < total; start += chunk) {
+        int count = (int)std::min(chunk, total - start);
         TimedLaunch tl(ctx, BL_K_GEODESIC);
-        hipLaunchKernelGGL(k_geodesic<false>, dim3((count + 63) / 64), dim3(64), 0, ctx->stream, P, cam_params(cam),
-                           ctx->d_frame, start, count, nullptr, nullptr, nullptr, nullptr, nullptr, aux_out,
-                           state_out);
+        hipLaunchKernelGGL((k_geodesic<false, false>), dim3((count + 63) / 64), dim3(64), 0, ctx->stream, P, B, start,
+                           count, nullptr, nullptr, nullptr, nullptr, nullptr, state_out);
         HIPCHK(ctx, hipGetLastError());
     }
     return BL_OK;
@@ -704,111 +1002,133 @@ bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *s
                     const bl_grid *grid, const bl_plasma *plasma, const bl_mode *mode, double *image_out,
                     double *aux_out) {
     if (!ctx) return BL_E_INVALID_ARG;
-    bl_status s;
-    if ((s = check_camera(ctx, cam)) != BL_OK || (s = check_spacetime(ctx, st)) != BL_OK ||
-        (s = check_integrator(ctx, integ)) != BL_OK)
-        return s;
-    if (!grid || !plasma || !image_out || !aux_out) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
-    if (mode && (mode->precision < 0 || mode->precision > 1))
-        return fail(ctx, BL_E_INVALID_ARG, "precision must be 0 (FP64) or 1 (mixed)");
-    if (mode && mode->step_model != 0) return fail(ctx, BL_E_UNSUPPORTED, "only step_model 0 is available");
-    const bool mixed = mode && mode->precision == 1;
-    if (grid->g.dtype != 0 && !mixed) return fail(ctx, BL_E_UNSUPPORTED, "float32 grids need precision 1");
-    if (!(plasma->mu > 0.0) || !(plasma->ne_ni > 0.0) || !(plasma->sigma_max >= 0.0))
-        return fail(ctx, BL_E_INVALID_ARG, "plasma mu, ne_ni must be positive and sigma_max >= 0");
+    if (!cam || !st) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
+    return render_images(ctx, 1, &cam, &st, &image_out, &aux_out, integ, grid, plasma, mode, ctx->tuning, false);
+}
+
+bl_status bl_render_batch(bl_context *ctx, int32_t n_images, const bl_image_desc *images, const bl_integrator *integ,
+                          const bl_grid *grid, const bl_plasma *plasma, const bl_mode *mode,
+                          const bl_tuning *tuning) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    return render_batch_impl(ctx, n_images, images, integ, grid, plasma, mode, tuning ? *tuning : ctx->tuning);
+}
+
+bl_status bl_set_tuning(bl_context *ctx, const bl_tuning *tuning) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    bl_status s = check_tuning(ctx, tuning);
+    if (s != BL_OK) return s;
+    ctx->tuning = *tuning;
+    return BL_OK;
+}
+
+bl_status bl_get_tuning(const bl_context *ctx, bl_tuning *tuning_out) {
+    if (!ctx || !tuning_out) return BL_E_INVALID_ARG;
+    *tuning_out = ctx->tuning;
+    return BL_OK;
+}
+
+bl_status bl_autotune(bl_context *ctx, int32_t n_images, const bl_image_desc *images, const bl_integrator *integ,
+                      const bl_grid *grid, const bl_plasma *plasma, const bl_mode *mode, int32_t max_trials,
+                      bl_tuning *best_out, double *best_ms_out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    if (max_trials < 1) return fail(ctx, BL_E_INVALID_ARG, "max_trials must be >= 1");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    if ((s = launch_frame(ctx, cam, st)) != BL_OK) return s;
-    long long NN = (long long)cam->n * cam->n;
-    GeoParams P = geo_params(cam, st, integ);
-    size_t rec_per_ray = (size_t)P.cap * kRecDoubles * sizeof(double);
-    long long chunk = (long long)(ctx->ws_limit / rec_per_ray);
-    chunk = std::max(64LL, chunk - chunk % 64);
-    chunk = std::min(chunk, (NN + 63) / 64 * 64);
-    if ((s = ensure(ctx, &ctx->d_rec, ctx->rec_bytes, (size_t)chunk * rec_per_ray)) != BL_OK) return s;
-    size_t have_meta = ctx->slot_cap * 2 * sizeof(double), have_nacc = ctx->slot_cap * sizeof(int);
-    if ((s = ensure(ctx, &ctx->d_meta, have_meta, (size_t)chunk * 2 * sizeof(double))) != BL_OK) return s;
-    if ((s = ensure(ctx, &ctx->d_nacc, have_nacc, (size_t)chunk * sizeof(int))) != BL_OK) return s;
-    ctx->slot_cap = std::min(have_meta / (2 * sizeof(double)), have_nacc / sizeof(int));
-    size_t one = sizeof(int);
-    size_t have_cnt = ctx->d_ovf_count ? one : 0;
-    if ((s = ensure(ctx, &ctx->d_ovf_count, have_cnt, one)) != BL_OK) return s;
-    if ((s = ensure(ctx, &ctx->d_ovf_list, ctx->ovf_cap, (size_t)NN * sizeof(int))) != BL_OK) return s;
-    int big_cap = (int)std::min<long long>(P.max_steps + 1, 1LL << 30);
-    if ((s = ensure(ctx, &ctx->d_big, ctx->big_bytes, (size_t)64 * big_cap * kRecDoubles * sizeof(double))) != BL_OK)
-        return s;
-    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, ctx->d_ovf_count, 0, 1);
-    HIPCHK(ctx, hipGetLastError());
-    PlasmaParams pp;
-    pp.mu = plasma->mu;
-    pp.ne_ni = plasma->ne_ni;
-    pp.r_high = plasma->r_high;
-    pp.r_low = plasma->r_low;
-    pp.sigma_max = plasma->sigma_max;
-    pp.mass_msun = st->mass_msun;
-    pp.polarized = plasma->polarized ? 1 : 0;
-    pp.interp = plasma->interp ? 1 : 0;
-    TransferParams tp;
-    tp.ds_max = integ->ds_max;
-    tp.L = kG * st->mass_msun * kMsun / (kC * kC);
-    tp.nu_cam = cam->nu_hz;
-    CamParams cp = cam_params(cam);
-    long long nchunk = (NN + chunk - 1) / chunk;
-    if ((s = ensure(ctx, &ctx->d_queue, ctx->queue_bytes, (size_t)nchunk * 2 * sizeof(int))) != BL_OK) return s;
-    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((2 * nchunk + 63) / 64)), dim3(64), 0, ctx->stream, ctx->d_queue, 0,
-                       (int)(2 * nchunk));
-    HIPCHK(ctx, hipGetLastError());
-    if ((s = persistent_waves(ctx)) != BL_OK) return s;
-    long long ichunk = 0;
-    for (long long start = 0; start < NN; start += chunk, ++ichunk) {
-        int count = (int)std::min(chunk, NN - start);
-        dim3 grd((count + 63) / 64), blk(64);
-        {
-            TimedLaunch tl(ctx, BL_K_GEODESIC);
-            hipLaunchKernelGGL(k_geodesic<true>, grd, blk, 0, ctx->stream, P, cp, ctx->d_frame, start, count,
-                               ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_ovf_count, ctx->d_ovf_list, aux_out,
-                               nullptr);
-        }
-        HIPCHK(ctx, hipGetLastError());
-        {
-            TimedLaunch tl(ctx, BL_K_TRANSFER);
-            int *q = ctx->d_queue + 2 * ichunk;
-            int kidx = 2 * pp.polarized + (mixed ? 1 : 0);
-            dim3 pg(std::min<int>(grd.x, ctx->waves_tr[kidx]));
-            if (pp.polarized && mixed)
-                hipLaunchKernelGGL((k_transfer<true, float>), pg, blk, 0, ctx->stream, P, cp, grid->g, pp, tp,
-                                   ctx->d_frame, start, count, ctx->d_rec, ctx->d_meta, ctx->d_nacc, q, image_out,
-                                   aux_out);
-            else if (pp.polarized)
-                hipLaunchKernelGGL((k_transfer<true, double>), pg, blk, 0, ctx->stream, P, cp, grid->g, pp, tp,
-                                   ctx->d_frame, start, count, ctx->d_rec, ctx->d_meta, ctx->d_nacc, q, image_out,
-                                   aux_out);
-            else if (mixed)
-                hipLaunchKernelGGL((k_transfer<false, float>), pg, blk, 0, ctx->stream, P, cp, grid->g, pp, tp,
-                                   ctx->d_frame, start, count, ctx->d_rec, ctx->d_meta, ctx->d_nacc, q, image_out,
-                                   aux_out);
-            else
-                hipLaunchKernelGGL((k_transfer<false, double>), pg, blk, 0, ctx->stream, P, cp, grid->g, pp, tp,
-                                   ctx->d_frame, start, count, ctx->d_rec, ctx->d_meta, ctx->d_nacc, q, image_out,
-                                   aux_out);
-        }
-        HIPCHK(ctx, hipGetLastError());
+    hipEvent_t ea = nullptr, eb = nullptr;
+    HIPCHK(ctx, hipEventCreate(&ea));
+    if (hipEventCreate(&eb) != hipSuccess) {
+        (void)hipEventDestroy(ea);
+        return fail(ctx, BL_E_DEVICE, "hipEventCreate failed");
     }
-    {
-        TimedLaunch tl(ctx, BL_K_OVERFLOW);
-        if (pp.polarized && mixed)
-            hipLaunchKernelGGL((k_overflow<true, float>), dim3(1), dim3(64), 0, ctx->stream, P, cp, grid->g, pp, tp,
-                               ctx->d_frame, ctx->d_ovf_count, ctx->d_ovf_list, ctx->d_big, big_cap, image_out, aux_out);
-        else if (pp.polarized)
-            hipLaunchKernelGGL((k_overflow<true, double>), dim3(1), dim3(64), 0, ctx->stream, P, cp, grid->g, pp, tp,
-                               ctx->d_frame, ctx->d_ovf_count, ctx->d_ovf_list, ctx->d_big, big_cap, image_out, aux_out);
-        else if (mixed)
-            hipLaunchKernelGGL((k_overflow<false, float>), dim3(1), dim3(64), 0, ctx->stream, P, cp, grid->g, pp, tp,
-                               ctx->d_frame, ctx->d_ovf_count, ctx->d_ovf_list, ctx->d_big, big_cap, image_out, aux_out);
-        else
-            hipLaunchKernelGGL((k_overflow<false, double>), dim3(1), dim3(64), 0, ctx->stream, P, cp, grid->g, pp, tp,
-                               ctx->d_frame, ctx->d_ovf_count, ctx->d_ovf_list, ctx->d_big, big_cap, image_out, aux_out);
+    int trials = 0;
+    bl_status err = BL_OK;
+    // one untimed render (allocations, first-touch) and one timed render
+    auto timed = [&](const bl_tuning &t, double &ms) -> bl_status {
+        bl_status s = render_batch_impl(ctx, n_images, images, integ, grid, plasma, mode, t);
+        if (s != BL_OK) return s;
+        if (hipEventRecord(ea, ctx->stream) != hipSuccess) return fail(ctx, BL_E_DEVICE, "hipEventRecord failed");
+        s = render_batch_impl(ctx, n_images, images, integ, grid, plasma, mode, t);
+        if (s != BL_OK) return s;
+        if (hipEventRecord(eb, ctx->stream) != hipSuccess || hipEventSynchronize(eb) != hipSuccess)
+            return fail(ctx, BL_E_DEVICE, "event timing failed");
+        float f = 0.0f;
+        if (hipEventElapsedTime(&f, ea, eb) != hipSuccess) return fail(ctx, BL_E_DEVICE, "hipEventElapsedTime failed");
+        ms = f;
+        ++trials;
+        return BL_OK;
+    };
+    bl_tuning best = ctx->tuning;
+    double best_ms = 0.0;
+    err = timed(best, best_ms);
+    if (err == BL_OK) {
+        size_t rec_per_ray = (size_t)((integ && integ->record_cap > 0) ? integ->record_cap : 512) * kRecDoubles *
+                             sizeof(double);
+        const long long base = (long long)(ctx->ws_limit / rec_per_ray) / 64 * 64;
+        const int occ = std::max(1, ctx->blocks_tr[7]);
+        // coordinate search: each knob in turn over its candidates, keeping
+        // the rest at the best values so far; a change must gain 1 %
+        for (int knob = 0; knob < 5 && err == BL_OK; ++knob) {
+            std::vector<bl_tuning> cand;
+            bl_tuning c = best;
+            if (knob == 0) {
+                const int tiles[4][2] = {{0, 0}, {64, 1}, {16, 4}, {8, 8}};
+                for (auto &tl : tiles) {
+                    c = best;
+                    c.tile_w = tl[0];
+                    c.tile_h = tl[1];
+                    cand.push_back(c);
+                }
+            } else if (knob == 1) {
+                for (int w : {0, std::max(1, occ / 2), 1}) {
+                    c = best;
+                    c.transfer_waves_per_cu = w;
+                    cand.push_back(c);
+                }
+            } else if (knob == 2) {
+                for (int r : {1, 4, 16}) {
+                    c = best;
+                    c.refill_min = r;
+                    cand.push_back(c);
+                }
+            } else if (knob == 3) {
+                for (long long m : {0LL, std::max(64LL, base / 2 / 64 * 64), 2 * base}) {
+                    c = best;
+                    c.chunk_rays = m;
+                    cand.push_back(c);
+                }
+            } else {
+                for (int o : {0, 1}) {
+                    c = best;
+                    c.order = o;
+                    cand.push_back(c);
+                }
+            }
+            for (size_t ci = 0; ci < cand.size(); ++ci) {
+                const bl_tuning &t = cand[ci];
+                bool seen = std::memcmp(&t, &best, sizeof(bl_tuning)) == 0;
+                for (size_t cj = 0; cj < ci && !seen; ++cj)
+                    seen = std::memcmp(&t, &cand[cj], sizeof(bl_tuning)) == 0;
+                if (seen) continue;
+                if (trials >= max_trials) break;
+                double ms = 0.0;
+                err = timed(t, ms);
+                if (err == BL_E_OOM) {   // a workspace this size does not fit: skip the candidate
+                    err = BL_OK;
+                    continue;
+                }
+                if (err != BL_OK) break;
+                if (ms < 0.99 * best_ms) {
+                    best = t;
+                    best_ms = ms;
+                }
+            }
+        }
     }
-    HIPCHK(ctx, hipGetLastError());
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    if (err != BL_OK) return err;
+    ctx->tuning = best;
+    if (best_out) *best_out = best;
+    if (best_ms_out) *best_ms_out = best_ms;
     return BL_OK;
 }
 

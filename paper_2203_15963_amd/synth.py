@@ -181,6 +181,33 @@ def workload(name, n=None):
     return dict(camera=cam, spacetime=st, integrator=integ, plasma=pl, grid_args=grid_args)
 
 
+def batch_workload(n_images=64, n_min=64, n_max=512, seed=2, polarized=1):
+    """Batched workload: n_images images over the shared 128^3 uniform grid
+    of the 256^2 polarized workload.  Sizes N = round(exp(U[ln n_min,
+    ln n_max])); (frequency, inclination, spin) drawn without replacement from
+    the 128 combinations of 8 frequencies 86 (690/86)^(j/7) GHz, inclinations
+    17, 45, 75, 90 degrees and spins 0, 0.5, 0.9, 0.98.  Returns
+    dict(images=[(camera, spacetime)], integrator, plasma, grid_args)."""
+    deg = math.pi / 180.0
+    rng = np.random.default_rng(seed)
+    freqs = [86e9 * (690.0 / 86.0) ** (j / 7.0) for j in range(8)]
+    incs = [17.0, 45.0, 75.0, 90.0]
+    spins = [0.0, 0.5, 0.9, 0.98]
+    combos = [(f, i, a) for f in freqs for i in incs for a in spins]
+    pick = rng.choice(len(combos), size=n_images, replace=n_images > len(combos))
+    sizes = np.rint(np.exp(rng.uniform(math.log(n_min), math.log(n_max), size=n_images))).astype(int)
+    images = []
+    for k in range(n_images):
+        f, inc, a = combos[pick[k]]
+        cam = dict(r=100.0, theta=inc * deg, phi=0.0, u_normal=(0.0, 0.0, 0.0), k_cov=(1.0, 0.0, 0.0),
+                   width=30.0, n=int(sizes[k]), freq_mode=0, psi=0.0, nu_hz=f)
+        st = dict(a=a, mass_msun=4.152e6, r_in=1.01 * r_horizon(a), flat=0)
+        images.append((cam, st))
+    base = workload("c2_256_pol")
+    pl = dict(base["plasma"], polarized=polarized)
+    return dict(images=images, integrator=base["integrator"], plasma=pl, grid_args=base["grid_args"])
+
+
 def make_grid(grid_args, dtype=np.float64):
     g = dict(grid_args)
     kind = g.pop("kind")

@@ -309,3 +309,124 @@ def test_full_size_sampled_mixed_f64_grid(ctx, oracle):
     rng = np.random.default_rng(13)
     pix = rng.choice(1024 * 1024, size=32, replace=False)
     _compare_render(ctx, oracle, w, pixels=pix, precision=1, tol=TOL_MIXED)
+
+
+# ------------------------------------------------------------ batched renders
+def _batch_small(seed=7, n_images=6, n_min=5, n_max=14, polarized=1):
+    from paper_2203_15963_amd import synth
+    return synth.batch_workload(n_images=n_images, n_min=n_min, n_max=n_max, seed=seed, polarized=polarized)
+
+
+def _batch_grid(bw):
+    return _grid({"grid_args": bw["grid_args"]})
+
+
+def test_batch_matches_single_and_oracle(ctx, oracle):
+    """Each image of a batch (uneven sizes, spins, inclinations, frequencies)
+    equals its own bl_render and matches the oracle at the FP64 tolerance."""
+    bw = _batch_small()
+    g = _grid({"grid_args": bw["grid_args"]})
+    gg = ctx.grid(g)
+    outs = ctx.render_batch(bw["images"], bw["integrator"], gg, bw["plasma"], precision=0,
+                            tuning_=dict(tile_w=8, tile_h=8, order=1, refill_min=4))
+    torch.cuda.synchronize()
+    for k, (cam, st) in enumerate(bw["images"]):
+        ib, ab = outs[k][0].cpu().numpy(), outs[k][1].cpu().numpy()
+        i1, a1 = ctx.render(cam, st, bw["integrator"], gg, bw["plasma"], precision=0)
+        torch.cuda.synchronize()
+        i1, a1 = i1.cpu().numpy(), a1.cpu().numpy()
+        assert np.array_equal(ab[5:8], a1[5:8]) and np.array_equal(ab[8:10], a1[8:10])
+        e_self = epix(ib, i1, np.ones(ib.shape[1:], bool))[0]
+        io, ao = oracle.render(cam, st, bw["integrator"], g, bw["plasma"])
+        match = (ao[5] == ab[5]) & (ao[6] == ab[6])
+        e_or = epix(ib, io, match)[0]
+        _say("batch image", k, "n", cam["n"], "a", st["a"], "nu", cam["nu_hz"], "E vs single", e_self,
+             "E vs oracle", e_or, "mismatched", int((~match).sum()))
+        assert e_self <= 1e-13
+        assert e_or <= TOL_FP64 and (~match).sum() <= max(1, 0.02 * match.size)
+
+
+def test_batch_mixed_matches_oracle(ctx, oracle):
+    bw = _batch_small(seed=8, n_images=4)
+    g = _grid({"grid_args": bw["grid_args"]})
+    g32 = dict(g, prims=g["prims"].astype(np.float32))
+    g64r = dict(g, prims=g32["prims"].astype(np.float64))
+    gg = ctx.grid(g32)
+    outs = ctx.render_batch(bw["images"], bw["integrator"], gg, bw["plasma"], precision=1,
+                            tuning_=dict(tile_w=16, tile_h=4))
+    torch.cuda.synchronize()
+    for k, (cam, st) in enumerate(bw["images"]):
+        ib, ab = outs[k][0].cpu().numpy(), outs[k][1].cpu().numpy()
+        io, ao = oracle.render(cam, st, bw["integrator"], g64r, bw["plasma"])
+        match = (ao[5] == ab[5]) & (ao[6] == ab[6])
+        e = epix(ib, io, match)[0]
+        _say("mixed batch image", k, "n", cam["n"], "E", e)
+        assert e <= TOL_MIXED and (~match).sum() <= max(1, 0.02 * match.size)
+
+
+def test_schedule_does_not_change_results(ctx):
+    """Pixel tiles (ragged at the image edge), tiny chunks, wave caps and
+    refill thresholds change only the schedule: the single-image render is
+    bit-identical under every schedule."""
+    w = _wl("c2_256_pol", 20)
+    gg = ctx.grid(_grid(w))
+    ref_i, ref_a = ctx.render(w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"], precision=0)
+    torch.cuda.synchronize()
+    ref_i, ref_a = ref_i.cpu(), ref_a.cpu()
+    default = ctx.get_tuning()
+    schedules = [dict(tile_w=8, tile_h=8), dict(tile_w=64, tile_h=1, chunk_rays=64),
+                 dict(tile_w=16, tile_h=4, transfer_waves_per_cu=1, refill_min=16, chunk_rays=128),
+                 dict(refill_min=64, chunk_rays=192)]
+    try:
+        for t in schedules:
+            ctx.set_tuning(t)
+            i, a = ctx.render(w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"], precision=0)
+            torch.cuda.synchronize()
+            _say("schedule", t)
+            assert torch.equal(i.cpu(), ref_i) and torch.equal(a.cpu(), ref_a)
+            # the batch kernels take per-lane image parameters: same steps, rounding-level differences
+            (ib, ab), = ctx.render_batch([(w["camera"], w["spacetime"])], w["integrator"], gg, w["plasma"],
+                                         precision=0)
+            torch.cuda.synchronize()
+            assert torch.equal(ab.cpu()[5:], ref_a[5:])
+            assert epix(ib.cpu().numpy(), ref_i.numpy(), np.ones((20, 20), bool))[0] <= 1e-13
+    finally:
+        ctx.set_tuning(default)
+
+
+def test_batch_overflow_path(ctx, oracle):
+    """Rays longer than a small record slot go through the overflow kernel,
+    which maps queued ray ids back to their images."""
+    bw = _batch_small(seed=9, n_images=3, n_min=6, n_max=9)
+    integ = dict(bw["integrator"], record_cap=24)
+    g = _grid({"grid_args": bw["grid_args"]})
+    gg = ctx.grid(g)
+    outs = ctx.render_batch(bw["images"], integ, gg, bw["plasma"], precision=0, tuning_=dict(tile_w=8, tile_h=8))
+    torch.cuda.synchronize()
+    for k, (cam, st) in enumerate(bw["images"]):
+        ib, ab = outs[k][0].cpu().numpy(), outs[k][1].cpu().numpy()
+        io, ao = oracle.render(cam, st, bw["integrator"], g, bw["plasma"])
+        match = (ao[5] == ab[5]) & (ao[6] == ab[6])
+        e = epix(ib, io, match)[0]
+        _say("overflow batch image", k, "E", e, "long rays", int((ab[5] + 2 > 24).sum()))
+        assert e <= TOL_FP64
+
+
+def test_autotune_returns_valid_schedule(ctx):
+    bw = _batch_small(seed=10, n_images=5, n_min=8, n_max=24)
+    gg = ctx.grid(_grid({"grid_args": bw["grid_args"]}))
+    default = ctx.get_tuning()
+    try:
+        ref = ctx.render_batch(bw["images"], bw["integrator"], gg, bw["plasma"], precision=0)
+        torch.cuda.synchronize()
+        ref = [(i.cpu(), a.cpu()) for i, a in ref]
+        best, ms = ctx.autotune(bw["images"], bw["integrator"], gg, bw["plasma"], precision=0, max_trials=6)
+        _say("autotune", best, ms)
+        assert ms > 0 and ctx.get_tuning() == best
+        assert best["tile_w"] * best["tile_h"] in (0, 64)
+        outs = ctx.render_batch(bw["images"], bw["integrator"], gg, bw["plasma"], precision=0)
+        torch.cuda.synchronize()
+        for (i, a), (ri, ra) in zip(outs, ref):
+            assert torch.equal(i.cpu(), ri) and torch.equal(a.cpu(), ra)
+    finally:
+        ctx.set_tuning(default)
