@@ -141,7 +141,9 @@ typedef struct {
 typedef struct {
     int32_t precision;        /* 0: FP64 throughout; 1: FP64 geodesics with
                                  FP32 coefficients and transfer               */
-    int32_t step_model;       /* 0: the plain step-size controller            */
+    int32_t step_model;       /* 0: the plain step-size controller; 1: learned
+                                 step proposals from the network installed
+                                 with bl_set_step_model                       */
 } bl_mode;
 
 /* ABI version of the loaded library (BLGPU_ABI_VERSION). */
@@ -236,6 +238,68 @@ bl_status bl_render_batch(bl_context *ctx, int32_t n_images, const bl_image_desc
 bl_status bl_autotune(bl_context *ctx, int32_t n_images, const bl_image_desc *images,
                       const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
                       const bl_mode *mode, int32_t max_trials, bl_tuning *best_out, double *best_ms_out);
+
+/* Learned step proposals.  A multilayer perceptron 11 -> 64 -> 64 -> 64 -> 1
+   (SiLU) maps the state at the start of a step -- x^mu, k_mu, spin, log|h|
+   and log eps (eps floored at 1e-10) of the last accepted step -- to log|h| of
+   the step to try; the embedded RK5(4) error estimate of section 2.2 still
+   accepts or rejects every trial, and after a rejection the plain
+   controller shrinks the step.  BF16 weights and activations on the matrix
+   cores with FP32 accumulation; FP32 master weights trained with Adam.
+   Model vector (FP32, BL_MLP_NMODEL floats): W1[64][11], b1[64], W2[64][64],
+   b2[64], W3[64][64], b3[64], w4[64], b4, feature mean[11], feature
+   standard deviation[11] (features are normalised as (x - mean) / std). */
+#define BL_MLP_NIN 11
+#define BL_MLP_NHID 64
+#define BL_MLP_NPARAM 9153
+#define BL_MLP_NMODEL 9175
+#define BL_STEPLOG_REC 12     /* floats per step-log record: 11 features, target */
+
+/* Step log of the plain integrator (section 2.2 controller): traces the rays
+   of the given images (geodesics only; their aux_out maps receive the
+   geodesic auxiliary maps, image_out is not used) and appends one record per
+   accepted step to records_out (device [capacity][12]): the features of the
+   step's start state (previous accepted step's log|h| and log eps; h0 and
+   eps = 1 before the first) and the accepted log|h|.  *n_out (host) receives
+   the number of accepted steps (records beyond capacity are dropped; their
+   order is not deterministic).  Synchronises the stream. */
+bl_status bl_steplog(bl_context *ctx, int32_t n_images, const bl_image_desc *images, const bl_integrator *integ,
+                     float *records_out, int64_t capacity, int64_t *n_out);
+
+/* Initial model (device [BL_MLP_NMODEL]) for records device [n][12]: feature
+   mean and standard deviation of the records, LeCun-uniform weights from a
+   counter-based generator seeded by `seed`, zero biases, output bias at the
+   mean target. */
+bl_status bl_mlp_init(bl_context *ctx, const float *records, int64_t n, int64_t seed, float *model_out);
+
+typedef struct {
+    int32_t epochs;           /* passes over the training rows               */
+    int32_t batch;            /* rows per Adam step (multiple of 64)         */
+    float lr, beta1, beta2, eps;   /* Adam                                   */
+    int64_t seed;             /* order of the rows (a fresh affine
+                                 permutation per epoch)                      */
+    int64_t n_val;            /* records held out: the last n_val of a fixed
+                                 pseudo-random order of the rows (seeded)     */
+} bl_mlp_hparams;
+
+/* Train model_inout (device [BL_MLP_NMODEL], FP32 master weights; the feature
+   statistics are kept) on records device [n][12] by Adam on the mean squared
+   error of log|h|.  loss_out device [epochs][2]: mean training loss of the
+   epoch and the held-out loss after it. */
+bl_status bl_mlp_train(bl_context *ctx, const float *records, int64_t n, const bl_mlp_hparams *hp,
+                       float *model_inout, float *loss_out);
+
+/* One forward and backward pass (exposed for gradient checks): for model
+   device [BL_MLP_NMODEL] and records device [n][12] writes the outputs
+   y_out device [n] (may be NULL), the mean squared error loss_out device [1]
+   and its gradient grad_out device [BL_MLP_NPARAM] with respect to the
+   first BL_MLP_NPARAM model entries. */
+bl_status bl_mlp_forward_backward(bl_context *ctx, const float *model, const float *records, int64_t n, float *y_out,
+                                  float *loss_out, float *grad_out);
+
+/* Install the network used by step_model = 1 (copied and packed; the caller
+   may free the model afterwards). */
+bl_status bl_set_step_model(bl_context *ctx, const float *model);
 
 /* Per-sample evaluation for checking (paper sections 2.2, 2.4, 2.5): for
    states device [n][8] and norms device [n], writes out device [n][64]:

@@ -66,6 +66,14 @@ class bl_image_desc(C.Structure):
     _fields_ = [("cam", bl_camera), ("st", bl_spacetime), ("image_out", C.c_void_p), ("aux_out", C.c_void_p)]
 
 
+MLP_NIN, MLP_NHID, MLP_NPARAM, MLP_NMODEL, STEPLOG_REC = 11, 64, 9153, 9175, 12
+
+
+class bl_mlp_hparams(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("seed", C.c_int64), ("n_val", C.c_int64)]
+
+
 TUNING_FIELDS = ["tile_w", "tile_h", "transfer_waves_per_cu", "refill_min", "chunk_rays", "order"]
 
 
@@ -122,6 +130,17 @@ def load():
                               C.POINTER(bl_plasma), C.POINTER(bl_mode), i32, C.POINTER(bl_tuning),
                               C.POINTER(C.c_double)]
     L.bl_autotune.restype = C.c_int
+    L.bl_steplog.argtypes = [vp, i32, C.POINTER(bl_image_desc), C.POINTER(bl_integrator), vp, i64,
+                             C.POINTER(C.c_int64)]
+    L.bl_steplog.restype = C.c_int
+    L.bl_mlp_init.argtypes = [vp, vp, i64, i64, vp]
+    L.bl_mlp_init.restype = C.c_int
+    L.bl_mlp_train.argtypes = [vp, vp, i64, C.POINTER(bl_mlp_hparams), vp, vp]
+    L.bl_mlp_train.restype = C.c_int
+    L.bl_mlp_forward_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    L.bl_mlp_forward_backward.restype = C.c_int
+    L.bl_set_step_model.argtypes = [vp, vp]
+    L.bl_set_step_model.restype = C.c_int
     L.bl_eval_samples.argtypes = [vp, C.POINTER(bl_spacetime), vp, C.POINTER(bl_plasma), i64, vp, vp, vp]
     L.bl_eval_samples.restype = C.c_int
     L.bl_profile_enable.argtypes = [vp, C.c_int]
@@ -277,11 +296,11 @@ class Context:
                                               _ptr(state), _ptr(aux)))
         return state, aux
 
-    def render(self, cam, st, integ, grid, pl, precision=0, image=None, aux=None):
+    def render(self, cam, st, integ, grid, pl, precision=0, image=None, aux=None, step_model=0):
         n = int(cam["n"])
         image = self._empty(4, n, n) if image is None else image
         aux = self._empty(NAUX, n, n) if aux is None else aux
-        c, s, g, p, m = camera(cam), spacetime(st), integrator(integ), plasma(pl), mode(precision)
+        c, s, g, p, m = camera(cam), spacetime(st), integrator(integ), plasma(pl), mode(precision, step_model)
         self._check(load().bl_render(self.handle, C.byref(c), C.byref(s), C.byref(g), grid.handle,
                                      C.byref(p), C.byref(m), _ptr(image), _ptr(aux)))
         return image, aux
@@ -305,11 +324,11 @@ class Context:
             outs.append((im, ax))
         return descs, outs
 
-    def render_batch(self, images, integ, grid, pl, precision=0, tuning_=None, outputs=None):
+    def render_batch(self, images, integ, grid, pl, precision=0, tuning_=None, outputs=None, step_model=0):
         """Render many images in one batched launch sequence; returns a list
         of (image, aux) tensors in the order given."""
         descs, outs = self._batch_descs(images, outputs)
-        g, p, m = integrator(integ), plasma(pl), mode(precision)
+        g, p, m = integrator(integ), plasma(pl), mode(precision, step_model)
         t = C.byref(tuning(tuning_)) if tuning_ is not None else None
         self._check(load().bl_render_batch(self.handle, len(images), descs, C.byref(g), grid.handle, C.byref(p),
                                            C.byref(m), t))
@@ -333,6 +352,51 @@ class Context:
         self._check(load().bl_autotune(self.handle, len(images), descs, C.byref(g), grid.handle, C.byref(p),
                                        C.byref(m), int(max_trials), C.byref(best), C.byref(ms)))
         return tuning_dict(best), ms.value
+
+    # ------------------------------------------------ learned step proposals
+    def steplog(self, images, integ, capacity):
+        """Step log of the plain integrator over the rays of the images;
+        returns (records [min(n, capacity)][12] float32 tensor, n)."""
+        import torch
+        descs, outs = self._batch_descs(images, None)
+        rec = torch.empty(int(capacity), STEPLOG_REC, dtype=torch.float32, device=self.device)
+        n = C.c_int64()
+        g = integrator(integ)
+        self._check(load().bl_steplog(self.handle, len(images), descs, C.byref(g), _ptr(rec), int(capacity),
+                                      C.byref(n)))
+        return rec[:min(n.value, int(capacity))], n.value
+
+    def mlp_init(self, records, seed=0):
+        import torch
+        model = torch.empty(MLP_NMODEL, dtype=torch.float32, device=self.device)
+        self._check(load().bl_mlp_init(self.handle, _ptr(records), records.shape[0], int(seed), _ptr(model)))
+        return model
+
+    def mlp_train(self, records, model, epochs=4, batch=8192, lr=2e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0,
+                  n_val=0):
+        """Train model (in place); returns losses [epochs][2] (train, held out)."""
+        import torch
+        hp = bl_mlp_hparams()
+        hp.epochs, hp.batch, hp.lr, hp.beta1, hp.beta2, hp.eps = int(epochs), int(batch), lr, beta1, beta2, eps
+        hp.seed, hp.n_val = int(seed), int(n_val)
+        losses = torch.empty(int(epochs), 2, dtype=torch.float32, device=self.device)
+        self._check(load().bl_mlp_train(self.handle, _ptr(records), records.shape[0], C.byref(hp), _ptr(model),
+                                        _ptr(losses)))
+        return losses
+
+    def mlp_forward_backward(self, model, records):
+        """(outputs [n], mean squared error [1], gradient [NPARAM])."""
+        import torch
+        n = records.shape[0]
+        y = torch.empty(n, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=self.device)
+        self._check(load().bl_mlp_forward_backward(self.handle, _ptr(model), _ptr(records), n, _ptr(y), _ptr(loss),
+                                                   _ptr(grad)))
+        return y, loss, grad
+
+    def set_step_model(self, model):
+        self._check(load().bl_set_step_model(self.handle, _ptr(model)))
 
     def profile_enable(self, on=True):
         self._check(load().bl_profile_enable(self.handle, int(bool(on))))

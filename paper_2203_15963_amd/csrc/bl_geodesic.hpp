@@ -18,6 +18,7 @@
 #pragma once
 
 #include "bl_kerr.hpp"
+#include "bl_mlp.hpp"
 
 namespace bl {
 
@@ -43,98 +44,148 @@ struct TraceOut {
     double lambda, s, dt;
 };
 
+// One Dormand-Prince trial step of size h from y (with k1 = f(y)): the
+// fifth-order state y5, k7 = f(y5) (the next k1 when accepted), the Shampine
+// midpoint ym, the error norm eps and whether anything was not finite.
+__device__ __forceinline__ void dp_trial(const GeoParams &P, const double y[7], double kt, const double k1[7],
+                                         double h, double y5[7], double k7[7], double ym[7], double &eps,
+                                         bool &bad) {
+    const double a = P.a;
+    const int flat = P.flat;
+    double k2[7], k3[7], k4[7], k5[7], k6[7], ys[7];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) ys[m] = y[m] + h * (A21 * k1[m]);
+    geo_rhs(a, flat, ys, kt, k2);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) ys[m] = y[m] + h * (A31 * k1[m] + A32 * k2[m]);
+    geo_rhs(a, flat, ys, kt, k3);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) ys[m] = y[m] + h * (A41 * k1[m] + A42 * k2[m] + A43 * k3[m]);
+    geo_rhs(a, flat, ys, kt, k4);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) ys[m] = y[m] + h * (A51 * k1[m] + A52 * k2[m] + A53 * k3[m] + A54 * k4[m]);
+    geo_rhs(a, flat, ys, kt, k5);
+#pragma unroll
+    for (int m = 0; m < 7; ++m)
+        ys[m] = y[m] + h * (A61 * k1[m] + A62 * k2[m] + A63 * k3[m] + A64 * k4[m] + A65 * k5[m]);
+    geo_rhs(a, flat, ys, kt, k6);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) y5[m] = y[m] + h * (B1 * k1[m] + B3 * k3[m] + B4 * k4[m] + B5 * k5[m] + B6 * k6[m]);
+    geo_rhs(a, flat, y5, kt, k7);
+    // error norm over (t, x, y, z, k_t, k_x, k_y, k_z); the k_t error is 0
+    eps = 0.0;
+    bad = false;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        double err, y0m, y5m;
+        if (m < 4) {
+            err = h * (E1 * k1[m] + E3 * k3[m] + E4 * k4[m] + E5 * k5[m] + E6 * k6[m] + E7 * k7[m]);
+            y0m = y[m];
+            y5m = y5[m];
+        } else if (m == 4) {
+            err = 0.0;
+            y0m = kt;
+            y5m = kt;
+        } else {
+            int q = m - 1;
+            err = h * (E1 * k1[q] + E3 * k3[q] + E4 * k4[q] + E5 * k5[q] + E6 * k6[q] + E7 * k7[q]);
+            y0m = y[q];
+            y5m = y5[q];
+        }
+        double sc = P.f_abs + P.f_rel * fmax(fabs(y0m), fabs(y5m));
+        double e = (err == 0.0) ? 0.0 : fabs(err) / sc;
+        if (isnan(e)) bad = true;
+        else if (e > eps) eps = e;
+    }
+    bool fin = true;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) fin = fin && isfinite(y5[m]);
+    bad = bad || !fin;
+#pragma unroll
+    for (int m = 0; m < 7; ++m)
+        ym[m] = y[m] + 0.5 * h * (M1 * k1[m] + M3 * k3[m] + M4 * k4[m] + M5 * k5[m] + M6 * k6[m] + M7 * k7[m]);
+}
+
+// Controller factor after an accepted step (rounded to a multiple of 1/4096).
+__device__ __forceinline__ double grow_factor(double eps) {
+    double fac = (eps == 0.0) ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * pow(eps, -0.2)));
+    return rint(fac * 4096.0) / 4096.0;
+}
+__device__ __forceinline__ double shrink_factor(double eps) {
+    return rint(fmax(0.2, 0.9 * pow(eps, -0.2)) * 4096.0) / 4096.0;
+}
+
+// Store an accepted step's record.
+__device__ __forceinline__ void write_record(double *rec, int nacc, const double y[7], double h, const double ym[7],
+                                             double ds) {
+    double *r = rec + (long long)nacc * kRecDoubles;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) r[m] = y[m];
+    r[7] = h;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) r[8 + m] = ym[m];
+    r[15] = ds;
+}
+
+// Step log: one record per accepted step of the plain controller, the
+// features of the step's start state (x^mu, k_mu, spin, log|h| and log eps of
+// the previous accepted step; h0 and eps = 1 before the first) and the
+// accepted log|h|.
+struct StepLog {
+    float *buf;
+    long long cap;
+    unsigned long long *count;
+};
+
 // Trace one ray from its pixel state y (x^mu, k_x, k_y, k_z; k_t = kt held
 // fixed).  Step records (16 doubles each, see below) go to rec[0..cap); the
 // final state goes to record n_acc.  A ray needing more than cap records
-// stops with status kRayOverflow.  Without WREC nothing is stored.
+// stops with status kRayOverflow.  Without WREC nothing is stored; with LOG
+// every accepted step is appended to the step log.
 //   record: [0..3] x^mu of y0, [4..6] k_a of y0, [7] h,
 //           [8..11] x^mu of y_mid, [12..14] k_a of y_mid, [15] ds of the step
-template <bool WREC>
+template <bool WREC, bool LOG = false>
 __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], double kt, double *rec, int cap,
-                                          TraceOut &o) {
+                                          TraceOut &o, StepLog lg = StepLog{nullptr, 0, nullptr}) {
     const double a = P.a;
     const int flat = P.flat;
-    double k1[7], k2[7], k3[7], k4[7], k5[7], k6[7], k7[7], ys[7];
+    double k1[7], y5[7], k7[7], ym[7];
     double t_pix = y[0];
     geo_rhs(a, flat, y, kt, k1);
     double r_prev = ks_r(a, y[1], y[2], y[3]);
     double h = -P.h0_frac * (rint(r_prev * 1024.0) / 1024.0);
+    double h_last = h, eps_last = 1.0;
     double lambda = 0.0, s = 0.0;
     int nacc = 0, nrej = 0, status = kRunning;
     bool no_grow = false;
     while (status == kRunning) {
         if ((long long)nacc + nrej >= P.max_steps) { status = kMaxSteps; break; }
         if (fabs(h) < 1e-14 * (1.0 + fabs(lambda))) { status = kUnderflow; break; }
-#pragma unroll
-        for (int m = 0; m < 7; ++m) ys[m] = y[m] + h * (A21 * k1[m]);
-        geo_rhs(a, flat, ys, kt, k2);
-#pragma unroll
-        for (int m = 0; m < 7; ++m) ys[m] = y[m] + h * (A31 * k1[m] + A32 * k2[m]);
-        geo_rhs(a, flat, ys, kt, k3);
-#pragma unroll
-        for (int m = 0; m < 7; ++m) ys[m] = y[m] + h * (A41 * k1[m] + A42 * k2[m] + A43 * k3[m]);
-        geo_rhs(a, flat, ys, kt, k4);
-#pragma unroll
-        for (int m = 0; m < 7; ++m) ys[m] = y[m] + h * (A51 * k1[m] + A52 * k2[m] + A53 * k3[m] + A54 * k4[m]);
-        geo_rhs(a, flat, ys, kt, k5);
-#pragma unroll
-        for (int m = 0; m < 7; ++m)
-            ys[m] = y[m] + h * (A61 * k1[m] + A62 * k2[m] + A63 * k3[m] + A64 * k4[m] + A65 * k5[m]);
-        geo_rhs(a, flat, ys, kt, k6);
-        double y5[7];
-#pragma unroll
-        for (int m = 0; m < 7; ++m) y5[m] = y[m] + h * (B1 * k1[m] + B3 * k3[m] + B4 * k4[m] + B5 * k5[m] + B6 * k6[m]);
-        geo_rhs(a, flat, y5, kt, k7);
-        // error norm over (t, x, y, z, k_t, k_x, k_y, k_z); the k_t error is 0
-        double eps = 0.0;
-        bool bad = false;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            double err, y0m, y5m;
-            if (m < 4) {
-                err = h * (E1 * k1[m] + E3 * k3[m] + E4 * k4[m] + E5 * k5[m] + E6 * k6[m] + E7 * k7[m]);
-                y0m = y[m];
-                y5m = y5[m];
-            } else if (m == 4) {
-                err = 0.0;
-                y0m = kt;
-                y5m = kt;
-            } else {
-                int q = m - 1;
-                err = h * (E1 * k1[q] + E3 * k3[q] + E4 * k4[q] + E5 * k5[q] + E6 * k6[q] + E7 * k7[q]);
-                y0m = y[q];
-                y5m = y5[q];
-            }
-            double sc = P.f_abs + P.f_rel * fmax(fabs(y0m), fabs(y5m));
-            double e = (err == 0.0) ? 0.0 : fabs(err) / sc;
-            if (isnan(e)) bad = true;
-            else if (e > eps) eps = e;
-        }
-        bool fin = true;
-#pragma unroll
-        for (int m = 0; m < 7; ++m) fin = fin && isfinite(y5[m]);
-        if (bad || !fin) { status = kNonfinite; break; }
+        double eps;
+        bool bad;
+        dp_trial(P, y, kt, k1, h, y5, k7, ym, eps, bad);
+        if (bad) { status = kNonfinite; break; }
         if (eps <= 1.0) {
             if (WREC && nacc + 2 > cap) { status = kRayOverflow; break; }
-            double ym[7];
-#pragma unroll
-            for (int m = 0; m < 7; ++m)
-                ym[m] = y[m] + 0.5 * h * (M1 * k1[m] + M3 * k3[m] + M4 * k4[m] + M5 * k5[m] + M6 * k6[m] + M7 * k7[m]);
             double ds = fabs(h) * ds_dlambda(a, flat, ym, kt);
-            if (WREC) {
-                double *r = rec + (long long)nacc * kRecDoubles;
+            if (WREC) write_record(rec, nacc, y, h, ym, ds);
+            if (LOG) {
+                unsigned long long idx = atomicAdd(lg.count, 1ull);
+                if ((long long)idx < lg.cap) {
+                    float f[kMlpIn];
+                    step_features(y, kt, a, h_last, eps_last, f);
+                    float *q = lg.buf + idx * kLogRec;
 #pragma unroll
-                for (int m = 0; m < 7; ++m) r[m] = y[m];
-                r[7] = h;
-#pragma unroll
-                for (int m = 0; m < 7; ++m) r[8 + m] = ym[m];
-                r[15] = ds;
+                    for (int m = 0; m < kMlpIn; ++m) q[m] = f[m];
+                    q[kMlpIn] = (float)log(fabs(h));
+                }
+                h_last = h;
+                eps_last = eps;
             }
             ++nacc;
             lambda += h;
             s += ds;
-            double fac = (eps == 0.0) ? 10.0 : fmin(10.0, fmax(0.2, 0.9 * pow(eps, -0.2)));
-            fac = rint(fac * 4096.0) / 4096.0;
+            double fac = grow_factor(eps);
             if (no_grow) fac = fmin(fac, 1.0);
             no_grow = false;
 #pragma unroll
@@ -149,11 +200,95 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
             h *= fac;
         } else {
             ++nrej;
-            h *= rint(fmax(0.2, 0.9 * pow(eps, -0.2)) * 4096.0) / 4096.0;
+            h *= shrink_factor(eps);
             no_grow = true;
         }
     }
     if (WREC && status != kRayOverflow) {
+        double *r = rec + (long long)nacc * kRecDoubles;
+#pragma unroll
+        for (int m = 0; m < 7; ++m) r[m] = y[m];
+    }
+    o.status = status;
+    o.n_acc = nacc;
+    o.n_rej = nrej;
+    o.lambda = fabs(lambda);
+    o.s = s;
+    o.dt = t_pix - y[0];
+}
+
+// The same integration with learned step proposals: after every accepted
+// step (and for the first) the wave evaluates the step-proposal network for
+// its lanes and a lane tries h = -exp(net) (clamped to 0.2..10 times the last
+// accepted |h|; the plain controller's proposal if the output is not
+// finite).  The embedded error estimate still accepts or rejects each trial;
+// after a rejection the plain controller shrinks h for the retry.  The loop
+// runs wave-converged (every lane reaches the network call each iteration);
+// lanes with active = false only take part in it.
+template <bool WREC>
+__device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool active, double y[7], double kt, double *rec,
+                                                  int cap, TraceOut &o, const u32x4 *pk, const float *tail,
+                                                  u32x4 *stage) {
+    const double a = P.a;
+    const int flat = P.flat;
+    double k1[7], y5[7], k7[7], ym[7];
+    double t_pix = y[0];
+    double r_prev = 0.0, h = -1.0;
+    if (active) {
+        geo_rhs(a, flat, y, kt, k1);
+        r_prev = ks_r(a, y[1], y[2], y[3]);
+        h = -P.h0_frac * (rint(r_prev * 1024.0) / 1024.0);
+    }
+    double h_last = h, eps_last = 1.0;
+    double lambda = 0.0, s = 0.0;
+    int nacc = 0, nrej = 0, status = active ? kRunning : kEscaped;
+    bool need = true;
+    for (;;) {
+        const bool run = status == kRunning;
+        if (__ballot(run && need)) {
+            float f[kMlpIn];
+            step_features(y, kt, a, h_last, eps_last, f);
+            const float lh = mlp_forward(pk, tail, f, stage);
+            if (run && need) {
+                const double hp = exp((double)lh), hl = fabs(h_last);
+                if (isfinite(hp) && hp > 0.0) h = -fmin(10.0 * hl, fmax(0.2 * hl, hp));
+                else if (nacc > 0) h = h_last * grow_factor(eps_last);
+                need = false;
+            }
+        }
+        if (__ballot(run) == 0) break;
+        if (!run) continue;
+        if ((long long)nacc + nrej >= P.max_steps) { status = kMaxSteps; continue; }
+        if (fabs(h) < 1e-14 * (1.0 + fabs(lambda))) { status = kUnderflow; continue; }
+        double eps;
+        bool bad;
+        dp_trial(P, y, kt, k1, h, y5, k7, ym, eps, bad);
+        if (bad) { status = kNonfinite; continue; }
+        if (eps <= 1.0) {
+            if (WREC && nacc + 2 > cap) { status = kRayOverflow; continue; }
+            double ds = fabs(h) * ds_dlambda(a, flat, ym, kt);
+            if (WREC) write_record(rec, nacc, y, h, ym, ds);
+            ++nacc;
+            lambda += h;
+            s += ds;
+            h_last = h;
+            eps_last = eps;
+            need = true;
+#pragma unroll
+            for (int m = 0; m < 7; ++m) {
+                y[m] = y5[m];
+                k1[m] = k7[m];
+            }
+            double r_new = ks_r(a, y[1], y[2], y[3]);
+            if (r_new < P.r_in) status = kCaptured;
+            else if (r_prev < P.r_cam && r_new >= P.r_cam) status = kEscaped;
+            r_prev = r_new;
+        } else {
+            ++nrej;
+            h *= shrink_factor(eps);
+        }
+    }
+    if (WREC && active && status != kRayOverflow) {
         double *r = rec + (long long)nacc * kRecDoubles;
 #pragma unroll
         for (int m = 0; m < 7; ++m) r[m] = y[m];

@@ -373,6 +373,412 @@ __global__ void __launch_bounds__(64) k_overflow(GeoParams P, Batch B, DevGrid g
     }
 }
 
+// ============================================================ learned step
+// Geodesics with learned step proposals: blocks of four waves share the
+// packed network (forward fragments and FP32 tail) in LDS; each wave has its
+// own staging rows.  Lanes without a ray still take part in the network calls.
+template <bool WREC, bool BATCH>
+__global__ void __launch_bounds__(256) k_geodesic_learned(GeoParams P, Batch B, long long start, int count,
+                                                          const u32x4 *__restrict__ pk_g,
+                                                          const float *__restrict__ tail_g, double *__restrict__ rec,
+                                                          double *__restrict__ meta, int *__restrict__ nacc_out,
+                                                          int *__restrict__ ovf_count, int *__restrict__ ovf_list) {
+    __shared__ u32x4 s_pk[kPkFwd];
+    __shared__ float s_tail[kTailN];
+    __shared__ u32x4 s_stage[4][64 * 4];
+    for (int i = threadIdx.x; i < kPkFwd; i += blockDim.x) s_pk[i] = pk_g[i];
+    for (int i = threadIdx.x; i < kTailN; i += blockDim.x) s_tail[i] = tail_g[i];
+    __syncthreads();
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    const long long gid = start + slot;
+    bool active = slot < count;
+    int img = 0, pi = 0, pj = 0;
+    if (active) {
+        img = BATCH ? find_image(B, gid) : 0;
+        active = ray_pixel(B, B.imgs[img].cp.n, gid - (BATCH ? B.ray0[img] : 0), pi, pj);
+        if (!active && WREC) nacc_out[slot] = -2;
+    }
+    const ImgDev &im = B.imgs[img];
+    const GeoParams Q = lane_params<BATCH>(P, im);
+    double y8[8] = {0, 0, 0, 0, -1, 0, 0, 0}, n = 1.0;
+    if (active) camera_pixel(im.fr, im.cp, Q.a, Q.flat, pi, pj, y8, n);
+    double y[7] = {y8[0], y8[1], y8[2], y8[3], y8[5], y8[6], y8[7]};
+    const double kt = y8[4];
+    TraceOut o;
+    trace_ray_learned<WREC>(Q, active, y, kt, WREC && active ? rec + (long long)slot * Q.cap * kRecDoubles : nullptr,
+                            Q.cap, o, s_pk, s_tail, s_stage[threadIdx.x >> 6]);
+    if (!active) return;
+    const long long NN = (long long)im.cp.n * im.cp.n, pix = (long long)pj * im.cp.n + pi;
+    double *aux = im.aux;
+    if (WREC) {
+        meta[2 * slot] = kt;
+        meta[2 * slot + 1] = n;
+        if (o.status == kRayOverflow) {
+            nacc_out[slot] = -1;
+            int idx = atomicAdd(ovf_count, 1);
+            ovf_list[idx] = (int)gid;
+            return;
+        }
+        nacc_out[slot] = o.n_acc;
+    }
+    aux[BL_AUX_DT * NN + pix] = o.dt;
+    aux[BL_AUX_S * NN + pix] = o.s;
+    aux[BL_AUX_LAMBDA * NN + pix] = o.lambda;
+    aux[BL_AUX_NACC * NN + pix] = (double)o.n_acc;
+    aux[BL_AUX_NREJ * NN + pix] = (double)o.n_rej;
+    aux[BL_AUX_STATUS * NN + pix] = (double)o.status;
+}
+
+// Step log of the plain integrator over the rays of a batch (no records);
+// geodesic auxiliary maps are written as by bl_trace_geodesics.
+__global__ void __launch_bounds__(64) k_steplog(GeoParams P, Batch B, long long start, int count, StepLog lg) {
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= count) return;
+    const long long gid = start + slot;
+    const int img = find_image(B, gid);
+    const ImgDev &im = B.imgs[img];
+    int pi, pj;
+    if (!ray_pixel(B, im.cp.n, gid - B.ray0[img], pi, pj)) return;
+    const GeoParams Q = lane_params<true>(P, im);
+    double y8[8], n;
+    camera_pixel(im.fr, im.cp, Q.a, Q.flat, pi, pj, y8, n);
+    double y[7] = {y8[0], y8[1], y8[2], y8[3], y8[5], y8[6], y8[7]};
+    TraceOut o;
+    trace_ray<false, true>(Q, y, y8[4], nullptr, 0, o, lg);
+    const long long NN = (long long)im.cp.n * im.cp.n, pix = (long long)pj * im.cp.n + pi;
+    double *aux = im.aux;
+    aux[BL_AUX_DT * NN + pix] = o.dt;
+    aux[BL_AUX_S * NN + pix] = o.s;
+    aux[BL_AUX_LAMBDA * NN + pix] = o.lambda;
+    aux[BL_AUX_TAU * NN + pix] = 0.0;
+    aux[BL_AUX_IJ * NN + pix] = 0.0;
+    aux[BL_AUX_NACC * NN + pix] = (double)o.n_acc;
+    aux[BL_AUX_NREJ * NN + pix] = (double)o.n_rej;
+    aux[BL_AUX_STATUS * NN + pix] = (double)o.status;
+    aux[BL_AUX_NSAMP * NN + pix] = 0.0;
+    aux[BL_AUX_NREC * NN + pix] = 0.0;
+}
+
+// ------------------------------------------------------------- the network
+// Packed A-operand fragments and the FP32 tail from the FP32 model.
+__global__ void k_mlp_pack(const float *__restrict__ model, u32x4 *__restrict__ pk, float *__restrict__ tail) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < kPkAll) {
+        const int lane = t & 63, slot = t >> 6, g = lane >> 4, i = lane & 15;
+        float v[8];
+        for (int e = 0; e < 8; ++e) {
+            if (slot < 4) {   // forward layer 1: W1[16 mt + i][8 g + e]
+                const int k = 8 * g + e;
+                v[e] = k < kMlpIn ? model[kW1 + (16 * slot + i) * kMlpIn + k] : 0.0f;
+            } else {
+                const int q = (slot - 4) % 8, mt = q / 2, kk = q % 2, k = hid_k(kk, g, e), u = 16 * mt + i;
+                const int base = slot < 12 ? kW2 : slot < 20 ? kW3 : slot < 28 ? kW2 : kW3;
+                v[e] = slot < 20 ? model[base + u * kMlpH + k]      // forward: W[u][k]
+                                 : model[base + k * kMlpH + u];     // backward: W^T[u][k] = W[k][u]
+            }
+        }
+        pk[t] = u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), pack2(v[6], v[7])};
+    }
+    if (t < kTailN) {
+        float v = 0.0f;
+        if (t < 64) v = model[kB1 + t];
+        else if (t < 128) v = model[kB2 + t - 64];
+        else if (t < 192) v = model[kB3 + t - 128];
+        else if (t < 256) v = model[kW4 + t - 192];
+        else if (t == kTB4) v = model[kB4];
+        else if (t < kTSig) v = model[kMu + t - kTMu];
+        else if (t < kTSig + kMlpIn) v = model[kSig + t - kTSig];
+        tail[t] = v;
+    }
+}
+
+// Per-block sums and sums of squares (double) of the 12 record columns.
+__global__ void __launch_bounds__(256) k_mlp_stats(const float *__restrict__ rec, long long n,
+                                                   double *__restrict__ part) {
+    __shared__ double sh[256][2];
+    for (int c = 0; c < kLogRec; ++c) {
+        double s = 0.0, q = 0.0;
+        for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (long long)gridDim.x * blockDim.x) {
+            double v = rec[r * kLogRec + c];
+            s += v;
+            q += v * v;
+        }
+        sh[threadIdx.x][0] = s;
+        sh[threadIdx.x][1] = q;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                sh[threadIdx.x][0] += sh[threadIdx.x + w][0];
+                sh[threadIdx.x][1] += sh[threadIdx.x + w][1];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            part[(blockIdx.x * kLogRec + c) * 2] = sh[0][0];
+            part[(blockIdx.x * kLogRec + c) * 2 + 1] = sh[0][1];
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ double splitmix_u01(unsigned long long x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return (double)(x >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Initial model: feature mean and standard deviation from the statistics
+// (fixed summation order), LeCun-uniform weights U(-sqrt(3/fan_in),
+// sqrt(3/fan_in)) from a counter-based generator, zero hidden biases and the
+// output bias at the mean target.
+__global__ void k_mlp_init(const double *__restrict__ part, int nblk, long long n, unsigned long long seed,
+                           float *__restrict__ model) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= kMlpNModel) return;
+    auto col = [&](int c, double &mean, double &sd) {
+        double s = 0.0, q = 0.0;
+        for (int b = 0; b < nblk; ++b) {
+            s += part[(b * kLogRec + c) * 2];
+            q += part[(b * kLogRec + c) * 2 + 1];
+        }
+        mean = s / (double)n;
+        double var = fmax(0.0, q / (double)n - mean * mean);
+        sd = sqrt(var);
+        if (!(sd > 1e-6 * (1.0 + fabs(mean)))) sd = 1.0;
+    };
+    float v = 0.0f;
+    if (t >= kMu) {
+        double m, sd;
+        col((t - kMu) % kMlpIn, m, sd);
+        v = (float)(t < kSig ? m : sd);
+    } else if (t == kB4) {
+        double m, sd;
+        col(kMlpIn, m, sd);
+        v = (float)m;
+    } else {
+        int fan = 0;
+        if (t < kB1) fan = kMlpIn;
+        else if ((t >= kW2 && t < kB2) || (t >= kW3 && t < kB3) || (t >= kW4 && t < kB4)) fan = kMlpH;
+        if (fan) v = (float)((2.0 * splitmix_u01(seed * 0x100000001B3ull + (unsigned long long)t) - 1.0) *
+                             sqrt(3.0 / fan));
+    }
+    model[t] = v;
+}
+
+// Forward and backward pass over tiles of 64 records, one tile per wave:
+// rows r = tile 64 + lane < n_rows are records idx(r) = (mul (offset + r) +
+// add) mod n_mod (an affine permutation of the training set; mul = 1, add =
+// 0 for the plain order).  Writes the per-tile partial gradient of
+// sum (y - target)^2 * inv_n (all kMlpNParam entries) and the per-tile
+// partial sum of (y - target)^2; y_out (optional) receives the outputs.
+// BF16 operands on the matrix cores: normalised inputs, weights, hidden
+// activations and backpropagated pre-activation gradients; everything else
+// FP32.
+__global__ void __launch_bounds__(64) k_mlp_fwdbwd(const u32x4 *__restrict__ pk, const float *__restrict__ tail,
+                                                   const float *__restrict__ rec, long long n_rows, long long offset,
+                                                   long long mul, long long add, long long n_mod, float inv_n,
+                                                   int want_grad, float *__restrict__ grad_part,
+                                                   float *__restrict__ loss_part, float *__restrict__ y_out) {
+    __shared__ u32x4 s_stage[64 * 4];
+    __shared__ __attribute__((aligned(16))) unsigned short s_xt[32 * 64];       // inputs, [feature][ray]
+    __shared__ __attribute__((aligned(16))) unsigned short s_h1[64 * 64];       // BF16 h1, [unit][ray]
+    __shared__ __attribute__((aligned(16))) unsigned short s_h2[64 * 64];
+    __shared__ __attribute__((aligned(16))) unsigned short s_dz[64 * 64];       // BF16 dz of the current layer, [unit][ray]
+    __shared__ f32x4 s_z1[16 * 64], s_z2[16 * 64]; // pre-activations, [mt * 4 + nt][lane]
+    const int lane = threadIdx.x, g = lane >> 4, j = lane & 15;
+    const long long row = (long long)blockIdx.x * 64 + lane;
+    const bool valid = row < n_rows;
+    float x[kMlpIn], target = 0.0f;
+    if (valid) {
+        const long long idx = (long long)(((unsigned long long)mul * (unsigned long long)(offset + row) + (unsigned long long)add) %
+                                          (unsigned long long)n_mod);
+        const float *q = rec + idx * kLogRec;
+        for (int m = 0; m < kMlpIn; ++m) x[m] = q[m];
+        target = q[kMlpIn];
+    } else {
+        for (int m = 0; m < kMlpIn; ++m) x[m] = tail[kTMu + m];
+    }
+    // ---- forward
+    stage_input(tail, x, s_stage, lane);
+    for (int f = 0; f < 32; ++f)
+        s_xt[f * 64 + lane] = f < kMlpIn ? (unsigned short)bf16_bits((x[f] - tail[kTMu + f]) / tail[kTSig + f]) : 0;
+    wave_lds_sync();
+    u32x4 b1[4][1];
+    input_bfrag(s_stage, b1, lane);
+    f32x4 h[4][4];
+    u32x4 bq[4][2];
+    mm_layer<1>(pk + kPkL1, b1, h, lane);
+    for (int L = 1; L <= 3; ++L) {
+        const float *bias = tail + (L == 1 ? kTB1 : L == 2 ? kTB2 : kTB3);
+        for (int mt = 0; mt < 4; ++mt)
+            for (int e = 0; e < 4; ++e) {
+                const float bb = bias[16 * mt + 4 * g + e];
+                for (int nt = 0; nt < 4; ++nt) h[mt][nt][e] += bb;
+            }
+        if (L < 3) {
+            f32x4 *zs = L == 1 ? s_z1 : s_z2;
+            unsigned short *hs = L == 1 ? s_h1 : s_h2;
+            for (int mt = 0; mt < 4; ++mt)
+                for (int nt = 0; nt < 4; ++nt) {
+                    zs[(mt * 4 + nt) * 64 + lane] = h[mt][nt];
+                    for (int e = 0; e < 4; ++e) {
+                        h[mt][nt][e] = silu(h[mt][nt][e]);
+                        hs[(16 * mt + 4 * g + e) * 64 + 16 * nt + j] = (unsigned short)bf16_bits(h[mt][nt][e]);
+                    }
+                }
+            to_bfrag(h, bq);
+            mm_layer<2>(pk + (L == 1 ? kPkL2 : kPkL3), bq, h, lane);
+        }
+    }
+    // h now holds z3; keep it and form h3
+    f32x4 z3[4][4], h3[4][4];
+    for (int mt = 0; mt < 4; ++mt)
+        for (int nt = 0; nt < 4; ++nt) {
+            z3[mt][nt] = h[mt][nt];
+            for (int e = 0; e < 4; ++e) h3[mt][nt][e] = silu(z3[mt][nt][e]);
+        }
+    const float y = out_layer(h3, tail, lane);
+    if (valid && y_out) y_out[row] = y;
+    const float diff = valid ? y - target : 0.0f;
+    float lsum = diff * diff;
+    for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o);
+    if (lane == 0) loss_part[blockIdx.x] = lsum;
+    if (!want_grad) return;
+    float *gp = grad_part + (long long)blockIdx.x * kMlpNParam;
+    // ---- backward
+    const float dy = 2.0f * diff * inv_n;
+    float dyn[4];
+    for (int nt = 0; nt < 4; ++nt) dyn[nt] = __shfl(dy, 16 * nt + j);
+    float db4 = dy;
+    for (int o = 32; o > 0; o >>= 1) db4 += __shfl_xor(db4, o);
+    if (lane == 0) gp[kB4] = db4;
+    // w4 and dz3
+    f32x4 dz[4][4];
+    for (int mt = 0; mt < 4; ++mt)
+        for (int e = 0; e < 4; ++e) {
+            const int u = 16 * mt + 4 * g + e;
+            const float w = tail[kTW4 + u];
+            float gw = 0.0f;
+            for (int nt = 0; nt < 4; ++nt) {
+                gw += h3[mt][nt][e] * dyn[nt];
+                dz[mt][nt][e] = w * dyn[nt] * dsilu(z3[mt][nt][e]);
+            }
+            for (int o = 1; o < 16; o <<= 1) gw += __shfl_xor(gw, o);
+            if (j == 0) gp[kW4 + u] = gw;
+        }
+    for (int L = 3; L >= 1; --L) {
+        // bias gradient: sum over the rays of dz
+        for (int mt = 0; mt < 4; ++mt)
+            for (int e = 0; e < 4; ++e) {
+                float sb = dz[mt][0][e] + dz[mt][1][e] + dz[mt][2][e] + dz[mt][3][e];
+                for (int o = 1; o < 16; o <<= 1) sb += __shfl_xor(sb, o);
+                if (j == 0) gp[(L == 3 ? kB3 : L == 2 ? kB2 : kB1) + 16 * mt + 4 * g + e] = sb;
+            }
+        // weight gradient dW = dz h_prev^T (K = the 64 rays), through LDS
+        wave_lds_sync();
+        for (int mt = 0; mt < 4; ++mt)
+            for (int nt = 0; nt < 4; ++nt)
+                for (int e = 0; e < 4; ++e)
+                    s_dz[(16 * mt + 4 * g + e) * 64 + 16 * nt + j] = (unsigned short)bf16_bits(dz[mt][nt][e]);
+        wave_lds_sync();
+        const unsigned short *hp = L == 3 ? s_h2 : L == 2 ? s_h1 : s_xt;
+        const int ntn = L == 1 ? 2 : 4;   // input features of layer 1: 32 (11 used)
+        f32x4 gw[4][4];
+        for (int mt = 0; mt < 4; ++mt)
+            for (int nt = 0; nt < ntn; ++nt) gw[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int kk = 0; kk < 2; ++kk) {
+            u32x4 bB[4];
+            for (int nt = 0; nt < ntn; ++nt)
+                bB[nt] = *(const u32x4 *)(hp + (16 * nt + j) * 64 + 32 * kk + 8 * g);
+            for (int mt = 0; mt < 4; ++mt) {
+                const u32x4 aA = *(const u32x4 *)(s_dz + (16 * mt + j) * 64 + 32 * kk + 8 * g);
+                for (int nt = 0; nt < ntn; ++nt) gw[mt][nt] = mma(aA, bB[nt], gw[mt][nt]);
+            }
+        }
+        for (int mt = 0; mt < 4; ++mt)
+            for (int nt = 0; nt < ntn; ++nt)
+                for (int e = 0; e < 4; ++e) {
+                    const int o = 16 * mt + 4 * g + e, i = 16 * nt + j;
+                    if (L == 1) {
+                        if (i < kMlpIn) gp[kW1 + o * kMlpIn + i] = gw[mt][nt][e];
+                    } else {
+                        gp[(L == 3 ? kW3 : kW2) + o * kMlpH + i] = gw[mt][nt][e];
+                    }
+                }
+        if (L == 1) break;
+        // dh_prev = W^T dz, then dz_prev = dh_prev silu'(z_prev)
+        to_bfrag(dz, bq);
+        mm_layer<2>(pk + (L == 3 ? kPkB3 : kPkB2), bq, h, lane);
+        const f32x4 *zs = L == 3 ? s_z2 : s_z1;
+        for (int mt = 0; mt < 4; ++mt)
+            for (int nt = 0; nt < 4; ++nt) {
+                const f32x4 zz = zs[(mt * 4 + nt) * 64 + lane];
+                for (int e = 0; e < 4; ++e) dz[mt][nt][e] = h[mt][nt][e] * dsilu(zz[e]);
+            }
+    }
+}
+
+// grad[p] = sum over tiles of the partials (fixed order); loss_acc[0] +=
+// the sum of the tile losses (one thread, launches in stream order).
+__global__ void k_mlp_reduce(const float *__restrict__ part, int n_tiles, float *__restrict__ grad,
+                             const float *__restrict__ loss_part, double *__restrict__ loss_acc, int want_grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (want_grad && p < kMlpNParam) {
+        double s = 0.0;
+        for (int t = 0; t < n_tiles; ++t) s += part[(long long)t * kMlpNParam + p];
+        grad[p] = (float)s;
+    }
+    if (p == 0) {
+        double l = 0.0;
+        for (int t = 0; t < n_tiles; ++t) l += loss_part[t];
+        loss_acc[0] += l;
+    }
+}
+
+// Adam on the FP32 master weights (bias-corrected moments).
+__global__ void k_mlp_adam(float *__restrict__ model, float *__restrict__ m, float *__restrict__ v,
+                           const float *__restrict__ grad, float lr, float b1, float b2, float eps, float c1,
+                           float c2) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kMlpNParam) return;
+    const float gr = grad[p];
+    const float mm = b1 * m[p] + (1.0f - b1) * gr;
+    const float vv = b2 * v[p] + (1.0f - b2) * gr * gr;
+    m[p] = mm;
+    v[p] = vv;
+    model[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+__global__ void k_mlp_store_loss(double *__restrict__ acc, double denom, float *__restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        out[0] = (float)(acc[0] / denom);
+        acc[0] = 0.0;
+    }
+}
+
+// dst[i] = src[(mul i + add) mod n] for record rows.
+__global__ void k_gather_rows(const float *__restrict__ src, float *__restrict__ dst, long long n, long long mul,
+                              long long add) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const long long j = (long long)(((unsigned long long)mul * (unsigned long long)i + (unsigned long long)add) %
+                                    (unsigned long long)n);
+#pragma unroll
+    for (int c = 0; c < kLogRec; ++c) dst[i * kLogRec + c] = src[j * kLogRec + c];
+}
+
+__global__ void k_fill_f64(double *p, double v, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f32(float *p, float v, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 // ============================================================ per-sample check
 __global__ void k_eval_samples(double a, int flat, DevGrid g, PlasmaParams pp, long long n,
                                const double *__restrict__ states, const double *__restrict__ norms,
@@ -437,6 +843,23 @@ struct bl_context {
     int cus = 0;
     int blocks_tr[8] = {0};              // resident waves per CU of k_transfer<pol, R, batch>:
                                          // [4 batch + 2 pol + (R == float)]
+    // step-proposal network installed by bl_set_step_model (packed form)
+    u32x4 *d_step_pk = nullptr;
+    float *d_step_tail = nullptr;
+    bool has_step_model = false;
+    // network training workspace
+    u32x4 *d_mlp_pk = nullptr;
+    float *d_mlp_tail = nullptr;
+    float *d_mlp_gpart = nullptr;
+    size_t mlp_gpart_bytes = 0;
+    float *d_mlp_lpart = nullptr;
+    size_t mlp_lpart_bytes = 0;
+    float *d_mlp_grad = nullptr, *d_mlp_m = nullptr, *d_mlp_v = nullptr;
+    double *d_mlp_acc = nullptr;
+    double *d_mlp_stats = nullptr;
+    float *d_mlp_rows = nullptr;     // the records in shuffled order
+    size_t mlp_rows_bytes = 0;
+    unsigned long long *d_log_count = nullptr;
     bool prof = false;
     struct Timed {
         int kind;
@@ -695,7 +1118,11 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     if (!grid || !plasma) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
     if (mode && (mode->precision < 0 || mode->precision > 1))
         return fail(ctx, BL_E_INVALID_ARG, "precision must be 0 (FP64) or 1 (mixed)");
-    if (mode && mode->step_model != 0) return fail(ctx, BL_E_UNSUPPORTED, "only step_model 0 is available");
+    if (mode && (mode->step_model < 0 || mode->step_model > 1))
+        return fail(ctx, BL_E_INVALID_ARG, "step_model must be 0 (controller) or 1 (learned)");
+    const bool learned = mode && mode->step_model == 1;
+    if (learned && !ctx->has_step_model)
+        return fail(ctx, BL_E_INVALID_ARG, "step_model 1 needs a network installed with bl_set_step_model");
     const bool mixed = mode && mode->precision == 1;
     if (grid->g.dtype != 0 && !mixed) return fail(ctx, BL_E_UNSUPPORTED, "float32 grids need precision 1");
     if (!(plasma->mu > 0.0) || !(plasma->ne_ni > 0.0) || !(plasma->sigma_max >= 0.0))
@@ -752,12 +1179,23 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         dim3 grd((count + 63) / 64), blk(64);
         {
             TimedLaunch tl(ctx, BL_K_GEODESIC);
-            if (batch)
+            if (learned) {
+                dim3 lg((count + 255) / 256), lb(256);
+                if (batch)
+                    hipLaunchKernelGGL((k_geodesic_learned<true, true>), lg, lb, 0, ctx->stream, P, B, start, count,
+                                       ctx->d_step_pk, ctx->d_step_tail, ctx->d_rec, ctx->d_meta, ctx->d_nacc,
+                                       ctx->d_ovf_count, ctx->d_ovf_list);
+                else
+                    hipLaunchKernelGGL((k_geodesic_learned<true, false>), lg, lb, 0, ctx->stream, P, B, start, count,
+                                       ctx->d_step_pk, ctx->d_step_tail, ctx->d_rec, ctx->d_meta, ctx->d_nacc,
+                                       ctx->d_ovf_count, ctx->d_ovf_list);
+            } else if (batch) {
                 hipLaunchKernelGGL((k_geodesic<true, true>), grd, blk, 0, ctx->stream, P, B, start, count, ctx->d_rec,
                                    ctx->d_meta, ctx->d_nacc, ctx->d_ovf_count, ctx->d_ovf_list, nullptr);
-            else
+            } else {
                 hipLaunchKernelGGL((k_geodesic<true, false>), grd, blk, 0, ctx->stream, P, B, start, count,
                                    ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_ovf_count, ctx->d_ovf_list, nullptr);
+            }
         }
         HIPCHK(ctx, hipGetLastError());
         {
@@ -846,6 +1284,19 @@ void bl_destroy(bl_context *ctx) {
         (void)hipEventDestroy(t.b);
     }
     (void)hipFree(ctx->d_imgs);
+    (void)hipFree(ctx->d_step_pk);
+    (void)hipFree(ctx->d_step_tail);
+    (void)hipFree(ctx->d_mlp_pk);
+    (void)hipFree(ctx->d_mlp_tail);
+    (void)hipFree(ctx->d_mlp_gpart);
+    (void)hipFree(ctx->d_mlp_lpart);
+    (void)hipFree(ctx->d_mlp_grad);
+    (void)hipFree(ctx->d_mlp_m);
+    (void)hipFree(ctx->d_mlp_v);
+    (void)hipFree(ctx->d_mlp_acc);
+    (void)hipFree(ctx->d_mlp_stats);
+    (void)hipFree(ctx->d_mlp_rows);
+    (void)hipFree(ctx->d_log_count);
     (void)hipFree(ctx->d_ray0);
     if (ctx->upload_done) (void)hipEventDestroy(ctx->upload_done);
     (void)hipFree(ctx->d_rec);
@@ -1129,6 +1580,235 @@ bl_status bl_autotune(bl_context *ctx, int32_t n_images, const bl_image_desc *im
     ctx->tuning = best;
     if (best_out) *best_out = best;
     if (best_ms_out) *best_ms_out = best_ms;
+    return BL_OK;
+}
+
+// ------------------------------------------------------------ step network
+namespace {
+
+bl_status mlp_buffers(bl_context *ctx) {
+    bl_status s;
+    size_t have = ctx->d_mlp_pk ? (size_t)kPkAll * sizeof(u32x4) : 0;
+    if ((s = ensure(ctx, &ctx->d_mlp_pk, have, (size_t)kPkAll * sizeof(u32x4))) != BL_OK) return s;
+    have = ctx->d_mlp_tail ? (size_t)kTailN * sizeof(float) : 0;
+    if ((s = ensure(ctx, &ctx->d_mlp_tail, have, (size_t)kTailN * sizeof(float))) != BL_OK) return s;
+    const size_t np = (size_t)kMlpNParam * sizeof(float);
+    have = ctx->d_mlp_grad ? np : 0;
+    if ((s = ensure(ctx, &ctx->d_mlp_grad, have, np)) != BL_OK) return s;
+    have = ctx->d_mlp_m ? np : 0;
+    if ((s = ensure(ctx, &ctx->d_mlp_m, have, np)) != BL_OK) return s;
+    have = ctx->d_mlp_v ? np : 0;
+    if ((s = ensure(ctx, &ctx->d_mlp_v, have, np)) != BL_OK) return s;
+    have = ctx->d_mlp_acc ? 2 * sizeof(double) : 0;
+    if ((s = ensure(ctx, &ctx->d_mlp_acc, have, 2 * sizeof(double))) != BL_OK) return s;
+    return BL_OK;
+}
+
+bl_status mlp_tiles(bl_context *ctx, long long tiles) {
+    bl_status s;
+    if ((s = ensure(ctx, &ctx->d_mlp_gpart, ctx->mlp_gpart_bytes, (size_t)tiles * kMlpNParam * sizeof(float))) != BL_OK)
+        return s;
+    return ensure(ctx, &ctx->d_mlp_lpart, ctx->mlp_lpart_bytes, (size_t)tiles * sizeof(float));
+}
+
+void mlp_pack(bl_context *ctx, const float *model, u32x4 *pk, float *tail) {
+    hipLaunchKernelGGL(k_mlp_pack, dim3((kPkAll + 255) / 256), dim3(256), 0, ctx->stream, model, pk, tail);
+}
+
+// One pass of k_mlp_fwdbwd + reduction over rows [offset, offset + n_rows) of
+// the permutation; adds the summed squared error to d_mlp_acc[0].
+bl_status mlp_pass(bl_context *ctx, const float *records, long long n_rows, long long offset, long long mul,
+                   long long add, long long n_mod, float inv_n, bool want_grad, float *y_out) {
+    const long long tiles = (n_rows + 63) / 64;
+    bl_status s = mlp_tiles(ctx, tiles);
+    if (s != BL_OK) return s;
+    hipLaunchKernelGGL(k_mlp_fwdbwd, dim3((unsigned)tiles), dim3(64), 0, ctx->stream, ctx->d_mlp_pk, ctx->d_mlp_tail,
+                       records, n_rows, offset, mul, add, n_mod, inv_n, want_grad ? 1 : 0, ctx->d_mlp_gpart,
+                       ctx->d_mlp_lpart, y_out);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpNParam + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_mlp_gpart,
+                       (int)tiles, ctx->d_mlp_grad, ctx->d_mlp_lpart, ctx->d_mlp_acc, want_grad ? 1 : 0);
+    HIPCHK(ctx, hipGetLastError());
+    return BL_OK;
+}
+
+bool coprime(unsigned long long a, unsigned long long b) {
+    while (b) {
+        unsigned long long t = a % b;
+        a = b;
+        b = t;
+    }
+    return a == 1;
+}
+
+}  // namespace
+
+bl_status bl_steplog(bl_context *ctx, int32_t n_images, const bl_image_desc *images, const bl_integrator *integ,
+                     float *records_out, int64_t capacity, int64_t *n_out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    bl_status s;
+    if ((s = check_integrator(ctx, integ)) != BL_OK) return s;
+    if (n_images < 1 || !images || !records_out || capacity < 0 || !n_out)
+        return fail(ctx, BL_E_INVALID_ARG, "invalid argument");
+    std::vector<const bl_camera *> cams(n_images);
+    std::vector<const bl_spacetime *> sts(n_images);
+    std::vector<double *> ims(n_images), auxs(n_images);
+    for (int k = 0; k < n_images; ++k) {
+        cams[k] = &images[k].cam;
+        sts[k] = &images[k].st;
+        ims[k] = images[k].image_out;
+        auxs[k] = images[k].aux_out;
+        if ((s = check_camera(ctx, cams[k])) != BL_OK || (s = check_spacetime(ctx, sts[k])) != BL_OK) return s;
+        if (!auxs[k]) return fail(ctx, BL_E_INVALID_ARG, "aux outputs must be non-NULL");
+    }
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    bl_tuning t = ctx->tuning;
+    t.order = 0;
+    Batch B;
+    long long total = 0;
+    if ((s = upload_images(ctx, n_images, cams.data(), sts.data(), ims.data(), auxs.data(), t, B, total)) != BL_OK)
+        return s;
+    size_t have = ctx->d_log_count ? sizeof(unsigned long long) : 0;
+    if ((s = ensure(ctx, &ctx->d_log_count, have, sizeof(unsigned long long))) != BL_OK) return s;
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, ctx->stream, (double *)ctx->d_log_count, 0.0, 1);
+    GeoParams P = geo_params(cams[0], sts[0], integ);
+    StepLog lg{records_out, capacity, ctx->d_log_count};
+    const long long chunk = 1 << 20;
+    for (long long start = 0; start < total; start += chunk) {
+        int count = (int)std::min(chunk, total - start);
+        TimedLaunch tl(ctx, BL_K_GEODESIC);
+        hipLaunchKernelGGL(k_steplog, dim3((count + 63) / 64), dim3(64), 0, ctx->stream, P, B, start, count, lg);
+        HIPCHK(ctx, hipGetLastError());
+    }
+    unsigned long long cnt = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&cnt, ctx->d_log_count, sizeof cnt, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    *n_out = (int64_t)cnt;
+    return BL_OK;
+}
+
+bl_status bl_mlp_init(bl_context *ctx, const float *records, int64_t n, int64_t seed, float *model_out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    if (!records || n < 1 || !model_out) return fail(ctx, BL_E_INVALID_ARG, "invalid argument");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int nblk = 256;
+    size_t have = ctx->d_mlp_stats ? (size_t)nblk * kLogRec * 2 * sizeof(double) : 0;
+    bl_status s;
+    if ((s = ensure(ctx, &ctx->d_mlp_stats, have, (size_t)nblk * kLogRec * 2 * sizeof(double))) != BL_OK) return s;
+    hipLaunchKernelGGL(k_mlp_stats, dim3(nblk), dim3(256), 0, ctx->stream, records, (long long)n, ctx->d_mlp_stats);
+    hipLaunchKernelGGL(k_mlp_init, dim3((kMlpNModel + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_mlp_stats, nblk,
+                       (long long)n, (unsigned long long)seed, model_out);
+    HIPCHK(ctx, hipGetLastError());
+    return BL_OK;
+}
+
+bl_status bl_mlp_forward_backward(bl_context *ctx, const float *model, const float *records, int64_t n, float *y_out,
+                                  float *loss_out, float *grad_out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    if (!model || !records || n < 1 || !loss_out || !grad_out) return fail(ctx, BL_E_INVALID_ARG, "invalid argument");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    bl_status s;
+    if ((s = mlp_buffers(ctx)) != BL_OK) return s;
+    mlp_pack(ctx, model, ctx->d_mlp_pk, ctx->d_mlp_tail);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, ctx->stream, ctx->d_mlp_acc, 0.0, 2);
+    if ((s = mlp_pass(ctx, records, n, 0, 1, 0, n, 1.0f / (float)n, true, y_out)) != BL_OK) return s;
+    HIPCHK(ctx, hipMemcpyAsync(grad_out, ctx->d_mlp_grad, (size_t)kMlpNParam * sizeof(float),
+                               hipMemcpyDeviceToDevice, ctx->stream));
+    hipLaunchKernelGGL(k_mlp_store_loss, dim3(1), dim3(64), 0, ctx->stream, ctx->d_mlp_acc, (double)n, loss_out);
+    HIPCHK(ctx, hipGetLastError());
+    return BL_OK;
+}
+
+bl_status bl_mlp_train(bl_context *ctx, const float *records, int64_t n, const bl_mlp_hparams *hp, float *model,
+                       float *loss_out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    if (!records || !hp || !model || !loss_out) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
+    if (hp->epochs < 1 || hp->batch < 64 || hp->batch % 64 != 0 || hp->n_val < 0 || n - hp->n_val < hp->batch ||
+        !(hp->lr > 0.0f) || !(hp->beta1 >= 0.0f && hp->beta1 < 1.0f) || !(hp->beta2 >= 0.0f && hp->beta2 < 1.0f) ||
+        !(hp->eps > 0.0f))
+        return fail(ctx, BL_E_INVALID_ARG, "need epochs >= 1, batch a multiple of 64 with n - n_val >= batch, "
+                                           "lr > 0, 0 <= beta < 1, eps > 0");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    bl_status s;
+    if ((s = mlp_buffers(ctx)) != BL_OK) return s;
+    const long long n_train = n - hp->n_val, steps = n_train / hp->batch;
+    hipLaunchKernelGGL(k_fill_f32, dim3((kMlpNParam + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_mlp_m, 0.0f,
+                       kMlpNParam);
+    hipLaunchKernelGGL(k_fill_f32, dim3((kMlpNParam + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_mlp_v, 0.0f,
+                       kMlpNParam);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, ctx->stream, ctx->d_mlp_acc, 0.0, 2);
+    unsigned long long rng = 0x9E3779B97F4A7C15ull ^ (unsigned long long)hp->seed;
+    auto next = [&]() {
+        rng += 0x9E3779B97F4A7C15ull;
+        unsigned long long z = rng;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    auto affine = [&](unsigned long long m, unsigned long long &mul, unsigned long long &add) {
+        mul = 1;
+        add = 0;
+        if (m > 1) {
+            do mul = next() % m; while (mul == 0 || !coprime(mul, m));
+            add = next() % m;
+        }
+    };
+    // rows in a fixed pseudo-random order: the held-out rows are the last
+    // n_val of it, a scattered subset of the log
+    if ((s = ensure(ctx, &ctx->d_mlp_rows, ctx->mlp_rows_bytes, (size_t)n * kLogRec * sizeof(float))) != BL_OK)
+        return s;
+    {
+        unsigned long long mul, add;
+        affine((unsigned long long)n, mul, add);
+        hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream, records,
+                           ctx->d_mlp_rows, (long long)n, (long long)mul, (long long)add);
+        HIPCHK(ctx, hipGetLastError());
+    }
+    records = ctx->d_mlp_rows;
+    long long t_step = 0;
+    const float b1 = hp->beta1, b2 = hp->beta2;
+    for (int ep = 0; ep < hp->epochs; ++ep) {
+        // a fresh affine permutation of the training rows per epoch
+        unsigned long long mul, add;
+        affine((unsigned long long)n_train, mul, add);
+        for (long long st = 0; st < steps; ++st) {
+            mlp_pack(ctx, model, ctx->d_mlp_pk, ctx->d_mlp_tail);
+            if ((s = mlp_pass(ctx, records, hp->batch, st * hp->batch, (long long)mul, (long long)add, n_train,
+                              1.0f / (float)hp->batch, true, nullptr)) != BL_OK)
+                return s;
+            ++t_step;
+            const float c1 = 1.0f - std::pow(b1, (float)t_step), c2 = 1.0f - std::pow(b2, (float)t_step);
+            hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpNParam + 255) / 256), dim3(256), 0, ctx->stream, model,
+                               ctx->d_mlp_m, ctx->d_mlp_v, ctx->d_mlp_grad, hp->lr, b1, b2, hp->eps, c1, c2);
+        }
+        hipLaunchKernelGGL(k_mlp_store_loss, dim3(1), dim3(64), 0, ctx->stream, ctx->d_mlp_acc,
+                           (double)(steps * hp->batch), loss_out + 2 * ep);
+        if (hp->n_val > 0) {
+            mlp_pack(ctx, model, ctx->d_mlp_pk, ctx->d_mlp_tail);
+            if ((s = mlp_pass(ctx, records + n_train * kLogRec, hp->n_val, 0, 1, 0, hp->n_val, 1.0f, false,
+                              nullptr)) != BL_OK)
+                return s;
+            hipLaunchKernelGGL(k_mlp_store_loss, dim3(1), dim3(64), 0, ctx->stream, ctx->d_mlp_acc,
+                               (double)hp->n_val, loss_out + 2 * ep + 1);
+        } else {
+            hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(64), 0, ctx->stream, loss_out + 2 * ep + 1, 0.0f, 1);
+        }
+        HIPCHK(ctx, hipGetLastError());
+    }
+    return BL_OK;
+}
+
+bl_status bl_set_step_model(bl_context *ctx, const float *model) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    if (!model) return fail(ctx, BL_E_INVALID_ARG, "model is NULL");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    bl_status s;
+    size_t have = ctx->d_step_pk ? (size_t)kPkAll * sizeof(u32x4) : 0;
+    if ((s = ensure(ctx, &ctx->d_step_pk, have, (size_t)kPkAll * sizeof(u32x4))) != BL_OK) return s;
+    have = ctx->d_step_tail ? (size_t)kTailN * sizeof(float) : 0;
+    if ((s = ensure(ctx, &ctx->d_step_tail, have, (size_t)kTailN * sizeof(float))) != BL_OK) return s;
+    mlp_pack(ctx, model, ctx->d_step_pk, ctx->d_step_tail);
+    HIPCHK(ctx, hipGetLastError());
+    ctx->has_step_model = true;
     return BL_OK;
 }
 

@@ -208,6 +208,24 @@ def batch_workload(n_images=64, n_min=64, n_max=512, seed=2, polarized=1):
     return dict(images=images, integrator=base["integrator"], plasma=pl, grid_args=base["grid_args"])
 
 
+def steplog_workload(n_images=128, n=32, seed=3):
+    """Cameras for logging the plain integrator's steps: spins a ~ U[0, 0.98],
+    cos(inclination) ~ U[0, 1], camera at r = 100 M, n x n pixels over
+    +-15 M each (a square pixel lattice standing in for uniformly drawn
+    pixels).  Returns dict(images=[(camera, spacetime)], integrator)."""
+    rng = np.random.default_rng(seed)
+    images = []
+    for _ in range(n_images):
+        a = float(rng.uniform(0.0, 0.98))
+        th = math.acos(float(rng.uniform(0.0, 1.0)))
+        cam = dict(r=100.0, theta=th, phi=0.0, u_normal=(0.0, 0.0, 0.0), k_cov=(1.0, 0.0, 0.0), width=30.0,
+                   n=n, freq_mode=0, psi=0.0, nu_hz=230e9)
+        st = dict(a=a, mass_msun=4.152e6, r_in=1.01 * r_horizon(a), flat=0)
+        images.append((cam, st))
+    integ = dict(f_abs=1e-8, f_rel=1e-8, ds_max=0.0, h0_frac=0.1, max_steps=100000)
+    return dict(images=images, integrator=integ)
+
+
 def make_grid(grid_args, dtype=np.float64):
     g = dict(grid_args)
     kind = g.pop("kind")
