@@ -184,6 +184,88 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_learned(args):
+    """Learned step proposals on the single-image workload: log the plain
+    integrator over 128 random cameras (spin U[0, 0.98], cos inclination
+    U[0, 1], 32^2 pixels each), train the network on the GPU (untimed), then
+    time renders with learned proposals and with the plain controller."""
+    import numpy as np
+    import torch
+    from paper_2203_15963_amd import blgpu, learned, synth
+
+    w = synth.workload(args.workload, n=args.n)
+    n = int(w["camera"]["n"])
+    grid_f32 = args.precision == 1 and not args.grid_f64
+    grid = synth.make_grid(w["grid_args"], dtype=np.float32 if grid_f32 else np.float64)
+    ctx = blgpu.Context(0)
+    gg = ctx.grid(grid)
+    t0 = time.perf_counter()
+    model, losses, n_steps, rec = learned.train_step_model(ctx, n_images=128, n=32, seed=3, epochs=args.epochs,
+                                                           batch=16384)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    losses = losses.cpu().numpy()
+    log(f"logged {n_steps} steps, trained in {t_train:.1f} s, losses {losses.tolist()}")
+    del rec
+    ctx.set_step_model(model)
+    res = {}
+    for sm in (0, 1):
+        img = torch.empty(4, n, n, dtype=torch.float64, device="cuda")
+        aux = torch.empty(blgpu.NAUX, n, n, dtype=torch.float64, device="cuda")
+
+        def step():
+            ctx.render(w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"], precision=args.precision,
+                       image=img, aux=aux, step_model=sm)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        ctx.profile_read()
+        ta = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        prof = ctx.profile_read()
+        ctx.profile_enable(False)
+        a = aux.cpu().numpy()
+        res[sm] = {"ms": (tb - ta) * 1e3 / args.steps, "kern": kernel_table(prof, args.steps),
+                   "img": img.cpu().numpy(), "acc": float(a[5].mean()), "rej": float(a[6].mean()),
+                   "units": {"trial": float(a[5].sum() + a[6].sum()), "acc": float(a[5].sum()),
+                             "samp": float(a[8].sum()), "rec": float(a[9].sum()), "ray": float(n * n)}}
+        log("step_model", sm, f"{res[sm]['ms']:.2f} ms")
+    il, ip = res[1]["img"], res[0]["img"]
+    den = np.maximum(np.abs(ip[0]), 1e-3 * np.abs(ip[0]).max())
+    diff = {"E_pix": float((np.abs(il - ip) / den).max()),
+            "L1_I": float(np.abs(il[0] - ip[0]).sum() / np.abs(ip[0]).sum())}
+
+    def summary(r):
+        return {"rays_per_s": n * n / (r["ms"] / 1e3), "ms_per_step": r["ms"],
+                "rejected_fraction": r["rej"] / (r["acc"] + r["rej"]), "accepted_per_ray": r["acc"],
+                "trials_per_ray": r["acc"] + r["rej"],
+                "geodesic_ms_per_step": r["kern"]["geodesic"]["ms_per_step"],
+                "transfer_ms_per_step": r["kern"]["transfer"]["ms_per_step"]}
+
+    out = {
+        "metric": "rays/sec at 1024² (geodesic+polarized transfer) with learned step proposals",
+        "value": n * n / (res[1]["ms"] / 1e3), "unit": "rays/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res[1]["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32+bf16" if args.precision == 1 else "f64+bf16", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {n}x{n} pixels with learned step proposals (MLP 11-64-64-64-1, "
+                               "BF16 on the matrix cores)", "precision": args.precision,
+                   "grid_dtype": "f32" if grid_f32 else "f64", "pixels": n * n},
+        "learned": summary(res[1]), "plain": summary(res[0]),
+        "speedup_vs_plain": res[0]["ms"] / res[1]["ms"],
+        "image_difference_learned_vs_plain": diff,
+        "training": {"logged_steps": n_steps, "epochs": args.epochs, "seconds": t_train,
+                     "loss_train_heldout": losses.tolist()},
+        "kernels": res[1]["kern"],
+        "roofline": roofline(args.precision, "transfer", res[1]["kern"], res[1]["units"]),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +283,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="single image: autotune the schedule first (untimed)")
     ap.add_argument("--tuning", default=None, help="schedule as JSON, e.g. '{\"tile_w\": 8, \"tile_h\": 8}'")
     ap.add_argument("--tune-trials", type=int, default=14)
+    ap.add_argument("--step-model", type=int, default=0, help="1: learned step proposals (trains the network first)")
+    ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -211,6 +295,9 @@ def main():
         sys.exit(2)
     if args.workload.startswith("c4"):
         run_batch(args)
+        return
+    if args.step_model == 1:
+        run_learned(args)
         return
 
     import numpy as np
