@@ -177,7 +177,7 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
                     float *q = lg.buf + idx * kLogRec;
 #pragma unroll
                     for (int m = 0; m < kMlpIn; ++m) q[m] = f[m];
-                    q[kMlpIn] = (float)log(fabs(h));
+                    q[kMlpIn] = __logf(fabsf((float)h));   // the same map as the log|h| feature
                 }
                 h_last = h;
                 eps_last = eps;

@@ -43,27 +43,27 @@ constexpr int kPkFwd = kPkL3 + 8 * 64;     // end of the forward fragments
 constexpr int kPkB2 = kPkFwd;              // backward (W^T) layer 2: [mt 4][kk 2][lane 64]
 constexpr int kPkB3 = kPkB2 + 8 * 64;      // backward layer 3
 constexpr int kPkAll = kPkB3 + 8 * 64;
-// FP32 tail (floats): b1, b2, b3, w4, b4, mean, std
-constexpr int kTB1 = 0, kTB2 = 64, kTB3 = 128, kTW4 = 192, kTB4 = 256, kTMu = 257, kTSig = 268, kTailN = 288;
+// FP32 tail (floats): b1, b2, b3, w4, b4, feature mean, 1 / feature std
+constexpr int kTB1 = 0, kTB2 = 64, kTB3 = 128, kTW4 = 192, kTB4 = 256, kTMu = 257, kTISig = 268, kTailN = 288;
 
-// BF16 with round-to-nearest-even (NaN kept quiet).
-__host__ __device__ __forceinline__ unsigned int bf16_bits(float f) {
-    unsigned int u = __builtin_bit_cast(unsigned int, f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return 0x7fc0u;
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return u >> 16;
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// two floats to BF16 (round to nearest even; one v_cvt_pk_bf16_f32), lo in
+// the low half
+__device__ __forceinline__ unsigned int pack2(float lo, float hi) {
+    return __builtin_bit_cast(unsigned int, __builtin_convertvector(f32x2{lo, hi}, bf16x2));
 }
-__device__ __forceinline__ float bf16_round(float f) { return __builtin_bit_cast(float, bf16_bits(f) << 16); }
-__device__ __forceinline__ unsigned int pack2(float lo, float hi) { return bf16_bits(lo) | (bf16_bits(hi) << 16); }
 
 __device__ __forceinline__ f32x4 mma(u32x4 a, u32x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
                                                    0, 0, 0);
 }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with the hardware exp and a fast reciprocal (a few
+// ulp, far below the BF16 resolution of the values they feed)
+__device__ __forceinline__ float silu(float z) { return __fdividef(z, 1.0f + __expf(-z)); }
 __device__ __forceinline__ float dsilu(float z) {
-    float s = 1.0f / (1.0f + __expf(-z));
+    float s = __fdividef(1.0f, 1.0f + __expf(-z));
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -110,7 +110,7 @@ __device__ __forceinline__ void to_bfrag(const f32x4 (&h)[4][4], u32x4 (&bq)[4][
 __device__ __forceinline__ void stage_input(const float *tail, const float x[kMlpIn], u32x4 *stage, int lane) {
     float xn[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) xn[i] = i < kMlpIn ? (x[i] - tail[kTMu + i]) / tail[kTSig + i] : 0.0f;
+    for (int i = 0; i < 16; ++i) xn[i] = i < kMlpIn ? (x[i] - tail[kTMu + i]) * tail[kTISig + i] : 0.0f;
     stage[lane * 4 + 0] = u32x4{pack2(xn[0], xn[1]), pack2(xn[2], xn[3]), pack2(xn[4], xn[5]), pack2(xn[6], xn[7])};
     stage[lane * 4 + 1] = u32x4{pack2(xn[8], xn[9]), pack2(xn[10], xn[11]), pack2(xn[12], xn[13]),
                                 pack2(xn[14], xn[15])};
@@ -194,8 +194,8 @@ __device__ __forceinline__ void step_features(const double y[7], double kt, doub
     x[6] = (float)y[5];
     x[7] = (float)y[6];
     x[8] = (float)a;
-    x[9] = (float)log(fabs(h_last));
-    x[10] = (float)log(fmax(eps_last, 1e-10));
+    x[9] = __logf(fabsf((float)h_last));
+    x[10] = __logf(fmaxf((float)eps_last, 1e-10f));
 }
 
 }  // namespace bl

@@ -486,8 +486,8 @@ __global__ void k_mlp_pack(const float *__restrict__ model, u32x4 *__restrict__ 
         else if (t < 192) v = model[kB3 + t - 128];
         else if (t < 256) v = model[kW4 + t - 192];
         else if (t == kTB4) v = model[kB4];
-        else if (t < kTSig) v = model[kMu + t - kTMu];
-        else if (t < kTSig + kMlpIn) v = model[kSig + t - kTSig];
+        else if (t < kTISig) v = model[kMu + t - kTMu];
+        else if (t < kTISig + kMlpIn) v = 1.0f / model[kSig + t - kTISig];
         tail[t] = v;
     }
 }
@@ -603,7 +603,7 @@ __global__ void __launch_bounds__(64) k_mlp_fwdbwd(const u32x4 *__restrict__ pk,
     // ---- forward
     stage_input(tail, x, s_stage, lane);
     for (int f = 0; f < 32; ++f)
-        s_xt[f * 64 + lane] = f < kMlpIn ? (unsigned short)bf16_bits((x[f] - tail[kTMu + f]) / tail[kTSig + f]) : 0;
+        s_xt[f * 64 + lane] = f < kMlpIn ? (unsigned short)(pack2((x[f] - tail[kTMu + f]) * tail[kTISig + f], 0.0f) & 0xffffu) : 0;
     wave_lds_sync();
     u32x4 b1[4][1];
     input_bfrag(s_stage, b1, lane);
@@ -625,7 +625,7 @@ __global__ void __launch_bounds__(64) k_mlp_fwdbwd(const u32x4 *__restrict__ pk,
                     zs[(mt * 4 + nt) * 64 + lane] = h[mt][nt];
                     for (int e = 0; e < 4; ++e) {
                         h[mt][nt][e] = silu(h[mt][nt][e]);
-                        hs[(16 * mt + 4 * g + e) * 64 + 16 * nt + j] = (unsigned short)bf16_bits(h[mt][nt][e]);
+                        hs[(16 * mt + 4 * g + e) * 64 + 16 * nt + j] = (unsigned short)(pack2(h[mt][nt][e], 0.0f) & 0xffffu);
                     }
                 }
             to_bfrag(h, bq);
@@ -681,7 +681,7 @@ __global__ void __launch_bounds__(64) k_mlp_fwdbwd(const u32x4 *__restrict__ pk,
         for (int mt = 0; mt < 4; ++mt)
             for (int nt = 0; nt < 4; ++nt)
                 for (int e = 0; e < 4; ++e)
-                    s_dz[(16 * mt + 4 * g + e) * 64 + 16 * nt + j] = (unsigned short)bf16_bits(dz[mt][nt][e]);
+                    s_dz[(16 * mt + 4 * g + e) * 64 + 16 * nt + j] = (unsigned short)(pack2(dz[mt][nt][e], 0.0f) & 0xffffu);
         wave_lds_sync();
         const unsigned short *hp = L == 3 ? s_h2 : L == 2 ? s_h1 : s_xt;
         const int ntn = L == 1 ? 2 : 4;   // input features of layer 1: 32 (11 used)
