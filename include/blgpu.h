@@ -122,7 +122,8 @@ typedef struct {
                                  the smallest block size                      */
     const void *prims;        /* device [n_blocks][bnz][bny][bnx][8]:
                                  rho, p, u~x, u~y, u~z, Bx, By, Bz in code
-                                 units (u~ = CKS normal-frame velocity)       */
+                                 units (u~ = CKS normal-frame velocity);
+                                 16-byte aligned                              */
     int32_t dtype;            /* 0: float64, 1: float32 (mixed precision)     */
     int32_t pad;
     double rho_unit;          /* g cm^-3 per code density unit; p is in units
@@ -196,7 +197,7 @@ typedef struct {
                                  of its lanes are idle (1..64; default 1)     */
     int64_t chunk_rays;       /* rays traced per geodesic/transfer launch pair
                                  (multiple of 64; 0 = as many as the step-
-                                 record workspace holds, the default: 32 GiB
+                                 record workspace holds, the default: 64 GiB
                                  or a quarter of the free device memory at
                                  bl_create, whichever is less)                */
     int32_t order;            /* 0: images in the given order; 1: largest

@@ -25,7 +25,7 @@ enum : int { kRunning = 0, kEscaped = 1, kCaptured = 2, kMaxSteps = 3, kUnderflo
              kNonfinite = 5, kRayOverflow = 99 };
 
 constexpr int kNaux = 9;
-constexpr int kRecDoubles = 16;   // one step record = 128 bytes
+constexpr int kRecDoubles = 24;   // one step record = 192 bytes
 
 // Camera frame in CKS coordinate components (computed once per image on the
 // device): centre, observer 4-velocity, line of sight K, horizontal H,

@@ -115,9 +115,9 @@ __device__ __forceinline__ double shrink_factor(double eps) {
     return rint(fmax(0.2, 0.9 * pow(eps, -0.2)) * 4096.0) / 4096.0;
 }
 
-// Store an accepted step's record.
+// Store an accepted step's record (f0 = the right-hand side at y0).
 __device__ __forceinline__ void write_record(double *rec, int nacc, const double y[7], double h, const double ym[7],
-                                             double ds) {
+                                             double ds, const double f0[7]) {
     double *r = rec + (long long)nacc * kRecDoubles;
 #pragma unroll
     for (int m = 0; m < 7; ++m) r[m] = y[m];
@@ -125,6 +125,17 @@ __device__ __forceinline__ void write_record(double *rec, int nacc, const double
 #pragma unroll
     for (int m = 0; m < 7; ++m) r[8 + m] = ym[m];
     r[15] = ds;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) r[16 + m] = f0[m];
+}
+
+// The final state and its right-hand side after the last step.
+__device__ __forceinline__ void write_final(double *rec, int nacc, const double y[7], const double f[7]) {
+    double *r = rec + (long long)nacc * kRecDoubles;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) r[m] = y[m];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) r[16 + m] = f[m];
 }
 
 // Step log: one record per accepted step of the plain controller, the
@@ -143,7 +154,9 @@ struct StepLog {
 // stops with status kRayOverflow.  Without WREC nothing is stored; with LOG
 // every accepted step is appended to the step log.
 //   record: [0..3] x^mu of y0, [4..6] k_a of y0, [7] h,
-//           [8..11] x^mu of y_mid, [12..14] k_a of y_mid, [15] ds of the step
+//           [8..11] x^mu of y_mid, [12..14] k_a of y_mid, [15] ds of the step,
+//           [16..22] dy/dlambda at y0 (the first stage of the step), [23] unused
+//   final record n_acc: [0..6] the final state, [16..22] dy/dlambda there
 template <bool WREC, bool LOG = false>
 __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], double kt, double *rec, int cap,
                                           TraceOut &o, StepLog lg = StepLog{nullptr, 0, nullptr}) {
@@ -168,7 +181,7 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
         if (eps <= 1.0) {
             if (WREC && nacc + 2 > cap) { status = kRayOverflow; break; }
             double ds = fabs(h) * ds_dlambda(a, flat, ym, kt);
-            if (WREC) write_record(rec, nacc, y, h, ym, ds);
+            if (WREC) write_record(rec, nacc, y, h, ym, ds, k1);
             if (LOG) {
                 unsigned long long idx = atomicAdd(lg.count, 1ull);
                 if ((long long)idx < lg.cap) {
@@ -204,11 +217,7 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
             no_grow = true;
         }
     }
-    if (WREC && status != kRayOverflow) {
-        double *r = rec + (long long)nacc * kRecDoubles;
-#pragma unroll
-        for (int m = 0; m < 7; ++m) r[m] = y[m];
-    }
+    if (WREC && status != kRayOverflow) write_final(rec, nacc, y, k1);
     o.status = status;
     o.n_acc = nacc;
     o.n_rej = nrej;
@@ -267,7 +276,7 @@ __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool activ
         if (eps <= 1.0) {
             if (WREC && nacc + 2 > cap) { status = kRayOverflow; continue; }
             double ds = fabs(h) * ds_dlambda(a, flat, ym, kt);
-            if (WREC) write_record(rec, nacc, y, h, ym, ds);
+            if (WREC) write_record(rec, nacc, y, h, ym, ds, k1);
             ++nacc;
             lambda += h;
             s += ds;
@@ -288,11 +297,7 @@ __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool activ
             h *= shrink_factor(eps);
         }
     }
-    if (WREC && active && status != kRayOverflow) {
-        double *r = rec + (long long)nacc * kRecDoubles;
-#pragma unroll
-        for (int m = 0; m < 7; ++m) r[m] = y[m];
-    }
+    if (WREC && active && status != kRayOverflow) write_final(rec, nacc, y, k1);
     o.status = status;
     o.n_acc = nacc;
     o.n_rej = nrej;

@@ -36,10 +36,29 @@ __device__ __forceinline__ int find_block(const DevGrid &g, const double x[3]) {
     return g.table[(idx[2] * g.tn[1] + idx[1]) * g.tn[0] + idx[0]];
 }
 
-template <typename R, typename T>
-__device__ __forceinline__ void load_cell(const T *base, long long off, R acc[8], R wt) {
+// One cell's 8 primitives (32 or 64 contiguous bytes, 16-byte aligned) in
+// 16-byte vector loads, accumulated with weight wt.
+typedef float gf4 __attribute__((ext_vector_type(4)));
+typedef double gd2 __attribute__((ext_vector_type(2)));
+template <typename R>
+__device__ __forceinline__ void load_cell(const float *base, long long off, R acc[8], R wt) {
+    const gf4 *p = reinterpret_cast<const gf4 *>(base + off * 8);
+    const gf4 v0 = p[0], v1 = p[1];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) acc[m] += wt * (R)base[off * 8 + m];
+    for (int m = 0; m < 4; ++m) {
+        acc[m] += wt * (R)v0[m];
+        acc[4 + m] += wt * (R)v1[m];
+    }
+}
+template <typename R>
+__device__ __forceinline__ void load_cell(const double *base, long long off, R acc[8], R wt) {
+    const gd2 *p = reinterpret_cast<const gd2 *>(base + off * 8);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const gd2 v = p[q];
+        acc[2 * q] += wt * (R)v[0];
+        acc[2 * q + 1] += wt * (R)v[1];
+    }
 }
 
 // Interpolated primitives at x; returns the block id or -1 (vacuum).  Block

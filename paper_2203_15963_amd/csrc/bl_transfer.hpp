@@ -371,9 +371,10 @@ __device__ __forceinline__ void next_step(RayWalk<R> &w, const GeoParams &P, con
 #pragma unroll
     for (int m = 0; m < 7; ++m) s_q[m * 64 + lane] = y0[m];
     if (nsub > 1) {
+        // right-hand sides at both ends, stored with the records
         double f0[7], f1[7];
-        geo_rhs(P.a, P.flat, y0, w.kt, f0);
-        geo_rhs(P.a, P.flat, y1, w.kt, f1);
+        load_state7(r + 16, f0);
+        load_state7(r + kRecDoubles + 16, f1);
 #pragma unroll
         for (int m = 0; m < 7; ++m) {
             double A = y1[m] - y0[m] - h * f0[m];

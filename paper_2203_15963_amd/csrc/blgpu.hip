@@ -837,7 +837,7 @@ struct bl_context {
     size_t ovf_cap = 0;
     double *d_big = nullptr;
     size_t big_bytes = 0;
-    size_t ws_limit = (size_t)32 << 30;  // bytes of step records per chunk (set at creation)
+    size_t ws_limit = (size_t)64 << 30;  // bytes of step records per chunk (set at creation)
     int *d_queue = nullptr;              // per-chunk work counters of the persistent kernels
     size_t queue_bytes = 0;
     int cus = 0;
@@ -1267,7 +1267,7 @@ bl_status bl_create(int device, void *hip_stream, bl_context **out) {
         delete ctx;
         return BL_E_DEVICE;
     }
-    // step-record workspace per chunk: 32 GiB, at most a quarter of free memory
+    // step-record workspace per chunk: 64 GiB, at most a quarter of free memory
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
         ctx->ws_limit = std::max<size_t>((size_t)64 << 20, std::min(ctx->ws_limit, free_b / 4));
@@ -1319,6 +1319,7 @@ bl_status bl_grid_create(bl_context *ctx, const bl_grid_desc *d, bl_grid **out) 
     if (!d->bounds || !d->prims) return fail(ctx, BL_E_INVALID_ARG, "bounds and prims must be non-NULL");
     if (d->dtype != 0 && d->dtype != 1) return fail(ctx, BL_E_INVALID_ARG, "dtype must be 0 (f64) or 1 (f32)");
     if (!(d->rho_unit > 0.0)) return fail(ctx, BL_E_INVALID_ARG, "rho_unit must be positive");
+    if (((uintptr_t)d->prims & 15) != 0) return fail(ctx, BL_E_INVALID_ARG, "prims must be 16-byte aligned");
     HIPCHK(ctx, hipSetDevice(ctx->device));
     int nb = d->n_blocks;
     DevGrid g{};
