@@ -292,20 +292,29 @@ struct TransferParams {
 //   depths    a' = alpha_nu L dl omega,  r' = rho_nu L dl omega,
 // which equal nu_cam^3 j/nu^2 dlambda_phys and alpha nu dlambda_phys with
 // dlambda_phys = L dl/n, nu = n omega.  The quartic of the step being cut into
-// pieces lives in LDS (35 doubles per lane, lane-interleaved) and is read back
+// pieces lives in LDS (the node in FP64, coefficients in R; lane-interleaved) and is read back
 // for every piece through an offset the compiler cannot hoist, so it does not
 // occupy registers across pieces.  blockDim.x == 64.
+// The open step's dense output in LDS, lane-interleaved: the node y0 in FP64
+// and the quartic's coefficients c1..c4 (7 components each) in R, so that
+// y(theta) = y0 + theta (c1 + theta (c2 + theta (c3 + theta c4))).
+template <typename R>
+struct QuartLds {
+    double y0[7 * 64];
+    R c[28 * 64];
+};
+
 template <typename R>
 struct RayWalk {
     const double *rec;   // the ray's records
-    double kt, n_norm;
-    double L;            // GM/c^2 in cm
-    double lj;           // L (nu_cam/n)^3
+    R kt, n_norm;        // k_t (held fixed) and the frequency normalisation
+    R L;                 // GM/c^2 in cm
+    R lj;                // L (nu_cam/n)^3
     int st;              // next step to open (counting down), -1: all opened
     int p;               // next piece of the open step (counting down), -1: none
     int nsub;
     bool inb, started;
-    double dl, pdl;
+    R dl, pdl;           // affine length of the open step's pieces, and of the previous piece
     R I, tau, Ij;
     R tau_c, Ij_c;       // compensation terms of the two sums
     int nsamp, nrec;
@@ -317,17 +326,17 @@ template <typename R>
 __device__ __forceinline__ void begin_ray(RayWalk<R> &w, const double *rec, int n_acc, double kt, double n_norm,
                                           const TransferParams &tp) {
     w.rec = rec;
-    w.kt = kt;
-    w.n_norm = n_norm;
+    w.kt = (R)kt;
+    w.n_norm = (R)n_norm;
     double q = tp.nu_cam / n_norm;
-    w.L = tp.L;
-    w.lj = tp.L * q * q * q;
+    w.L = (R)tp.L;
+    w.lj = (R)(tp.L * q * q * q);
     w.st = n_acc - 1;
     w.p = -1;
     w.nsub = 0;
     w.inb = false;
     w.started = false;
-    w.dl = w.pdl = 0.0;
+    w.dl = w.pdl = R(0);
     w.I = w.tau = w.Ij = w.tau_c = w.Ij_c = R(0);
     w.nsamp = w.nrec = 0;
 #pragma unroll
@@ -353,7 +362,7 @@ __device__ __forceinline__ void load_state7(const double *r, double y[7]) {
 // Open step w.st: sampling decision, number of pieces, quartic into LDS.
 template <typename R>
 __device__ __forceinline__ void next_step(RayWalk<R> &w, const GeoParams &P, const DevGrid &g,
-                                          const TransferParams &tp, double *s_q, int lane) {
+                                          const TransferParams &tp, QuartLds<R> &s_q, int lane) {
     const double *r = w.rec + (long long)w.st * kRecDoubles;
     double y0[7], ym[7], y1[7];
     load_state7(r, y0);
@@ -369,7 +378,7 @@ __device__ __forceinline__ void next_step(RayWalk<R> &w, const GeoParams &P, con
         nsub = (q >= 1.0) ? (int)fmin(q, 16777216.0) : 1;
     }
 #pragma unroll
-    for (int m = 0; m < 7; ++m) s_q[m * 64 + lane] = y0[m];
+    for (int m = 0; m < 7; ++m) s_q.y0[m * 64 + lane] = y0[m];
     if (nsub > 1) {
         // right-hand sides at both ends, stored with the records
         double f0[7], f1[7];
@@ -380,26 +389,30 @@ __device__ __forceinline__ void next_step(RayWalk<R> &w, const GeoParams &P, con
             double A = y1[m] - y0[m] - h * f0[m];
             double B = h * (f1[m] - f0[m]);
             double C = 16.0 * (ym[m] - y0[m]) - 8.0 * h * f0[m];
-            s_q[(7 + m) * 64 + lane] = h * f0[m];
-            s_q[(14 + m) * 64 + lane] = -5.0 * A + B + C;
-            s_q[(21 + m) * 64 + lane] = 14.0 * A - 3.0 * B - 2.0 * C;
-            s_q[(28 + m) * 64 + lane] = -8.0 * A + 2.0 * B + C;
+            s_q.c[m * 64 + lane] = (R)(h * f0[m]);
+            s_q.c[(7 + m) * 64 + lane] = (R)(-5.0 * A + B + C);
+            s_q.c[(14 + m) * 64 + lane] = (R)(14.0 * A - 3.0 * B - 2.0 * C);
+            s_q.c[(21 + m) * 64 + lane] = (R)(-8.0 * A + 2.0 * B + C);
         }
     }
     w.nsub = nsub;
-    w.dl = fabs(h) / (double)nsub;
+    w.dl = (R)(fabs(h) / (double)nsub);
     w.nrec += nsub;
     w.p = nsub - 1;
     --w.st;
 }
 
-__device__ __forceinline__ void quartic_at(const double *s_q, int off, double th, double y[8], double kt) {
+template <typename R>
+__device__ __forceinline__ void quartic_at(const QuartLds<R> &s_q, int off, double th, double y[8], double kt) {
+    const R t = (R)th;
 #pragma unroll
     for (int m = 0; m < 7; ++m) {
         int q = m < 4 ? m : m + 1;
-        y[q] = s_q[m * 64 + off] +
-               th * (s_q[(7 + m) * 64 + off] +
-                     th * (s_q[(14 + m) * 64 + off] + th * (s_q[(21 + m) * 64 + off] + th * s_q[(28 + m) * 64 + off])));
+        R v = s_q.c[(21 + m) * 64 + off];
+        v = s_q.c[(14 + m) * 64 + off] + t * v;
+        v = s_q.c[(7 + m) * 64 + off] + t * v;
+        v = s_q.c[m * 64 + off] + t * v;
+        y[q] = s_q.y0[m * 64 + off] + th * (double)v;
     }
     y[4] = kt;
 }
@@ -413,7 +426,7 @@ __device__ __forceinline__ void to_state_r(const R p7[7], R kt, R y[8]) {
 // Process piece w.p of the open step.
 template <bool POL, typename R>
 __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
-                                      const double *s_q, int lane) {
+                                      const QuartLds<R> &s_q, int lane) {
     const int flat = P.flat;
     int off = lane;
     asm volatile("" : "+v"(off));   // keep the LDS reads here
@@ -423,25 +436,25 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
         const double *rr = w.rec + (long long)(w.st + 1) * kRecDoubles + 8;
         ys[0] = rr[0]; ys[1] = rr[1]; ys[2] = rr[2]; ys[3] = rr[3];
         ys[5] = rr[4]; ys[6] = rr[5]; ys[7] = rr[6];
-        ys[4] = w.kt;
+        ys[4] = (double)w.kt;
     } else {
-        quartic_at(s_q, off, ((double)p + 0.5) / (double)w.nsub, ys, w.kt);
+        quartic_at(s_q, off, ((double)p + 0.5) / (double)w.nsub, ys, (double)w.kt);
     }
     if (p == 0) {
 #pragma unroll
-        for (int m = 0; m < 7; ++m) yb[m < 4 ? m : m + 1] = s_q[m * 64 + off];
-        yb[4] = w.kt;
+        for (int m = 0; m < 7; ++m) yb[m < 4 ? m : m + 1] = s_q.y0[m * 64 + off];
+        yb[4] = (double)w.kt;
     } else {
-        quartic_at(s_q, off, (double)p / (double)w.nsub, yb, w.kt);
+        quartic_at(s_q, off, (double)p / (double)w.nsub, yb, (double)w.kt);
     }
     w.p = p - 1;
     Sample<R> smp;
     smp.plasma = false;
-    if (w.inb) sample_point<R>(P.a, flat, g, pp, ys, w.n_norm, smp);
+    if (w.inb) sample_point<R>(P.a, flat, g, pp, ys, (double)w.n_norm, smp);
     R c[8];
     if (smp.plasma) {
-        R lt = (R)(w.L * w.dl) * smp.omega;
-        R ljw = (R)(w.lj * w.dl) / (smp.omega * smp.omega);
+        R lt = w.L * w.dl * smp.omega;
+        R ljw = w.lj * w.dl / (smp.omega * smp.omega);
 #pragma unroll
         for (int m = 0; m < 3; ++m) c[m] = smp.co[m] * ljw;
 #pragma unroll
@@ -463,7 +476,7 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
         R ya[8], yc[8];
         to_state_r(w.pys, ktr, ya);
         to_state_r(w.pyb, ktr, yc);
-        transport_step<R>(ar, flat, ya, yc, (R)(0.5 * (w.pdl + w.dl)), w.N);
+        transport_step<R>(ar, flat, ya, yc, R(0.5) * (w.pdl + w.dl), w.N);
     }
     w.started = true;
 #pragma unroll
@@ -513,7 +526,7 @@ __device__ __forceinline__ void finish_ray(RayWalk<R> &w, const GeoParams &P, co
     y0[4] = ktr; y0[5] = (R)rec[4]; y0[6] = (R)rec[5]; y0[7] = (R)rec[6];
     R ya[8];
     to_state_r(w.pys, ktr, ya);
-    transport_step<R>(ar, P.flat, ya, y0, (R)(0.5 * w.pdl), w.N);
+    transport_step<R>(ar, P.flat, ya, y0, R(0.5) * w.pdl, w.N);
     KS<R> k = ks_point<R>(ar, P.flat, y0[1], y0[2], y0[3]);
     R mH[4] = {(R)-Hv[0], (R)-Hv[1], (R)-Hv[2], (R)-Hv[3]};
     R up[4] = {(R)upix[0], (R)upix[1], (R)upix[2], (R)upix[3]};
@@ -530,7 +543,7 @@ __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &
                                              const TransferParams &tp, const double *rec, int n_acc, double kt,
                                              double n_norm, const double upix[4], const double Hv[4],
                                              TransferOut &o) {
-    __shared__ double s_q[35 * 64];
+    __shared__ QuartLds<R> s_q;
     const int lane = threadIdx.x;
     RayWalk<R> w;
     begin_ray(w, rec, n_acc, kt, n_norm, tp);

@@ -263,12 +263,19 @@ __device__ __forceinline__ void pixel_observer(const Frame &fr, const GeoParams 
 // though rays hold from tens to thousands of pieces.  A wave takes new rays
 // once at least refill_min lanes are idle, or when none holds a ray.  Every
 // lane leaves the loop once the queue is exhausted and its ray is written.
+// Resident waves per SIMD the FP32 transfer kernels are compiled for (the
+// register budget: 168 VGPRs for three, 128 for four); the FP64 ones keep the
+// compiler's choice.
+template <bool POL, typename R>
+constexpr int transfer_waves() { return sizeof(R) == 4 ? (POL ? 3 : 4) : 1; }
+
 template <bool POL, typename R, bool BATCH>
-__global__ void __launch_bounds__(64) k_transfer(GeoParams P, Batch B, DevGrid g, PlasmaParams pp, TransferParams tp,
+__global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(GeoParams P, Batch B, DevGrid g,
+                                                                             PlasmaParams pp, TransferParams tp,
                                                  long long start, int count, int refill_min,
                                                  const double *__restrict__ rec, const double *__restrict__ meta,
                                                  const int *__restrict__ nacc, int *__restrict__ queue) {
-    __shared__ double s_q[35 * 64];
+    __shared__ QuartLds<R> s_q;
     const int lane = threadIdx.x;
     RayWalk<R> w;
     int slot = -1, img = 0;
