@@ -28,7 +28,7 @@ __device__ __forceinline__ int find_block(const DevGrid &g, const double x[3]) {
     int idx[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        double u = (x[d] - g.t0[d]) / g.tb[d];
+        double u = (x[d] - g.t0[d]) * g.itb[d];
         if (!(u >= 0.0) || u >= (double)g.tn[d]) return -1;
         idx[d] = (int)floor(u);
         if (idx[d] >= g.tn[d]) return -1;
@@ -74,14 +74,14 @@ __device__ __forceinline__ int sample_grid(const DevGrid &g, int interp, const d
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         if (interp) {
-            double u = (x[d] - bm[d]) / bm[3 + d] - 0.5;
+            double u = (x[d] - bm[d]) * bm[3 + d] - 0.5;
             double fl = floor(u);
             i0[d] = (int)fl;
             w[d] = u - fl;
             if (i0[d] < 0) { i0[d] = 0; w[d] = 0.0; }
             if (i0[d] > nn[d] - 2) { i0[d] = nn[d] - 2; w[d] = 1.0; }
         } else {
-            int ii = (int)floor((x[d] - bm[d]) / bm[3 + d]);
+            int ii = (int)floor((x[d] - bm[d]) * bm[3 + d]);
             ii = ii < 0 ? 0 : (ii > nn[d] - 1 ? nn[d] - 1 : ii);
             i0[d] = ii;
             w[d] = 0.0;

@@ -101,17 +101,28 @@ __device__ __forceinline__ void coh_to_stokes(const KS<R> &k, const R e1[4], con
     R p[4], q[4];
     lower(k, e1, p);
     lower(k, e2, q);
-    R n11 = R(0), n22 = R(0), n12r = R(0), n12i = R(0);
+    // N_ab p^a p^b etc. through the vectors Re(N) p, Re(N) q and Im(N) q
+    R rp[4], rq[4], iq[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) {
+        rp[a] = R(0);
+        rq[a] = R(0);
+        iq[a] = R(0);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            R Rv = Rget(N, a, b);
-            n11 += p[a] * p[b] * Rv;
-            n22 += q[a] * q[b] * Rv;
-            n12r += p[a] * q[b] * Rv;
-            n12i += p[a] * q[b] * Iget(N, a, b);
+            rp[a] += Rget(N, a, b) * p[b];
+            rq[a] += Rget(N, a, b) * q[b];
+            if (a != b) iq[a] += Iget(N, a, b) * q[b];
         }
+    }
+    R n11 = R(0), n22 = R(0), n12r = R(0), n12i = R(0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        n11 += p[a] * rp[a];
+        n22 += q[a] * rq[a];
+        n12r += p[a] * rq[a];
+        n12i += p[a] * iq[a];
+    }
     S[0] = n11 + n22;
     S[1] = n11 - n22;
     S[2] = R(2) * n12r;
@@ -122,11 +133,17 @@ __device__ __forceinline__ void coh_to_stokes(const KS<R> &k, const R e1[4], con
 template <typename R>
 __device__ __forceinline__ void stokes_to_coh(const R e1[4], const R e2[4], const R S[4], Coh<R> &N) {
     R n11 = R(0.5) * (S[0] + S[1]), n22 = R(0.5) * (S[0] - S[1]), n12r = R(0.5) * S[2], n12i = R(-0.5) * S[3];
+    // Re N^ab = al^a e1^b + be^a e2^b with al = n11 e1 + n12r e2, be = n22 e2 + n12r e1
+    R al[4], be[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        al[a] = n11 * e1[a] + n12r * e2[a];
+        be[a] = n22 * e2[a] + n12r * e1[a];
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = a; b < 4; ++b)
-            N.r[sidx(a, b)] = n11 * e1[a] * e1[b] + n22 * e2[a] * e2[b] + n12r * (e1[a] * e2[b] + e2[a] * e1[b]);
+        for (int b = a; b < 4; ++b) N.r[sidx(a, b)] = al[a] * e1[b] + be[a] * e2[b];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll

@@ -1361,7 +1361,7 @@ bl_status bl_grid_create(bl_context *ctx, const bl_grid_desc *d, bl_grid **out) 
             if (std::fabs(ql - lo[c]) > 1e-9 * (1.0 + ql) || std::fabs(qh - hi[c]) > 1e-9 * (1.0 + qh))
                 return fail(ctx, BL_E_UNSUPPORTED, "block not aligned to the block lattice");
             bmeta[6 * b + c] = x0;
-            bmeta[6 * b + 3 + c] = (x1 - x0) / nn[c];
+            bmeta[6 * b + 3 + c] = nn[c] / (x1 - x0);
         }
         for (long long k = lo[2]; k < hi[2]; ++k)
             for (long long j = lo[1]; j < hi[1]; ++j)
@@ -1391,6 +1391,7 @@ bl_status bl_grid_create(bl_context *ctx, const bl_grid_desc *d, bl_grid **out) 
     for (int c = 0; c < 3; ++c) {
         g.t0[c] = bb[2 * c];
         g.tb[c] = tb[c];
+        g.itb[c] = 1.0 / tb[c];
         g.tn[c] = (int)tn[c];
     }
     g.nb = nb;
