@@ -263,6 +263,60 @@ __device__ __forceinline__ void pixel_observer(const Frame &fr, const GeoParams 
 // though rays hold from tens to thousands of pieces.  A wave takes new rays
 // once at least refill_min lanes are idle, or when none holds a ray.  Every
 // lane leaves the loop once the queue is exhausted and its ray is written.
+// ------------------------------------------------------------- ray order
+// The transfer takes the rays of a chunk longest first (by accepted steps),
+// so that the few very long rays near the photon ring start early and their
+// serial walks overlap the bulk instead of trailing it: a counting sort on
+// kOrderBins bins of n_acc / 8 (the last bin open-ended), in descending bin
+// order.  Each block of 256 rays counts and ranks its rays in LDS and makes
+// one global atomic per non-empty bin.  Slots without a ray for the transfer
+// (nacc < 0) go last.  The order within a bin is not deterministic; results
+// do not depend on it.
+constexpr int kOrderBins = 64;
+
+__device__ __forceinline__ int order_key(int na) { return na < 0 ? 0 : min(na >> 3, kOrderBins - 1); }
+
+__global__ void __launch_bounds__(256) k_order_hist(const int *__restrict__ nacc, int count, int *__restrict__ hist) {
+    __shared__ int lh[kOrderBins];
+    if (threadIdx.x < kOrderBins) lh[threadIdx.x] = 0;
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) atomicAdd(lh + order_key(nacc[i]), 1);
+    __syncthreads();
+    if (threadIdx.x < kOrderBins && lh[threadIdx.x]) atomicAdd(hist + threadIdx.x, lh[threadIdx.x]);
+}
+
+// Exclusive offsets in descending bin order (one block of kOrderBins threads).
+__global__ void __launch_bounds__(kOrderBins) k_order_scan(int *__restrict__ hist) {
+    __shared__ int sc[kOrderBins];
+    const int t = threadIdx.x;
+    const int key = kOrderBins - 1 - t;   // position t in descending order
+    const int own = hist[key];
+    sc[t] = own;
+    __syncthreads();
+    for (int off = 1; off < kOrderBins; off <<= 1) {
+        int v = t >= off ? sc[t - off] : 0;
+        __syncthreads();
+        sc[t] += v;
+        __syncthreads();
+    }
+    hist[key] = sc[t] - own;
+}
+
+__global__ void __launch_bounds__(256) k_order_scatter(const int *__restrict__ nacc, int count, int *__restrict__ offs,
+                                                       int *__restrict__ order) {
+    __shared__ int lh[kOrderBins], lb[kOrderBins];
+    if (threadIdx.x < kOrderBins) lh[threadIdx.x] = 0;
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int key = i < count ? order_key(nacc[i]) : 0;
+    const int rank = i < count ? atomicAdd(lh + key, 1) : 0;
+    __syncthreads();
+    if (threadIdx.x < kOrderBins) lb[threadIdx.x] = lh[threadIdx.x] ? atomicAdd(offs + threadIdx.x, lh[threadIdx.x]) : 0;
+    __syncthreads();
+    if (i < count) order[lb[key] + rank] = i;
+}
+
 // Resident waves per SIMD the FP32 transfer kernels are compiled for (the
 // register budget: 168 VGPRs for three, 128 for four); the FP64 ones keep the
 // compiler's choice.
@@ -274,7 +328,8 @@ __global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(Geo
                                                                              PlasmaParams pp, TransferParams tp,
                                                  long long start, int count, int refill_min,
                                                  const double *__restrict__ rec, const double *__restrict__ meta,
-                                                 const int *__restrict__ nacc, int *__restrict__ queue) {
+                                                 const int *__restrict__ nacc, const int *__restrict__ order,
+                                                 int *__restrict__ queue) {
     __shared__ QuartLds<R> s_q;
     const int lane = threadIdx.x;
     RayWalk<R> w;
@@ -290,10 +345,11 @@ __global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(Geo
             if (lane == leader) base = atomicAdd(queue, __popcll(need));
             base = __shfl(base, leader);
             if (slot < 0 && !done) {
-                int id = base + __popcll(need & ((1ull << lane) - 1ull));
-                if (id >= count) {
+                const int pos = base + __popcll(need & ((1ull << lane) - 1ull));
+                if (pos >= count) {
                     done = true;
                 } else {
+                    const int id = order[pos];
                     int na = nacc[id];
                     if (na >= 0) {   // -1: finished by the overflow kernel, -2: no pixel
                         slot = id;
@@ -838,6 +894,9 @@ struct bl_context {
     size_t rec_bytes = 0;
     double *d_meta = nullptr;
     int *d_nacc = nullptr;
+    int *d_order = nullptr;              // processing order of the chunk's slots
+    size_t order_bytes = 0;
+    int *d_hist = nullptr;               // counting-sort bins
     size_t slot_cap = 0;
     int *d_ovf_count = nullptr;
     int *d_ovf_list = nullptr;
@@ -1100,7 +1159,7 @@ void launch_transfer(bl_context *ctx, dim3 grd, const GeoParams &P, const Batch 
                      const PlasmaParams &pp, const TransferParams &tp, long long start, int count, int refill,
                      int *q) {
     hipLaunchKernelGGL((k_transfer<POL, R, BATCH>), grd, dim3(64), 0, ctx->stream, P, B, g, pp, tp, start, count,
-                       refill, ctx->d_rec, ctx->d_meta, ctx->d_nacc, q);
+                       refill, ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_order, q);
 }
 
 template <bool POL, typename R>
@@ -1149,6 +1208,11 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     if ((s = ensure(ctx, &ctx->d_meta, have_meta, (size_t)chunk * 2 * sizeof(double))) != BL_OK) return s;
     if ((s = ensure(ctx, &ctx->d_nacc, have_nacc, (size_t)chunk * sizeof(int))) != BL_OK) return s;
     ctx->slot_cap = std::min(have_meta / (2 * sizeof(double)), have_nacc / sizeof(int));
+    if ((s = ensure(ctx, &ctx->d_order, ctx->order_bytes, (size_t)chunk * sizeof(int))) != BL_OK) return s;
+    {
+        size_t have_hist = ctx->d_hist ? (size_t)kOrderBins * sizeof(int) : 0;
+        if ((s = ensure(ctx, &ctx->d_hist, have_hist, (size_t)kOrderBins * sizeof(int))) != BL_OK) return s;
+    }
     size_t one = sizeof(int);
     size_t have_cnt = ctx->d_ovf_count ? one : 0;
     if ((s = ensure(ctx, &ctx->d_ovf_count, have_cnt, one)) != BL_OK) return s;
@@ -1203,6 +1267,16 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
                 hipLaunchKernelGGL((k_geodesic<true, false>), grd, blk, 0, ctx->stream, P, B, start, count,
                                    ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_ovf_count, ctx->d_ovf_list, nullptr);
             }
+        }
+        HIPCHK(ctx, hipGetLastError());
+        {
+            TimedLaunch tl(ctx, BL_K_SETUP);
+            const unsigned nb = (unsigned)((count + 255) / 256);
+            hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(kOrderBins), 0, ctx->stream, ctx->d_hist, 0, kOrderBins);
+            hipLaunchKernelGGL(k_order_hist, dim3(nb), dim3(256), 0, ctx->stream, ctx->d_nacc, count, ctx->d_hist);
+            hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderBins), 0, ctx->stream, ctx->d_hist);
+            hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(256), 0, ctx->stream, ctx->d_nacc, count, ctx->d_hist,
+                               ctx->d_order);
         }
         HIPCHK(ctx, hipGetLastError());
         {
@@ -1309,6 +1383,8 @@ void bl_destroy(bl_context *ctx) {
     (void)hipFree(ctx->d_rec);
     (void)hipFree(ctx->d_meta);
     (void)hipFree(ctx->d_nacc);
+    (void)hipFree(ctx->d_order);
+    (void)hipFree(ctx->d_hist);
     (void)hipFree(ctx->d_ovf_count);
     (void)hipFree(ctx->d_ovf_list);
     (void)hipFree(ctx->d_big);
