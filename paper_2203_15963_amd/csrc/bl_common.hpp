@@ -19,6 +19,17 @@ constexpr double kKb = 1.380649e-16;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kEulerGamma = 0.57721566490153286061;
 
+// Exponential, logarithm and cube root for smooth fitting-formula terms: the
+// hardware transcendental unit in FP32 (relative error a few 1e-7 times the
+// argument's magnitude for exp, far inside the mixed form's tolerance), the
+// accurate library functions in FP64.
+__device__ __forceinline__ float fexp(float x) { return __expf(x); }
+__device__ __forceinline__ double fexp(double x) { return exp(x); }
+__device__ __forceinline__ float flog(float x) { return __logf(x); }
+__device__ __forceinline__ double flog(double x) { return log(x); }
+__device__ __forceinline__ float fcbrt(float x) { return __expf(__logf(x) * (1.0f / 3.0f)); }   // x > 0
+__device__ __forceinline__ double fcbrt(double x) { return cbrt(x); }
+
 // per-ray status codes (blgpu.h bl_ray_status); kRayOverflow is internal:
 // the ray needs more step records than the fast path keeps.
 enum : int { kRunning = 0, kEscaped = 1, kCaptured = 2, kMaxSteps = 3, kUnderflow = 4,

@@ -141,7 +141,7 @@ __device__ __forceinline__ void bessel_ratios(R x, R &r0, R &r1) {
     R K0, K1, K2;
     if (x <= R(2)) {
         R y = R(0.25) * x * x;
-        R L = log(R(0.5) * x) + R(kEulerGamma);
+        R L = flog(R(0.5) * x) + R(kEulerGamma);
         R t0 = R(1), t1 = R(1), H = R(0);
         R I0 = R(1), S0 = R(0), A = R(1), S1 = R(1);   // k = 0 terms (H_0 = 0, H_1 = 1)
 #pragma unroll
@@ -169,7 +169,7 @@ __device__ __forceinline__ void bessel_ratios(R x, R &r0, R &r1) {
             R em = expm1(t);
             R cm = em * em / (R(2) * (R(1) + em));   // cosh t - 1
             R c = R(1) + cm;
-            R wgt = exp(-x * cm);
+            R wgt = fexp(-x * cm);
             s0 += wgt;
             s1 += wgt * c;
             s2 += wgt * (R(2) * c * c - R(1));
@@ -205,10 +205,10 @@ __device__ __forceinline__ void thermal_coeffs(R ne, R th, R B, R nu, R cth, int
     R nuB = R(kNuB) * B;
     R nuc = R(1.5) * nuB * sth * th * th;
     R x = nu / nuc;
-    R x13 = cbrt(x);
+    R x13 = fcbrt(x);
     R xm13 = R(1) / x13;
     R xm23 = xm13 * xm13;
-    R E = exp(R(-1.8899) * x13);
+    R E = fexp(R(-1.8899) * x13);
     R pre = (ne * R(kPreI)) * nu / (th * th);
     R jI = pre * R(2.5651) * (R(1) + R(1.92) * xm13 + R(0.9977) * xm23) * E;
     R nu9 = nu * R(1e-9);
@@ -228,12 +228,12 @@ __device__ __forceinline__ void thermal_coeffs(R ne, R th, R B, R nu, R cth, int
     R r0, r1;
     bessel_ratios(R(1) / th, r0, r1);
     // powers of X through one logarithm: X^-1/2, X^-0.5175, X^-0.6, X^4/3
-    R lX = log(Xr);
-    R ism = exp(R(-0.5) * lX);
-    R e169 = R(0.011) * exp(R(-1.69) * ism);
-    R f0 = R(2.011) * exp(R(-19.78) * exp(R(-0.5175) * lX)) -
-           cos(R(39.89) * ism) * exp(R(-70.16) * exp(R(-0.6) * lX)) - e169;
-    R fm = f0 + (e169 - R(0.003135) * exp(R(4.0 / 3.0) * lX)) * R(0.5) *
+    R lX = flog(Xr);
+    R ism = fexp(R(-0.5) * lX);
+    R e169 = R(0.011) * fexp(R(-1.69) * ism);
+    R f0 = R(2.011) * fexp(R(-19.78) * fexp(R(-0.5175) * lX)) -
+           cos(R(39.89) * ism) * fexp(R(-70.16) * fexp(R(-0.6) * lX)) - e169;
+    R fm = f0 + (e169 - R(0.003135) * fexp(R(4.0 / 3.0) * lX)) * R(0.5) *
                     (R(1) + tanh(R(10) * (R(-0.4082690354408987) - R(0.5) * lX)));   // ln(0.6648)
     R gX = R(1) - R(0.11) * log1p(R(0.035) * Xr);
     R base = ne * R(kRotBase);
