@@ -108,6 +108,17 @@ struct Batch {
     int n_img, tw, th, pad;
 };
 
+// Rays that outgrow their record slot are traced again into extension slots
+// of cap_rec records (up to cap_rays per chunk): list[k] is the chunk slot of
+// extension k, of[slot] the extension of a slot (-1: none).
+struct ExtQueue {
+    int *count;
+    int *list;
+    int *of;
+    double *rec;
+    int cap_rays, cap_rec;
+};
+
 __device__ __forceinline__ int find_image(const Batch &B, long long gid) {
     int lo = 0, hi = B.n_img - 1;
     while (lo < hi) {

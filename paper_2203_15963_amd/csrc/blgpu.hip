@@ -181,11 +181,12 @@ __device__ __forceinline__ GeoParams lane_params(const GeoParams &P, const ImgDe
 
 // One lane per ray id of the chunk [start, start + count).  With WREC the step
 // records are written into the lane's slot; rays that outgrow the slot are
-// queued on ovf_list; ids of tile pixels outside their image get nacc = -2.
+// queued for an extension slot (X), or on ovf_list when those are taken; ids
+// of tile pixels outside their image get nacc = -2.
 template <bool WREC, bool BATCH>
 __global__ void __launch_bounds__(64) k_geodesic(GeoParams P, Batch B, long long start, int count,
                                                  double *__restrict__ rec, double *__restrict__ meta,
-                                                 int *__restrict__ nacc_out, int *__restrict__ ovf_count,
+                                                 int *__restrict__ nacc_out, ExtQueue X, int *__restrict__ ovf_count,
                                                  int *__restrict__ ovf_list, double *__restrict__ state_out) {
     int slot = blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= count) return;
@@ -212,8 +213,13 @@ __global__ void __launch_bounds__(64) k_geodesic(GeoParams P, Batch B, long long
         meta[2 * slot + 1] = n;
         if (o.status == kRayOverflow) {
             nacc_out[slot] = -1;
-            int idx = atomicAdd(ovf_count, 1);
-            ovf_list[idx] = (int)gid;
+            const int k = atomicAdd(X.count, 1);
+            if (k < X.cap_rays) {
+                X.list[k] = slot;
+            } else {
+                int idx = atomicAdd(ovf_count, 1);
+                ovf_list[idx] = (int)gid;
+            }
             return;
         }
         nacc_out[slot] = o.n_acc;
@@ -240,6 +246,48 @@ __global__ void __launch_bounds__(64) k_geodesic(GeoParams P, Batch B, long long
             state_out[pix * 8 + 7] = y[6];
         }
     }
+}
+
+// The rays queued for extension slots, traced again with X.cap_rec records
+// (one lane per queued ray); rays that outgrow those too go to ovf_list.
+template <bool BATCH>
+__global__ void __launch_bounds__(64) k_geodesic_ext(GeoParams P, Batch B, long long start, ExtQueue X,
+                                                     double *__restrict__ meta, int *__restrict__ nacc_out,
+                                                     int *__restrict__ ovf_count, int *__restrict__ ovf_list) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= min(*X.count, X.cap_rays)) return;
+    const int slot = X.list[k];
+    const long long gid = start + slot;
+    const int img = BATCH ? find_image(B, gid) : 0;
+    const ImgDev &im = B.imgs[img];
+    int pi, pj;
+    ray_pixel(B, im.cp.n, gid - (BATCH ? B.ray0[img] : 0), pi, pj);
+    GeoParams Q = lane_params<BATCH>(P, im);
+    Q.cap = X.cap_rec;
+    const long long NN = (long long)im.cp.n * im.cp.n;
+    const long long pix = (long long)pj * im.cp.n + pi;
+    double *aux = im.aux;
+    double y8[8], n;
+    camera_pixel(im.fr, im.cp, Q.a, Q.flat, pi, pj, y8, n);
+    double y[7] = {y8[0], y8[1], y8[2], y8[3], y8[5], y8[6], y8[7]};
+    double kt = y8[4];
+    TraceOut o;
+    trace_ray<true>(Q, y, kt, X.rec + (long long)k * X.cap_rec * kRecDoubles, X.cap_rec, o);
+    meta[2 * slot] = kt;
+    meta[2 * slot + 1] = n;
+    if (o.status == kRayOverflow) {
+        int idx = atomicAdd(ovf_count, 1);
+        ovf_list[idx] = (int)gid;
+        return;
+    }
+    X.of[slot] = k;
+    nacc_out[slot] = o.n_acc;
+    aux[BL_AUX_DT * NN + pix] = o.dt;
+    aux[BL_AUX_S * NN + pix] = o.s;
+    aux[BL_AUX_LAMBDA * NN + pix] = o.lambda;
+    aux[BL_AUX_NACC * NN + pix] = (double)o.n_acc;
+    aux[BL_AUX_NREJ * NN + pix] = (double)o.n_rej;
+    aux[BL_AUX_STATUS * NN + pix] = (double)o.status;
 }
 
 // Transfer results are already in camera units (I_nu = nu^3 I).
@@ -329,7 +377,7 @@ __global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(Geo
                                                  long long start, int count, int refill_min,
                                                  const double *__restrict__ rec, const double *__restrict__ meta,
                                                  const int *__restrict__ nacc, const int *__restrict__ order,
-                                                 int *__restrict__ queue) {
+                                                 ExtQueue X, int *__restrict__ queue) {
     __shared__ QuartLds<R> s_q;
     const int lane = threadIdx.x;
     RayWalk<R> w;
@@ -362,8 +410,10 @@ __global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(Geo
                             tl.L = im.L;
                             tl.nu_cam = im.cp.nu;
                         }
-                        begin_ray(w, rec + (long long)id * P.cap * kRecDoubles, na, meta[2 * id], meta[2 * id + 1],
-                                  tl);
+                        const int e = X.of[id];
+                        const double *rp = e >= 0 ? X.rec + (long long)e * X.cap_rec * kRecDoubles
+                                                  : rec + (long long)id * P.cap * kRecDoubles;
+                        begin_ray(w, rp, na, meta[2 * id], meta[2 * id + 1], tl);
                     }
                 }
             }
@@ -894,6 +944,8 @@ struct bl_context {
     size_t rec_bytes = 0;
     double *d_meta = nullptr;
     int *d_nacc = nullptr;
+    ExtQueue ext{};                      // extension slots of the current chunk
+    size_t ext_rec_bytes = 0, ext_of_bytes = 0;
     int *d_order = nullptr;              // processing order of the chunk's slots
     size_t order_bytes = 0;
     int *d_hist = nullptr;               // counting-sort bins
@@ -1159,7 +1211,7 @@ void launch_transfer(bl_context *ctx, dim3 grd, const GeoParams &P, const Batch 
                      const PlasmaParams &pp, const TransferParams &tp, long long start, int count, int refill,
                      int *q) {
     hipLaunchKernelGGL((k_transfer<POL, R, BATCH>), grd, dim3(64), 0, ctx->stream, P, B, g, pp, tp, start, count,
-                       refill, ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_order, q);
+                       refill, ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_order, ctx->ext, q);
 }
 
 template <bool POL, typename R>
@@ -1209,6 +1261,23 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     if ((s = ensure(ctx, &ctx->d_nacc, have_nacc, (size_t)chunk * sizeof(int))) != BL_OK) return s;
     ctx->slot_cap = std::min(have_meta / (2 * sizeof(double)), have_nacc / sizeof(int));
     if ((s = ensure(ctx, &ctx->d_order, ctx->order_bytes, (size_t)chunk * sizeof(int))) != BL_OK) return s;
+    // extension slots for rays longer than a record slot: 1024 per chunk of
+    // 2048 records (or max_steps + 1 if less), when that is more than a slot
+    {
+        ExtQueue &X = ctx->ext;
+        const int cap_rec = (int)std::min<long long>(2048, P.max_steps + 1);
+        X.cap_rays = cap_rec > P.cap ? 1024 : 0;
+        X.cap_rec = cap_rec;
+        size_t have = X.count ? sizeof(int) : 0;
+        if ((s = ensure(ctx, &X.count, have, sizeof(int))) != BL_OK) return s;
+        have = X.list ? (size_t)1024 * sizeof(int) : 0;
+        if ((s = ensure(ctx, &X.list, have, (size_t)1024 * sizeof(int))) != BL_OK) return s;
+        if ((s = ensure(ctx, &X.of, ctx->ext_of_bytes, (size_t)chunk * sizeof(int))) != BL_OK) return s;
+        if (X.cap_rays > 0 &&
+            (s = ensure(ctx, &X.rec, ctx->ext_rec_bytes,
+                        (size_t)X.cap_rays * X.cap_rec * kRecDoubles * sizeof(double))) != BL_OK)
+            return s;
+    }
     {
         size_t have_hist = ctx->d_hist ? (size_t)kOrderBins * sizeof(int) : 0;
         if ((s = ensure(ctx, &ctx->d_hist, have_hist, (size_t)kOrderBins * sizeof(int))) != BL_OK) return s;
@@ -1248,6 +1317,9 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     for (long long start = 0; start < total; start += chunk, ++ichunk) {
         int count = (int)std::min(chunk, total - start);
         dim3 grd((count + 63) / 64), blk(64);
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, ctx->ext.count, 0, 1);
+        hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, ctx->stream, ctx->ext.of, -1,
+                           count);
         {
             TimedLaunch tl(ctx, BL_K_GEODESIC);
             if (learned) {
@@ -1262,10 +1334,20 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
                                        ctx->d_ovf_count, ctx->d_ovf_list);
             } else if (batch) {
                 hipLaunchKernelGGL((k_geodesic<true, true>), grd, blk, 0, ctx->stream, P, B, start, count, ctx->d_rec,
-                                   ctx->d_meta, ctx->d_nacc, ctx->d_ovf_count, ctx->d_ovf_list, nullptr);
+                                   ctx->d_meta, ctx->d_nacc, ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list, nullptr);
             } else {
                 hipLaunchKernelGGL((k_geodesic<true, false>), grd, blk, 0, ctx->stream, P, B, start, count,
-                                   ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_ovf_count, ctx->d_ovf_list, nullptr);
+                                   ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list,
+                                   nullptr);
+            }
+            if (!learned && ctx->ext.cap_rays > 0) {
+                dim3 eg((unsigned)(ctx->ext.cap_rays / 64));
+                if (batch)
+                    hipLaunchKernelGGL((k_geodesic_ext<true>), eg, blk, 0, ctx->stream, P, B, start, ctx->ext,
+                                       ctx->d_meta, ctx->d_nacc, ctx->d_ovf_count, ctx->d_ovf_list);
+                else
+                    hipLaunchKernelGGL((k_geodesic_ext<false>), eg, blk, 0, ctx->stream, P, B, start, ctx->ext,
+                                       ctx->d_meta, ctx->d_nacc, ctx->d_ovf_count, ctx->d_ovf_list);
             }
         }
         HIPCHK(ctx, hipGetLastError());
@@ -1384,6 +1466,10 @@ void bl_destroy(bl_context *ctx) {
     (void)hipFree(ctx->d_meta);
     (void)hipFree(ctx->d_nacc);
     (void)hipFree(ctx->d_order);
+    (void)hipFree(ctx->ext.count);
+    (void)hipFree(ctx->ext.list);
+    (void)hipFree(ctx->ext.of);
+    (void)hipFree(ctx->ext.rec);
     (void)hipFree(ctx->d_hist);
     (void)hipFree(ctx->d_ovf_count);
     (void)hipFree(ctx->d_ovf_list);
@@ -1528,7 +1614,7 @@ bl_status bl_trace_geodesics(bl_context *ctx, const bl_camera *cam, const bl_spa
         int count = (int)std::min(chunk, total - start);
         TimedLaunch tl(ctx, BL_K_GEODESIC);
         hipLaunchKernelGGL((k_geodesic<false, false>), dim3((count + 63) / 64), dim3(64), 0, ctx->stream, P, B, start,
-                           count, nullptr, nullptr, nullptr, nullptr, nullptr, state_out);
+                           count, nullptr, nullptr, nullptr, ExtQueue{}, nullptr, nullptr, state_out);
         HIPCHK(ctx, hipGetLastError());
     }
     return BL_OK;

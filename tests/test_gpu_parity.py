@@ -211,10 +211,20 @@ def test_render_polarized_smr(ctx, oracle):
 
 
 def test_overflow_path_matches(ctx, oracle):
-    """With a tiny per-ray record slot every ray goes through the slow
-    single-wave path; the image must not change."""
+    """With a tiny per-ray record slot every long ray is traced again into an
+    extension slot; the image must not change."""
     w = _wl("c2_256_pol", 10, integrator=dict(record_cap=24))
     _compare_render(ctx, oracle, w)
+
+
+def test_overflow_beyond_extension_slots(ctx, oracle):
+    """More long rays than a chunk has extension slots (1024): the rest go to
+    the single-wave fallback.  Both paths in one render, against the oracle."""
+    w = _wl("c2_256_pol", 40, integrator=dict(record_cap=24))
+    img, aux, io, ao = _compare_render(ctx, oracle, w)
+    n_long = int((aux[5] + 2 > 24).sum())
+    _say("rays beyond the record slot", n_long)
+    assert n_long > 1024
 
 
 def test_edge_cases(ctx, oracle):
