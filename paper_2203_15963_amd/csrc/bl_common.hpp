@@ -108,12 +108,11 @@ struct Batch {
     int n_img, tw, th, pad;
 };
 
-// Rays that outgrow their record slot are traced again into extension slots
-// of cap_rec records (up to cap_rays per chunk): list[k] is the chunk slot of
-// extension k, of[slot] the extension of a slot (-1: none).
+// Rays that outgrow their record slot move to an extension slot of cap_rec
+// records (up to cap_rays per chunk, taken in order by count): of[slot] is
+// the extension of a slot (-1: none).
 struct ExtQueue {
     int *count;
-    int *list;
     int *of;
     double *rec;
     int cap_rays, cap_rec;

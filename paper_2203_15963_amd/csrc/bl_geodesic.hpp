@@ -138,6 +138,33 @@ __device__ __forceinline__ void write_final(double *rec, int nacc, const double 
     for (int m = 0; m < 7; ++m) r[16 + m] = f[m];
 }
 
+// A ray that has filled its record slot moves to an extension slot (when one
+// is free): its records so far are copied there and the integration goes on
+// with the extension's capacity.  Returns false when none is free.
+__device__ __forceinline__ bool move_to_extension(const ExtQueue *X, int slot, int nacc, double *&rec, int &cap) {
+    if (!X || X->cap_rec <= cap) return false;
+    const int k = atomicAdd(X->count, 1);
+    if (k >= X->cap_rays) return false;
+    double *nr = X->rec + (long long)k * X->cap_rec * kRecDoubles;
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 *src = reinterpret_cast<const d2 *>(rec);
+    d2 *dst = reinterpret_cast<d2 *>(nr);
+    const long long n2 = (long long)nacc * (kRecDoubles / 2);
+    long long i = 0;
+    for (; i + 8 <= n2; i += 8) {   // eight loads in flight
+        d2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[i + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) dst[i + u] = v[u];
+    }
+    for (; i < n2; ++i) dst[i] = src[i];
+    X->of[slot] = k;
+    rec = nr;
+    cap = X->cap_rec;
+    return true;
+}
+
 // Step log: one record per accepted step of the plain controller, the
 // features of the step's start state (x^mu, k_mu, spin, log|h| and log eps of
 // the previous accepted step; h0 and eps = 1 before the first) and the
@@ -159,7 +186,8 @@ struct StepLog {
 //   final record n_acc: [0..6] the final state, [16..22] dy/dlambda there
 template <bool WREC, bool LOG = false>
 __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], double kt, double *rec, int cap,
-                                          TraceOut &o, StepLog lg = StepLog{nullptr, 0, nullptr}) {
+                                          TraceOut &o, StepLog lg = StepLog{nullptr, 0, nullptr},
+                                          const ExtQueue *X = nullptr, int slot = -1) {
     const double a = P.a;
     const int flat = P.flat;
     double k1[7], y5[7], k7[7], ym[7];
@@ -179,7 +207,10 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
         dp_trial(P, y, kt, k1, h, y5, k7, ym, eps, bad);
         if (bad) { status = kNonfinite; break; }
         if (eps <= 1.0) {
-            if (WREC && nacc + 2 > cap) { status = kRayOverflow; break; }
+            if (WREC && nacc + 2 > cap && !move_to_extension(X, slot, nacc, rec, cap)) {
+                status = kRayOverflow;
+                break;
+            }
             double ds = fabs(h) * ds_dlambda(a, flat, ym, kt);
             if (WREC) write_record(rec, nacc, y, h, ym, ds, k1);
             if (LOG) {
@@ -237,7 +268,7 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
 template <bool WREC>
 __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool active, double y[7], double kt, double *rec,
                                                   int cap, TraceOut &o, const u32x4 *pk, const float *tail,
-                                                  u32x4 *stage) {
+                                                  u32x4 *stage, const ExtQueue *X = nullptr, int slot = -1) {
     const double a = P.a;
     const int flat = P.flat;
     double k1[7], y5[7], k7[7], ym[7];
@@ -274,7 +305,10 @@ __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool activ
         dp_trial(P, y, kt, k1, h, y5, k7, ym, eps, bad);
         if (bad) { status = kNonfinite; continue; }
         if (eps <= 1.0) {
-            if (WREC && nacc + 2 > cap) { status = kRayOverflow; continue; }
+            if (WREC && nacc + 2 > cap && !move_to_extension(X, slot, nacc, rec, cap)) {
+                status = kRayOverflow;
+                continue;
+            }
             double ds = fabs(h) * ds_dlambda(a, flat, ym, kt);
             if (WREC) write_record(rec, nacc, y, h, ym, ds, k1);
             ++nacc;

@@ -180,9 +180,9 @@ __device__ __forceinline__ GeoParams lane_params(const GeoParams &P, const ImgDe
 }
 
 // One lane per ray id of the chunk [start, start + count).  With WREC the step
-// records are written into the lane's slot; rays that outgrow the slot are
-// queued for an extension slot (X), or on ovf_list when those are taken; ids
-// of tile pixels outside their image get nacc = -2.
+// records are written into the lane's slot (moving to an extension slot of X
+// when it fills); rays that outgrow that too are queued on ovf_list; ids of
+// tile pixels outside their image get nacc = -2.
 template <bool WREC, bool BATCH>
 __global__ void __launch_bounds__(64) k_geodesic(GeoParams P, Batch B, long long start, int count,
                                                  double *__restrict__ rec, double *__restrict__ meta,
@@ -207,19 +207,15 @@ __global__ void __launch_bounds__(64) k_geodesic(GeoParams P, Batch B, long long
     double y[7] = {y8[0], y8[1], y8[2], y8[3], y8[5], y8[6], y8[7]};
     double kt = y8[4];
     TraceOut o;
-    trace_ray<WREC>(Q, y, kt, WREC ? rec + (long long)slot * Q.cap * kRecDoubles : nullptr, Q.cap, o);
+    trace_ray<WREC>(Q, y, kt, WREC ? rec + (long long)slot * Q.cap * kRecDoubles : nullptr, Q.cap, o,
+                    StepLog{nullptr, 0, nullptr}, &X, slot);
     if (WREC) {
         meta[2 * slot] = kt;
         meta[2 * slot + 1] = n;
         if (o.status == kRayOverflow) {
             nacc_out[slot] = -1;
-            const int k = atomicAdd(X.count, 1);
-            if (k < X.cap_rays) {
-                X.list[k] = slot;
-            } else {
-                int idx = atomicAdd(ovf_count, 1);
-                ovf_list[idx] = (int)gid;
-            }
+            int idx = atomicAdd(ovf_count, 1);
+            ovf_list[idx] = (int)gid;
             return;
         }
         nacc_out[slot] = o.n_acc;
@@ -246,48 +242,6 @@ __global__ void __launch_bounds__(64) k_geodesic(GeoParams P, Batch B, long long
             state_out[pix * 8 + 7] = y[6];
         }
     }
-}
-
-// The rays queued for extension slots, traced again with X.cap_rec records
-// (one lane per queued ray); rays that outgrow those too go to ovf_list.
-template <bool BATCH>
-__global__ void __launch_bounds__(64) k_geodesic_ext(GeoParams P, Batch B, long long start, ExtQueue X,
-                                                     double *__restrict__ meta, int *__restrict__ nacc_out,
-                                                     int *__restrict__ ovf_count, int *__restrict__ ovf_list) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= min(*X.count, X.cap_rays)) return;
-    const int slot = X.list[k];
-    const long long gid = start + slot;
-    const int img = BATCH ? find_image(B, gid) : 0;
-    const ImgDev &im = B.imgs[img];
-    int pi, pj;
-    ray_pixel(B, im.cp.n, gid - (BATCH ? B.ray0[img] : 0), pi, pj);
-    GeoParams Q = lane_params<BATCH>(P, im);
-    Q.cap = X.cap_rec;
-    const long long NN = (long long)im.cp.n * im.cp.n;
-    const long long pix = (long long)pj * im.cp.n + pi;
-    double *aux = im.aux;
-    double y8[8], n;
-    camera_pixel(im.fr, im.cp, Q.a, Q.flat, pi, pj, y8, n);
-    double y[7] = {y8[0], y8[1], y8[2], y8[3], y8[5], y8[6], y8[7]};
-    double kt = y8[4];
-    TraceOut o;
-    trace_ray<true>(Q, y, kt, X.rec + (long long)k * X.cap_rec * kRecDoubles, X.cap_rec, o);
-    meta[2 * slot] = kt;
-    meta[2 * slot + 1] = n;
-    if (o.status == kRayOverflow) {
-        int idx = atomicAdd(ovf_count, 1);
-        ovf_list[idx] = (int)gid;
-        return;
-    }
-    X.of[slot] = k;
-    nacc_out[slot] = o.n_acc;
-    aux[BL_AUX_DT * NN + pix] = o.dt;
-    aux[BL_AUX_S * NN + pix] = o.s;
-    aux[BL_AUX_LAMBDA * NN + pix] = o.lambda;
-    aux[BL_AUX_NACC * NN + pix] = (double)o.n_acc;
-    aux[BL_AUX_NREJ * NN + pix] = (double)o.n_rej;
-    aux[BL_AUX_STATUS * NN + pix] = (double)o.status;
 }
 
 // Transfer results are already in camera units (I_nu = nu^3 I).
@@ -495,7 +449,8 @@ __global__ void __launch_bounds__(256) k_geodesic_learned(GeoParams P, Batch B, 
                                                           const u32x4 *__restrict__ pk_g,
                                                           const float *__restrict__ tail_g, double *__restrict__ rec,
                                                           double *__restrict__ meta, int *__restrict__ nacc_out,
-                                                          int *__restrict__ ovf_count, int *__restrict__ ovf_list) {
+                                                          ExtQueue X, int *__restrict__ ovf_count,
+                                                          int *__restrict__ ovf_list) {
     __shared__ u32x4 s_pk[kPkFwd];
     __shared__ float s_tail[kTailN];
     __shared__ u32x4 s_stage[4][64 * 4];
@@ -519,7 +474,7 @@ __global__ void __launch_bounds__(256) k_geodesic_learned(GeoParams P, Batch B, 
     const double kt = y8[4];
     TraceOut o;
     trace_ray_learned<WREC>(Q, active, y, kt, WREC && active ? rec + (long long)slot * Q.cap * kRecDoubles : nullptr,
-                            Q.cap, o, s_pk, s_tail, s_stage[threadIdx.x >> 6]);
+                            Q.cap, o, s_pk, s_tail, s_stage[threadIdx.x >> 6], &X, slot);
     if (!active) return;
     const long long NN = (long long)im.cp.n * im.cp.n, pix = (long long)pj * im.cp.n + pi;
     double *aux = im.aux;
@@ -1270,8 +1225,6 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         X.cap_rec = cap_rec;
         size_t have = X.count ? sizeof(int) : 0;
         if ((s = ensure(ctx, &X.count, have, sizeof(int))) != BL_OK) return s;
-        have = X.list ? (size_t)1024 * sizeof(int) : 0;
-        if ((s = ensure(ctx, &X.list, have, (size_t)1024 * sizeof(int))) != BL_OK) return s;
         if ((s = ensure(ctx, &X.of, ctx->ext_of_bytes, (size_t)chunk * sizeof(int))) != BL_OK) return s;
         if (X.cap_rays > 0 &&
             (s = ensure(ctx, &X.rec, ctx->ext_rec_bytes,
@@ -1327,11 +1280,11 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
                 if (batch)
                     hipLaunchKernelGGL((k_geodesic_learned<true, true>), lg, lb, 0, ctx->stream, P, B, start, count,
                                        ctx->d_step_pk, ctx->d_step_tail, ctx->d_rec, ctx->d_meta, ctx->d_nacc,
-                                       ctx->d_ovf_count, ctx->d_ovf_list);
+                                       ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list);
                 else
                     hipLaunchKernelGGL((k_geodesic_learned<true, false>), lg, lb, 0, ctx->stream, P, B, start, count,
                                        ctx->d_step_pk, ctx->d_step_tail, ctx->d_rec, ctx->d_meta, ctx->d_nacc,
-                                       ctx->d_ovf_count, ctx->d_ovf_list);
+                                       ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list);
             } else if (batch) {
                 hipLaunchKernelGGL((k_geodesic<true, true>), grd, blk, 0, ctx->stream, P, B, start, count, ctx->d_rec,
                                    ctx->d_meta, ctx->d_nacc, ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list, nullptr);
@@ -1339,15 +1292,6 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
                 hipLaunchKernelGGL((k_geodesic<true, false>), grd, blk, 0, ctx->stream, P, B, start, count,
                                    ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list,
                                    nullptr);
-            }
-            if (!learned && ctx->ext.cap_rays > 0) {
-                dim3 eg((unsigned)(ctx->ext.cap_rays / 64));
-                if (batch)
-                    hipLaunchKernelGGL((k_geodesic_ext<true>), eg, blk, 0, ctx->stream, P, B, start, ctx->ext,
-                                       ctx->d_meta, ctx->d_nacc, ctx->d_ovf_count, ctx->d_ovf_list);
-                else
-                    hipLaunchKernelGGL((k_geodesic_ext<false>), eg, blk, 0, ctx->stream, P, B, start, ctx->ext,
-                                       ctx->d_meta, ctx->d_nacc, ctx->d_ovf_count, ctx->d_ovf_list);
             }
         }
         HIPCHK(ctx, hipGetLastError());
@@ -1467,7 +1411,6 @@ void bl_destroy(bl_context *ctx) {
     (void)hipFree(ctx->d_nacc);
     (void)hipFree(ctx->d_order);
     (void)hipFree(ctx->ext.count);
-    (void)hipFree(ctx->ext.list);
     (void)hipFree(ctx->ext.of);
     (void)hipFree(ctx->ext.rec);
     (void)hipFree(ctx->d_hist);
