@@ -169,7 +169,9 @@ __device__ __forceinline__ void stokes_to_coh(const R e1[4], const R e2[4], cons
 // Nothing cancels when the step is optically thin and B_nu dwarfs S0:
 // 1 - e^{-a} cosh L1 = -(expm1(L1 - a) + expm1(-L1 - a))/2 with a >= L1, and
 // when p - q <= 1 (so |p|, |q| <= 1) the divided differences are summed from
-// the Taylor series of C and Sh instead of differenced.  If alpha_I >= 100 the
+// the Taylor series of C and Sh instead of differenced; in that common case
+// cos L2 = C(q) and 1 - e^{-a} cosh L1 = -expm1(-a) - e^{-a} (C(p) - 1) come
+// from the series too, so one expm1 and one square root remain.  If alpha_I >= 100 the
 // result is B_nu e_I.  c = jI, jQ, jV, aI, aQ, aV, rQ, rV.
 template <typename R>
 __device__ __forceinline__ void kprime(const R c[8], const R v[4], R w[4]) {
@@ -196,6 +198,16 @@ __device__ __forceinline__ R sh_series(R x) {
 #pragma unroll
     for (int k = K; k >= 1; --k) s = (s + R(inv_factorial(2 * k + 1))) * x;
     return s + R(1);
+}
+
+// C(x) - 1 = sum_{k>=1} x^k / (2k)! for |x| <= 1
+template <typename R>
+__device__ __forceinline__ R cm1_series(R x) {
+    constexpr int K = sizeof(R) == 8 ? 10 : 6;
+    R s = R(0);
+#pragma unroll
+    for (int k = K; k >= 1; --k) s = (s + R(inv_factorial(2 * k))) * x;
+    return s;
 }
 
 // C[p,q] and Sh[p,q] from the series: sum_{k>=1} h_{k-1}(p,q) / (2k)! and
@@ -242,22 +254,29 @@ __device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
         L1s = L2s > R(0) ? ar * ar / L2s : R(0);
     }
     const R Th = L1s + L2s;
-    const R E = exp(-aI);
-    const R L1 = sqrt(L1s), L2 = sqrt(L2s);
-    const R ep = exp(L1 - aI), em = exp(-L1 - aI);   // e^{-aI} e^{+-L1}
-    R sn, cs;
-    sincos_r(L2, sn, cs);
-    const R shq = L2s <= R(1) ? sh_series(-L2s) : sn / L2;
-    const R shp = L1s <= R(1) ? E * sh_series(L1s) : R(0.5) * (ep - em) / L1;   // e^{-aI} Sh(p)
-    R dc, ds;   // e^{-aI} C[p,q], e^{-aI} Sh[p,q]
+    const R em1 = expm1(-aI);
+    const R E = R(1) + em1;   // e^{-aI}
+    R cs, shq, shp, dc, ds, fp;   // cos L2, Sh(q), e^{-a} Sh(p), e^{-a} C[p,q], e^{-a} Sh[p,q], 1 - e^{-a} cosh L1
     if (Th <= R(1)) {
+        // |p|, |q| <= 1: everything from the series; cos L2 = C(q)
+        cs = R(1) + cm1_series(-L2s);
+        shq = sh_series(-L2s);
+        shp = E * sh_series(L1s);
         dd_series(L1s, -L2s, dc, ds);
         dc *= E;
         ds *= E;
+        fp = -em1 - E * cm1_series(L1s);
     } else {
+        const R L1 = sqrt(L1s), L2 = sqrt(L2s);
+        R sn;
+        sincos_r(L2, sn, cs);
+        const R ep = exp(L1 - aI), em = exp(-L1 - aI);   // e^{-aI} e^{+-L1}
+        shq = L2s <= R(1) ? sh_series(-L2s) : sn / L2;
+        shp = L1s <= R(1) ? E * sh_series(L1s) : R(0.5) * (ep - em) / L1;
         const R iT = R(1) / Th;
         dc = (R(0.5) * (ep + em) - E * cs) * iT;
         ds = (shp - E * shq) * iT;
+        fp = R(-0.5) * (expm1(L1 - aI) + expm1(-L1 - aI));
     }
     const R ec = E * cs, es = E * shq;
 #pragma unroll
@@ -269,7 +288,6 @@ __device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
         const R u0 = den > R(0) ? X * X / den : R(0);
         // K' e_I = (0, aQ, 0, aV);  K' u for u = (u0, 0, -X, 0)
         const R ku1 = c[4] * u0 - c[7] * X, ku3 = c[5] * u0 + c[6] * X;
-        const R fp = R(-0.5) * (expm1(L1 - aI) + expm1(-L1 - aI));   // 1 - e^{-aI} cosh L1
         S[0] += Bnu * (fp - dc * u0);
         S[1] += Bnu * (shp * c[4] + ds * ku1);
         S[2] += Bnu * (dc * X);
