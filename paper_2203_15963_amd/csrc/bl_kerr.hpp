@@ -114,21 +114,31 @@ __device__ __forceinline__ void ks_deriv(R a, int flat, R x, R y, R z, const KS<
 //   dx^mu/dl = eta^mu nu k_nu - f l^mu (l.k),
 //   dk_c/dl = -1/2 d_c g^ab k_a k_b = 1/2 d_c f (l.k)^2 + f (l.k) (d_c l . k).
 __device__ __forceinline__ void geo_rhs(double a, int flat, const double *y, double kt, double *dy) {
-    KS<double> k = ks_point(a, flat, y[1], y[2], y[3]);
-    double kc[4] = {kt, y[4], y[5], y[6]};
-    double lk = l_dot_dn(k, kc);
-    double flk = k.f * lk;
+    // the metric functions and their derivatives from three reciprocals
+    const double x = y[1], yy = y[2], z = y[3];
+    const double r = ks_r(a, x, yy, z), r2 = r * r, a2 = a * a;
+    const double ir = 1.0 / r, ira = 1.0 / (r2 + a2);
+    const double D = r2 * r2 + a2 * z * z, iD = 1.0 / D;
+    const double l[3] = {(r * x + a * yy) * ira, (r * yy - a * x) * ira, z * ir};
+    const double f = flat ? 0.0 : 2.0 * r2 * r * iD;
+    const double lk = -kt + l[0] * y[4] + l[1] * y[5] + l[2] * y[6];   // l^mu k_mu
+    const double flk = f * lk;
     dy[0] = -kt + flk;
-    dy[1] = y[4] - flk * k.l[0];
-    dy[2] = y[5] - flk * k.l[1];
-    dy[3] = y[6] - flk * k.l[2];
+    dy[1] = y[4] - flk * l[0];
+    dy[2] = y[5] - flk * l[1];
+    dy[3] = y[6] - flk * l[2];
     // (no early return for the flat case: it keeps dy out of private memory)
-    KSDeriv<double> d;
-    ks_deriv(a, flat, y[1], y[2], y[3], k, d);
+    const double pos[3] = {x, yy, z};
+    const double dr[3] = {x * r2 * r * iD, yy * r2 * r * iD, z * r * (r2 + a2) * iD};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        double dlk = d.dl[c][0] * y[4] + d.dl[c][1] * y[5] + d.dl[c][2] * y[6];
-        dy[4 + c] = flat ? 0.0 : 0.5 * d.df[c] * lk * lk + flk * dlk;
+        const double dD = 4.0 * r2 * r * dr[c] + (c == 2 ? 2.0 * a2 * z : 0.0);
+        const double df = flat ? 0.0 : f * (3.0 * dr[c] * ir - dD * iD);
+        const double dl0 = (dr[c] * pos[0] + (c == 0 ? r : 0.0) + (c == 1 ? a : 0.0) - 2.0 * r * l[0] * dr[c]) * ira;
+        const double dl1 = (dr[c] * pos[1] + (c == 1 ? r : 0.0) - (c == 0 ? a : 0.0) - 2.0 * r * l[1] * dr[c]) * ira;
+        const double dl2 = ((c == 2 ? 1.0 : 0.0) - l[2] * dr[c]) * ir;
+        const double dlk = dl0 * y[4] + dl1 * y[5] + dl2 * y[6];
+        dy[4 + c] = flat ? 0.0 : 0.5 * df * lk * lk + flk * dlk;
     }
 }
 
