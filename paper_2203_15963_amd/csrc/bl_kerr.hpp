@@ -81,34 +81,6 @@ __device__ __forceinline__ R gdot(const KS<R> &k, const R A[4], const R B[4]) {
     return -A[0] * B[0] + A[1] * B[1] + A[2] * B[2] + A[3] * B[3] + k.f * l_dot_up(k, A) * l_dot_up(k, B);
 }
 
-// Spatial derivatives of r, f and l at (x, y, z): dr[c], df[c], dl[c][b]
-// (c = derivative direction, b = component x, y, z).  From
-// r^4 - (R^2 - a^2) r^2 - a^2 z^2 = 0 and the definitions of f and l.
-template <typename R>
-struct KSDeriv {
-    R dr[3], df[3], dl[3][3];
-};
-
-template <typename R>
-__device__ __forceinline__ void ks_deriv(R a, int flat, R x, R y, R z, const KS<R> &k, KSDeriv<R> &d) {
-    R r = k.r, r2 = r * r;
-    R D = r2 * r2 + a * a * z * z;
-    R iD = R(1) / D;
-    R ira = R(1) / (r2 + a * a);
-    R ir = R(1) / r;
-    d.dr[0] = x * r2 * r * iD;
-    d.dr[1] = y * r2 * r * iD;
-    d.dr[2] = z * r * (r2 + a * a) * iD;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        R dD = R(4) * r2 * r * d.dr[c] + (c == 2 ? R(2) * a * a * z : R(0));
-        d.df[c] = flat ? R(0) : k.f * (R(3) * d.dr[c] * ir - dD * iD);
-        d.dl[c][0] = (d.dr[c] * x + (c == 0 ? r : R(0)) + (c == 1 ? a : R(0)) - R(2) * r * k.l[0] * d.dr[c]) * ira;
-        d.dl[c][1] = (d.dr[c] * y + (c == 1 ? r : R(0)) - (c == 0 ? a : R(0)) - R(2) * r * k.l[1] * d.dr[c]) * ira;
-        d.dl[c][2] = ((c == 2 ? R(1) : R(0)) - k.l[2] * d.dr[c]) * ir;
-    }
-}
-
 // Geodesic right-hand side, eq. (geodesic), for the seven evolving components
 // y = (t, x, y, z, k_x, k_y, k_z) with the conserved k_t passed separately:
 //   dx^mu/dl = eta^mu nu k_nu - f l^mu (l.k),
@@ -159,79 +131,102 @@ __device__ __forceinline__ double ds_dlambda(double a, int flat, const double *y
 }
 
 // Connection contracted with the photon momentum, G^a_d = Gamma^a_{c d} k^c,
-// from scalars prepared once per point.  With C_ed = Gamma_{e c d} k^c =
-// 1/2 (T1_ed + T2_ed - T2_de),
-//   T1_ed = k^c d_c g_ed = (k.df) l_e l_d + f ((k.dl_e) l_d + l_e (k.dl_d)),
-//   T2_ed = d_d g_ec k^c = q (d_d f l_e + f d_d l_e) + f l_e (d_d l . k),
-// q = l_mu k^mu, d_t = 0, and G^a_d = g^{a e} C_ed.  conn_col gives one column
-// d of G at a time, which keeps 4x4 temporaries out of the registers when G is
-// applied immediately.
+// in factored form.  With C_ed = Gamma_{e c d} k^c =
+// 1/2 (k^c d_c g_ed + k^c d_d g_ec - k^c d_e g_dc), g = eta + f l l and
+// d_t = 0, and with the spatial derivatives of l written as
+// d_c l_b = dr_c m_b + K_cb (m and the constant-pattern K from differentiating
+// the definition of l), the terms collect into
+//   C_ed = l_e A_d + Y_e l_d + h Om_ed,   h = q f / 2,   Om_ed = d_d l_e - d_e l_d,
+//   A = (Df l + f Dl + q df + f W) / 2,   Y = (f Dl - q df - f W) / 2,
+// q = l_mu k^mu, Df = k^c d_c f, Dl_b = k^c d_c l_b, W_d = k^e d_d l_e
+// (A_t = Df/2, Y_t = 0, Om spatial and antisymmetric).  Raising the first
+// index with g^-1 = eta - f lu lu (lu = l^mu) gives
+//   G^a_d = lu^a B_d + Yt^a l_d + h Om_ad,
+//   B = (1 - f lu.l) A - h f (l.Om),   Yt = Y - f (lu.Y) lu,
+// where lu.l vanishes for the Kerr-Schild l and is kept only so that rounding
+// in l cannot matter.  G applied to a tensor then costs three row vectors and
+// a 3x3 antisymmetric product instead of 16 entries of G.
 template <typename R>
-struct ConnGeom {
-    R f, q, Df;
-    R l4[4], lu[4], Dl[4], W[4], df4[4];
-    R dl[3][3];
+struct ConnF {
+    R lu[4], l4[4], B[4], Yt[4];
+    R oxy, oxz, oyz;   // h Om for the spatial pairs (x, y), (x, z), (y, z)
 };
 
 template <typename R>
-__device__ __forceinline__ void conn_geom(R a, int flat, const R x[4], const R kc[4], ConnGeom<R> &c) {
-    KS<R> k = ks_point(a, flat, x[1], x[2], x[3]);
-    KSDeriv<R> d;
-    ks_deriv(a, flat, x[1], x[2], x[3], k, d);
-    R ku[4];
-    raise(k, kc, ku);
-    c.f = k.f;
-    c.q = l_dot_up(k, ku);
-    c.l4[0] = R(1);
+__device__ __forceinline__ void conn_geom(R a, int flat, const R x[4], const R kc[4], ConnF<R> &c) {
+    const R X = x[1], Yy = x[2], Z = x[3];
+    const R r = ks_r(a, X, Yy, Z), r2 = r * r, a2 = a * a;
+    const R ir = R(1) / r, ira = R(1) / (r2 + a2);
+    const R iD = R(1) / (r2 * r2 + a2 * Z * Z);
+    const R l[3] = {(r * X + a * Yy) * ira, (r * Yy - a * X) * ira, Z * ir};
+    const R r3iD = r2 * r * iD;
+    const R f = flat ? R(0) : R(2) * r3iD;
+    // k^mu = g^mu nu k_nu
+    const R flk = f * (-kc[0] + l[0] * kc[1] + l[1] * kc[2] + l[2] * kc[3]);
+    const R kt = -kc[0] + flk;
+    const R kv[3] = {kc[1] - flk * l[0], kc[2] - flk * l[1], kc[3] - flk * l[2]};
+    const R q = kt + l[0] * kv[0] + l[1] * kv[1] + l[2] * kv[2];
+    // d_c r and m
+    const R dr[3] = {X * r3iD, Yy * r3iD, Z * r * (r2 + a2) * iD};
+    const R m[3] = {(X - R(2) * r * l[0]) * ira, (Yy - R(2) * r * l[1]) * ira, -l[2] * ir};
+    const R mk = m[0] * kv[0] + m[1] * kv[1] + m[2] * kv[2];
+    const R drk = dr[0] * kv[0] + dr[1] * kv[1] + dr[2] * kv[2];
+    const R W[3] = {dr[0] * mk + ira * (r * kv[0] - a * kv[1]), dr[1] * mk + ira * (a * kv[0] + r * kv[1]),
+                    dr[2] * mk + ir * kv[2]};
+    const R Dl[3] = {m[0] * drk + ira * (r * kv[0] + a * kv[1]), m[1] * drk + ira * (r * kv[1] - a * kv[0]),
+                     m[2] * drk + ir * kv[2]};
+    // d_c f = f (3/r - 4 r^3/D) d_c r - [c = z] 2 f a^2 z / D
+    const R g1 = f * (R(3) * ir - R(4) * r3iD);
+    const R df[3] = {g1 * dr[0], g1 * dr[1], g1 * dr[2] - R(2) * f * a2 * Z * iD};
+    const R Df = df[0] * kv[0] + df[1] * kv[1] + df[2] * kv[2];
+    const R h = R(0.5) * q * f;
+    const R oxy = dr[1] * m[0] - dr[0] * m[1] + R(2) * a * ira;
+    const R oxz = dr[2] * m[0] - dr[0] * m[2];
+    const R oyz = dr[2] * m[1] - dr[1] * m[2];
+    // l.Om (spatial components) and lu.l
+    const R om[3] = {-l[1] * oxy - l[2] * oxz, l[0] * oxy - l[2] * oyz, l[0] * oxz + l[1] * oyz};
+    const R s0 = R(-1) + l[0] * l[0] + l[1] * l[1] + l[2] * l[2];
+    const R cA = R(1) - f * s0, hf = h * f;
     c.lu[0] = R(-1);
-    c.Dl[0] = R(0);
-    c.W[0] = R(0);
-    c.df4[0] = R(0);
+    c.l4[0] = R(1);
+    c.B[0] = cA * R(0.5) * Df;
+    R lY = R(0), Yb[3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        c.l4[1 + b] = k.l[b];
-        c.lu[1 + b] = k.l[b];
-        c.df4[1 + b] = d.df[b];
-        c.Dl[1 + b] = d.dl[0][b] * ku[1] + d.dl[1][b] * ku[2] + d.dl[2][b] * ku[3];
-        c.W[1 + b] = d.dl[b][0] * ku[1] + d.dl[b][1] * ku[2] + d.dl[b][2] * ku[3];
-#pragma unroll
-        for (int e = 0; e < 3; ++e) c.dl[b][e] = d.dl[b][e];
+        const R fD = f * Dl[b], qd = q * df[b], fW = f * W[b];
+        Yb[b] = R(0.5) * (fD - qd - fW);
+        lY += l[b] * Yb[b];
+        c.lu[1 + b] = l[b];
+        c.l4[1 + b] = l[b];
+        c.B[1 + b] = cA * R(0.5) * (Df * l[b] + fD + qd + fW) - hf * om[b];
     }
-    c.Df = d.df[0] * ku[1] + d.df[1] * ku[2] + d.df[2] * ku[3];
+    c.Yt[0] = f * lY;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) c.Yt[1 + b] = Yb[b] - f * lY * l[b];
+    c.oxy = h * oxy;
+    c.oxz = h * oxz;
+    c.oyz = h * oyz;
 }
 
+// (h Om)_ad n^d for spatial a (1..3), n = (n1, n2, n3) the spatial part of a column
 template <typename R>
-__device__ __forceinline__ void conn_col(const ConnGeom<R> &c, int dd, R Gc[4]) {
-    R C[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        R T1 = c.Df * c.l4[e] * c.l4[dd] + c.f * (c.Dl[e] * c.l4[dd] + c.l4[e] * c.Dl[dd]);
-        R T2ed = (dd == 0) ? R(0)
-                           : c.q * (c.df4[dd] * c.l4[e] + c.f * (e == 0 ? R(0) : c.dl[dd - 1][e - 1])) +
-                                 c.f * c.l4[e] * c.W[dd];
-        R T2de = (e == 0) ? R(0)
-                          : c.q * (c.df4[e] * c.l4[dd] + c.f * (dd == 0 ? R(0) : c.dl[e - 1][dd - 1])) +
-                                c.f * c.l4[dd] * c.W[e];
-        C[e] = R(0.5) * (T1 + T2ed - T2de);
-    }
-    R lc = c.lu[0] * C[0] + c.lu[1] * C[1] + c.lu[2] * C[2] + c.lu[3] * C[3];
-    Gc[0] = -C[0] - c.f * c.lu[0] * lc;
-    Gc[1] = C[1] - c.f * c.lu[1] * lc;
-    Gc[2] = C[2] - c.f * c.lu[2] * lc;
-    Gc[3] = C[3] - c.f * c.lu[3] * lc;
+__device__ __forceinline__ R conn_om(const ConnF<R> &c, int a, R n1, R n2, R n3) {
+    return a == 1 ? c.oxy * n2 + c.oxz * n3 : (a == 2 ? c.oyz * n3 - c.oxy * n1 : -(c.oxz * n1 + c.oyz * n2));
 }
 
 // Full G (row-major a, d), FP64, for checking.
 __device__ __forceinline__ void conn_k(double a, int flat, const double x[4], const double kc[4], double G[16]) {
-    ConnGeom<double> c;
+    ConnF<double> c;
     conn_geom(a, flat, x, kc, c);
 #pragma unroll
-    for (int dd = 0; dd < 4; ++dd) {
-        double Gc[4];
-        conn_col(c, dd, Gc);
+    for (int aa = 0; aa < 4; ++aa)
 #pragma unroll
-        for (int aa = 0; aa < 4; ++aa) G[4 * aa + dd] = flat ? 0.0 : Gc[aa];
-    }
+        for (int dd = 0; dd < 4; ++dd) {
+            double v = c.lu[aa] * c.B[dd] + c.Yt[aa] * c.l4[dd];
+            if (aa > 0 && dd > 0)
+                v += conn_om(c, aa, dd == 1 ? 1.0 : 0.0, dd == 2 ? 1.0 : 0.0, dd == 3 ? 1.0 : 0.0);
+            G[4 * aa + dd] = flat ? 0.0 : v;
+        }
 }
 
 // 4-velocity from CKS normal-frame components ut at point k:

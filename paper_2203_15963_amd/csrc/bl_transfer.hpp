@@ -50,26 +50,48 @@ __device__ __forceinline__ R Iget(const Coh<R> &N, int a, int b) {
 }
 
 // dN^ab/dlambda = -(G^a_d N^db + G^b_d N^ad), the parallel transport of N,
-// with the connection applied one column of G at a time.
+// with G in the factored form of conn_geom:
+//   (G N)^ab = lu^a (B.N)^b + Yt^a (l.N)^b + (h Om N)^ab,
+// and dRe N = -(G R + (G R)^T), dIm N = -(G I - (G I)^T) for the symmetric
+// real part R and the antisymmetric imaginary part I.
 template <typename R>
-__device__ __forceinline__ void transport_apply(const ConnGeom<R> &c, const Coh<R> &N, Coh<R> &dN) {
+__device__ __forceinline__ void transport_apply(const ConnF<R> &c, const Coh<R> &N, Coh<R> &dN) {
+    R bR[4], bI[4], lR[4], lI[4];
 #pragma unroll
-    for (int m = 0; m < 10; ++m) dN.r[m] = R(0);
+    for (int b = 0; b < 4; ++b) {
+        bR[b] = R(0);
+        bI[b] = R(0);
+        lR[b] = R(0);
+        lI[b] = R(0);
 #pragma unroll
-    for (int m = 0; m < 6; ++m) dN.i[m] = R(0);
-#pragma unroll
-    for (int dd = 0; dd < 4; ++dd) {
-        R Gc[4];
-        conn_col(c, dd, Gc);
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = a; b < 4; ++b) dN.r[sidx(a, b)] -= Gc[a] * Rget(N, dd, b) + Gc[b] * Rget(N, a, dd);
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = a + 1; b < 4; ++b) dN.i[aidx(a, b)] -= Gc[a] * Iget(N, dd, b) + Gc[b] * Iget(N, a, dd);
+        for (int d = 0; d < 4; ++d) {
+            bR[b] += c.B[d] * Rget(N, d, b);
+            lR[b] += c.l4[d] * Rget(N, d, b);
+            if (d != b) {
+                bI[b] += c.B[d] * Iget(N, d, b);
+                lI[b] += c.l4[d] * Iget(N, d, b);
+            }
+        }
     }
+    // (G R)^ab and (G I)^ab
+    auto GR = [&](int a, int b) -> R {
+        R v = c.lu[a] * bR[b] + c.Yt[a] * lR[b];
+        if (a > 0) v += conn_om(c, a, Rget(N, 1, b), Rget(N, 2, b), Rget(N, 3, b));
+        return v;
+    };
+    auto GI = [&](int a, int b) -> R {
+        R v = c.lu[a] * bI[b] + c.Yt[a] * lI[b];
+        if (a > 0) v += conn_om(c, a, Iget(N, 1, b), Iget(N, 2, b), Iget(N, 3, b));
+        return v;
+    };
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a; b < 4; ++b) dN.r[sidx(a, b)] = -(GR(a, b) + GR(b, a));
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a + 1; b < 4; ++b) dN.i[aidx(a, b)] = GI(b, a) - GI(a, b);
 }
 
 // One explicit-midpoint transport step of length dl: predictor with the
@@ -77,7 +99,7 @@ __device__ __forceinline__ void transport_apply(const ConnGeom<R> &c, const Coh<
 template <typename R>
 __device__ __forceinline__ void transport_step(R a, int flat, const R ya[8], const R yb[8], R dl, Coh<R> &N) {
     if (flat) return;   // the connection vanishes
-    ConnGeom<R> c;
+    ConnF<R> c;
     Coh<R> d, h;
     conn_geom(a, flat, ya, ya + 4, c);
     transport_apply(c, N, d);
@@ -348,6 +370,7 @@ struct RayWalk {
     int st;              // next step to open (counting down), -1: all opened
     int p;               // next piece of the open step (counting down), -1: none
     int nsub;
+    double inv_nsub;     // 1 / nsub
     bool inb, started;
     R dl, pdl;           // affine length of the open step's pieces, and of the previous piece
     R I, tau, Ij;
@@ -369,6 +392,7 @@ __device__ __forceinline__ void begin_ray(RayWalk<R> &w, const double *rec, int 
     w.st = n_acc - 1;
     w.p = -1;
     w.nsub = 0;
+    w.inv_nsub = 1.0;
     w.inb = false;
     w.started = false;
     w.dl = w.pdl = R(0);
@@ -431,7 +455,8 @@ __device__ __forceinline__ void next_step(RayWalk<R> &w, const GeoParams &P, con
         }
     }
     w.nsub = nsub;
-    w.dl = (R)(fabs(h) / (double)nsub);
+    w.inv_nsub = 1.0 / (double)nsub;
+    w.dl = (R)(fabs(h) * w.inv_nsub);
     w.nrec += nsub;
     w.p = nsub - 1;
     --w.st;
@@ -473,14 +498,14 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
         ys[5] = rr[4]; ys[6] = rr[5]; ys[7] = rr[6];
         ys[4] = (double)w.kt;
     } else {
-        quartic_at(s_q, off, ((double)p + 0.5) / (double)w.nsub, ys, (double)w.kt);
+        quartic_at(s_q, off, ((double)p + 0.5) * w.inv_nsub, ys, (double)w.kt);
     }
     if (p == 0) {
 #pragma unroll
         for (int m = 0; m < 7; ++m) yb[m < 4 ? m : m + 1] = s_q.y0[m * 64 + off];
         yb[4] = (double)w.kt;
     } else {
-        quartic_at(s_q, off, (double)p / (double)w.nsub, yb, (double)w.kt);
+        quartic_at(s_q, off, (double)p * w.inv_nsub, yb, (double)w.kt);
     }
     w.p = p - 1;
     Sample<R> smp;
