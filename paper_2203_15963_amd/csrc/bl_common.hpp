@@ -29,6 +29,27 @@ __device__ __forceinline__ float flog(float x) { return __logf(x); }
 __device__ __forceinline__ double flog(double x) { return log(x); }
 __device__ __forceinline__ float fcbrt(float x) { return __expf(__logf(x) * (1.0f / 3.0f)); }   // x > 0
 __device__ __forceinline__ double fcbrt(double x) { return cbrt(x); }
+// e^x - 1 with relative accuracy near zero: in FP32 the Taylor polynomial
+// through x^8/8! for |x| < 0.35 (truncation below 1e-9 relative), the hardware
+// exponential minus one elsewhere; in FP64 the library function.
+__device__ __forceinline__ float fexpm1(float x) {
+    float p = 1.0f / 40320.0f;
+    p = p * x + 1.0f / 5040.0f;
+    p = p * x + 1.0f / 720.0f;
+    p = p * x + 1.0f / 120.0f;
+    p = p * x + 1.0f / 24.0f;
+    p = p * x + 1.0f / 6.0f;
+    p = p * x + 0.5f;
+    p = p * x + 1.0f;
+    return fabsf(x) < 0.35f ? p * x : __expf(x) - 1.0f;
+}
+__device__ __forceinline__ double fexpm1(double x) { return expm1(x); }
+// cos for arguments of moderate size: the hardware unit in FP32, the library in FP64
+__device__ __forceinline__ float fcos(float x) { return __cosf(x); }
+__device__ __forceinline__ double fcos(double x) { return cos(x); }
+// ln(1 + x) for x >= 0 where only absolute accuracy is needed
+__device__ __forceinline__ float flog1p_abs(float x) { return __logf(1.0f + x); }
+__device__ __forceinline__ double flog1p_abs(double x) { return log1p(x); }
 
 // per-ray status codes (blgpu.h bl_ray_status); kRayOverflow is internal:
 // the ray needs more step records than the fast path keeps.

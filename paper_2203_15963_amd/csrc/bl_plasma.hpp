@@ -36,74 +36,125 @@ __device__ __forceinline__ int find_block(const DevGrid &g, const double x[3]) {
     return g.table[(idx[2] * g.tn[1] + idx[1]) * g.tn[0] + idx[0]];
 }
 
-// One cell's 8 primitives (32 or 64 contiguous bytes, 16-byte aligned) in
-// 16-byte vector loads, accumulated with weight wt.
+// Cells hold 8 primitives (32 or 64 contiguous bytes, 16-byte aligned) and
+// are read with 16-byte vector loads.
 typedef float gf4 __attribute__((ext_vector_type(4)));
 typedef double gd2 __attribute__((ext_vector_type(2)));
-template <typename R>
-__device__ __forceinline__ void load_cell(const float *base, long long off, R acc[8], R wt) {
-    const gf4 *p = reinterpret_cast<const gf4 *>(base + off * 8);
-    const gf4 v0 = p[0], v1 = p[1];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        acc[m] += wt * (R)v0[m];
-        acc[4 + m] += wt * (R)v1[m];
-    }
+
+// A block's origin and inverse cell sizes (six doubles, 16-byte aligned).
+__device__ __forceinline__ void block_meta(const DevGrid &g, int b, double o[3], double is[3]) {
+    const gd2 *p = reinterpret_cast<const gd2 *>(g.bmeta + 6 * (long long)b);
+    const gd2 m0 = p[0], m1 = p[1], m2 = p[2];
+    o[0] = m0[0];
+    o[1] = m0[1];
+    o[2] = m1[0];
+    is[0] = m1[1];
+    is[1] = m2[0];
+    is[2] = m2[1];
 }
+
+// Trilinear weights of the eight corners, corner q = (di, dj, dk) = (q & 1, (q >> 1) & 1, q >> 2).
 template <typename R>
-__device__ __forceinline__ void load_cell(const double *base, long long off, R acc[8], R wt) {
-    const gd2 *p = reinterpret_cast<const gd2 *>(base + off * 8);
+__device__ __forceinline__ void corner_weights(const R w[3], R wt[8]) {
+    const R x0 = R(1) - w[0], y0 = R(1) - w[1], z0 = R(1) - w[2];
+    const R wxy[4] = {x0 * y0, w[0] * y0, x0 * w[1], w[0] * w[1]};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const gd2 v = p[q];
-        acc[2 * q] += wt * (R)v[0];
-        acc[2 * q + 1] += wt * (R)v[1];
+    for (int q = 0; q < 8; ++q) wt[q] = wxy[q & 3] * ((q >> 2) ? w[2] : z0);
+}
+
+// Weighted sum of the eight corner cells of cell c0 (strides 1, sy, sz).  The
+// corners are read in groups of G whose loads are all issued before any is
+// used, so a lane waits for one round trip per group instead of one per
+// corner (G = 4 for the FP32 grid, 2 for the FP64 grid: 32 registers of
+// cell data in flight either way; 1 for the FP64 grid in the all-FP64 form,
+// whose register budget is spent elsewhere).
+template <int G, typename T, typename R>
+__device__ __forceinline__ void trilerp(const T *base, long long c0, long long sy, long long sz, const R w[3],
+                                        R prim[8]) {
+    typedef T tv __attribute__((ext_vector_type(16 / sizeof(T))));
+    constexpr int NV = 8 * sizeof(T) / 16;   // vectors per cell
+    constexpr int NE = 16 / sizeof(T);       // elements per vector
+    R wt[8];
+    corner_weights(w, wt);
+#pragma unroll
+    for (int g0 = 0; g0 < 8; g0 += G) {
+        tv v[G][NV];
+#pragma unroll
+        for (int qq = 0; qq < G; ++qq) {
+            const int q = g0 + qq;
+            const tv *p = reinterpret_cast<const tv *>(base + (c0 + (q >> 2) * sz + ((q >> 1) & 1) * sy + (q & 1)) * 8);
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[qq][k] = p[k];
+        }
+#pragma unroll
+        for (int qq = 0; qq < G; ++qq)
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+#pragma unroll
+                for (int e = 0; e < NE; ++e) prim[k * NE + e] += wt[g0 + qq] * (R)v[qq][k][e];
     }
 }
 
 // Interpolated primitives at x; returns the block id or -1 (vacuum).  Block
-// search and weights in double, accumulation in R.
+// search and cell location in double, weights and accumulation in R.  Blocks
+// have at least two cells per axis (checked when the grid is made), so the
+// clamped corner indices i0, i0 + 1 always lie inside the block and all eight
+// corners are read, those of weight zero included.
 template <typename R>
 __device__ __forceinline__ int sample_grid(const DevGrid &g, int interp, const double x[3], R prim[8]) {
-    int b = find_block(g, x);
+    const int b = find_block(g, x);
     if (b < 0) return -1;
-    const double *bm = g.bmeta + 6 * b;
-    int nn[3] = {g.bnx, g.bny, g.bnz};
-    int i0[3];
-    double w[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        if (interp) {
-            double u = (x[d] - bm[d]) * bm[3 + d] - 0.5;
-            double fl = floor(u);
-            i0[d] = (int)fl;
-            w[d] = u - fl;
-            if (i0[d] < 0) { i0[d] = 0; w[d] = 0.0; }
-            if (i0[d] > nn[d] - 2) { i0[d] = nn[d] - 2; w[d] = 1.0; }
-        } else {
-            int ii = (int)floor((x[d] - bm[d]) * bm[3 + d]);
-            ii = ii < 0 ? 0 : (ii > nn[d] - 1 ? nn[d] - 1 : ii);
-            i0[d] = ii;
-            w[d] = 0.0;
-        }
-    }
+    double o[3], is[3];
+    block_meta(g, b, o, is);
+    const int nn[3] = {g.bnx, g.bny, g.bnz};
 #pragma unroll
     for (int m = 0; m < 8; ++m) prim[m] = R(0);
-    long long bbase = (long long)b * g.bnx * g.bny * g.bnz;
+    const long long sy = g.bnx, sz = (long long)g.bny * g.bnx;
+    const long long cb = (long long)b * g.bnz * sz;
+    if (!interp) {
+        int i0[3];
 #pragma unroll
-    for (int dk = 0; dk < 2; ++dk)
+        for (int d = 0; d < 3; ++d) {
+            const int ii = (int)floor((x[d] - o[d]) * is[d]);
+            i0[d] = ii < 0 ? 0 : (ii > nn[d] - 1 ? nn[d] - 1 : ii);
+        }
+        const long long c0 = cb + i0[2] * sz + i0[1] * sy + i0[0];
+        if (g.dtype != 0) {
+            const gf4 *p = reinterpret_cast<const gf4 *>((const float *)g.prims + c0 * 8);
+            const gf4 v0 = p[0], v1 = p[1];
 #pragma unroll
-        for (int dj = 0; dj < 2; ++dj)
-#pragma unroll
-            for (int di = 0; di < 2; ++di) {
-                double wt = (di ? w[0] : 1.0 - w[0]) * (dj ? w[1] : 1.0 - w[1]) * (dk ? w[2] : 1.0 - w[2]);
-                if (wt == 0.0) continue;
-                long long off = bbase + ((long long)(i0[2] + dk) * g.bny + (i0[1] + dj)) * g.bnx + (i0[0] + di);
-                if (g.dtype == 0)
-                    load_cell<R>((const double *)g.prims, off, prim, (R)wt);
-                else
-                    load_cell<R>((const float *)g.prims, off, prim, (R)wt);
+            for (int m = 0; m < 4; ++m) {
+                prim[m] = (R)v0[m];
+                prim[4 + m] = (R)v1[m];
             }
+        } else {
+            const gd2 *p = reinterpret_cast<const gd2 *>((const double *)g.prims + c0 * 8);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const gd2 v = p[k];
+                prim[2 * k] = (R)v[0];
+                prim[2 * k + 1] = (R)v[1];
+            }
+        }
+        return b;
+    }
+    int i0[3];
+    R w[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double u = (x[d] - o[d]) * is[d] - 0.5;
+        const double fl = floor(u);
+        const int i = (int)fl;
+        const R wd = (R)(u - fl);
+        const bool lo = i < 0, hi = i > nn[d] - 2;
+        i0[d] = lo ? 0 : (hi ? nn[d] - 2 : i);
+        w[d] = lo ? R(0) : (hi ? R(1) : wd);
+    }
+    const long long c0 = cb + i0[2] * sz + i0[1] * sy + i0[0];
+    if (g.dtype != 0)
+        trilerp<4>((const float *)g.prims, c0, sy, sz, w, prim);
+    else
+        trilerp<sizeof(R) == 8 ? 1 : 2>((const double *)g.prims, c0, sy, sz, w, prim);
     return b;
 }
 
@@ -212,7 +263,7 @@ __device__ __forceinline__ void thermal_coeffs(R ne, R th, R B, R nu, R cth, int
     R pre = (ne * R(kPreI)) * nu / (th * th);
     R jI = pre * R(2.5651) * (R(1) + R(1.92) * xm13 + R(0.9977) * xm23) * E;
     R nu9 = nu * R(1e-9);
-    R Bnu = R(kPlanck9) * nu9 * nu9 * nu9 / expm1(R(kHoverMec2) * nu / th);
+    R Bnu = R(kPlanck9) * nu9 * nu9 * nu9 / fexpm1(R(kHoverMec2) * nu / th);
     R iB = R(1) / Bnu;
     out[0] = jI;
     out[3] = jI * iB;
@@ -232,10 +283,11 @@ __device__ __forceinline__ void thermal_coeffs(R ne, R th, R B, R nu, R cth, int
     R ism = fexp(R(-0.5) * lX);
     R e169 = R(0.011) * fexp(R(-1.69) * ism);
     R f0 = R(2.011) * fexp(R(-19.78) * fexp(R(-0.5175) * lX)) -
-           cos(R(39.89) * ism) * fexp(R(-70.16) * fexp(R(-0.6) * lX)) - e169;
-    R fm = f0 + (e169 - R(0.003135) * fexp(R(4.0 / 3.0) * lX)) * R(0.5) *
-                    (R(1) + tanh(R(10) * (R(-0.4082690354408987) - R(0.5) * lX)));   // ln(0.6648)
-    R gX = R(1) - R(0.11) * log1p(R(0.035) * Xr);
+           fcos(R(39.89) * ism) * fexp(R(-70.16) * fexp(R(-0.6) * lX)) - e169;
+    // (1 + tanh y) / 2 = 1 / (1 + e^{-2y}), y = 10 (ln 0.6648 - lX / 2)
+    R fm = f0 + (e169 - R(0.003135) * fexp(R(4.0 / 3.0) * lX)) /
+                    (R(1) + fexp(R(-20) * (R(-0.4082690354408987) - R(0.5) * lX)));
+    R gX = R(1) - R(0.11) * flog1p_abs(R(0.035) * Xr);
     R base = ne * R(kRotBase);
     R rb = nuB / nu;
     out[6] = base * rb * rb * sth * sth / nu * fm * (r1 + R(6) * th);
@@ -246,6 +298,7 @@ __device__ __forceinline__ void thermal_coeffs(R ne, R th, R B, R nu, R cth, int
 template <typename R>
 struct Sample {
     bool plasma;          // emitting plasma (else vacuum)
+    KS<R> k;              // metric functions at the sample point (set when the cell holds matter)
     R co[8];              // fluid-frame jI, jQ, jV, aI, aQ, aV, rQ, rV (CGS)
     R u[4], b[4];         // fluid 4-velocity and magnetic 4-vector (contravariant)
     R omega;              // -k.u for the unnormalised k
@@ -269,7 +322,8 @@ __device__ __forceinline__ void sample_point(double a, int flat, const DevGrid &
     if (sample_grid<R>(g, pp.interp, yd + 1, prim) < 0) return;
     R rho = prim[0], p = prim[1];
     if (!(rho > R(0))) return;
-    KS<R> k = ks_point<R>((R)a, flat, (R)yd[1], (R)yd[2], (R)yd[3]);
+    s.k = ks_point<R>((R)a, flat, (R)yd[1], (R)yd[2], (R)yd[3]);
+    const KS<R> &k = s.k;
     R ut[3] = {prim[2], prim[3], prim[4]};
     velocity_from_normal(k, ut, s.u);
     R ul[4];

@@ -276,12 +276,12 @@ __device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
         L1s = L2s > R(0) ? ar * ar / L2s : R(0);
     }
     const R Th = L1s + L2s;
-    const R em1 = expm1(-aI);
+    const R em1 = fexpm1(-aI);
     const R E = R(1) + em1;   // e^{-aI}
-    R cs, shq, shp, dc, ds, fp;   // cos L2, Sh(q), e^{-a} Sh(p), e^{-a} C[p,q], e^{-a} Sh[p,q], 1 - e^{-a} cosh L1
+    R cq, shq, shp, dc, ds, fp;   // cos L2 - 1, Sh(q), e^{-a} Sh(p), e^{-a} C[p,q], e^{-a} Sh[p,q], 1 - e^{-a} cosh L1
     if (Th <= R(1)) {
         // |p|, |q| <= 1: everything from the series; cos L2 = C(q)
-        cs = R(1) + cm1_series(-L2s);
+        cq = cm1_series(-L2s);
         shq = sh_series(-L2s);
         shp = E * sh_series(L1s);
         dd_series(L1s, -L2s, dc, ds);
@@ -290,20 +290,23 @@ __device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
         fp = -em1 - E * cm1_series(L1s);
     } else {
         const R L1 = sqrt(L1s), L2 = sqrt(L2s);
-        R sn;
+        R sn, cs;
         sincos_r(L2, sn, cs);
+        cq = L2s <= R(1) ? cm1_series(-L2s) : cs - R(1);
         const R ep = exp(L1 - aI), em = exp(-L1 - aI);   // e^{-aI} e^{+-L1}
         shq = L2s <= R(1) ? sh_series(-L2s) : sn / L2;
         shp = L1s <= R(1) ? E * sh_series(L1s) : R(0.5) * (ep - em) / L1;
         const R iT = R(1) / Th;
-        dc = (R(0.5) * (ep + em) - E * cs) * iT;
+        dc = (R(0.5) * (ep + em) - E * (R(1) + cq)) * iT;
         ds = (shp - E * shq) * iT;
         fp = R(-0.5) * (expm1(L1 - aI) + expm1(-L1 - aI));
     }
-    const R ec = E * cs, es = E * shq;
+    // e^{-a} cos L2 - 1 without forming e^{-a} cos L2 (a thin step's
+    // attenuation would otherwise be quantised to the spacing of numbers near 1)
+    const R ecm1 = em1 + E * cq, es = E * shq;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
-        S[m] = ec * S[m] + dc * (w2[m] + L2s * S[m]) - es * w1[m] - ds * (w3[m] + L2s * w1[m]);
+        S[m] += ecm1 * S[m] + dc * (w2[m] + L2s * S[m]) - es * w1[m] - ds * (w3[m] + L2s * w1[m]);
     if (Bnu > R(0)) {
         const R X = c[4] * c[7] - c[5] * c[6];
         const R den = R(0.5) * (al2 + rh2) + rt;
@@ -317,11 +320,14 @@ __device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
     }
 }
 
-// unpolarized segment, eq. (unpolarized), with j and alpha carrying the length
+// unpolarized segment, eq. (unpolarized), with j and alpha carrying the length:
+// e^{-dtau} (I + (e^{dtau} - 1) j/dtau) written as I + (e^{-dtau} - 1) (I - j/dtau),
+// which cannot overflow in FP32 below the cut at 100 and keeps a thin
+// segment's attenuation exact to the accuracy of e^{-dtau} - 1
 template <typename R>
 __device__ __forceinline__ R unpol_segment(R I, R j, R dtau) {
     if (dtau > R(0)) {
-        if (dtau < R(100)) return exp(-dtau) * (I + expm1(dtau) * j / dtau);
+        if (dtau < R(100)) return I + fexpm1(-dtau) * (I - j / dtau);
         return j / dtau;
     }
     return I + j;
@@ -553,7 +559,7 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
 #pragma unroll
         for (int m = 0; m < 8; ++m) any = any || (c[m] != R(0));
         if (any) {
-            KS<R> k = ks_point<R>(ar, flat, (R)ys[1], (R)ys[2], (R)ys[3]);
+            const KS<R> &k = smp.k;
             R kc[4] = {(R)ys[4], (R)ys[5], (R)ys[6], (R)ys[7]};
             R e[4][4];
             tetrad(k, smp.u, kc, smp.b, e);
