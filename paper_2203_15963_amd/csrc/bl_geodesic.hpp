@@ -115,18 +115,71 @@ __device__ __forceinline__ double shrink_factor(double eps) {
     return rint(fmax(0.2, 0.9 * pow(eps, -0.2)) * 4096.0) / 4096.0;
 }
 
-// Store an accepted step's record (f0 = the right-hand side at y0).
-__device__ __forceinline__ void write_record(double *rec, int nacc, const double y[7], double h, const double ym[7],
-                                             double ds, const double f0[7]) {
+// Does the chord from p to q (spatial components 1..3 of states (t, x, y, z,
+// ...)) meet the closed box?
+__device__ __forceinline__ bool chord_meets_box(const double bb[6], const double *p, const double *q) {
+    double t0 = 0.0, t1 = 1.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double a0 = p[1 + d], dd = q[1 + d] - p[1 + d];
+        if (dd == 0.0) {
+            if (a0 < bb[2 * d] || a0 > bb[2 * d + 1]) return false;
+        } else {
+            double ta = (bb[2 * d] - a0) / dd, tb = (bb[2 * d + 1] - a0) / dd;
+            double lo = fmin(ta, tb), hi = fmax(ta, tb);
+            t0 = fmax(t0, lo);
+            t1 = fmin(t1, hi);
+            if (t0 > t1) return false;
+        }
+    }
+    return true;
+}
+
+// Store an accepted step's record, with the transfer's per-step decisions
+// taken here, where the step's end state y1 and the right-hand sides f0 (at
+// y0) and f1 (at y1) are at hand (paper section 2.2, last paragraph): the
+// step is sampled against the grid when its chords y0-ym or ym-y1 meet the
+// grid's bounding box, and is then cut into n = ceil(ds/ds_max) pieces (at
+// most 2^24; one for a non-finite length or without a cut).  Slot 23 holds n
+// for a sampled step and -1 for a vacuum step.  In the FP32-quartic layout
+// (the mixed form) a step of n > 1 pieces stores, in place of ym, ds and f0,
+// the coefficients c1..c4 of its dense output
+//   y(theta) = y0 + theta (c1 + theta (c2 + theta (c3 + theta c4))),
+// the quartic through y0, y1, f0, f1 and ym, formed in FP64 and rounded to
+// FP32 (28 floats, c_j of component m at float 7 (j - 1) + m of slots 8..21).
+__device__ __forceinline__ void write_record(const GeoParams &P, double *rec, int nacc, const double y0[7], double h,
+                                             const double ym[7], const double y1[7], const double f0[7],
+                                             const double f1[7], double ds) {
     double *r = rec + (long long)nacc * kRecDoubles;
 #pragma unroll
-    for (int m = 0; m < 7; ++m) r[m] = y[m];
+    for (int m = 0; m < 7; ++m) r[m] = y0[m];
     r[7] = h;
+    const bool inb = chord_meets_box(P.bb, y0, ym) || chord_meets_box(P.bb, ym, y1);
+    int nsub = 1;
+    if (inb && P.ds_max > 0.0) {
+        const double q = ceil(ds / P.ds_max);
+        nsub = (q >= 1.0) ? (int)fmin(q, 16777216.0) : 1;
+    }
+    r[23] = inb ? (double)nsub : -1.0;
+    if (P.rec_quart32 && nsub > 1) {
+        float *c = reinterpret_cast<float *>(r + 8);
 #pragma unroll
-    for (int m = 0; m < 7; ++m) r[8 + m] = ym[m];
-    r[15] = ds;
+        for (int m = 0; m < 7; ++m) {
+            const double A = y1[m] - y0[m] - h * f0[m];
+            const double B = h * (f1[m] - f0[m]);
+            const double C = 16.0 * (ym[m] - y0[m]) - 8.0 * h * f0[m];
+            c[m] = (float)(h * f0[m]);
+            c[7 + m] = (float)(-5.0 * A + B + C);
+            c[14 + m] = (float)(14.0 * A - 3.0 * B - 2.0 * C);
+            c[21 + m] = (float)(-8.0 * A + 2.0 * B + C);
+        }
+    } else {
 #pragma unroll
-    for (int m = 0; m < 7; ++m) r[16 + m] = f0[m];
+        for (int m = 0; m < 7; ++m) r[8 + m] = ym[m];
+        r[15] = ds;
+#pragma unroll
+        for (int m = 0; m < 7; ++m) r[16 + m] = f0[m];
+    }
 }
 
 // The final state and its right-hand side after the last step.
@@ -182,7 +235,10 @@ struct StepLog {
 // every accepted step is appended to the step log.
 //   record: [0..3] x^mu of y0, [4..6] k_a of y0, [7] h,
 //           [8..11] x^mu of y_mid, [12..14] k_a of y_mid, [15] ds of the step,
-//           [16..22] dy/dlambda at y0 (the first stage of the step), [23] unused
+//           [16..22] dy/dlambda at y0 (the first stage of the step),
+//           [23] pieces of a sampled step, -1 for a vacuum step
+//           (slots 8..22 hold the FP32 quartic instead for a step of more
+//           than one piece in the FP32-quartic layout; see write_record)
 //   final record n_acc: [0..6] the final state, [16..22] dy/dlambda there
 template <bool WREC, bool LOG = false>
 __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], double kt, double *rec, int cap,
@@ -212,7 +268,7 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
                 break;
             }
             double ds = fabs(h) * ds_dlambda(a, flat, ym, kt);
-            if (WREC) write_record(rec, nacc, y, h, ym, ds, k1);
+            if (WREC) write_record(P, rec, nacc, y, h, ym, y5, k1, k7, ds);
             if (LOG) {
                 unsigned long long idx = atomicAdd(lg.count, 1ull);
                 if ((long long)idx < lg.cap) {
@@ -310,7 +366,7 @@ __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool activ
                 continue;
             }
             double ds = fabs(h) * ds_dlambda(a, flat, ym, kt);
-            if (WREC) write_record(rec, nacc, y, h, ym, ds, k1);
+            if (WREC) write_record(P, rec, nacc, y, h, ym, y5, k1, k7, ds);
             ++nacc;
             lambda += h;
             s += ds;

@@ -158,25 +158,6 @@ __device__ __forceinline__ int sample_grid(const DevGrid &g, int interp, const d
     return b;
 }
 
-// Does the chord from p to q (spatial components 1..3) meet the closed box?
-__device__ __forceinline__ bool chord_meets_box(const double bb[6], const double *p, const double *q) {
-    double t0 = 0.0, t1 = 1.0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        double a0 = p[1 + d], dd = q[1 + d] - p[1 + d];
-        if (dd == 0.0) {
-            if (a0 < bb[2 * d] || a0 > bb[2 * d + 1]) return false;
-        } else {
-            double ta = (bb[2 * d] - a0) / dd, tb = (bb[2 * d + 1] - a0) / dd;
-            double lo = fmin(ta, tb), hi = fmax(ta, tb);
-            t0 = fmax(t0, lo);
-            t1 = fmin(t1, hi);
-            if (t0 > t1) return false;
-        }
-    }
-    return true;
-}
-
 // ---------------------------------------------------------------- Bessel
 // Ratios K0(x)/K2(x) and K1(x)/K2(x).  For x <= 2 the ascending series
 // K0 = -(ln(x/2) + gamma) I0 + sum_k H_k y^k/(k!)^2 and

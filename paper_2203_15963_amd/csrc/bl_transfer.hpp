@@ -424,40 +424,47 @@ __device__ __forceinline__ void load_state7(const double *r, double y[7]) {
     for (int m = 0; m < 7; ++m) y[m] = r[m];
 }
 
-// Open step w.st: sampling decision, number of pieces, quartic into LDS.
+// Open step w.st: the sampling decision and number of pieces stored with the
+// record, the node and (for more than one piece) the quartic into LDS.  The
+// FP32 form reads the quartic's coefficients from the record (the
+// FP32-quartic layout); the FP64 form forms them from y0, y1, f0, f1 and y_mid.
 template <typename R>
-__device__ __forceinline__ void next_step(RayWalk<R> &w, const GeoParams &P, const DevGrid &g,
-                                          const TransferParams &tp, QuartLds<R> &s_q, int lane) {
+__device__ __forceinline__ void next_step(RayWalk<R> &w, QuartLds<R> &s_q, int lane) {
     const double *r = w.rec + (long long)w.st * kRecDoubles;
-    double y0[7], ym[7], y1[7];
+    double y0[7];
     load_state7(r, y0);
-    load_state7(r + 8, ym);
-    load_state7(r + kRecDoubles, y1);
-    double h = r[7], ds = r[15];
-    // chords use the spatial components 1..3 of (t, x, y, z, ...)
-    w.inb = chord_meets_box(g.bb, y0, ym) || chord_meets_box(g.bb, ym, y1);
-    int nsub = 1;
-    if (w.inb && tp.ds_max > 0.0) {
-        // at most 2^24 pieces per step; a non-finite length gives one piece
-        double q = ceil(ds / tp.ds_max);
-        nsub = (q >= 1.0) ? (int)fmin(q, 16777216.0) : 1;
-    }
+    const double h = r[7], code = r[23];
+    w.inb = code > 0.0;
+    const int nsub = w.inb ? (int)code : 1;
 #pragma unroll
     for (int m = 0; m < 7; ++m) s_q.y0[m * 64 + lane] = y0[m];
     if (nsub > 1) {
-        // right-hand sides at both ends, stored with the records
-        double f0[7], f1[7];
-        load_state7(r + 16, f0);
-        load_state7(r + kRecDoubles + 16, f1);
+        if constexpr (sizeof(R) == 4) {
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            const f4 *cv = reinterpret_cast<const f4 *>(r + 8);
+            f4 v[7];
 #pragma unroll
-        for (int m = 0; m < 7; ++m) {
-            double A = y1[m] - y0[m] - h * f0[m];
-            double B = h * (f1[m] - f0[m]);
-            double C = 16.0 * (ym[m] - y0[m]) - 8.0 * h * f0[m];
-            s_q.c[m * 64 + lane] = (R)(h * f0[m]);
-            s_q.c[(7 + m) * 64 + lane] = (R)(-5.0 * A + B + C);
-            s_q.c[(14 + m) * 64 + lane] = (R)(14.0 * A - 3.0 * B - 2.0 * C);
-            s_q.c[(21 + m) * 64 + lane] = (R)(-8.0 * A + 2.0 * B + C);
+            for (int k = 0; k < 7; ++k) v[k] = cv[k];
+#pragma unroll
+            for (int k = 0; k < 7; ++k)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s_q.c[(4 * k + e) * 64 + lane] = v[k][e];
+        } else {
+            double ym[7], y1[7], f0[7], f1[7];
+            load_state7(r + 8, ym);
+            load_state7(r + kRecDoubles, y1);
+            load_state7(r + 16, f0);
+            load_state7(r + kRecDoubles + 16, f1);
+#pragma unroll
+            for (int m = 0; m < 7; ++m) {
+                const double A = y1[m] - y0[m] - h * f0[m];
+                const double B = h * (f1[m] - f0[m]);
+                const double C = 16.0 * (ym[m] - y0[m]) - 8.0 * h * f0[m];
+                s_q.c[m * 64 + lane] = (R)(h * f0[m]);
+                s_q.c[(7 + m) * 64 + lane] = (R)(-5.0 * A + B + C);
+                s_q.c[(14 + m) * 64 + lane] = (R)(14.0 * A - 3.0 * B - 2.0 * C);
+                s_q.c[(21 + m) * 64 + lane] = (R)(-8.0 * A + 2.0 * B + C);
+            }
         }
     }
     w.nsub = nsub;
@@ -614,7 +621,7 @@ __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &
     RayWalk<R> w;
     begin_ray(w, rec, n_acc, kt, n_norm, tp);
     while (w.st >= 0 || w.p >= 0) {
-        if (w.p < 0) next_step(w, P, g, tp, s_q, lane);
+        if (w.p < 0) next_step(w, s_q, lane);
         piece<POL, R>(w, P, g, pp, s_q, lane);
     }
     finish_ray<POL, R>(w, P, upix, Hv, o);

@@ -391,7 +391,7 @@ __global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(Geo
                 write_pixel(t, (long long)im.cp.n * im.cp.n, (long long)pj * im.cp.n + pi, im.image, im.aux);
                 slot = -1;
             } else {
-                next_step(w, Pl, g, tp, s_q, lane);
+                next_step(w, s_q, lane);
             }
         }
         if (slot >= 0) piece<POL, R>(w, Pl, g, pp, s_q, lane);
@@ -1019,8 +1019,21 @@ GeoParams geo_params(const bl_camera *c, const bl_spacetime *st, const bl_integr
     P.flat = st->flat ? 1 : 0;
     P.cap = (in && in->record_cap > 0) ? in->record_cap : 512;
     P.n = c->n;
-    P.pad = 0;
+    // no records are sampled unless a render sets the grid box, the piece
+    // length and the record layout (record_layout)
+    P.rec_quart32 = 0;
+    for (int d = 0; d < 6; ++d) P.bb[d] = 0.0;
+    P.ds_max = 0.0;
     return P;
+}
+
+// What the geodesic kernels store with each record for the transfer: the grid
+// box and piece length for the sampling decision, and the FP32-quartic layout
+// for the mixed form (whose transfer kernels read it).
+void record_layout(GeoParams &P, const DevGrid &g, const bl_integrator *in, bool mixed) {
+    for (int d = 0; d < 6; ++d) P.bb[d] = g.bb[d];
+    P.ds_max = in->ds_max;
+    P.rec_quart32 = mixed ? 1 : 0;
 }
 
 template <typename T>
@@ -1206,6 +1219,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     long long total = 0;
     if ((s = upload_images(ctx, n, cams, sts, images, auxs, t, B, total)) != BL_OK) return s;
     GeoParams P = geo_params(cams[0], sts[0], integ);
+    record_layout(P, grid->g, integ, mixed);
     size_t rec_per_ray = (size_t)P.cap * kRecDoubles * sizeof(double);
     long long chunk = t.chunk_rays > 0 ? t.chunk_rays : (long long)(ctx->ws_limit / rec_per_ray);
     chunk = std::max(64LL, chunk - chunk % 64);
