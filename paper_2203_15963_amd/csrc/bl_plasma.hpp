@@ -345,18 +345,20 @@ __device__ __forceinline__ R det3(R a1, R a2, R a3, R b1, R b2, R b3, R c1, R c2
 // Orthonormal tetrad of observer u with photon momentum k (covariant kc):
 // e0 = u, e3 = (k - omega u)/omega with omega = -k.u, e2 along w projected
 // orthogonal to u and e3 (falling back to z, then x, when w is degenerate),
-// e1^a = [a b c d] u_b e2_c e3_d (sqrt(-g) = 1 in CKS): e1 x e2 = e3.
+// e1^a = [abcd] u_b e2_c e3_d (sqrt(-g) = 1 in CKS): e1 x e2 = e3.  Lowering
+// every index of the alternating symbol multiplies it by det g = -1, so the
+// covariant e1 is p_a = -[abcd] u^b e2^c e3^d, formed here from the
+// contravariant vectors and raised once.  Returns the screen vectors e1, e2
+// contravariant and p = e1_a, q = e2_a covariant, and e3.
 template <typename R>
-__device__ __forceinline__ void tetrad(const KS<R> &k, const R u[4], const R kc[4], const R w[4], R e[4][4]) {
+__device__ __forceinline__ void screen_basis(const KS<R> &k, const R u[4], const R kc[4], const R w[4], R e1[4],
+                                             R e2[4], R p[4], R q[4], R e3[4]) {
     R ku[4];
     raise(k, kc, ku);
-    R omega = -(kc[0] * u[0] + kc[1] * u[1] + kc[2] * u[2] + kc[3] * u[3]);
-    R iom = R(1) / omega;
+    const R omega = -(kc[0] * u[0] + kc[1] * u[1] + kc[2] * u[2] + kc[3] * u[3]);
+    const R iom = R(1) / omega;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        e[0][m] = u[m];
-        e[3][m] = (ku[m] - omega * u[m]) * iom;
-    }
+    for (int m = 0; m < 4; ++m) e3[m] = (ku[m] - omega * u[m]) * iom;
     R t[4], nrm = R(0);
     for (int attempt = 0; attempt < 3; ++attempt) {
         R v[4];
@@ -368,23 +370,30 @@ __device__ __forceinline__ void tetrad(const KS<R> &k, const R u[4], const R kc[
             v[0] = R(0); v[1] = R(1); v[2] = R(0); v[3] = R(0);
         }
         R vn = sqrt(fabs(gdot(k, v, v)));
-        R wu = gdot(k, v, u), we3 = gdot(k, v, e[3]);
+        R wu = gdot(k, v, u), we3 = gdot(k, v, e3);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) t[m] = v[m] + wu * u[m] - we3 * e[3][m];
+        for (int m = 0; m < 4; ++m) t[m] = v[m] + wu * u[m] - we3 * e3[m];
         nrm = sqrt(fabs(gdot(k, t, t)));
         if (vn > R(0) && nrm > R(1e-10) * vn) break;
     }
-    R inrm = R(1) / nrm;
+    const R inrm = R(1) / nrm;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) e[2][m] = t[m] * inrm;
-    R U[4], P[4], Q[4];
-    lower(k, u, U);
-    lower(k, e[2], P);
-    lower(k, e[3], Q);
-    e[1][0] = det3(U[1], U[2], U[3], P[1], P[2], P[3], Q[1], Q[2], Q[3]);
-    e[1][1] = -det3(U[0], U[2], U[3], P[0], P[2], P[3], Q[0], Q[2], Q[3]);
-    e[1][2] = det3(U[0], U[1], U[3], P[0], P[1], P[3], Q[0], Q[1], Q[3]);
-    e[1][3] = -det3(U[0], U[1], U[2], P[0], P[1], P[2], Q[0], Q[1], Q[2]);
+    for (int m = 0; m < 4; ++m) e2[m] = t[m] * inrm;
+    lower(k, e2, q);
+    p[0] = -det3(u[1], u[2], u[3], e2[1], e2[2], e2[3], e3[1], e3[2], e3[3]);
+    p[1] = det3(u[0], u[2], u[3], e2[0], e2[2], e2[3], e3[0], e3[2], e3[3]);
+    p[2] = -det3(u[0], u[1], u[3], e2[0], e2[1], e2[3], e3[0], e3[1], e3[3]);
+    p[3] = det3(u[0], u[1], u[2], e2[0], e2[1], e2[2], e3[0], e3[1], e3[2]);
+    raise(k, p, e1);
+}
+
+// The whole tetrad (rows e0..e3, contravariant).
+template <typename R>
+__device__ __forceinline__ void tetrad(const KS<R> &k, const R u[4], const R kc[4], const R w[4], R e[4][4]) {
+    R p[4], q[4];
+    screen_basis(k, u, kc, w, e[1], e[2], p, q, e[3]);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) e[0][m] = u[m];
 }
 
 }  // namespace bl

@@ -115,15 +115,12 @@ __device__ __forceinline__ void transport_step(R a, int flat, const R ya[8], con
     for (int m = 0; m < 6; ++m) N.i[m] += dl * d.i[m];
 }
 
-// Stokes parameters of N in the screen vectors e1, e2 (contravariant) of a
-// tetrad: I = N11 + N22, Q = N11 - N22, U = 2 Re N12, V = -2 Im N12.
+// Stokes parameters of N in the screen vectors of a tetrad, given covariant
+// (p = e1_a, q = e2_a): I = N11 + N22, Q = N11 - N22, U = 2 Re N12,
+// V = -2 Im N12 with N11 = N^ab p_a p_b etc.
 template <typename R>
-__device__ __forceinline__ void coh_to_stokes(const KS<R> &k, const R e1[4], const R e2[4], const Coh<R> &N,
-                                              R S[4]) {
-    R p[4], q[4];
-    lower(k, e1, p);
-    lower(k, e2, q);
-    // N_ab p^a p^b etc. through the vectors Re(N) p, Re(N) q and Im(N) q
+__device__ __forceinline__ void coh_to_stokes(const R p[4], const R q[4], const Coh<R> &N, R S[4]) {
+    // through the vectors Re(N) p, Re(N) q and Im(N) q
     R rp[4], rq[4], iq[4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -359,12 +356,15 @@ struct TransferParams {
 // for every piece through an offset the compiler cannot hoist, so it does not
 // occupy registers across pieces.  blockDim.x == 64.
 // The open step's dense output in LDS, lane-interleaved: the node y0 in FP64
-// and the quartic's coefficients c1..c4 (7 components each) in R, so that
-// y(theta) = y0 + theta (c1 + theta (c2 + theta (c3 + theta c4))).
+// and the quartic's coefficients c1..c4 in R, so that
+// y(theta) = y0 + theta (c1 + theta (c2 + theta (c3 + theta c4))), for the six
+// components x, y, z, k_x, k_y, k_z (the metric and the fluid data are
+// stationary, so nothing in the transfer reads the coordinate time).
+constexpr int kQC = 6;   // quartic components kept: state components 1..6
 template <typename R>
 struct QuartLds {
-    double y0[7 * 64];
-    R c[28 * 64];
+    double y0[kQC * 64];
+    R c[4 * kQC * 64];
 };
 
 template <typename R>
@@ -382,7 +382,7 @@ struct RayWalk {
     R I, tau, Ij;
     R tau_c, Ij_c;       // compensation terms of the two sums
     int nsamp, nrec;
-    R pys[7], pyb[7];    // previous record: sample and boundary (x^mu, k_a)
+    R pys[kQC], pyb[kQC];   // previous piece: sample and boundary (x, y, z, k_x, k_y, k_z)
     Coh<R> N;
 };
 
@@ -437,18 +437,18 @@ __device__ __forceinline__ void next_step(RayWalk<R> &w, QuartLds<R> &s_q, int l
     w.inb = code > 0.0;
     const int nsub = w.inb ? (int)code : 1;
 #pragma unroll
-    for (int m = 0; m < 7; ++m) s_q.y0[m * 64 + lane] = y0[m];
+    for (int m = 1; m < 7; ++m) s_q.y0[(m - 1) * 64 + lane] = y0[m];
     if (nsub > 1) {
         if constexpr (sizeof(R) == 4) {
+            // float 7 j + m of the record holds c_{j+1} of state component m
             typedef float f4 __attribute__((ext_vector_type(4)));
             const f4 *cv = reinterpret_cast<const f4 *>(r + 8);
             f4 v[7];
 #pragma unroll
             for (int k = 0; k < 7; ++k) v[k] = cv[k];
 #pragma unroll
-            for (int k = 0; k < 7; ++k)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) s_q.c[(4 * k + e) * 64 + lane] = v[k][e];
+            for (int i = 0; i < 28; ++i)
+                if (i % 7 != 0) s_q.c[(kQC * (i / 7) + i % 7 - 1) * 64 + lane] = v[i / 4][i % 4];
         } else {
             double ym[7], y1[7], f0[7], f1[7];
             load_state7(r + 8, ym);
@@ -456,14 +456,14 @@ __device__ __forceinline__ void next_step(RayWalk<R> &w, QuartLds<R> &s_q, int l
             load_state7(r + 16, f0);
             load_state7(r + kRecDoubles + 16, f1);
 #pragma unroll
-            for (int m = 0; m < 7; ++m) {
+            for (int m = 1; m < 7; ++m) {
                 const double A = y1[m] - y0[m] - h * f0[m];
                 const double B = h * (f1[m] - f0[m]);
                 const double C = 16.0 * (ym[m] - y0[m]) - 8.0 * h * f0[m];
-                s_q.c[m * 64 + lane] = (R)(h * f0[m]);
-                s_q.c[(7 + m) * 64 + lane] = (R)(-5.0 * A + B + C);
-                s_q.c[(14 + m) * 64 + lane] = (R)(14.0 * A - 3.0 * B - 2.0 * C);
-                s_q.c[(21 + m) * 64 + lane] = (R)(-8.0 * A + 2.0 * B + C);
+                s_q.c[(m - 1) * 64 + lane] = (R)(h * f0[m]);
+                s_q.c[(kQC + m - 1) * 64 + lane] = (R)(-5.0 * A + B + C);
+                s_q.c[(2 * kQC + m - 1) * 64 + lane] = (R)(14.0 * A - 3.0 * B - 2.0 * C);
+                s_q.c[(3 * kQC + m - 1) * 64 + lane] = (R)(-8.0 * A + 2.0 * B + C);
             }
         }
     }
@@ -475,25 +475,28 @@ __device__ __forceinline__ void next_step(RayWalk<R> &w, QuartLds<R> &s_q, int l
     --w.st;
 }
 
+// State (t, x, y, z, k_t, k_x, k_y, k_z) at theta of the open step; t is not
+// formed (set to 0).
 template <typename R>
 __device__ __forceinline__ void quartic_at(const QuartLds<R> &s_q, int off, double th, double y[8], double kt) {
     const R t = (R)th;
 #pragma unroll
-    for (int m = 0; m < 7; ++m) {
-        int q = m < 4 ? m : m + 1;
-        R v = s_q.c[(21 + m) * 64 + off];
-        v = s_q.c[(14 + m) * 64 + off] + t * v;
-        v = s_q.c[(7 + m) * 64 + off] + t * v;
+    for (int m = 0; m < kQC; ++m) {
+        const int q = m < 3 ? m + 1 : m + 2;
+        R v = s_q.c[(3 * kQC + m) * 64 + off];
+        v = s_q.c[(2 * kQC + m) * 64 + off] + t * v;
+        v = s_q.c[(kQC + m) * 64 + off] + t * v;
         v = s_q.c[m * 64 + off] + t * v;
         y[q] = s_q.y0[m * 64 + off] + th * (double)v;
     }
+    y[0] = 0.0;
     y[4] = kt;
 }
 
 template <typename R>
-__device__ __forceinline__ void to_state_r(const R p7[7], R kt, R y[8]) {
-    y[0] = p7[0]; y[1] = p7[1]; y[2] = p7[2]; y[3] = p7[3];
-    y[4] = kt; y[5] = p7[4]; y[6] = p7[5]; y[7] = p7[6];
+__device__ __forceinline__ void to_state_r(const R p6[kQC], R kt, R y[8]) {
+    y[0] = R(0); y[1] = p6[0]; y[2] = p6[1]; y[3] = p6[2];
+    y[4] = kt; y[5] = p6[3]; y[6] = p6[4]; y[7] = p6[5];
 }
 
 // Process piece w.p of the open step.
@@ -515,7 +518,8 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
     }
     if (p == 0) {
 #pragma unroll
-        for (int m = 0; m < 7; ++m) yb[m < 4 ? m : m + 1] = s_q.y0[m * 64 + off];
+        for (int m = 0; m < kQC; ++m) yb[m < 3 ? m + 1 : m + 2] = s_q.y0[m * 64 + off];
+        yb[0] = 0.0;
         yb[4] = (double)w.kt;
     } else {
         quartic_at(s_q, off, (double)p * w.inv_nsub, yb, (double)w.kt);
@@ -553,9 +557,9 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
     }
     w.started = true;
 #pragma unroll
-    for (int m = 0; m < 7; ++m) {
-        w.pys[m] = (R)ys[m < 4 ? m : m + 1];
-        w.pyb[m] = (R)yb[m < 4 ? m : m + 1];
+    for (int m = 0; m < kQC; ++m) {
+        w.pys[m] = (R)ys[m < 3 ? m + 1 : m + 2];
+        w.pyb[m] = (R)yb[m < 3 ? m + 1 : m + 2];
     }
     w.pdl = w.dl;
     if (smp.plasma) {
@@ -568,12 +572,12 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
         if (any) {
             const KS<R> &k = smp.k;
             R kc[4] = {(R)ys[4], (R)ys[5], (R)ys[6], (R)ys[7]};
-            R e[4][4];
-            tetrad(k, smp.u, kc, smp.b, e);
+            R e1[4], e2[4], p[4], q[4], e3[4];
+            screen_basis(k, smp.u, kc, smp.b, e1, e2, p, q, e3);
             R S[4];
-            coh_to_stokes(k, e[1], e[2], w.N, S);
+            coh_to_stokes(p, q, w.N, S);
             stokes_step(c, S);
-            stokes_to_coh(e[1], e[2], S, w.N);
+            stokes_to_coh(e1, e2, S, w.N);
         }
     }
 }
@@ -603,10 +607,10 @@ __device__ __forceinline__ void finish_ray(RayWalk<R> &w, const GeoParams &P, co
     KS<R> k = ks_point<R>(ar, P.flat, y0[1], y0[2], y0[3]);
     R mH[4] = {(R)-Hv[0], (R)-Hv[1], (R)-Hv[2], (R)-Hv[3]};
     R up[4] = {(R)upix[0], (R)upix[1], (R)upix[2], (R)upix[3]};
-    R e[4][4];
-    tetrad(k, up, y0 + 4, mH, e);
+    R e1[4], e2[4], p[4], q[4], e3[4];
+    screen_basis(k, up, y0 + 4, mH, e1, e2, p, q, e3);
     R S[4];
-    coh_to_stokes(k, e[1], e[2], w.N, S);
+    coh_to_stokes(p, q, w.N, S);
     for (int m = 0; m < 4; ++m) o.S[m] = (double)S[m];
 }
 

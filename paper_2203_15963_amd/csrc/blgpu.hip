@@ -319,11 +319,11 @@ __global__ void __launch_bounds__(256) k_order_scatter(const int *__restrict__ n
     if (i < count) order[lb[key] + rank] = i;
 }
 
-// Resident waves per SIMD the FP32 transfer kernels are compiled for (the
-// register budget: 168 VGPRs for three, 128 for four); the FP64 ones keep the
-// compiler's choice.
+// Resident waves per SIMD the transfer kernels are compiled for (the register
+// budget: 168 VGPRs for three, 128 for four, 256 for two); the polarized FP64
+// kernel keeps the compiler's choice (one).
 template <bool POL, typename R>
-constexpr int transfer_waves() { return sizeof(R) == 4 ? (POL ? 3 : 4) : 1; }
+constexpr int transfer_waves() { return sizeof(R) == 4 ? (POL ? 3 : 4) : (POL ? 1 : 2); }
 
 template <bool POL, typename R, bool BATCH>
 __global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(GeoParams P, Batch B, DevGrid g,
