@@ -44,9 +44,25 @@ __device__ __forceinline__ float fexpm1(float x) {
     return fabsf(x) < 0.35f ? p * x : __expf(x) - 1.0f;
 }
 __device__ __forceinline__ double fexpm1(double x) { return expm1(x); }
+// 1/sqrt(x): the hardware unit in FP32, a correctly rounded square root and
+// division in FP64
+__device__ __forceinline__ float rsqrt_r(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
 // cos for arguments of moderate size: the hardware unit in FP32, the library in FP64
 __device__ __forceinline__ float fcos(float x) { return __cosf(x); }
 __device__ __forceinline__ double fcos(double x) { return cos(x); }
+// sin and cos: in FP32 the argument is reduced by 2 pi in two parts (Cody and
+// Waite; 6.28125 has eight significant bits, so n * 6.28125 is exact for the
+// argument sizes met here) and the hardware unit evaluates on [-pi, pi]; in
+// FP64 the library function
+__device__ __forceinline__ void fsincos(float x, float &s, float &c) {
+    const float n = rintf(x * 0.15915494309189535f);
+    float r = fmaf(-n, 6.28125f, x);
+    r = fmaf(-n, 1.9353071795864769e-3f, r);
+    s = __sinf(r);
+    c = __cosf(r);
+}
+__device__ __forceinline__ void fsincos(double x, double &s, double &c) { sincos(x, &s, &c); }
 // ln(1 + x) for x >= 0 where only absolute accuracy is needed
 __device__ __forceinline__ float flog1p_abs(float x) { return __logf(1.0f + x); }
 __device__ __forceinline__ double flog1p_abs(double x) { return log1p(x); }

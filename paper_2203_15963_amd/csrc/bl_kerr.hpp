@@ -237,9 +237,9 @@ __device__ __forceinline__ void velocity_from_normal(const KS<R> &k, const R ut[
     R lu = k.l[0] * ut[0] + k.l[1] * ut[1] + k.l[2] * ut[2];
     R q = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2] + k.f * lu * lu;
     R gam = sqrt(R(1) + q);
-    R ialpha = sqrt(R(1) + k.f);
-    u[0] = gam * ialpha;
-    R sb = gam * ialpha * k.f / (R(1) + k.f);
+    R alpha = rsqrt_r(R(1) + k.f);
+    u[0] = gam * (R(1) + k.f) * alpha;   // gamma / alpha
+    R sb = gam * k.f * alpha;            // gamma beta^a / alpha = sb l^a
     u[1] = ut[0] - sb * k.l[0];
     u[2] = ut[1] - sb * k.l[1];
     u[3] = ut[2] - sb * k.l[2];

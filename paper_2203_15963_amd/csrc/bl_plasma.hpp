@@ -167,7 +167,7 @@ __device__ __forceinline__ int sample_grid(const DevGrid &g, int interp, const d
 // cosh(n t) dt, exponentially convergent in the step.  Terms and steps are
 // sized for the precision of R.
 template <typename R>
-__device__ __forceinline__ void bessel_ratios(R x, R &r0, R &r1) {
+__device__ __forceinline__ void bessel_ratios(R x, R ix, R &r0, R &r1) {   // ix = 1/x
     constexpr bool dbl = sizeof(R) == 8;
     constexpr int nterms = dbl ? 16 : 9;
     R K0, K1, K2;
@@ -190,15 +190,15 @@ __device__ __forceinline__ void bessel_ratios(R x, R &r0, R &r1) {
             S1 += (H + Hn) * t1;
         }
         K0 = -L * I0 + S0;
-        K1 = R(1) / x + R(0.5) * x * (L * A - R(0.5) * S1);
-        K2 = K0 + R(2) / x * K1;
+        K1 = ix + R(0.5) * x * (L * A - R(0.5) * S1);
+        K2 = K0 + R(2) * ix * K1;
     } else {
         R hq = dbl ? fmin(R(0.15), R(0.5) / sqrt(x)) : fmin(R(0.3), R(0.7) / sqrt(x));
         const R stop = dbl ? R(40) : R(20);
         R s0 = R(0.5), s1 = R(0.5), s2 = R(0.5);
         for (int i = 1; i < 400; ++i) {
             R t = (R)i * hq;
-            R em = expm1(t);
+            R em = fexpm1(t);
             R cm = em * em / (R(2) * (R(1) + em));   // cosh t - 1
             R c = R(1) + cm;
             R wgt = fexp(-x * cm);
@@ -211,8 +211,9 @@ __device__ __forceinline__ void bessel_ratios(R x, R &r0, R &r1) {
         K1 = s1;
         K2 = s2;
     }
-    r0 = K0 / K2;
-    r1 = K1 / K2;
+    const R iK2 = R(1) / K2;
+    r0 = K0 * iK2;
+    r1 = K1 * iK2;
 }
 
 // ------------------------------------------------------- thermal coefficients
@@ -227,6 +228,8 @@ constexpr double kRotBase = kQe * kQe / (kMe * kC);
 // Fluid-frame coefficients at frequency nu (Hz) for electron density ne,
 // temperature Theta_e, field B (gauss), and cos(theta_B):
 // out = jI, jQ, jV, aI, aQ, aV, rQ, rV (CGS).
+// The reciprocals 1/nu, 1/Theta_e, 1/sin(theta_B) and the powers of
+// x = nu/nu_c are formed once (x^1/3, x^-1/3, x^-1/2 from one logarithm).
 template <typename R>
 __device__ __forceinline__ void thermal_coeffs(R ne, R th, R B, R nu, R cth, int polarized, R out[8]) {
 #pragma unroll
@@ -234,45 +237,47 @@ __device__ __forceinline__ void thermal_coeffs(R ne, R th, R B, R nu, R cth, int
     cth = fmin(R(1), fmax(R(-1), cth));
     R sth = sqrt(R(1) - cth * cth);
     if (!(ne > R(0)) || !(th > R(0)) || !(B > R(0)) || !(sth > R(0))) return;
-    R nuB = R(kNuB) * B;
-    R nuc = R(1.5) * nuB * sth * th * th;
-    R x = nu / nuc;
-    R x13 = fcbrt(x);
-    R xm13 = R(1) / x13;
-    R xm23 = xm13 * xm13;
-    R E = fexp(R(-1.8899) * x13);
-    R pre = (ne * R(kPreI)) * nu / (th * th);
-    R jI = pre * R(2.5651) * (R(1) + R(1.92) * xm13 + R(0.9977) * xm23) * E;
-    R nu9 = nu * R(1e-9);
-    R Bnu = R(kPlanck9) * nu9 * nu9 * nu9 / fexpm1(R(kHoverMec2) * nu / th);
-    R iB = R(1) / Bnu;
+    const R inu = R(1) / nu, ith = R(1) / th;
+    const R nuB = R(kNuB) * B;
+    const R x = nu / (R(1.5) * nuB * sth * th * th);
+    const R lx = flog(x);
+    const R x13 = fexp(lx * R(1.0 / 3.0));
+    const R xm13 = fexp(lx * R(-1.0 / 3.0));
+    const R xm23 = xm13 * xm13;
+    const R E = fexp(R(-1.8899) * x13);
+    const R pre = (ne * R(kPreI)) * nu * (ith * ith);
+    const R jI = pre * R(2.5651) * (R(1) + R(1.92) * xm13 + R(0.9977) * xm23) * E;
+    // 1/B_nu = (e^{h nu/kT} - 1) / (2 h nu^3/c^2), nu in units of 1e9 Hz
+    const R inu9 = R(1e9) * inu;
+    const R iB = fexpm1(R(kHoverMec2) * nu * ith) * (R(1.0 / kPlanck9) * inu9 * inu9 * inu9);
     out[0] = jI;
     out[3] = jI * iB;
     if (!polarized) return;
-    R jQ = pre * R(2.5651) * (R(1) + R(0.932) * xm13 + R(0.4998) * xm23) * E;
-    R jV = (ne * R(kPreV)) * nu * (cth / sth) / (th * th * th) *
-           (R(1.8138) / x + R(3.423) * xm23 + R(0.02955) / sqrt(x) + R(2.0377) * xm13) * E;
+    const R jQ = pre * R(2.5651) * (R(1) + R(0.932) * xm13 + R(0.4998) * xm23) * E;
+    const R ix = xm13 * xm13 * xm13, isx = fexp(R(-0.5) * lx);
+    const R jV = (ne * R(kPreV)) * nu * (cth / sth) * (ith * ith * ith) *
+                 (R(1.8138) * ix + R(3.423) * xm23 + R(0.02955) * isx + R(2.0377) * xm13) * E;
     out[1] = jQ;
     out[2] = jV;
     out[4] = jQ * iB;
     out[5] = jV * iB;
-    R Xr = th * sqrt(R(1.4142135623730951) * sth * R(1e3) * nuB / nu);
+    const R Xr = th * sqrt(R(1.4142135623730951) * sth * R(1e3) * nuB * inu);
     R r0, r1;
-    bessel_ratios(R(1) / th, r0, r1);
+    bessel_ratios(ith, th, r0, r1);
     // powers of X through one logarithm: X^-1/2, X^-0.5175, X^-0.6, X^4/3
-    R lX = flog(Xr);
-    R ism = fexp(R(-0.5) * lX);
-    R e169 = R(0.011) * fexp(R(-1.69) * ism);
-    R f0 = R(2.011) * fexp(R(-19.78) * fexp(R(-0.5175) * lX)) -
-           fcos(R(39.89) * ism) * fexp(R(-70.16) * fexp(R(-0.6) * lX)) - e169;
+    const R lX = flog(Xr);
+    const R ism = fexp(R(-0.5) * lX);
+    const R e169 = R(0.011) * fexp(R(-1.69) * ism);
+    const R f0 = R(2.011) * fexp(R(-19.78) * fexp(R(-0.5175) * lX)) -
+                 fcos(R(39.89) * ism) * fexp(R(-70.16) * fexp(R(-0.6) * lX)) - e169;
     // (1 + tanh y) / 2 = 1 / (1 + e^{-2y}), y = 10 (ln 0.6648 - lX / 2)
-    R fm = f0 + (e169 - R(0.003135) * fexp(R(4.0 / 3.0) * lX)) /
-                    (R(1) + fexp(R(-20) * (R(-0.4082690354408987) - R(0.5) * lX)));
-    R gX = R(1) - R(0.11) * flog1p_abs(R(0.035) * Xr);
-    R base = ne * R(kRotBase);
-    R rb = nuB / nu;
-    out[6] = base * rb * rb * sth * sth / nu * fm * (r1 + R(6) * th);
-    out[7] = R(2) * base * rb / nu * r0 * cth * gX;
+    const R fm = f0 + (e169 - R(0.003135) * fexp(R(4.0 / 3.0) * lX)) /
+                          (R(1) + fexp(R(-20) * (R(-0.4082690354408987) - R(0.5) * lX)));
+    const R gX = R(1) - R(0.11) * flog1p_abs(R(0.035) * Xr);
+    const R base = ne * R(kRotBase);
+    const R rb = nuB * inu;
+    out[6] = base * rb * rb * sth * sth * inu * fm * (r1 + R(6) * th);
+    out[7] = R(2) * base * rb * inu * r0 * cth * gX;
 }
 
 // -------------------------------------------------------------- plasma

@@ -200,8 +200,6 @@ __device__ __forceinline__ void kprime(const R c[8], const R v[4], R w[4]) {
     w[3] = c[5] * v[0] - c[6] * v[2];
 }
 
-__device__ __forceinline__ void sincos_r(double x, double &s, double &c) { sincos(x, &s, &c); }
-__device__ __forceinline__ void sincos_r(float x, float &s, float &c) { sincosf(x, &s, &c); }
 
 constexpr double inv_factorial(int n) {
     double f = 1.0;
@@ -288,15 +286,15 @@ __device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
     } else {
         const R L1 = sqrt(L1s), L2 = sqrt(L2s);
         R sn, cs;
-        sincos_r(L2, sn, cs);
+        fsincos(L2, sn, cs);
         cq = L2s <= R(1) ? cm1_series(-L2s) : cs - R(1);
-        const R ep = exp(L1 - aI), em = exp(-L1 - aI);   // e^{-aI} e^{+-L1}
+        const R ep = fexp(L1 - aI), em = fexp(-L1 - aI);   // e^{-aI} e^{+-L1}
         shq = L2s <= R(1) ? sh_series(-L2s) : sn / L2;
         shp = L1s <= R(1) ? E * sh_series(L1s) : R(0.5) * (ep - em) / L1;
         const R iT = R(1) / Th;
         dc = (R(0.5) * (ep + em) - E * (R(1) + cq)) * iT;
         ds = (shp - E * shq) * iT;
-        fp = R(-0.5) * (expm1(L1 - aI) + expm1(-L1 - aI));
+        fp = R(-0.5) * (fexpm1(L1 - aI) + fexpm1(-L1 - aI));
     }
     // e^{-a} cos L2 - 1 without forming e^{-a} cos L2 (a thin step's
     // attenuation would otherwise be quantised to the spacing of numbers near 1)
@@ -612,6 +610,72 @@ __device__ __forceinline__ void finish_ray(RayWalk<R> &w, const GeoParams &P, co
     R S[4];
     coh_to_stokes(p, q, w.N, S);
     for (int m = 0; m < 4; ++m) o.S[m] = (double)S[m];
+}
+
+// A polarized ray's state at the end of its walk, handed from the persistent
+// transfer kernel to the finishing kernel so that the final transport and
+// projection (a few hundred operations for one lane) run converged over all
+// rays instead of with the rest of a wave waiting: kRayEnd values of R per ray,
+// N (16), the previous sample (6), pdl, tau, Ij, k_t, then nsamp, nrec and
+// started as integers stored bit for bit.
+constexpr int kRayEnd = 32;
+
+template <typename R>
+__device__ __forceinline__ int as_int(R v) {
+    if constexpr (sizeof(R) == 4) return __builtin_bit_cast(int, v);
+    else return (int)__builtin_bit_cast(long long, v);
+}
+template <typename R>
+__device__ __forceinline__ R from_int(int i) {
+    if constexpr (sizeof(R) == 4) return __builtin_bit_cast(float, i);
+    else return __builtin_bit_cast(double, (long long)i);
+}
+
+template <typename R>
+__device__ __forceinline__ void store_ray_end(const RayWalk<R> &w, R *e) {
+    R v[kRayEnd];
+#pragma unroll
+    for (int m = 0; m < 10; ++m) v[m] = w.N.r[m];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) v[10 + m] = w.N.i[m];
+#pragma unroll
+    for (int m = 0; m < kQC; ++m) v[16 + m] = w.pys[m];
+    v[22] = w.pdl;
+    v[23] = w.tau;
+    v[24] = w.Ij;
+    v[25] = w.kt;
+    v[26] = from_int<R>(w.nsamp);
+    v[27] = from_int<R>(w.nrec);
+    v[28] = from_int<R>(w.started ? 1 : 0);
+    v[29] = v[30] = v[31] = R(0);
+    typedef R rv __attribute__((ext_vector_type(16 / sizeof(R))));
+    constexpr int NE = 16 / sizeof(R);
+    rv *d = reinterpret_cast<rv *>(e);
+#pragma unroll
+    for (int k = 0; k < kRayEnd / NE; ++k) {
+        rv t;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) t[q] = v[NE * k + q];
+        d[k] = t;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void load_ray_end(RayWalk<R> &w, const R *e, const double *rec) {
+    w.rec = rec;
+#pragma unroll
+    for (int m = 0; m < 10; ++m) w.N.r[m] = e[m];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) w.N.i[m] = e[10 + m];
+#pragma unroll
+    for (int m = 0; m < kQC; ++m) w.pys[m] = e[16 + m];
+    w.pdl = e[22];
+    w.tau = e[23];
+    w.Ij = e[24];
+    w.kt = e[25];
+    w.nsamp = as_int(e[26]);
+    w.nrec = as_int(e[27]);
+    w.started = as_int(e[28]) != 0;
 }
 
 // Whole ray by one lane (used where rays are not interleaved).

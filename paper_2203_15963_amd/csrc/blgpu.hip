@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(Geo
                                                  long long start, int count, int refill_min,
                                                  const double *__restrict__ rec, const double *__restrict__ meta,
                                                  const int *__restrict__ nacc, const int *__restrict__ order,
-                                                 ExtQueue X, int *__restrict__ queue) {
+                                                 ExtQueue X, int *__restrict__ queue, R *__restrict__ ends) {
     __shared__ QuartLds<R> s_q;
     const int lane = threadIdx.x;
     RayWalk<R> w;
@@ -379,7 +379,11 @@ __global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(Geo
             Pl.flat = flat_l;
         }
         if (slot >= 0 && w.p < 0) {
-            if (w.st < 0) {
+            if (w.st < 0 && POL) {
+                // finished by k_finish
+                store_ray_end(w, ends + (long long)slot * kRayEnd);
+                slot = -1;
+            } else if (w.st < 0) {
                 const ImgDev &im = B.imgs[img];
                 const long long gid = start + slot;
                 int pi = 0, pj = 0;
@@ -396,6 +400,35 @@ __global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(Geo
         }
         if (slot >= 0) piece<POL, R>(w, Pl, g, pp, s_q, lane);
     }
+}
+
+// Final transport to the pixel and projection on the camera's Stokes basis
+// for the polarized rays of a chunk, from the end states the transfer kernel
+// stored (one lane per ray slot).
+template <typename R, bool BATCH>
+__global__ void __launch_bounds__(64) k_finish(GeoParams P, Batch B, long long start, int count,
+                                               const double *__restrict__ rec, const int *__restrict__ nacc,
+                                               ExtQueue X, const R *__restrict__ ends) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= count || nacc[id] < 0) return;   // -1: finished by the overflow kernel, -2: no pixel
+    const int img = BATCH ? find_image(B, start + id) : 0;
+    const ImgDev &im = B.imgs[img];
+    GeoParams Pl = P;
+    if (BATCH) {
+        Pl.a = im.a;
+        Pl.flat = im.flat;
+    }
+    const int e = X.of[id];
+    const double *rp = e >= 0 ? X.rec + (long long)e * X.cap_rec * kRecDoubles : rec + (long long)id * P.cap * kRecDoubles;
+    RayWalk<R> w;
+    load_ray_end(w, ends + (long long)id * kRayEnd, rp);
+    int pi = 0, pj = 0;
+    ray_pixel(B, im.cp.n, start + id - (BATCH ? B.ray0[img] : 0), pi, pj);
+    double upix[4];
+    pixel_observer(im.fr, Pl, rp, upix);
+    TransferOut t;
+    finish_ray<true, R>(w, Pl, upix, im.fr.H, t);
+    write_pixel(t, (long long)im.cp.n * im.cp.n, (long long)pj * im.cp.n + pi, im.image, im.aux);
 }
 
 // Rays queued by k_geodesic: one wave, each lane traces and transfers its
@@ -913,6 +946,8 @@ struct bl_context {
     size_t ws_limit = (size_t)64 << 30;  // bytes of step records per chunk (set at creation)
     int *d_queue = nullptr;              // per-chunk work counters of the persistent kernels
     size_t queue_bytes = 0;
+    char *d_ends = nullptr;              // polarized rays' end states, kRayEnd reals per ray slot
+    size_t ends_bytes = 0;
     int cus = 0;
     int blocks_tr[8] = {0};              // resident waves per CU of k_transfer<pol, R, batch>:
                                          // [4 batch + 2 pol + (R == float)]
@@ -1178,8 +1213,12 @@ template <bool POL, typename R, bool BATCH>
 void launch_transfer(bl_context *ctx, dim3 grd, const GeoParams &P, const Batch &B, const DevGrid &g,
                      const PlasmaParams &pp, const TransferParams &tp, long long start, int count, int refill,
                      int *q) {
+    R *ends = reinterpret_cast<R *>(ctx->d_ends);
     hipLaunchKernelGGL((k_transfer<POL, R, BATCH>), grd, dim3(64), 0, ctx->stream, P, B, g, pp, tp, start, count,
-                       refill, ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_order, ctx->ext, q);
+                       refill, ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_order, ctx->ext, q, ends);
+    if (POL)
+        hipLaunchKernelGGL((k_finish<R, BATCH>), dim3((count + 63) / 64), dim3(64), 0, ctx->stream, P, B, start, count,
+                           ctx->d_rec, ctx->d_nacc, ctx->ext, (const R *)ends);
 }
 
 template <bool POL, typename R>
@@ -1230,6 +1269,9 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     if ((s = ensure(ctx, &ctx->d_nacc, have_nacc, (size_t)chunk * sizeof(int))) != BL_OK) return s;
     ctx->slot_cap = std::min(have_meta / (2 * sizeof(double)), have_nacc / sizeof(int));
     if ((s = ensure(ctx, &ctx->d_order, ctx->order_bytes, (size_t)chunk * sizeof(int))) != BL_OK) return s;
+    if ((s = ensure(ctx, &ctx->d_ends, ctx->ends_bytes,
+                    (size_t)chunk * kRayEnd * (mixed ? sizeof(float) : sizeof(double)))) != BL_OK)
+        return s;
     // extension slots for rays longer than a record slot: 1024 per chunk of
     // 2048 records (or max_steps + 1 if less), when that is more than a slot
     {
@@ -1432,6 +1474,7 @@ void bl_destroy(bl_context *ctx) {
     (void)hipFree(ctx->d_ovf_list);
     (void)hipFree(ctx->d_big);
     (void)hipFree(ctx->d_queue);
+    (void)hipFree(ctx->d_ends);
     delete ctx;
 }
 
