@@ -147,7 +147,7 @@ __device__ __forceinline__ bool chord_meets_box(const double bb[6], const double
 //   y(theta) = y0 + theta (c1 + theta (c2 + theta (c3 + theta c4))),
 // the quartic through y0, y1, f0, f1 and ym, formed in FP64 and rounded to
 // FP32 (28 floats, c_j of component m at float 7 (j - 1) + m of slots 8..21).
-__device__ __forceinline__ void write_record(const GeoParams &P, double *rec, int nacc, const double y0[7], double h,
+__device__ __forceinline__ bool write_record(const GeoParams &P, double *rec, int nacc, const double y0[7], double h,
                                              const double ym[7], const double y1[7], const double f0[7],
                                              const double f1[7], double ds) {
     double *r = rec + (long long)nacc * kRecDoubles;
@@ -180,15 +180,21 @@ __device__ __forceinline__ void write_record(const GeoParams &P, double *rec, in
 #pragma unroll
         for (int m = 0; m < 7; ++m) r[16 + m] = f0[m];
     }
+    return inb;
 }
 
-// The final state and its right-hand side after the last step.
-__device__ __forceinline__ void write_final(double *rec, int nacc, const double y[7], const double f[7]) {
+// The final state and its right-hand side after the last step, and in slot
+// 23 the index of the last step sampled against the grid (-1 if none): the
+// transfer starts there, the vacuum steps beyond it (towards the source)
+// leaving nothing to do before the first emitting sample.
+__device__ __forceinline__ void write_final(double *rec, int nacc, const double y[7], const double f[7],
+                                            int last_sampled) {
     double *r = rec + (long long)nacc * kRecDoubles;
 #pragma unroll
     for (int m = 0; m < 7; ++m) r[m] = y[m];
 #pragma unroll
     for (int m = 0; m < 7; ++m) r[16 + m] = f[m];
+    r[23] = (double)last_sampled;
 }
 
 // A ray that has filled its record slot moves to an extension slot (when one
@@ -239,7 +245,8 @@ struct StepLog {
 //           [23] pieces of a sampled step, -1 for a vacuum step
 //           (slots 8..22 hold the FP32 quartic instead for a step of more
 //           than one piece in the FP32-quartic layout; see write_record)
-//   final record n_acc: [0..6] the final state, [16..22] dy/dlambda there
+//   final record n_acc: [0..6] the final state, [16..22] dy/dlambda there,
+//           [23] the last step sampled against the grid (-1: none)
 template <bool WREC, bool LOG = false>
 __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], double kt, double *rec, int cap,
                                           TraceOut &o, StepLog lg = StepLog{nullptr, 0, nullptr},
@@ -253,7 +260,7 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
     double h = -P.h0_frac * (rint(r_prev * 1024.0) / 1024.0);
     double h_last = h, eps_last = 1.0;
     double lambda = 0.0, s = 0.0;
-    int nacc = 0, nrej = 0, status = kRunning;
+    int nacc = 0, nrej = 0, status = kRunning, last_sampled = -1;
     bool no_grow = false;
     while (status == kRunning) {
         if ((long long)nacc + nrej >= P.max_steps) { status = kMaxSteps; break; }
@@ -268,7 +275,7 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
                 break;
             }
             double ds = fabs(h) * ds_dlambda(a, flat, ym, kt);
-            if (WREC) write_record(P, rec, nacc, y, h, ym, y5, k1, k7, ds);
+            if (WREC && write_record(P, rec, nacc, y, h, ym, y5, k1, k7, ds)) last_sampled = nacc;
             if (LOG) {
                 unsigned long long idx = atomicAdd(lg.count, 1ull);
                 if ((long long)idx < lg.cap) {
@@ -304,7 +311,7 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
             no_grow = true;
         }
     }
-    if (WREC && status != kRayOverflow) write_final(rec, nacc, y, k1);
+    if (WREC && status != kRayOverflow) write_final(rec, nacc, y, k1, last_sampled);
     o.status = status;
     o.n_acc = nacc;
     o.n_rej = nrej;
@@ -337,7 +344,7 @@ __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool activ
     }
     double h_last = h, eps_last = 1.0;
     double lambda = 0.0, s = 0.0;
-    int nacc = 0, nrej = 0, status = active ? kRunning : kEscaped;
+    int nacc = 0, nrej = 0, status = active ? kRunning : kEscaped, last_sampled = -1;
     bool need = true;
     for (;;) {
         const bool run = status == kRunning;
@@ -366,7 +373,7 @@ __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool activ
                 continue;
             }
             double ds = fabs(h) * ds_dlambda(a, flat, ym, kt);
-            if (WREC) write_record(P, rec, nacc, y, h, ym, y5, k1, k7, ds);
+            if (WREC && write_record(P, rec, nacc, y, h, ym, y5, k1, k7, ds)) last_sampled = nacc;
             ++nacc;
             lambda += h;
             s += ds;
@@ -387,7 +394,7 @@ __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool activ
             h *= shrink_factor(eps);
         }
     }
-    if (WREC && active && status != kRayOverflow) write_final(rec, nacc, y, k1);
+    if (WREC && active && status != kRayOverflow) write_final(rec, nacc, y, k1, last_sampled);
     o.status = status;
     o.n_acc = nacc;
     o.n_rej = nrej;

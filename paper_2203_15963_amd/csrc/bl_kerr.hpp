@@ -27,6 +27,40 @@ __device__ __forceinline__ R ks_r(R a, R x, R y, R z) {
     return sqrt(r2);
 }
 
+// r with the reciprocals the metric functions need: 1/r, 1/(r^2 + a^2) and
+// 1/s, s = sqrt((R^2 - a^2)^2 + 4 a^2 z^2).  From the quartic defining r,
+// r^4 + a^2 z^2 = r^2 s, so f = 2 r^3/(r^4 + a^2 z^2) = 2 r/s and
+// 1/(r^4 + a^2 z^2) = (1/r)^2 (1/s): one square root, one reciprocal square
+// root and one reciprocal in FP32, one square root and one division in FP64.
+template <typename R>
+struct KSCore {
+    R r, ir, ira, is;
+};
+
+template <typename R>
+__device__ __forceinline__ KSCore<R> ks_core(R a, R x, R y, R z) {
+    const R a2 = a * a;
+    const R d = x * x + y * y + z * z - a2;
+    const R s = sqrt(d * d + R(4) * a2 * z * z);
+    const R r2 = (d >= R(0)) ? R(0.5) * (d + s) : ((s - d) > R(0) ? R(2) * a2 * z * z / (s - d) : R(0));
+    const R q = r2 + a2;
+    KSCore<R> c;
+    if constexpr (sizeof(R) == 4) {
+        c.ir = rsqrtf(r2);
+        c.r = r2 > R(0) ? r2 * c.ir : R(0);
+        const R inv = R(1) / (q * s);
+        c.ira = s * inv;
+        c.is = q * inv;
+    } else {
+        c.r = sqrt(r2);
+        const R inv = R(1) / (c.r * q * s);
+        c.ir = q * s * inv;
+        c.ira = c.r * s * inv;
+        c.is = c.r * q * inv;
+    }
+    return c;
+}
+
 // f and the spatial l (l_x, l_y, l_z); lower l_t = 1, upper l^t = -1.
 template <typename R>
 struct KS {
@@ -36,14 +70,12 @@ struct KS {
 template <typename R>
 __device__ __forceinline__ KS<R> ks_point(R a, int flat, R x, R y, R z) {
     KS<R> k;
-    R r = ks_r(a, x, y, z);
-    R r2 = r * r;
-    R ira = R(1) / (r2 + a * a);
-    k.r = r;
-    k.l[0] = (r * x + a * y) * ira;
-    k.l[1] = (r * y - a * x) * ira;
-    k.l[2] = z / r;
-    k.f = flat ? R(0) : R(2) * r2 * r / (r2 * r2 + a * a * z * z);
+    const KSCore<R> c = ks_core(a, x, y, z);
+    k.r = c.r;
+    k.l[0] = (c.r * x + a * y) * c.ira;
+    k.l[1] = (c.r * y - a * x) * c.ira;
+    k.l[2] = z * c.ir;
+    k.f = flat ? R(0) : R(2) * c.r * c.is;
     return k;
 }
 
@@ -86,13 +118,14 @@ __device__ __forceinline__ R gdot(const KS<R> &k, const R A[4], const R B[4]) {
 //   dx^mu/dl = eta^mu nu k_nu - f l^mu (l.k),
 //   dk_c/dl = -1/2 d_c g^ab k_a k_b = 1/2 d_c f (l.k)^2 + f (l.k) (d_c l . k).
 __device__ __forceinline__ void geo_rhs(double a, int flat, const double *y, double kt, double *dy) {
-    // the metric functions and their derivatives from three reciprocals
+    // the metric functions and their derivatives from one division (ks_core)
     const double x = y[1], yy = y[2], z = y[3];
-    const double r = ks_r(a, x, yy, z), r2 = r * r, a2 = a * a;
-    const double ir = 1.0 / r, ira = 1.0 / (r2 + a2);
-    const double D = r2 * r2 + a2 * z * z, iD = 1.0 / D;
+    const KSCore<double> kc = ks_core(a, x, yy, z);
+    const double r = kc.r, r2 = r * r, a2 = a * a;
+    const double ir = kc.ir, ira = kc.ira;
+    const double iD = ir * ir * kc.is;   // 1/(r^4 + a^2 z^2)
     const double l[3] = {(r * x + a * yy) * ira, (r * yy - a * x) * ira, z * ir};
-    const double f = flat ? 0.0 : 2.0 * r2 * r * iD;
+    const double f = flat ? 0.0 : 2.0 * r * kc.is;
     const double lk = -kt + l[0] * y[4] + l[1] * y[5] + l[2] * y[6];   // l^mu k_mu
     const double flk = f * lk;
     dy[0] = -kt + flk;
@@ -101,7 +134,8 @@ __device__ __forceinline__ void geo_rhs(double a, int flat, const double *y, dou
     dy[3] = y[6] - flk * l[2];
     // (no early return for the flat case: it keeps dy out of private memory)
     const double pos[3] = {x, yy, z};
-    const double dr[3] = {x * r2 * r * iD, yy * r2 * r * iD, z * r * (r2 + a2) * iD};
+    const double r3iD = r * kc.is;   // r^3 / (r^4 + a^2 z^2)
+    const double dr[3] = {x * r3iD, yy * r3iD, z * (r2 + a2) * ir * kc.is};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const double dD = 4.0 * r2 * r * dr[c] + (c == 2 ? 2.0 * a2 * z : 0.0);
@@ -155,11 +189,12 @@ struct ConnF {
 template <typename R>
 __device__ __forceinline__ void conn_geom(R a, int flat, const R x[4], const R kc[4], ConnF<R> &c) {
     const R X = x[1], Yy = x[2], Z = x[3];
-    const R r = ks_r(a, X, Yy, Z), r2 = r * r, a2 = a * a;
-    const R ir = R(1) / r, ira = R(1) / (r2 + a2);
-    const R iD = R(1) / (r2 * r2 + a2 * Z * Z);
+    const KSCore<R> kcr = ks_core(a, X, Yy, Z);
+    const R r = kcr.r, r2 = r * r, a2 = a * a;
+    const R ir = kcr.ir, ira = kcr.ira;
+    const R iD = ir * ir * kcr.is;   // 1/(r^4 + a^2 z^2)
     const R l[3] = {(r * X + a * Yy) * ira, (r * Yy - a * X) * ira, Z * ir};
-    const R r3iD = r2 * r * iD;
+    const R r3iD = r * kcr.is;
     const R f = flat ? R(0) : R(2) * r3iD;
     // k^mu = g^mu nu k_nu
     const R flk = f * (-kc[0] + l[0] * kc[1] + l[1] * kc[2] + l[2] * kc[3]);
@@ -167,7 +202,7 @@ __device__ __forceinline__ void conn_geom(R a, int flat, const R x[4], const R k
     const R kv[3] = {kc[1] - flk * l[0], kc[2] - flk * l[1], kc[3] - flk * l[2]};
     const R q = kt + l[0] * kv[0] + l[1] * kv[1] + l[2] * kv[2];
     // d_c r and m
-    const R dr[3] = {X * r3iD, Yy * r3iD, Z * r * (r2 + a2) * iD};
+    const R dr[3] = {X * r3iD, Yy * r3iD, Z * (r2 + a2) * ir * kcr.is};
     const R m[3] = {(X - R(2) * r * l[0]) * ira, (Yy - R(2) * r * l[1]) * ira, -l[2] * ir};
     const R mk = m[0] * kv[0] + m[1] * kv[1] + m[2] * kv[2];
     const R drk = dr[0] * kv[0] + dr[1] * kv[1] + dr[2] * kv[2];

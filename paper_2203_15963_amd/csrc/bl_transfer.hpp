@@ -393,7 +393,10 @@ __device__ __forceinline__ void begin_ray(RayWalk<R> &w, const double *rec, int 
     double q = tp.nu_cam / n_norm;
     w.L = (R)tp.L;
     w.lj = (R)(tp.L * q * q * q);
-    w.st = n_acc - 1;
+    // the last step sampled against the grid (stored with the final state);
+    // the vacuum steps beyond it count one record each and are not walked
+    const int last = (int)rec[(long long)n_acc * kRecDoubles + 23];
+    w.st = last;
     w.p = -1;
     w.nsub = 0;
     w.inv_nsub = 1.0;
@@ -401,7 +404,8 @@ __device__ __forceinline__ void begin_ray(RayWalk<R> &w, const double *rec, int 
     w.started = false;
     w.dl = w.pdl = R(0);
     w.I = w.tau = w.Ij = w.tau_c = w.Ij_c = R(0);
-    w.nsamp = w.nrec = 0;
+    w.nsamp = 0;
+    w.nrec = n_acc - 1 - last;
 #pragma unroll
     for (int m = 0; m < 10; ++m) w.N.r[m] = R(0);
 #pragma unroll
