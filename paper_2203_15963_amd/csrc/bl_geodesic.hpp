@@ -116,8 +116,14 @@ __device__ __forceinline__ double shrink_factor(double eps) {
 }
 
 // Does the chord from p to q (spatial components 1..3 of states (t, x, y, z,
-// ...)) meet the closed box?
+// ...)) meet the closed box?  A chord starting inside the box meets it; the
+// slab test agrees exactly there (each slab's parameter interval then holds
+// t = 0: its bounds are quotients of numbers of opposite or zero sign), so
+// the shortcut changes no decision and saves the divisions for the steps
+// inside the grid.
 __device__ __forceinline__ bool chord_meets_box(const double bb[6], const double *p, const double *q) {
+    if (p[1] >= bb[0] && p[1] <= bb[1] && p[2] >= bb[2] && p[2] <= bb[3] && p[3] >= bb[4] && p[3] <= bb[5])
+        return true;
     double t0 = 0.0, t1 = 1.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {

@@ -364,7 +364,7 @@ __device__ __forceinline__ void screen_basis(const KS<R> &k, const R u[4], const
     const R iom = R(1) / omega;
 #pragma unroll
     for (int m = 0; m < 4; ++m) e3[m] = (ku[m] - omega * u[m]) * iom;
-    R t[4], nrm = R(0);
+    R t[4], nrm2 = R(0);
     for (int attempt = 0; attempt < 3; ++attempt) {
         R v[4];
         if (attempt == 0) {
@@ -374,14 +374,17 @@ __device__ __forceinline__ void screen_basis(const KS<R> &k, const R u[4], const
         } else {
             v[0] = R(0); v[1] = R(1); v[2] = R(0); v[3] = R(0);
         }
-        R vn = sqrt(fabs(gdot(k, v, v)));
-        R wu = gdot(k, v, u), we3 = gdot(k, v, e3);
+        R V[4];
+        lower(k, v, V);
+        const R vv = fabs(V[0] * v[0] + V[1] * v[1] + V[2] * v[2] + V[3] * v[3]);
+        const R wu = V[0] * u[0] + V[1] * u[1] + V[2] * u[2] + V[3] * u[3];
+        const R we3 = V[0] * e3[0] + V[1] * e3[1] + V[2] * e3[2] + V[3] * e3[3];
 #pragma unroll
         for (int m = 0; m < 4; ++m) t[m] = v[m] + wu * u[m] - we3 * e3[m];
-        nrm = sqrt(fabs(gdot(k, t, t)));
-        if (vn > R(0) && nrm > R(1e-10) * vn) break;
+        nrm2 = fabs(gdot(k, t, t));
+        if (vv > R(0) && nrm2 > R(1e-20) * vv) break;
     }
-    const R inrm = R(1) / nrm;
+    const R inrm = rsqrt_r(nrm2);
 #pragma unroll
     for (int m = 0; m < 4; ++m) e2[m] = t[m] * inrm;
     lower(k, e2, q);

@@ -184,7 +184,7 @@ __device__ __forceinline__ GeoParams lane_params(const GeoParams &P, const ImgDe
 // when it fills); rays that outgrow that too are queued on ovf_list; ids of
 // tile pixels outside their image get nacc = -2.
 template <bool WREC, bool BATCH>
-__global__ void __launch_bounds__(64) k_geodesic(GeoParams P, Batch B, long long start, int count,
+__global__ void __launch_bounds__(64, 2) k_geodesic(GeoParams P, Batch B, long long start, int count,
                                                  double *__restrict__ rec, double *__restrict__ meta,
                                                  int *__restrict__ nacc_out, ExtQueue X, int *__restrict__ ovf_count,
                                                  int *__restrict__ ovf_list, double *__restrict__ state_out) {
