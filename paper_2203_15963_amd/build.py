@@ -11,10 +11,14 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # FP32 division and square root need not be correctly rounded (a few ulp):
 # only the mixed form's FP32 arithmetic and the step network use them, both
-# far coarser than that; FP64 code is unaffected.
+# far coarser than that.  FP32 values below 2^-126 are flushed to zero, which
+# lets a division or square root be one hardware instruction instead of a
+# scaled sequence: the mixed form keeps its quantities many decades above
+# that range (intensities in camera units), so nothing it computes is lost.
+# FP64 code is unaffected by both.
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+         "-fno-hip-fp32-correctly-rounded-divide-sqrt", "-fgpu-flush-denormals-to-zero",
          "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
 
 

@@ -48,6 +48,10 @@ __device__ __forceinline__ double fexpm1(double x) { return expm1(x); }
 // division in FP64
 __device__ __forceinline__ float rsqrt_r(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
+// a / b: the hardware reciprocal in FP32 (about 1 ulp), a correctly rounded
+// division in FP64
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
 // cos for arguments of moderate size: the hardware unit in FP32, the library in FP64
 __device__ __forceinline__ float fcos(float x) { return __cosf(x); }
 __device__ __forceinline__ double fcos(double x) { return cos(x); }
@@ -119,6 +123,10 @@ struct PlasmaParams {
     double mu, ne_ni, r_high, r_low, sigma_max;
     double mass_msun;
     int polarized, interp;
+    // per-render constants of the plasma state, formed on the host:
+    double ne_per_rho;   // rho_unit / (mu m_p) / (1 + 1/(n_e/n_i))
+    double th_per_pr;    // mu m_p / m_e
+    double gauss_per_b;  // c sqrt(4 pi rho_unit)
 };
 
 // One image of a render (a batch of one for bl_render): the camera frame

@@ -323,10 +323,10 @@ __device__ __forceinline__ void sample_point(double a, int flat, const DevGrid &
     s.sigma = b2 / rho;
     if (s.sigma > (R)pp.sigma_max) return;
     R binv = b2 / (R(2) * p);
-    R ne = rho * (R)(g.rho_unit / (pp.mu * kMp) / (1.0 + 1.0 / pp.ne_ni));
+    R ne = rho * (R)pp.ne_per_rho;
     R tr = ((R)pp.r_high + binv * binv * (R)pp.r_low) / (R(1) + binv * binv);
-    R th = (R)(pp.mu * kMp / kMe) * (p / rho) * (R)(pp.ne_ni + 1.0) / ((R)pp.ne_ni + tr);
-    R Bg = sqrt(b2) * (R)(kC * sqrt(4.0 * kPi * g.rho_unit));
+    R th = (R)pp.th_per_pr * (p / rho) * (R)(pp.ne_ni + 1.0) / ((R)pp.ne_ni + tr);
+    R Bg = sqrt(b2) * (R)pp.gauss_per_b;
     R kc[4] = {(R)yd[4], (R)yd[5], (R)yd[6], (R)yd[7]};
     R omega = -(kc[0] * s.u[0] + kc[1] * s.u[1] + kc[2] * s.u[2] + kc[3] * s.u[3]);
     R kb = kc[0] * s.b[0] + kc[1] * s.b[1] + kc[2] * s.b[2] + kc[3] * s.b[3];
@@ -361,7 +361,7 @@ __device__ __forceinline__ void screen_basis(const KS<R> &k, const R u[4], const
     R ku[4];
     raise(k, kc, ku);
     const R omega = -(kc[0] * u[0] + kc[1] * u[1] + kc[2] * u[2] + kc[3] * u[3]);
-    const R iom = R(1) / omega;
+    const R iom = fdiv(R(1), omega);
 #pragma unroll
     for (int m = 0; m < 4; ++m) e3[m] = (ku[m] - omega * u[m]) * iom;
     R t[4], nrm2 = R(0);

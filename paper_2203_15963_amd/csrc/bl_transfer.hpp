@@ -265,10 +265,10 @@ __device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
     R L1s, L2s;
     if (dif >= R(0)) {
         L1s = rt + dif;
-        L2s = L1s > R(0) ? ar * ar / L1s : R(0);
+        L2s = L1s > R(0) ? fdiv(ar * ar, L1s) : R(0);
     } else {
         L2s = rt - dif;
-        L1s = L2s > R(0) ? ar * ar / L2s : R(0);
+        L1s = L2s > R(0) ? fdiv(ar * ar, L2s) : R(0);
     }
     const R Th = L1s + L2s;
     const R em1 = fexpm1(-aI);

@@ -1062,6 +1062,22 @@ GeoParams geo_params(const bl_camera *c, const bl_spacetime *st, const bl_integr
     return P;
 }
 
+PlasmaParams plasma_params(const bl_plasma *plasma, const DevGrid &g, double mass_msun) {
+    PlasmaParams pp;
+    pp.mu = plasma->mu;
+    pp.ne_ni = plasma->ne_ni;
+    pp.r_high = plasma->r_high;
+    pp.r_low = plasma->r_low;
+    pp.sigma_max = plasma->sigma_max;
+    pp.mass_msun = mass_msun;
+    pp.polarized = plasma->polarized ? 1 : 0;
+    pp.interp = plasma->interp ? 1 : 0;
+    pp.ne_per_rho = g.rho_unit / (pp.mu * kMp) / (1.0 + 1.0 / pp.ne_ni);
+    pp.th_per_pr = pp.mu * kMp / kMe;
+    pp.gauss_per_b = kC * sqrt(4.0 * kPi * g.rho_unit);
+    return pp;
+}
+
 // What the geodesic kernels store with each record for the transfer: the grid
 // box and piece length for the sampling decision, and the FP32-quartic layout
 // for the mixed form (whose transfer kernels read it).
@@ -1300,15 +1316,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         return s;
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, ctx->d_ovf_count, 0, 1);
     HIPCHK(ctx, hipGetLastError());
-    PlasmaParams pp;
-    pp.mu = plasma->mu;
-    pp.ne_ni = plasma->ne_ni;
-    pp.r_high = plasma->r_high;
-    pp.r_low = plasma->r_low;
-    pp.sigma_max = plasma->sigma_max;
-    pp.mass_msun = sts[0]->mass_msun;
-    pp.polarized = plasma->polarized ? 1 : 0;
-    pp.interp = plasma->interp ? 1 : 0;
+    const PlasmaParams pp = plasma_params(plasma, grid->g, sts[0]->mass_msun);
     TransferParams tp;
     tp.ds_max = integ->ds_max;
     tp.L = kG * sts[0]->mass_msun * kMsun / (kC * kC);
@@ -1992,15 +2000,7 @@ bl_status bl_eval_samples(bl_context *ctx, const bl_spacetime *st, const bl_grid
     if (grid->g.dtype != 0) return fail(ctx, BL_E_UNSUPPORTED, "float32 grids need precision 1");
     if (n == 0) return BL_OK;
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    PlasmaParams pp;
-    pp.mu = plasma->mu;
-    pp.ne_ni = plasma->ne_ni;
-    pp.r_high = plasma->r_high;
-    pp.r_low = plasma->r_low;
-    pp.sigma_max = plasma->sigma_max;
-    pp.mass_msun = st->mass_msun;
-    pp.polarized = plasma->polarized ? 1 : 0;
-    pp.interp = plasma->interp ? 1 : 0;
+    const PlasmaParams pp = plasma_params(plasma, grid->g, st->mass_msun);
     hipLaunchKernelGGL(k_eval_samples, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, ctx->stream, st->a,
                        st->flat ? 1 : 0, grid->g, pp, (long long)n, states, norms, out);
     HIPCHK(ctx, hipGetLastError());
