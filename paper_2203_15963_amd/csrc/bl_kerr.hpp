@@ -42,7 +42,19 @@ __device__ __forceinline__ KSCore<R> ks_core(R a, R x, R y, R z) {
     const R a2 = a * a;
     const R d = x * x + y * y + z * z - a2;
     const R s = sqrt(d * d + R(4) * a2 * z * z);
-    const R r2 = (d >= R(0)) ? R(0.5) * (d + s) : ((s - d) > R(0) ? R(2) * a2 * z * z / (s - d) : R(0));
+    // R^2 < a^2 (inside the ring's radius, never on a ray outside the
+    // horizon): the same root without cancellation.  In FP64 that branch is
+    // taken only when a lane of the wave needs it, so its division is not
+    // evaluated speculatively; in FP32 the select is cheaper.
+    R r2;
+    if constexpr (sizeof(R) == 8) {
+        r2 = R(0.5) * (d + s);
+        if (__ballot(d < R(0)) != 0ull) {
+            if (d < R(0)) r2 = (s - d) > R(0) ? R(2) * a2 * z * z / (s - d) : R(0);
+        }
+    } else {
+        r2 = (d >= R(0)) ? R(0.5) * (d + s) : ((s - d) > R(0) ? R(2) * a2 * z * z / (s - d) : R(0));
+    }
     const R q = r2 + a2;
     KSCore<R> c;
     if constexpr (sizeof(R) == 4) {
