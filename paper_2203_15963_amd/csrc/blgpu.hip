@@ -478,7 +478,7 @@ __global__ void __launch_bounds__(64) k_overflow(GeoParams P, Batch B, DevGrid g
 // packed network (forward fragments and FP32 tail) in LDS; each wave has its
 // own staging rows.  Lanes without a ray still take part in the network calls.
 template <bool WREC, bool BATCH>
-__global__ void __launch_bounds__(256) k_geodesic_learned(GeoParams P, Batch B, long long start, int count,
+__global__ void __launch_bounds__(256, 2) k_geodesic_learned(GeoParams P, Batch B, long long start, int count,
                                                           const u32x4 *__restrict__ pk_g,
                                                           const float *__restrict__ tail_g, double *__restrict__ rec,
                                                           double *__restrict__ meta, int *__restrict__ nacc_out,
