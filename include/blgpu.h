@@ -197,8 +197,8 @@ typedef struct {
                                  of its lanes are idle (1..64; default 1)     */
     int64_t chunk_rays;       /* rays traced per geodesic/transfer launch pair
                                  (multiple of 64; 0 = as many as the step-
-                                 record workspace holds, the default: 64 GiB
-                                 or a quarter of the free device memory at
+                                 record workspace holds, the default: 128 GiB
+                                 or half the free device memory at
                                  bl_create, whichever is less)                */
     int32_t order;            /* 0: images in the given order; 1: largest
                                  first                                        */
