@@ -229,7 +229,8 @@ constexpr double kRotBase = kQe * kQe / (kMe * kC);
 // temperature Theta_e, field B (gauss), and cos(theta_B):
 // out = jI, jQ, jV, aI, aQ, aV, rQ, rV (CGS).
 // The reciprocals 1/nu, 1/Theta_e, 1/sin(theta_B) and the powers of
-// x = nu/nu_c are formed once (x^1/3, x^-1/3, x^-1/2 from one logarithm).
+// x = nu/nu_c are formed once (x^1/3 from one logarithm and exponential, its
+// reciprocal and 1/sqrt(x) without further transcendentals).
 template <typename R>
 __device__ __forceinline__ void thermal_coeffs(R ne, R th, R B, R nu, R cth, int polarized, R out[8]) {
 #pragma unroll
@@ -240,9 +241,8 @@ __device__ __forceinline__ void thermal_coeffs(R ne, R th, R B, R nu, R cth, int
     const R inu = R(1) / nu, ith = R(1) / th;
     const R nuB = R(kNuB) * B;
     const R x = nu / (R(1.5) * nuB * sth * th * th);
-    const R lx = flog(x);
-    const R x13 = fexp(lx * R(1.0 / 3.0));
-    const R xm13 = fexp(lx * R(-1.0 / 3.0));
+    const R x13 = fexp(flog(x) * R(1.0 / 3.0));
+    const R xm13 = R(1) / x13;
     const R xm23 = xm13 * xm13;
     const R E = fexp(R(-1.8899) * x13);
     const R pre = (ne * R(kPreI)) * nu * (ith * ith);
@@ -254,7 +254,7 @@ __device__ __forceinline__ void thermal_coeffs(R ne, R th, R B, R nu, R cth, int
     out[3] = jI * iB;
     if (!polarized) return;
     const R jQ = pre * R(2.5651) * (R(1) + R(0.932) * xm13 + R(0.4998) * xm23) * E;
-    const R ix = xm13 * xm13 * xm13, isx = fexp(R(-0.5) * lx);
+    const R ix = xm13 * xm13 * xm13, isx = rsqrt_r(x);
     const R jV = (ne * R(kPreV)) * nu * (cth / sth) * (ith * ith * ith) *
                  (R(1.8138) * ix + R(3.423) * xm23 + R(0.02955) * isx + R(2.0377) * xm13) * E;
     out[1] = jQ;
@@ -266,7 +266,7 @@ __device__ __forceinline__ void thermal_coeffs(R ne, R th, R B, R nu, R cth, int
     bessel_ratios(ith, th, r0, r1);
     // powers of X through one logarithm: X^-1/2, X^-0.5175, X^-0.6, X^4/3
     const R lX = flog(Xr);
-    const R ism = fexp(R(-0.5) * lX);
+    const R ism = rsqrt_r(Xr);
     const R e169 = R(0.011) * fexp(R(-1.69) * ism);
     const R f0 = R(2.011) * fexp(R(-19.78) * fexp(R(-0.5175) * lX)) -
                  fcos(R(39.89) * ism) * fexp(R(-70.16) * fexp(R(-0.6) * lX)) - e169;
