@@ -65,9 +65,9 @@ __device__ __forceinline__ void corner_weights(const R w[3], R wt[8]) {
 // Weighted sum of the eight corner cells of cell c0 (strides 1, sy, sz).  The
 // corners are read in groups of G whose loads are all issued before any is
 // used, so a lane waits for one round trip per group instead of one per
-// corner (G = 4 for the FP32 grid, 2 for the FP64 grid: 32 registers of
-// cell data in flight either way; 1 for the FP64 grid in the all-FP64 form,
-// whose register budget is spent elsewhere).
+// corner (G = 4 for the FP32 grid, 2 for the FP64 grid in the mixed form: 32
+// registers of cell data in flight either way; 4 for the FP64 grid in the
+// all-FP64 form, which runs one wave per SIMD and has round trips to hide).
 template <int G, typename T, typename R>
 __device__ __forceinline__ void trilerp(const T *base, long long c0, long long sy, long long sz, const R w[3],
                                         R prim[8]) {
@@ -154,7 +154,7 @@ __device__ __forceinline__ int sample_grid(const DevGrid &g, int interp, const d
     if (g.dtype != 0)
         trilerp<4>((const float *)g.prims, c0, sy, sz, w, prim);
     else
-        trilerp<sizeof(R) == 8 ? 1 : 2>((const double *)g.prims, c0, sy, sz, w, prim);
+        trilerp<sizeof(R) == 8 ? 4 : 2>((const double *)g.prims, c0, sy, sz, w, prim);
     return b;
 }
 
