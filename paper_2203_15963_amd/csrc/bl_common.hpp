@@ -21,17 +21,43 @@ constexpr double kEulerGamma = 0.57721566490153286061;
 
 // Exponential, logarithm and cube root for smooth fitting-formula terms: the
 // hardware transcendental unit in FP32 (relative error a few 1e-7 times the
-// argument's magnitude for exp, far inside the mixed form's tolerance), the
-// accurate library functions in FP64.
+// argument's magnitude for exp, far inside the mixed form's tolerance); in
+// FP64 the exponentials below (about one ulp) and the library logarithm and
+// cube root.
 __device__ __forceinline__ float fexp(float x) { return __expf(x); }
-__device__ __forceinline__ double fexp(double x) { return exp(x); }
+// e^x in FP64: x = k ln2 + r with the reduction in two parts (Cody and Waite;
+// ln2_hi has eleven trailing zero bits, so k ln2_hi is exact), e^r from its
+// Taylor polynomial through r^13/13! on |r| <= ln2/2 (truncation below 1e-17;
+// even and odd parts in r^2 evaluated side by side to halve the chain of
+// dependent operations), then scaled by 2^k: within about one ulp.
+__device__ __forceinline__ double fexp(double x) {
+    x = x < -750.0 ? -750.0 : (x > 710.0 ? 710.0 : x);
+    const double k = rint(x * 1.4426950408889634);
+    double r = fma(-k, 0x1.62e42fefa3800p-1, x);
+    r = fma(-k, 5.497923018708371e-14, r);
+    const double u = r * r;
+    double ev = 1.0 / 479001600.0, od = 1.0 / 6227020800.0;   // 1/12!, 1/13!
+    ev = fma(ev, u, 1.0 / 3628800.0);
+    od = fma(od, u, 1.0 / 39916800.0);
+    ev = fma(ev, u, 1.0 / 40320.0);
+    od = fma(od, u, 1.0 / 362880.0);
+    ev = fma(ev, u, 1.0 / 720.0);
+    od = fma(od, u, 1.0 / 5040.0);
+    ev = fma(ev, u, 1.0 / 24.0);
+    od = fma(od, u, 1.0 / 120.0);
+    ev = fma(ev, u, 0.5);
+    od = fma(od, u, 1.0 / 6.0);
+    ev = fma(ev, u, 1.0);
+    od = fma(od, u, 1.0);
+    return ldexp(fma(r, od, ev), (int)k);
+}
 __device__ __forceinline__ float flog(float x) { return __logf(x); }
 __device__ __forceinline__ double flog(double x) { return log(x); }
 __device__ __forceinline__ float fcbrt(float x) { return __expf(__logf(x) * (1.0f / 3.0f)); }   // x > 0
 __device__ __forceinline__ double fcbrt(double x) { return cbrt(x); }
 // e^x - 1 with relative accuracy near zero: in FP32 the Taylor polynomial
 // through x^8/8! for |x| < 0.35 (truncation below 1e-9 relative), the hardware
-// exponential minus one elsewhere; in FP64 the library function.
+// exponential minus one elsewhere.
 __device__ __forceinline__ float fexpm1(float x) {
     float p = 1.0f / 40320.0f;
     p = p * x + 1.0f / 5040.0f;
@@ -43,7 +69,25 @@ __device__ __forceinline__ float fexpm1(float x) {
     p = p * x + 1.0f;
     return fabsf(x) < 0.35f ? p * x : __expf(x) - 1.0f;
 }
-__device__ __forceinline__ double fexpm1(double x) { return expm1(x); }
+// In FP64: for |x| < 0.7 the Taylor polynomial x (1 + x/2! + ... + x^15/16!)
+// (truncation below 1e-17 relative; even and odd parts side by side), else
+// fexp(x) - 1 (within a few ulp there, |e^x - 1| >= 0.5 |e^x|).
+constexpr double rfact(int n) {   // 1/n!
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= (double)i;
+    return 1.0 / f;
+}
+__device__ __forceinline__ double fexpm1(double x) {
+    const double u = x * x;
+    double ev = rfact(15), od = rfact(16);   // c_j = 1/(j+1)!, j = 14, 15
+#pragma unroll
+    for (int j = 12; j >= 0; j -= 2) {
+        ev = fma(ev, u, rfact(j + 1));
+        od = fma(od, u, rfact(j + 2));
+    }
+    const double small = x * fma(x, od, ev);
+    return fabs(x) < 0.7 ? small : fexp(x) - 1.0;
+}
 // 1/sqrt(x): the hardware unit in FP32, a correctly rounded square root and
 // division in FP64
 __device__ __forceinline__ float rsqrt_r(float x) { return rsqrtf(x); }

@@ -201,11 +201,6 @@ __device__ __forceinline__ void kprime(const R c[8], const R v[4], R w[4]) {
 }
 
 
-constexpr double inv_factorial(int n) {
-    double f = 1.0;
-    for (int i = 2; i <= n; ++i) f *= (double)i;
-    return 1.0 / f;
-}
 
 // Sh(x) = sum_k x^k / (2k+1)! for |x| <= 1
 template <typename R>
@@ -213,7 +208,7 @@ __device__ __forceinline__ R sh_series(R x) {
     constexpr int K = sizeof(R) == 8 ? 9 : 5;
     R s = R(0);
 #pragma unroll
-    for (int k = K; k >= 1; --k) s = (s + R(inv_factorial(2 * k + 1))) * x;
+    for (int k = K; k >= 1; --k) s = (s + R(rfact(2 * k + 1))) * x;
     return s + R(1);
 }
 
@@ -223,7 +218,7 @@ __device__ __forceinline__ R cm1_series(R x) {
     constexpr int K = sizeof(R) == 8 ? 10 : 6;
     R s = R(0);
 #pragma unroll
-    for (int k = K; k >= 1; --k) s = (s + R(inv_factorial(2 * k))) * x;
+    for (int k = K; k >= 1; --k) s = (s + R(rfact(2 * k))) * x;
     return s;
 }
 
@@ -237,8 +232,8 @@ __device__ __forceinline__ void dd_series(R p, R q, R &dc, R &ds) {
     ds = R(0);
 #pragma unroll
     for (int k = 1; k <= K; ++k) {
-        dc += h * R(inv_factorial(2 * k));
-        ds += h * R(inv_factorial(2 * k + 1));
+        dc += h * R(rfact(2 * k));
+        ds += h * R(rfact(2 * k + 1));
         qk *= q;
         h = p * h + qk;                               // h_k = p h_{k-1} + q^k
     }
