@@ -198,6 +198,21 @@ def test_samples_match_oracle(ctx, oracle):
     assert nplasma > 100
 
 
+def test_render_rays_missing_the_grid(ctx, oracle):
+    """A 120 M wide field around the grid (80 M and 100 M boxes): corner rays
+    never meet the grid's box (no step is sampled, the walk has nothing to do
+    and every step counts as one vacuum record) and others only graze it;
+    polarized and unpolarized, FP64 and mixed.  (Impact parameters stay below
+    the camera radius of 100 M, so every ray passes inside the camera sphere
+    and escapes through it.)"""
+    for name, pol in (("c1_64_unpol", 0), ("c2_256_pol", 1)):
+        w = _wl(name, 12, camera={"width": 120.0})
+        img, aux, io, ao = _compare_render(ctx, oracle, w)
+        assert (ao[9] == ao[5]).sum() > 0, "no ray without a sampled step"
+        assert (io[0] == 0).any()
+        _compare_render(ctx, oracle, w, precision=1, tol=TOL_MIXED)
+
+
 def test_render_unpolarized_uniform(ctx, oracle):
     _compare_render(ctx, oracle, _wl("c1_64_unpol", 20))
 
