@@ -189,12 +189,12 @@ bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *s
 typedef struct {
     int32_t tile_w, tile_h;   /* pixels that share a wave: a tile_w x tile_h
                                  tile with tile_w * tile_h = 64 (default
-                                 16 x 4); 0, 0 = plain row-major order        */
+                                 8 x 8); 0, 0 = plain row-major order         */
     int32_t transfer_waves_per_cu; /* resident waves of the persistent transfer
                                  kernel per compute unit; 0 = as many as fit
                                  (default)                                    */
     int32_t refill_min;       /* a transfer wave takes new rays once this many
-                                 of its lanes are idle (1..64; default 1)     */
+                                 of its lanes are idle (1..64; default 4)     */
     int64_t chunk_rays;       /* rays traced per geodesic/transfer launch pair
                                  (multiple of 64; 0 = as many as the step-
                                  record workspace holds, the default: 128 GiB

@@ -927,7 +927,7 @@ struct bl_context {
     std::vector<ImgDev> h_imgs;
     std::vector<long long> h_ray0;
     hipEvent_t upload_done = nullptr;
-    bl_tuning tuning = {16, 4, 0, 1, 0, 0, 0};
+    bl_tuning tuning = {8, 8, 0, 4, 0, 0, 0};   // the autotuner's choice for the 1024^2 SMR image
     double *d_rec = nullptr;
     size_t rec_bytes = 0;
     double *d_meta = nullptr;
