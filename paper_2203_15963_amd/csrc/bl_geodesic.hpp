@@ -41,6 +41,7 @@ constexpr double M1 = 6025192743.0 / 30085553152.0, M3 = 51252292925.0 / 6540082
 struct TraceOut {
     int status;
     int n_acc, n_rej;
+    int work;   // transfer iterations: pieces of the steps from the last sampled one to the camera
     double lambda, s, dt;
 };
 
@@ -170,7 +171,7 @@ __device__ __forceinline__ bool chord_meets_box(const double bb[6], const double
 //   y(theta) = y0 + theta (c1 + theta (c2 + theta (c3 + theta c4))),
 // the quartic through y0, y1, f0, f1 and ym, formed in FP64 and rounded to
 // FP32 (28 floats, c_j of component m at float 7 (j - 1) + m of slots 8..21).
-__device__ __forceinline__ bool write_record(const GeoParams &P, double *rec, int nacc, const double y0[7], double h,
+__device__ __forceinline__ int write_record(const GeoParams &P, double *rec, int nacc, const double y0[7], double h,
                                              const double ym[7], const double y1[7], const double f0[7],
                                              const double f1[7], double ds) {
     double *r = rec + (long long)nacc * kRecDoubles;
@@ -203,7 +204,7 @@ __device__ __forceinline__ bool write_record(const GeoParams &P, double *rec, in
 #pragma unroll
         for (int m = 0; m < 7; ++m) r[16 + m] = f0[m];
     }
-    return inb;
+    return inb ? nsub : 0;
 }
 
 // The final state and its right-hand side after the last step, and in slot
@@ -283,7 +284,7 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
     double h = -P.h0_frac * (rint(r_prev * 1024.0) / 1024.0);
     double h_last = h, eps_last = 1.0;
     double lambda = 0.0, s = 0.0;
-    int nacc = 0, nrej = 0, status = kRunning, last_sampled = -1;
+    int nacc = 0, nrej = 0, status = kRunning, last_sampled = -1, pieces = 0, work = 0;
     bool no_grow = false;
     while (status == kRunning) {
         if ((long long)nacc + nrej >= P.max_steps) { status = kMaxSteps; break; }
@@ -298,7 +299,14 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
                 break;
             }
             double ds = fabs(h) * ds_dlambda(a, flat, ym, kt);
-            if (WREC && write_record(P, rec, nacc, y, h, ym, y5, k1, k7, ds)) last_sampled = nacc;
+            if (WREC) {
+                const int np = write_record(P, rec, nacc, y, h, ym, y5, k1, k7, ds);
+                pieces += np > 0 ? np : 1;
+                if (np > 0) {
+                    last_sampled = nacc;
+                    work = pieces;
+                }
+            }
             if (LOG) {
                 unsigned long long idx = atomicAdd(lg.count, 1ull);
                 if ((long long)idx < lg.cap) {
@@ -338,6 +346,7 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
     o.status = status;
     o.n_acc = nacc;
     o.n_rej = nrej;
+    o.work = work + (nacc - 1 - last_sampled);
     o.lambda = fabs(lambda);
     o.s = s;
     o.dt = t_pix - y[0];
@@ -367,7 +376,7 @@ __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool activ
     }
     double h_last = h, eps_last = 1.0;
     double lambda = 0.0, s = 0.0;
-    int nacc = 0, nrej = 0, status = active ? kRunning : kEscaped, last_sampled = -1;
+    int nacc = 0, nrej = 0, status = active ? kRunning : kEscaped, last_sampled = -1, pieces = 0, work = 0;
     bool need = true;
     for (;;) {
         const bool run = status == kRunning;
@@ -396,7 +405,14 @@ __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool activ
                 continue;
             }
             double ds = fabs(h) * ds_dlambda(a, flat, ym, kt);
-            if (WREC && write_record(P, rec, nacc, y, h, ym, y5, k1, k7, ds)) last_sampled = nacc;
+            if (WREC) {
+                const int np = write_record(P, rec, nacc, y, h, ym, y5, k1, k7, ds);
+                pieces += np > 0 ? np : 1;
+                if (np > 0) {
+                    last_sampled = nacc;
+                    work = pieces;
+                }
+            }
             ++nacc;
             lambda += h;
             s += ds;
@@ -421,6 +437,7 @@ __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool activ
     o.status = status;
     o.n_acc = nacc;
     o.n_rej = nrej;
+    o.work = work + (nacc - 1 - last_sampled);
     o.lambda = fabs(lambda);
     o.s = s;
     o.dt = t_pix - y[0];

@@ -186,7 +186,8 @@ __device__ __forceinline__ GeoParams lane_params(const GeoParams &P, const ImgDe
 template <bool WREC, bool BATCH>
 __global__ void __launch_bounds__(64, 2) k_geodesic(GeoParams P, Batch B, long long start, int count,
                                                  double *__restrict__ rec, double *__restrict__ meta,
-                                                 int *__restrict__ nacc_out, ExtQueue X, int *__restrict__ ovf_count,
+                                                 int *__restrict__ nacc_out, int *__restrict__ work_out, ExtQueue X,
+                                                 int *__restrict__ ovf_count,
                                                  int *__restrict__ ovf_list, double *__restrict__ state_out) {
     int slot = blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= count) return;
@@ -195,7 +196,7 @@ __global__ void __launch_bounds__(64, 2) k_geodesic(GeoParams P, Batch B, long l
     const ImgDev &im = B.imgs[img];
     int pi, pj;
     if (!ray_pixel(B, im.cp.n, gid - (BATCH ? B.ray0[img] : 0), pi, pj)) {
-        if (WREC) nacc_out[slot] = -2;
+        if (WREC) nacc_out[slot] = work_out[slot] = -2;
         return;
     }
     const GeoParams Q = lane_params<BATCH>(P, im);
@@ -213,12 +214,13 @@ __global__ void __launch_bounds__(64, 2) k_geodesic(GeoParams P, Batch B, long l
         meta[2 * slot] = kt;
         meta[2 * slot + 1] = n;
         if (o.status == kRayOverflow) {
-            nacc_out[slot] = -1;
+            nacc_out[slot] = work_out[slot] = -1;
             int idx = atomicAdd(ovf_count, 1);
             ovf_list[idx] = (int)gid;
             return;
         }
         nacc_out[slot] = o.n_acc;
+        work_out[slot] = o.work;
     }
     aux[BL_AUX_DT * NN + pix] = o.dt;
     aux[BL_AUX_S * NN + pix] = o.s;
@@ -266,24 +268,26 @@ __device__ __forceinline__ void pixel_observer(const Frame &fr, const GeoParams 
 // once at least refill_min lanes are idle, or when none holds a ray.  Every
 // lane leaves the loop once the queue is exhausted and its ray is written.
 // ------------------------------------------------------------- ray order
-// The transfer takes the rays of a chunk longest first (by accepted steps),
-// so that the few very long rays near the photon ring start early and their
-// serial walks overlap the bulk instead of trailing it: a counting sort on
-// kOrderBins bins of n_acc / 8 (the last bin open-ended), in descending bin
-// order.  Each block of 256 rays counts and ranks its rays in LDS and makes
-// one global atomic per non-empty bin.  Slots without a ray for the transfer
-// (nacc < 0) go last.  The order within a bin is not deterministic; results
-// do not depend on it.
+// The transfer takes the rays of a chunk longest first, by the number of
+// walk iterations the geodesic kernel counted for each (the pieces of the
+// steps from the last sampled one to the camera), so that the few very long
+// rays near the photon ring start early and their serial walks overlap the
+// bulk instead of trailing it: a counting sort on kOrderBins bins of
+// work / 32 (the last bin open-ended), in descending bin order.  Each block
+// of 256 rays counts and ranks its rays in LDS and makes one global atomic
+// per non-empty bin.  Slots without a ray for the transfer (work < 0) go
+// last.  The order within a bin is not deterministic; results do not depend
+// on it.
 constexpr int kOrderBins = 64;
 
-__device__ __forceinline__ int order_key(int na) { return na < 0 ? 0 : min(na >> 3, kOrderBins - 1); }
+__device__ __forceinline__ int order_key(int work) { return work < 0 ? 0 : min(work >> 5, kOrderBins - 1); }
 
-__global__ void __launch_bounds__(256) k_order_hist(const int *__restrict__ nacc, int count, int *__restrict__ hist) {
+__global__ void __launch_bounds__(256) k_order_hist(const int *__restrict__ work, int count, int *__restrict__ hist) {
     __shared__ int lh[kOrderBins];
     if (threadIdx.x < kOrderBins) lh[threadIdx.x] = 0;
     __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) atomicAdd(lh + order_key(nacc[i]), 1);
+    if (i < count) atomicAdd(lh + order_key(work[i]), 1);
     __syncthreads();
     if (threadIdx.x < kOrderBins && lh[threadIdx.x]) atomicAdd(hist + threadIdx.x, lh[threadIdx.x]);
 }
@@ -305,13 +309,13 @@ __global__ void __launch_bounds__(kOrderBins) k_order_scan(int *__restrict__ his
     hist[key] = sc[t] - own;
 }
 
-__global__ void __launch_bounds__(256) k_order_scatter(const int *__restrict__ nacc, int count, int *__restrict__ offs,
+__global__ void __launch_bounds__(256) k_order_scatter(const int *__restrict__ work, int count, int *__restrict__ offs,
                                                        int *__restrict__ order) {
     __shared__ int lh[kOrderBins], lb[kOrderBins];
     if (threadIdx.x < kOrderBins) lh[threadIdx.x] = 0;
     __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int key = i < count ? order_key(nacc[i]) : 0;
+    const int key = i < count ? order_key(work[i]) : 0;
     const int rank = i < count ? atomicAdd(lh + key, 1) : 0;
     __syncthreads();
     if (threadIdx.x < kOrderBins) lb[threadIdx.x] = lh[threadIdx.x] ? atomicAdd(offs + threadIdx.x, lh[threadIdx.x]) : 0;
@@ -482,7 +486,8 @@ __global__ void __launch_bounds__(256, 2) k_geodesic_learned(GeoParams P, Batch 
                                                           const u32x4 *__restrict__ pk_g,
                                                           const float *__restrict__ tail_g, double *__restrict__ rec,
                                                           double *__restrict__ meta, int *__restrict__ nacc_out,
-                                                          ExtQueue X, int *__restrict__ ovf_count,
+                                                          int *__restrict__ work_out, ExtQueue X,
+                                                          int *__restrict__ ovf_count,
                                                           int *__restrict__ ovf_list) {
     __shared__ u32x4 s_pk[kPkFwd];
     __shared__ float s_tail[kTailN];
@@ -497,7 +502,7 @@ __global__ void __launch_bounds__(256, 2) k_geodesic_learned(GeoParams P, Batch 
     if (active) {
         img = BATCH ? find_image(B, gid) : 0;
         active = ray_pixel(B, B.imgs[img].cp.n, gid - (BATCH ? B.ray0[img] : 0), pi, pj);
-        if (!active && WREC) nacc_out[slot] = -2;
+        if (!active && WREC) nacc_out[slot] = work_out[slot] = -2;
     }
     const ImgDev &im = B.imgs[img];
     const GeoParams Q = lane_params<BATCH>(P, im);
@@ -515,12 +520,13 @@ __global__ void __launch_bounds__(256, 2) k_geodesic_learned(GeoParams P, Batch 
         meta[2 * slot] = kt;
         meta[2 * slot + 1] = n;
         if (o.status == kRayOverflow) {
-            nacc_out[slot] = -1;
+            nacc_out[slot] = work_out[slot] = -1;
             int idx = atomicAdd(ovf_count, 1);
             ovf_list[idx] = (int)gid;
             return;
         }
         nacc_out[slot] = o.n_acc;
+        work_out[slot] = o.work;
     }
     aux[BL_AUX_DT * NN + pix] = o.dt;
     aux[BL_AUX_S * NN + pix] = o.s;
@@ -932,6 +938,8 @@ struct bl_context {
     size_t rec_bytes = 0;
     double *d_meta = nullptr;
     int *d_nacc = nullptr;
+    int *d_work = nullptr;               // transfer iterations per ray slot (the ray order's key)
+    size_t work_bytes = 0;
     ExtQueue ext{};                      // extension slots of the current chunk
     size_t ext_rec_bytes = 0, ext_of_bytes = 0;
     int *d_order = nullptr;              // processing order of the chunk's slots
@@ -1291,6 +1299,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     if ((s = ensure(ctx, &ctx->d_nacc, have_nacc, (size_t)chunk * sizeof(int))) != BL_OK) return s;
     ctx->slot_cap = std::min(have_meta / (2 * sizeof(double)), have_nacc / sizeof(int));
     if ((s = ensure(ctx, &ctx->d_order, ctx->order_bytes, (size_t)chunk * sizeof(int))) != BL_OK) return s;
+    if ((s = ensure(ctx, &ctx->d_work, ctx->work_bytes, (size_t)chunk * sizeof(int))) != BL_OK) return s;
     if ((s = ensure(ctx, &ctx->d_ends, ctx->ends_bytes,
                     (size_t)chunk * kRayEnd * (mixed ? sizeof(float) : sizeof(double)))) != BL_OK)
         return s;
@@ -1352,17 +1361,19 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
                 if (batch)
                     hipLaunchKernelGGL((k_geodesic_learned<true, true>), lg, lb, 0, ctx->stream, P, B, start, count,
                                        ctx->d_step_pk, ctx->d_step_tail, ctx->d_rec, ctx->d_meta, ctx->d_nacc,
-                                       ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list);
+                                       ctx->d_work, ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list);
                 else
                     hipLaunchKernelGGL((k_geodesic_learned<true, false>), lg, lb, 0, ctx->stream, P, B, start, count,
                                        ctx->d_step_pk, ctx->d_step_tail, ctx->d_rec, ctx->d_meta, ctx->d_nacc,
-                                       ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list);
+                                       ctx->d_work, ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list);
             } else if (batch) {
                 hipLaunchKernelGGL((k_geodesic<true, true>), grd, blk, 0, ctx->stream, P, B, start, count, ctx->d_rec,
-                                   ctx->d_meta, ctx->d_nacc, ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list, nullptr);
+                                   ctx->d_meta, ctx->d_nacc, ctx->d_work, ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list,
+                                   nullptr);
             } else {
                 hipLaunchKernelGGL((k_geodesic<true, false>), grd, blk, 0, ctx->stream, P, B, start, count,
-                                   ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list,
+                                   ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_work, ctx->ext, ctx->d_ovf_count,
+                                   ctx->d_ovf_list,
                                    nullptr);
             }
         }
@@ -1371,9 +1382,9 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
             TimedLaunch tl(ctx, BL_K_SETUP);
             const unsigned nb = (unsigned)((count + 255) / 256);
             hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(kOrderBins), 0, ctx->stream, ctx->d_hist, 0, kOrderBins);
-            hipLaunchKernelGGL(k_order_hist, dim3(nb), dim3(256), 0, ctx->stream, ctx->d_nacc, count, ctx->d_hist);
+            hipLaunchKernelGGL(k_order_hist, dim3(nb), dim3(256), 0, ctx->stream, ctx->d_work, count, ctx->d_hist);
             hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderBins), 0, ctx->stream, ctx->d_hist);
-            hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(256), 0, ctx->stream, ctx->d_nacc, count, ctx->d_hist,
+            hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(256), 0, ctx->stream, ctx->d_work, count, ctx->d_hist,
                                ctx->d_order);
         }
         HIPCHK(ctx, hipGetLastError());
@@ -1482,6 +1493,7 @@ void bl_destroy(bl_context *ctx) {
     (void)hipFree(ctx->d_rec);
     (void)hipFree(ctx->d_meta);
     (void)hipFree(ctx->d_nacc);
+    (void)hipFree(ctx->d_work);
     (void)hipFree(ctx->d_order);
     (void)hipFree(ctx->ext.count);
     (void)hipFree(ctx->ext.of);
@@ -1631,7 +1643,7 @@ bl_status bl_trace_geodesics(bl_context *ctx, const bl_camera *cam, const bl_spa
         int count = (int)std::min(chunk, total - start);
         TimedLaunch tl(ctx, BL_K_GEODESIC);
         hipLaunchKernelGGL((k_geodesic<false, false>), dim3((count + 63) / 64), dim3(64), 0, ctx->stream, P, B, start,
-                           count, nullptr, nullptr, nullptr, ExtQueue{}, nullptr, nullptr, state_out);
+                           count, nullptr, nullptr, nullptr, nullptr, ExtQueue{}, nullptr, nullptr, state_out);
         HIPCHK(ctx, hipGetLastError());
     }
     return BL_OK;
