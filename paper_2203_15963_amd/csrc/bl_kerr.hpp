@@ -266,6 +266,29 @@ __device__ __forceinline__ R conn_om(const ConnF<R> &c, int a, R n1, R n2, R n3)
     return a == 1 ? c.oxy * n2 + c.oxz * n3 : (a == 2 ? c.oyz * n3 - c.oxy * n1 : -(c.oxz * n1 + c.oyz * n2));
 }
 
+// -G v for a contravariant v: the rate of change of a vector parallel
+// transported along the ray, dv^a/dlambda = -G^a_d v^d.
+template <typename R>
+__device__ __forceinline__ void conn_vec(const ConnF<R> &c, const R v[4], R out[4]) {
+    const R bv = c.B[0] * v[0] + c.B[1] * v[1] + c.B[2] * v[2] + c.B[3] * v[3];
+    const R lv = c.l4[0] * v[0] + c.l4[1] * v[1] + c.l4[2] * v[2] + c.l4[3] * v[3];
+    out[0] = -(c.lu[0] * bv + c.Yt[0] * lv);
+#pragma unroll
+    for (int a = 1; a < 4; ++a) out[a] = -(c.lu[a] * bv + c.Yt[a] * lv + conn_om(c, a, v[1], v[2], v[3]));
+}
+
+// The adjoint of conn_vec for a covariant x: out_d = -x_a G^a_d, so that
+// x . conn_vec(v) = conn_covec(x) . v.  The spatial h Om is antisymmetric,
+// so x_a (h Om)_ad = -((h Om) x)_d.
+template <typename R>
+__device__ __forceinline__ void conn_covec(const ConnF<R> &c, const R x[4], R out[4]) {
+    const R xl = c.lu[0] * x[0] + c.lu[1] * x[1] + c.lu[2] * x[2] + c.lu[3] * x[3];
+    const R xy = c.Yt[0] * x[0] + c.Yt[1] * x[1] + c.Yt[2] * x[2] + c.Yt[3] * x[3];
+    out[0] = -(xl * c.B[0] + xy * c.l4[0]);
+#pragma unroll
+    for (int d = 1; d < 4; ++d) out[d] = conn_om(c, d, x[1], x[2], x[3]) - (xl * c.B[d] + xy * c.l4[d]);
+}
+
 // Full G (row-major a, d), FP64, for checking.
 __device__ __forceinline__ void conn_k(double a, int flat, const double x[4], const double kc[4], double G[16]) {
     ConnF<double> c;

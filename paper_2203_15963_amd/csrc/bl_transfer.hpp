@@ -169,6 +169,100 @@ __device__ __forceinline__ void stokes_to_coh(const R e1[4], const R e2[4], cons
         for (int b = a + 1; b < 4; ++b) N.i[aidx(a, b)] = n12i * (e1[a] * e2[b] - e2[a] * e1[b]);
 }
 
+// Right after a Stokes step N = E S E^T exactly (stokes_to_coh), E = (e1, e2)
+// of that sample, so the state is kept as those two vectors and the Stokes
+// parameters, in the storage of N: r[0..3] = e1, r[4..7] = e2 and
+// (r[8], r[9], i[0], i[1]) = (I, Q, U, V).
+template <typename R>
+__device__ __forceinline__ void pack_screen(const R e1[4], const R e2[4], const R S[4], Coh<R> &N) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        N.r[m] = e1[m];
+        N.r[4 + m] = e2[m];
+    }
+    N.r[8] = S[0];
+    N.r[9] = S[1];
+    N.i[0] = S[2];
+    N.i[1] = S[3];
+}
+
+// The full N of a packed state.
+template <typename R>
+__device__ __forceinline__ void unpack_screen(Coh<R> &N) {
+    R e1[4], e2[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        e1[m] = N.r[m];
+        e2[m] = N.r[4 + m];
+    }
+    const R S[4] = {N.r[8], N.r[9], N.i[0], N.i[1]};
+    stokes_to_coh(e1, e2, S, N);
+}
+
+// a . b over four components
+template <typename R>
+__device__ __forceinline__ R dot4(const R *a, const R *b) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3];
+}
+
+// Stokes parameters on the screen (p, q: covariant e1, e2 of the new sample)
+// of a packed state after one merged transport step, without forming N.  The
+// step (transport_step) is N' = N + dl A_b(h), h = N + dl/2 A_a(N) with
+// A(N) = L N + N L^T, L = -G at the predictor (a) and corrector (b) points.
+// With N = E S E^T and F = L_a E (conn_vec at a):
+//   h  = P S P^T - dl^2/4 F S F^T,   P = E + dl/2 F,
+//   N' = E S E^T + dl (L_b P S P^T + P S (L_b P)^T)
+//        - dl^3/4 (L_b F S F^T + F S (L_b F)^T),
+// so x^T N' y needs only the contractions of E and F with x and with
+// xt = L_b^T x (conn_covec at b; (L_b P)^T x = P^T xt): the same numbers as
+// the merged transport followed by coh_to_stokes, up to rounding, in about
+// 40 % of the operations.  pt, qt = L_b^T p, L_b^T q.
+template <typename R>
+__device__ __forceinline__ void screen_transport_stokes(const Coh<R> &N, const R F[2][4], const R pt[4], const R qt[4],
+                                                        const R p[4], const R q[4], R dl, R S[4]) {
+    const R hd = R(0.5) * dl, c3 = R(0.25) * dl * dl * dl;
+    // per covector x and column I: E_x = E_I.x, F_x = F_I.x, R_x = F_I.xt,
+    // P_x = E_x + dl/2 F_x, Q_x = E_I.xt + dl/2 R_x
+    R Ep[2], Fp[2], Rp[2], Pp[2], Qp[2], Eq[2], Fq[2], Rq[2], Pq[2], Qq[2];
+#pragma unroll
+    for (int I = 0; I < 2; ++I) {
+        const R *EI = N.r + 4 * I;
+        Ep[I] = dot4(EI, p);
+        Fp[I] = dot4(F[I], p);
+        Rp[I] = dot4(F[I], pt);
+        Pp[I] = Ep[I] + hd * Fp[I];
+        Qp[I] = dot4(EI, pt) + hd * Rp[I];
+        Eq[I] = dot4(EI, q);
+        Fq[I] = dot4(F[I], q);
+        Rq[I] = dot4(F[I], qt);
+        Pq[I] = Eq[I] + hd * Fq[I];
+        Qq[I] = dot4(EI, qt) + hd * Rq[I];
+    }
+    // M_IJ(x, y) = E_x,I E_y,J + dl (Q_x,I P_y,J + P_x,I Q_y,J) - dl^3/4 (R_x,I F_y,J + F_x,I R_y,J)
+    auto M = [&](const R *Ex, const R *Fx, const R *Rx, const R *Px, const R *Qx, const R *Ey, const R *Fy,
+                 const R *Ry, const R *Py, const R *Qy, int I, int J) -> R {
+        return Ex[I] * Ey[J] + dl * (Qx[I] * Py[J] + Px[I] * Qy[J]) - c3 * (Rx[I] * Fy[J] + Fx[I] * Ry[J]);
+    };
+    // S_11 = (I + Q)/2, S_22 = (I - Q)/2, S_12 = conj S_21 = (U - i V)/2
+    const R s11 = R(0.5) * (N.r[8] + N.r[9]), s22 = R(0.5) * (N.r[8] - N.r[9]);
+    const R rho = R(0.5) * N.i[0], sig = R(-0.5) * N.i[1];
+    const R n11 = s11 * M(Ep, Fp, Rp, Pp, Qp, Ep, Fp, Rp, Pp, Qp, 0, 0) +
+                  s22 * M(Ep, Fp, Rp, Pp, Qp, Ep, Fp, Rp, Pp, Qp, 1, 1) +
+                  R(2) * rho * M(Ep, Fp, Rp, Pp, Qp, Ep, Fp, Rp, Pp, Qp, 0, 1);
+    const R n22 = s11 * M(Eq, Fq, Rq, Pq, Qq, Eq, Fq, Rq, Pq, Qq, 0, 0) +
+                  s22 * M(Eq, Fq, Rq, Pq, Qq, Eq, Fq, Rq, Pq, Qq, 1, 1) +
+                  R(2) * rho * M(Eq, Fq, Rq, Pq, Qq, Eq, Fq, Rq, Pq, Qq, 0, 1);
+    const R m01 = M(Ep, Fp, Rp, Pp, Qp, Eq, Fq, Rq, Pq, Qq, 0, 1);
+    const R m10 = M(Ep, Fp, Rp, Pp, Qp, Eq, Fq, Rq, Pq, Qq, 1, 0);
+    const R n12r = s11 * M(Ep, Fp, Rp, Pp, Qp, Eq, Fq, Rq, Pq, Qq, 0, 0) +
+                   s22 * M(Ep, Fp, Rp, Pp, Qp, Eq, Fq, Rq, Pq, Qq, 1, 1) + rho * (m01 + m10);
+    const R n12i = sig * (m01 - m10);
+    S[0] = n11 + n22;
+    S[1] = n11 - n22;
+    S[2] = R(2) * n12r;
+    S[3] = R(-2) * n12i;
+}
+
 // Exact solution of dS/ds = J - M S over unit length (the coefficients carry
 // the segment length) for thermal coefficients, where Kirchhoff's law gives
 // J = B_nu M e_I (B_nu = j_I/alpha_I):
@@ -371,6 +465,7 @@ struct RayWalk {
     int nsub;
     double inv_nsub;     // 1 / nsub
     bool inb, started;
+    bool fresh;          // N packed by pack_screen (the last sample did a Stokes step)
     R dl, pdl;           // affine length of the open step's pieces, and of the previous piece
     R I, tau, Ij;
     R tau_c, Ij_c;       // compensation terms of the two sums
@@ -397,6 +492,7 @@ __device__ __forceinline__ void begin_ray(RayWalk<R> &w, const double *rec, int 
     w.inv_nsub = 1.0;
     w.inb = false;
     w.started = false;
+    w.fresh = false;
     w.dl = w.pdl = R(0);
     w.I = w.tau = w.Ij = w.tau_c = w.Ij_c = R(0);
     w.nsamp = 0;
@@ -546,11 +642,60 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
     if (!w.started && !smp.plasma) return;
     const R ktr = (R)w.kt;
     const R ar = (R)P.a;
-    if (w.started) {
-        R ya[8], yc[8];
-        to_state_r(w.pys, ktr, ya);
-        to_state_r(w.pyb, ktr, yc);
-        transport_step<R>(ar, flat, ya, yc, R(0.5) * (w.pdl + w.dl), w.N);
+    bool stk = false;   // a Stokes step at this sample
+    if (smp.plasma) {
+        ++w.nsamp;
+        csum(w.tau, w.tau_c, c[3]);
+        csum(w.Ij, w.Ij_c, c[0]);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) stk = stk || (c[m] != R(0));
+    }
+    const R dlt = R(0.5) * (w.pdl + w.dl);
+    R ya[8], yc[8];
+    to_state_r(w.pys, ktr, ya);
+    to_state_r(w.pyb, ktr, yc);
+    const R kc[4] = {(R)ys[4], (R)ys[5], (R)ys[6], (R)ys[7]};
+    R S[4] = {R(0), R(0), R(0), R(0)};
+    R e1[4], e2[4], pc[4], qc[4], e3[4];
+    // A lane that does a Stokes step here from a packed state (or from
+    // nothing, at the first sample of its walk) needs only the screen
+    // projection of the transported N.  The choice is the lane's own, so a
+    // ray's arithmetic does not depend on the rays that share its wave.
+    if (stk && (w.fresh || !w.started)) {
+        screen_basis(smp.k, smp.u, kc, smp.b, e1, e2, pc, qc, e3);
+        if (w.started) {
+            R F[2][4], pt[4], qt[4];
+            if (flat) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) F[0][m] = F[1][m] = pt[m] = qt[m] = R(0);
+            } else {
+                ConnF<R> cn;
+                conn_geom(ar, flat, ya, ya + 4, cn);
+                conn_vec(cn, w.N.r, F[0]);
+                conn_vec(cn, w.N.r + 4, F[1]);
+                conn_geom(ar, flat, yc, yc + 4, cn);
+                conn_covec(cn, pc, pt);
+                conn_covec(cn, qc, qt);
+            }
+            screen_transport_stokes(w.N, F, pt, qt, pc, qc, dlt, S);
+        }
+    } else {
+        if (w.started) {
+            if (w.fresh) {
+                unpack_screen(w.N);
+                w.fresh = false;
+            }
+            transport_step<R>(ar, flat, ya, yc, dlt, w.N);
+        }
+        if (stk) {
+            screen_basis(smp.k, smp.u, kc, smp.b, e1, e2, pc, qc, e3);
+            coh_to_stokes(pc, qc, w.N, S);
+        }
+    }
+    if (stk) {
+        stokes_step(c, S);
+        pack_screen(e1, e2, S, w.N);
+        w.fresh = true;
     }
     w.started = true;
 #pragma unroll
@@ -559,24 +704,6 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
         w.pyb[m] = (R)yb[m < 3 ? m + 1 : m + 2];
     }
     w.pdl = w.dl;
-    if (smp.plasma) {
-        ++w.nsamp;
-        csum(w.tau, w.tau_c, c[3]);
-        csum(w.Ij, w.Ij_c, c[0]);
-        bool any = false;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) any = any || (c[m] != R(0));
-        if (any) {
-            const KS<R> &k = smp.k;
-            R kc[4] = {(R)ys[4], (R)ys[5], (R)ys[6], (R)ys[7]};
-            R e1[4], e2[4], p[4], q[4], e3[4];
-            screen_basis(k, smp.u, kc, smp.b, e1, e2, p, q, e3);
-            R S[4];
-            coh_to_stokes(p, q, w.N, S);
-            stokes_step(c, S);
-            stokes_to_coh(e1, e2, S, w.N);
-        }
-    }
 }
 
 // Close the ray at the pixel: final half transport, camera Stokes basis.
@@ -593,6 +720,7 @@ __device__ __forceinline__ void finish_ray(RayWalk<R> &w, const GeoParams &P, co
         return;
     }
     if (!w.started) return;
+    if (w.fresh) unpack_screen(w.N);
     const double *rec = w.rec;
     const R ktr = (R)w.kt, ar = (R)P.a;
     R y0[8];
@@ -615,8 +743,8 @@ __device__ __forceinline__ void finish_ray(RayWalk<R> &w, const GeoParams &P, co
 // transfer kernel to the finishing kernel so that the final transport and
 // projection (a few hundred operations for one lane) run converged over all
 // rays instead of with the rest of a wave waiting: kRayEnd values of R per ray,
-// N (16), the previous sample (6), pdl, tau, Ij, k_t, then nsamp, nrec and
-// started as integers stored bit for bit.
+// N (16, packed or full), the previous sample (6), pdl, tau, Ij, k_t, then
+// nsamp, nrec, started and the packed flag as integers stored bit for bit.
 constexpr int kRayEnd = 32;
 
 template <typename R>
@@ -646,7 +774,8 @@ __device__ __forceinline__ void store_ray_end(const RayWalk<R> &w, R *e) {
     v[26] = from_int<R>(w.nsamp);
     v[27] = from_int<R>(w.nrec);
     v[28] = from_int<R>(w.started ? 1 : 0);
-    v[29] = v[30] = v[31] = R(0);
+    v[29] = from_int<R>(w.fresh ? 1 : 0);
+    v[30] = v[31] = R(0);
     typedef R rv __attribute__((ext_vector_type(16 / sizeof(R))));
     constexpr int NE = 16 / sizeof(R);
     rv *d = reinterpret_cast<rv *>(e);
@@ -675,6 +804,7 @@ __device__ __forceinline__ void load_ray_end(RayWalk<R> &w, const R *e, const do
     w.nsamp = as_int(e[26]);
     w.nrec = as_int(e[27]);
     w.started = as_int(e[28]) != 0;
+    w.fresh = as_int(e[29]) != 0;
 }
 
 // Whole ray by one lane (used where rays are not interleaved).
