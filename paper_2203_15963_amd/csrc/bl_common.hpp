@@ -88,14 +88,29 @@ __device__ __forceinline__ double fexpm1(double x) {
     const double small = x * fma(x, od, ev);
     return fabs(x) < 0.7 ? small : fexp(x) - 1.0;
 }
-// 1/sqrt(x): the hardware unit in FP32, a correctly rounded square root and
-// division in FP64
+// 1/x in FP64: the hardware estimate refined by two Newton steps
+// y <- y + y (1 - x y), which square the estimate's relative error each time:
+// within about an ulp, though not always the correctly rounded quotient.  For
+// normal finite x (x = 0 gives a NaN rather than an infinity).
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) y = fma(y, fma(-x, y, 1.0), y);
+    return y;
+}
+// 1/sqrt(x): the hardware unit in FP32; in FP64 its estimate refined by two
+// Newton steps y <- y (3/2 - x y^2 / 2) (about an ulp), for normal x > 0
 __device__ __forceinline__ float rsqrt_r(float x) { return rsqrtf(x); }
-__device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
-// a / b: the hardware reciprocal in FP32 (about 1 ulp), a correctly rounded
-// division in FP64
+__device__ __forceinline__ double rsqrt_r(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) y = y * (1.5 - (0.5 * x) * (y * y));
+    return y;
+}
+// a / b: the hardware reciprocal in FP32 (about 1 ulp), in FP64 a times the
+// refined reciprocal (within about two ulp)
 __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ double fdiv(double a, double b) { return a * rcp_nr(b); }
 // cos for arguments of moderate size: the hardware unit in FP32, the library in FP64
 __device__ __forceinline__ float fcos(float x) { return __cosf(x); }
 __device__ __forceinline__ double fcos(double x) { return cos(x); }

@@ -94,7 +94,8 @@ __device__ __forceinline__ void dp_trial(const GeoParams &P, const double y[7], 
             y5m = y5[q];
         }
         double sc = P.f_abs + P.f_rel * fmax(fabs(y0m), fabs(y5m));
-        double e = (err == 0.0) ? 0.0 : fabs(err) / sc;
+        // (a zero scale, with both tolerances zero, divides: |err|/0 = inf)
+        double e = (err == 0.0) ? 0.0 : (sc > 0.0 ? fabs(err) * rcp_nr(sc) : fabs(err) / sc);
         if (isnan(e)) bad = true;
         else if (e > eps) eps = e;
     }

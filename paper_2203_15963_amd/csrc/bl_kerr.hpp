@@ -31,7 +31,8 @@ __device__ __forceinline__ R ks_r(R a, R x, R y, R z) {
 // 1/s, s = sqrt((R^2 - a^2)^2 + 4 a^2 z^2).  From the quartic defining r,
 // r^4 + a^2 z^2 = r^2 s, so f = 2 r^3/(r^4 + a^2 z^2) = 2 r/s and
 // 1/(r^4 + a^2 z^2) = (1/r)^2 (1/s): one square root, one reciprocal square
-// root and one reciprocal (a division in FP64).
+// root and one reciprocal (in FP64 both from the hardware estimates refined
+// by Newton steps).
 template <typename R>
 struct KSCore {
     R r, ir, ira, is;
@@ -65,13 +66,13 @@ __device__ __forceinline__ KSCore<R> ks_core(R a, R x, R y, R z) {
         c.is = q * inv;
     } else {
         // 1/sqrt(r2): the hardware estimate and two Newton steps (about one
-        // ulp), independent of the one division, so the two chains overlap
+        // ulp), independent of the one reciprocal, so the two chains overlap
         double y = __builtin_amdgcn_rsq(r2);
 #pragma unroll
         for (int it = 0; it < 2; ++it) y = y * (1.5 - (0.5 * r2) * (y * y));
         c.ir = y;
         c.r = r2 > R(0) ? r2 * y : R(0);
-        const R inv = R(1) / (q * s);
+        const R inv = rcp_nr(q * s);
         c.ira = s * inv;
         c.is = q * inv;
     }

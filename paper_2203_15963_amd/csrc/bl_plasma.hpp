@@ -193,13 +193,13 @@ __device__ __forceinline__ void bessel_ratios(R x, R ix, R &r0, R &r1) {   // ix
         K1 = ix + R(0.5) * x * (L * A - R(0.5) * S1);
         K2 = K0 + R(2) * ix * K1;
     } else {
-        R hq = dbl ? fmin(R(0.15), R(0.5) / sqrt(x)) : fmin(R(0.3), R(0.7) / sqrt(x));
+        R hq = dbl ? fmin(R(0.15), R(0.5) * rsqrt_r(x)) : fmin(R(0.3), R(0.7) * rsqrt_r(x));
         const R stop = dbl ? R(40) : R(20);
         R s0 = R(0.5), s1 = R(0.5), s2 = R(0.5);
         for (int i = 1; i < 400; ++i) {
             R t = (R)i * hq;
             R em = fexpm1(t);
-            R cm = em * em / (R(2) * (R(1) + em));   // cosh t - 1
+            R cm = fdiv(em * em, R(2) * (R(1) + em));   // cosh t - 1
             R c = R(1) + cm;
             R wgt = fexp(-x * cm);
             s0 += wgt;
@@ -211,7 +211,7 @@ __device__ __forceinline__ void bessel_ratios(R x, R ix, R &r0, R &r1) {   // ix
         K1 = s1;
         K2 = s2;
     }
-    const R iK2 = R(1) / K2;
+    const R iK2 = fdiv(R(1), K2);
     r0 = K0 * iK2;
     r1 = K1 * iK2;
 }
@@ -238,11 +238,11 @@ __device__ __forceinline__ void thermal_coeffs(R ne, R th, R B, R nu, R cth, int
     cth = fmin(R(1), fmax(R(-1), cth));
     R sth = sqrt(R(1) - cth * cth);
     if (!(ne > R(0)) || !(th > R(0)) || !(B > R(0)) || !(sth > R(0))) return;
-    const R inu = R(1) / nu, ith = R(1) / th;
+    const R inu = fdiv(R(1), nu), ith = fdiv(R(1), th);
     const R nuB = R(kNuB) * B;
-    const R x = nu / (R(1.5) * nuB * sth * th * th);
+    const R x = fdiv(nu, R(1.5) * nuB * sth * th * th);
     const R x13 = fexp(flog(x) * R(1.0 / 3.0));
-    const R xm13 = R(1) / x13;
+    const R xm13 = fdiv(R(1), x13);
     const R xm23 = xm13 * xm13;
     const R E = fexp(R(-1.8899) * x13);
     const R pre = (ne * R(kPreI)) * nu * (ith * ith);
@@ -255,7 +255,7 @@ __device__ __forceinline__ void thermal_coeffs(R ne, R th, R B, R nu, R cth, int
     if (!polarized) return;
     const R jQ = pre * R(2.5651) * (R(1) + R(0.932) * xm13 + R(0.4998) * xm23) * E;
     const R ix = xm13 * xm13 * xm13, isx = rsqrt_r(x);
-    const R jV = (ne * R(kPreV)) * nu * (cth / sth) * (ith * ith * ith) *
+    const R jV = (ne * R(kPreV)) * nu * fdiv(cth, sth) * (ith * ith * ith) *
                  (R(1.8138) * ix + R(3.423) * xm23 + R(0.02955) * isx + R(2.0377) * xm13) * E;
     out[1] = jQ;
     out[2] = jV;
@@ -316,22 +316,22 @@ __device__ __forceinline__ void sample_point(double a, int flat, const DevGrid &
     lower(k, s.u, ul);
     R bt = prim[5] * ul[1] + prim[6] * ul[2] + prim[7] * ul[3];
     s.b[0] = bt;
-    R iut = R(1) / s.u[0];
+    R iut = fdiv(R(1), s.u[0]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) s.b[1 + c] = (prim[5 + c] + bt * s.u[1 + c]) * iut;
     R b2 = gdot(k, s.b, s.b);
-    s.sigma = b2 / rho;
+    s.sigma = fdiv(b2, rho);
     if (s.sigma > (R)pp.sigma_max) return;
-    R binv = b2 / (R(2) * p);
+    R binv = fdiv(b2, R(2) * p);
     R ne = rho * (R)pp.ne_per_rho;
-    R tr = ((R)pp.r_high + binv * binv * (R)pp.r_low) / (R(1) + binv * binv);
-    R th = (R)pp.th_per_pr * (p / rho) * (R)(pp.ne_ni + 1.0) / ((R)pp.ne_ni + tr);
+    R tr = fdiv((R)pp.r_high + binv * binv * (R)pp.r_low, R(1) + binv * binv);
+    R th = (R)pp.th_per_pr * fdiv(p, rho) * fdiv((R)(pp.ne_ni + 1.0), (R)pp.ne_ni + tr);
     R Bg = sqrt(b2) * (R)pp.gauss_per_b;
     R kc[4] = {(R)yd[4], (R)yd[5], (R)yd[6], (R)yd[7]};
     R omega = -(kc[0] * s.u[0] + kc[1] * s.u[1] + kc[2] * s.u[2] + kc[3] * s.u[3]);
     R kb = kc[0] * s.b[0] + kc[1] * s.b[1] + kc[2] * s.b[2] + kc[3] * s.b[3];
     R nu = (R)n_norm * omega;
-    R cth = (b2 > R(0)) ? kb / (omega * sqrt(b2)) : R(0);
+    R cth = (b2 > R(0)) ? fdiv(kb, omega * sqrt(b2)) : R(0);
     thermal_coeffs<R>(ne, th, Bg, nu, cth, pp.polarized, s.co);
     s.omega = omega;
     s.ne = ne;

@@ -336,7 +336,7 @@ __device__ __forceinline__ void dd_series(R p, R q, R &dc, R &ds) {
 template <typename R>
 __device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
     const R aI = c[3];
-    const R Bnu = aI > R(0) ? c[0] / aI : R(0);
+    const R Bnu = aI > R(0) ? fdiv(c[0], aI) : R(0);
     if (aI >= R(100)) {
         S[0] = Bnu;
         S[1] = S[2] = S[3] = R(0);
@@ -378,9 +378,9 @@ __device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
         fsincos(L2, sn, cs);
         cq = L2s <= R(1) ? cm1_series(-L2s) : cs - R(1);
         const R ep = fexp(L1 - aI), em = fexp(-L1 - aI);   // e^{-aI} e^{+-L1}
-        shq = L2s <= R(1) ? sh_series(-L2s) : sn / L2;
-        shp = L1s <= R(1) ? E * sh_series(L1s) : R(0.5) * (ep - em) / L1;
-        const R iT = R(1) / Th;
+        shq = L2s <= R(1) ? sh_series(-L2s) : fdiv(sn, L2);
+        shp = L1s <= R(1) ? E * sh_series(L1s) : fdiv(R(0.5) * (ep - em), L1);
+        const R iT = fdiv(R(1), Th);
         dc = (R(0.5) * (ep + em) - E * (R(1) + cq)) * iT;
         ds = (shp - E * shq) * iT;
         fp = R(-0.5) * (fexpm1(L1 - aI) + fexpm1(-L1 - aI));
@@ -394,7 +394,7 @@ __device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
     if (Bnu > R(0)) {
         const R X = c[4] * c[7] - c[5] * c[6];
         const R den = R(0.5) * (al2 + rh2) + rt;
-        const R u0 = den > R(0) ? X * X / den : R(0);
+        const R u0 = den > R(0) ? fdiv(X * X, den) : R(0);
         // K' e_I = (0, aQ, 0, aV);  K' u for u = (u0, 0, -X, 0)
         const R ku1 = c[4] * u0 - c[7] * X, ku3 = c[5] * u0 + c[6] * X;
         S[0] += Bnu * (fp - dc * u0);
@@ -411,8 +411,8 @@ __device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
 template <typename R>
 __device__ __forceinline__ R unpol_segment(R I, R j, R dtau) {
     if (dtau > R(0)) {
-        if (dtau < R(100)) return I + fexpm1(-dtau) * (I - j / dtau);
-        return j / dtau;
+        if (dtau < R(100)) return I + fexpm1(-dtau) * (I - fdiv(j, dtau));
+        return fdiv(j, dtau);
     }
     return I + j;
 }
@@ -624,7 +624,7 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
     R c[8];
     if (smp.plasma) {
         R lt = w.L * w.dl * smp.omega;
-        R ljw = w.lj * w.dl / (smp.omega * smp.omega);
+        R ljw = fdiv(w.lj * w.dl, smp.omega * smp.omega);
 #pragma unroll
         for (int m = 0; m < 3; ++m) c[m] = smp.co[m] * ljw;
 #pragma unroll
