@@ -158,8 +158,12 @@ void bl_destroy(bl_context *ctx);
 const char *bl_last_error(const bl_context *ctx);
 
 /* Describe device-resident cell data for sampling; copies the block table
-   (host) and builds the block lookup table on the device.  The primitive
-   array is borrowed, not copied. */
+   (host) and builds the block lookup table on the device: 64 bytes per cell
+   of the lattice of the smallest block size (at most 2^24 cells, so at most
+   1 GiB), each holding what locating a point in its block needs.  The
+   primitive array is borrowed, not copied.  BL_E_UNSUPPORTED for blocks not
+   on that lattice or a larger lattice, BL_E_INVALID_ARG for overlapping
+   blocks, BL_E_OOM if the table does not fit. */
 bl_status bl_grid_create(bl_context *ctx, const bl_grid_desc *desc, bl_grid **out);
 void bl_grid_destroy(bl_grid *grid);
 

@@ -168,8 +168,11 @@ struct GeoParams {
 // Device view of the block-structured grid.
 struct DevGrid {
     const void *prims;        // [nb][bnz][bny][bnx][8], float64 or float32
-    const double *bmeta;      // [nb][6] = x0, y0, z0, 1/dx, 1/dy, 1/dz (inverse cell sizes)
-    const int *table;         // [tnz][tny][tnx] leaf block per table cell, -1 = none
+    // [tnz][tny][tnx][8] per cell of the block lattice, as doubles: the
+    // covering leaf block's origin x0, y0, z0, inverse cell sizes 1/dx, 1/dy,
+    // 1/dz and the index of its first cell (-1: no block), then a pad; 64
+    // bytes, so that one lookup brings what locating a cell needs
+    const double *table;
     double bb[6];             // bounding box x0,x1,y0,y1,z0,z1
     double t0[3], tb[3];      // table origin and cell size
     double itb[3];            // 1 / table cell size

@@ -22,18 +22,18 @@
 namespace bl {
 
 // ---------------------------------------------------------------- lookup
-// Block holding x: the table maps a cell of the finest block lattice to the
-// leaf block covering it (half-open boxes, so faces belong to the upper block).
-__device__ __forceinline__ int find_block(const DevGrid &g, const double x[3]) {
+// Table entry of the block lattice cell holding x (half-open boxes, so faces
+// belong to the upper block), or nullptr outside the lattice.
+__device__ __forceinline__ const double *find_block(const DevGrid &g, const double x[3]) {
     int idx[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         double u = (x[d] - g.t0[d]) * g.itb[d];
-        if (!(u >= 0.0) || u >= (double)g.tn[d]) return -1;
+        if (!(u >= 0.0) || u >= (double)g.tn[d]) return nullptr;
         idx[d] = (int)floor(u);
-        if (idx[d] >= g.tn[d]) return -1;
+        if (idx[d] >= g.tn[d]) return nullptr;
     }
-    return g.table[(idx[2] * g.tn[1] + idx[1]) * g.tn[0] + idx[0]];
+    return g.table + 8 * (long long)((idx[2] * g.tn[1] + idx[1]) * g.tn[0] + idx[0]);
 }
 
 // Cells hold 8 primitives (32 or 64 contiguous bytes, 16-byte aligned) and
@@ -41,16 +41,18 @@ __device__ __forceinline__ int find_block(const DevGrid &g, const double x[3]) {
 typedef float gf4 __attribute__((ext_vector_type(4)));
 typedef double gd2 __attribute__((ext_vector_type(2)));
 
-// A block's origin and inverse cell sizes (six doubles, 16-byte aligned).
-__device__ __forceinline__ void block_meta(const DevGrid &g, int b, double o[3], double is[3]) {
-    const gd2 *p = reinterpret_cast<const gd2 *>(g.bmeta + 6 * (long long)b);
-    const gd2 m0 = p[0], m1 = p[1], m2 = p[2];
+// A table entry: the block's origin, inverse cell sizes and first cell
+// (negative: no block), in four 16-byte loads.
+__device__ __forceinline__ long long block_meta(const double *e, double o[3], double is[3]) {
+    const gd2 *p = reinterpret_cast<const gd2 *>(e);
+    const gd2 m0 = p[0], m1 = p[1], m2 = p[2], m3 = p[3];
     o[0] = m0[0];
     o[1] = m0[1];
     o[2] = m1[0];
     is[0] = m1[1];
     is[1] = m2[0];
     is[2] = m2[1];
+    return (long long)m3[0];
 }
 
 // Trilinear weights of the eight corners, corner q = (di, dj, dk) = (q & 1, (q >> 1) & 1, q >> 2).
@@ -95,22 +97,22 @@ __device__ __forceinline__ void trilerp(const T *base, long long c0, long long s
     }
 }
 
-// Interpolated primitives at x; returns the block id or -1 (vacuum).  Block
-// search and cell location in double, weights and accumulation in R.  Blocks
+// Interpolated primitives at x; returns false outside every block (vacuum).
+// Block search and cell location in double, weights and accumulation in R.  Blocks
 // have at least two cells per axis (checked when the grid is made), so the
 // clamped corner indices i0, i0 + 1 always lie inside the block and all eight
 // corners are read, those of weight zero included.
 template <typename R>
-__device__ __forceinline__ int sample_grid(const DevGrid &g, int interp, const double x[3], R prim[8]) {
-    const int b = find_block(g, x);
-    if (b < 0) return -1;
+__device__ __forceinline__ bool sample_grid(const DevGrid &g, int interp, const double x[3], R prim[8]) {
+    const double *e = find_block(g, x);
+    if (!e) return false;
     double o[3], is[3];
-    block_meta(g, b, o, is);
+    const long long cb = block_meta(e, o, is);
+    if (cb < 0) return false;
     const int nn[3] = {g.bnx, g.bny, g.bnz};
 #pragma unroll
     for (int m = 0; m < 8; ++m) prim[m] = R(0);
     const long long sy = g.bnx, sz = (long long)g.bny * g.bnx;
-    const long long cb = (long long)b * g.bnz * sz;
     if (!interp) {
         int i0[3];
 #pragma unroll
@@ -136,7 +138,7 @@ __device__ __forceinline__ int sample_grid(const DevGrid &g, int interp, const d
                 prim[2 * k + 1] = (R)v[1];
             }
         }
-        return b;
+        return true;
     }
     int i0[3];
     R w[3];
@@ -155,7 +157,7 @@ __device__ __forceinline__ int sample_grid(const DevGrid &g, int interp, const d
         trilerp<4>((const float *)g.prims, c0, sy, sz, w, prim);
     else
         trilerp<sizeof(R) == 8 ? 4 : 2>((const double *)g.prims, c0, sy, sz, w, prim);
-    return b;
+    return true;
 }
 
 // ---------------------------------------------------------------- Bessel
@@ -305,7 +307,7 @@ __device__ __forceinline__ void sample_point(double a, int flat, const DevGrid &
 #pragma unroll
     for (int m = 0; m < 8; ++m) s.co[m] = R(0);
     R prim[8];
-    if (sample_grid<R>(g, pp.interp, yd + 1, prim) < 0) return;
+    if (!sample_grid<R>(g, pp.interp, yd + 1, prim)) return;
     R rho = prim[0], p = prim[1];
     if (!(rho > R(0))) return;
     s.k = ks_point<R>((R)a, flat, (R)yd[1], (R)yd[2], (R)yd[3]);

@@ -987,8 +987,7 @@ struct bl_context {
 struct bl_grid {
     bl_context *ctx = nullptr;
     DevGrid g{};
-    double *d_bmeta = nullptr;
-    int *d_table = nullptr;
+    double *d_table = nullptr;
 };
 
 namespace {
@@ -1539,11 +1538,15 @@ bl_status bl_grid_create(bl_context *ctx, const bl_grid_desc *d, bl_grid **out) 
             return fail(ctx, BL_E_UNSUPPORTED, "blocks are not aligned to a lattice of the smallest block size");
     }
     if (tn[0] * tn[1] * tn[2] > (1LL << 24)) return fail(ctx, BL_E_UNSUPPORTED, "block lattice larger than 2^24 cells");
-    std::vector<int> table((size_t)(tn[0] * tn[1] * tn[2]), -1);
-    std::vector<double> bmeta((size_t)nb * 6);
-    int nn[3] = {d->bnx, d->bny, d->bnz};
+    // per lattice cell: origin, inverse cell sizes and first cell of the
+    // covering block (slot 6; -1 = none), 8 doubles
+    std::vector<double> table((size_t)(tn[0] * tn[1] * tn[2]) * 8, 0.0);
+    for (size_t t = 0; t < table.size(); t += 8) table[t + 6] = -1.0;
+    const int nn[3] = {d->bnx, d->bny, d->bnz};
+    const double cells = (double)d->bnx * d->bny * d->bnz;
     for (int b = 0; b < nb; ++b) {
         long long lo[3], hi[3];
+        double ent[8];
         for (int c = 0; c < 3; ++c) {
             double x0 = d->bounds[6 * b + 2 * c], x1 = d->bounds[6 * b + 2 * c + 1];
             double ql = (x0 - bb[2 * c]) / tb[c], qh = (x1 - bb[2 * c]) / tb[c];
@@ -1551,32 +1554,28 @@ bl_status bl_grid_create(bl_context *ctx, const bl_grid_desc *d, bl_grid **out) 
             hi[c] = std::llround(qh);
             if (std::fabs(ql - lo[c]) > 1e-9 * (1.0 + ql) || std::fabs(qh - hi[c]) > 1e-9 * (1.0 + qh))
                 return fail(ctx, BL_E_UNSUPPORTED, "block not aligned to the block lattice");
-            bmeta[6 * b + c] = x0;
-            bmeta[6 * b + 3 + c] = nn[c] / (x1 - x0);
+            ent[c] = x0;
+            ent[3 + c] = nn[c] / (x1 - x0);
         }
+        ent[6] = (double)b * cells;
+        ent[7] = 0.0;
         for (long long k = lo[2]; k < hi[2]; ++k)
             for (long long j = lo[1]; j < hi[1]; ++j)
                 for (long long i = lo[0]; i < hi[0]; ++i) {
-                    int &t = table[(size_t)((k * tn[1] + j) * tn[0] + i)];
-                    if (t >= 0) return fail(ctx, BL_E_INVALID_ARG, "blocks overlap");
-                    t = b;
+                    double *t = &table[(size_t)((k * tn[1] + j) * tn[0] + i) * 8];
+                    if (t[6] >= 0.0) return fail(ctx, BL_E_INVALID_ARG, "blocks overlap");
+                    for (int m = 0; m < 8; ++m) t[m] = ent[m];
                 }
     }
     bl_grid *gr = new (std::nothrow) bl_grid();
     if (!gr) return fail(ctx, BL_E_OOM, "host allocation failed");
     gr->ctx = ctx;
-    hipError_t e1 = hipMalloc((void **)&gr->d_bmeta, bmeta.size() * sizeof(double));
-    hipError_t e2 = hipMalloc((void **)&gr->d_table, table.size() * sizeof(int));
-    if (e1 != hipSuccess || e2 != hipSuccess) {
-        (void)hipFree(gr->d_bmeta);
-        (void)hipFree(gr->d_table);
+    if (hipMalloc((void **)&gr->d_table, table.size() * sizeof(double)) != hipSuccess) {
         delete gr;
-        return fail(ctx, BL_E_OOM, "device allocation of the block tables failed");
+        return fail(ctx, BL_E_OOM, "device allocation of the block table failed");
     }
-    HIPCHK(ctx, hipMemcpy(gr->d_bmeta, bmeta.data(), bmeta.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(ctx, hipMemcpy(gr->d_table, table.data(), table.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(ctx, hipMemcpy(gr->d_table, table.data(), table.size() * sizeof(double), hipMemcpyHostToDevice));
     g.prims = d->prims;
-    g.bmeta = gr->d_bmeta;
     g.table = gr->d_table;
     for (int c = 0; c < 6; ++c) g.bb[c] = bb[c];
     for (int c = 0; c < 3; ++c) {
@@ -1599,7 +1598,6 @@ bl_status bl_grid_create(bl_context *ctx, const bl_grid_desc *d, bl_grid **out) 
 void bl_grid_destroy(bl_grid *gr) {
     if (!gr) return;
     if (gr->ctx) (void)hipSetDevice(gr->ctx->device);
-    (void)hipFree(gr->d_bmeta);
     (void)hipFree(gr->d_table);
     delete gr;
 }
