@@ -296,20 +296,22 @@ __device__ __forceinline__ void kprime(const R c[8], const R v[4], R w[4]) {
 
 
 
-// Sh(x) = sum_k x^k / (2k+1)! for |x| <= 1
+// Sh(x) = sum_k x^k / (2k+1)! for |x| <= 1 (the first omitted term is below
+// 1/(2K+3)!: 2e-20 in FP64, 3e-8 in FP32)
 template <typename R>
 __device__ __forceinline__ R sh_series(R x) {
-    constexpr int K = sizeof(R) == 8 ? 9 : 5;
+    constexpr int K = sizeof(R) == 8 ? 9 : 4;
     R s = R(0);
 #pragma unroll
     for (int k = K; k >= 1; --k) s = (s + R(rfact(2 * k + 1))) * x;
     return s + R(1);
 }
 
-// C(x) - 1 = sum_{k>=1} x^k / (2k)! for |x| <= 1
+// C(x) - 1 = sum_{k>=1} x^k / (2k)! for |x| <= 1 (omitted terms below
+// 1/(2K+2)!: 9e-22 in FP64, 2e-9 in FP32)
 template <typename R>
 __device__ __forceinline__ R cm1_series(R x) {
-    constexpr int K = sizeof(R) == 8 ? 10 : 6;
+    constexpr int K = sizeof(R) == 8 ? 10 : 5;
     R s = R(0);
 #pragma unroll
     for (int k = K; k >= 1; --k) s = (s + R(rfact(2 * k))) * x;
@@ -318,9 +320,11 @@ __device__ __forceinline__ R cm1_series(R x) {
 
 // C[p,q] and Sh[p,q] from the series: sum_{k>=1} h_{k-1}(p,q) / (2k)! and
 // / (2k+1)!, h_m the complete homogeneous polynomial of degree m.
+// (h_K <= K + 1 for |p|, |q| <= 1, so the omitted terms are below
+// (K + 1)/(2K+2)!: 1e-20 in FP64, 1e-8 in FP32)
 template <typename R>
 __device__ __forceinline__ void dd_series(R p, R q, R &dc, R &ds) {
-    constexpr int K = sizeof(R) == 8 ? 10 : 6;
+    constexpr int K = sizeof(R) == 8 ? 10 : 5;
     R h = R(1), qk = R(1);
     dc = R(0);
     ds = R(0);
