@@ -136,7 +136,7 @@ __device__ __forceinline__ R gdot(const KS<R> &k, const R A[4], const R B[4]) {
 //   dx^mu/dl = eta^mu nu k_nu - f l^mu (l.k),
 //   dk_c/dl = -1/2 d_c g^ab k_a k_b = 1/2 d_c f (l.k)^2 + f (l.k) (d_c l . k).
 __device__ __forceinline__ void geo_rhs(double a, int flat, const double *y, double kt, double *dy) {
-    // the metric functions and their derivatives from one division (ks_core)
+    // the metric functions and their derivatives from one reciprocal (ks_core)
     const double x = y[1], yy = y[2], z = y[3];
     const KSCore<double> kc = ks_core(a, x, yy, z);
     const double r = kc.r, r2 = r * r, a2 = a * a;
@@ -151,18 +151,21 @@ __device__ __forceinline__ void geo_rhs(double a, int flat, const double *y, dou
     dy[2] = y[5] - flk * l[1];
     dy[3] = y[6] - flk * l[2];
     // (no early return for the flat case: it keeps dy out of private memory)
-    const double pos[3] = {x, yy, z};
     const double r3iD = r * kc.is;   // r^3 / (r^4 + a^2 z^2)
     const double dr[3] = {x * r3iD, yy * r3iD, z * (r2 + a2) * ir * kc.is};
+    // d_c l_b = dr_c m_b + K_cb (differentiating the definition of l), so
+    // (d_c l).k = dr_c (m.k) + (K k)_c
+    const double m[3] = {(x - 2.0 * r * l[0]) * ira, (yy - 2.0 * r * l[1]) * ira, -l[2] * ir};
+    const double mk = m[0] * y[4] + m[1] * y[5] + m[2] * y[6];
+    const double Kk[3] = {ira * (r * y[4] - a * y[5]), ira * (a * y[4] + r * y[5]), ir * y[6]};
+    // d_c f = f (3/r - 4 r^3/D) d_c r - [c = z] 2 f a^2 z / D, D = r^4 + a^2 z^2
+    const double g1 = f * (3.0 * ir - 4.0 * r3iD);
+    const double hl2 = 0.5 * lk * lk;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double dD = 4.0 * r2 * r * dr[c] + (c == 2 ? 2.0 * a2 * z : 0.0);
-        const double df = flat ? 0.0 : f * (3.0 * dr[c] * ir - dD * iD);
-        const double dl0 = (dr[c] * pos[0] + (c == 0 ? r : 0.0) + (c == 1 ? a : 0.0) - 2.0 * r * l[0] * dr[c]) * ira;
-        const double dl1 = (dr[c] * pos[1] + (c == 1 ? r : 0.0) - (c == 0 ? a : 0.0) - 2.0 * r * l[1] * dr[c]) * ira;
-        const double dl2 = ((c == 2 ? 1.0 : 0.0) - l[2] * dr[c]) * ir;
-        const double dlk = dl0 * y[4] + dl1 * y[5] + dl2 * y[6];
-        dy[4 + c] = flat ? 0.0 : 0.5 * df * lk * lk + flk * dlk;
+        const double df = g1 * dr[c] - (c == 2 ? 2.0 * f * a2 * z * iD : 0.0);
+        const double dlk = dr[c] * mk + Kk[c];
+        dy[4 + c] = flat ? 0.0 : df * hl2 + flk * dlk;
     }
 }
 
