@@ -197,10 +197,11 @@ __device__ __forceinline__ double ds_dlambda(double a, int flat, const double *y
 // (A_t = Df/2, Y_t = 0, Om spatial and antisymmetric).  Raising the first
 // index with g^-1 = eta - f lu lu (lu = l^mu) gives
 //   G^a_d = lu^a B_d + Yt^a l_d + h Om_ad,
-//   B = (1 - f lu.l) A - h f (l.Om),   Yt = Y - f (lu.Y) lu,
-// where lu.l vanishes for the Kerr-Schild l and is kept only so that rounding
-// in l cannot matter.  G applied to a tensor then costs three row vectors and
-// a 3x3 antisymmetric product instead of 16 entries of G.
+//   B = (1 - f lu.l) A - h f (l.Om) = A - h f (l.Om),   Yt = Y - f (lu.Y) lu,
+// since lu.l = |l|^2 - 1 vanishes for the Kerr-Schild l (its definition of r
+// makes |l| = 1; in floating point lu.l is a rounding error, and dropping it
+// changes B at that level).  G applied to a tensor then costs three row
+// vectors and a 3x3 antisymmetric product instead of 16 entries of G.
 template <typename R>
 struct ConnF {
     R lu[4], l4[4], B[4], Yt[4];
@@ -218,10 +219,10 @@ __device__ __forceinline__ void conn_geom(R a, int flat, const R x[4], const R k
     const R r3iD = r * kcr.is;
     const R f = flat ? R(0) : R(2) * r3iD;
     // k^mu = g^mu nu k_nu
-    const R flk = f * (-kc[0] + l[0] * kc[1] + l[1] * kc[2] + l[2] * kc[3]);
-    const R kt = -kc[0] + flk;
+    // q = l_mu k^mu = (lu.k)(1 - f lu.l) = lu.k (lu.l = 0, as for B below)
+    const R q = -kc[0] + l[0] * kc[1] + l[1] * kc[2] + l[2] * kc[3];
+    const R flk = f * q;
     const R kv[3] = {kc[1] - flk * l[0], kc[2] - flk * l[1], kc[3] - flk * l[2]};
-    const R q = kt + l[0] * kv[0] + l[1] * kv[1] + l[2] * kv[2];
     // d_c r and m
     const R dr[3] = {X * r3iD, Yy * r3iD, Z * (r2 + a2) * ir * kcr.is};
     const R m[3] = {(X - R(2) * r * l[0]) * ira, (Yy - R(2) * r * l[1]) * ira, -l[2] * ir};
@@ -239,13 +240,12 @@ __device__ __forceinline__ void conn_geom(R a, int flat, const R x[4], const R k
     const R oxy = dr[1] * m[0] - dr[0] * m[1] + R(2) * a * ira;
     const R oxz = dr[2] * m[0] - dr[0] * m[2];
     const R oyz = dr[2] * m[1] - dr[1] * m[2];
-    // l.Om (spatial components) and lu.l
+    // l.Om (spatial components)
     const R om[3] = {-l[1] * oxy - l[2] * oxz, l[0] * oxy - l[2] * oyz, l[0] * oxz + l[1] * oyz};
-    const R s0 = R(-1) + l[0] * l[0] + l[1] * l[1] + l[2] * l[2];
-    const R cA = R(1) - f * s0, hf = h * f;
+    const R hf = h * f;
     c.lu[0] = R(-1);
     c.l4[0] = R(1);
-    c.B[0] = cA * R(0.5) * Df;
+    c.B[0] = R(0.5) * Df;
     R lY = R(0), Yb[3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
@@ -254,7 +254,7 @@ __device__ __forceinline__ void conn_geom(R a, int flat, const R x[4], const R k
         lY += l[b] * Yb[b];
         c.lu[1 + b] = l[b];
         c.l4[1 + b] = l[b];
-        c.B[1 + b] = cA * R(0.5) * (Df * l[b] + fD + qd + fW) - hf * om[b];
+        c.B[1 + b] = R(0.5) * (Df * l[b] + fD + qd + fW) - hf * om[b];
     }
     c.Yt[0] = f * lY;
 #pragma unroll

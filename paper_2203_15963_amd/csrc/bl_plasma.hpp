@@ -343,12 +343,6 @@ __device__ __forceinline__ void sample_point(double a, int flat, const DevGrid &
     s.plasma = true;
 }
 
-// 3x3 determinant of rows (a1 a2 a3), (b1 b2 b3), (c1 c2 c3)
-template <typename R>
-__device__ __forceinline__ R det3(R a1, R a2, R a3, R b1, R b2, R b3, R c1, R c2, R c3) {
-    return a1 * (b2 * c3 - b3 * c2) - a2 * (b1 * c3 - b3 * c1) + a3 * (b1 * c2 - b2 * c1);
-}
-
 // Orthonormal tetrad of observer u with photon momentum k (covariant kc):
 // e0 = u, e3 = (k - omega u)/omega with omega = -k.u, e2 along w projected
 // orthogonal to u and e3 (falling back to z, then x, when w is degenerate),
@@ -390,10 +384,14 @@ __device__ __forceinline__ void screen_basis(const KS<R> &k, const R u[4], const
 #pragma unroll
     for (int m = 0; m < 4; ++m) e2[m] = t[m] * inrm;
     lower(k, e2, q);
-    p[0] = -det3(u[1], u[2], u[3], e2[1], e2[2], e2[3], e3[1], e3[2], e3[3]);
-    p[1] = det3(u[0], u[2], u[3], e2[0], e2[2], e2[3], e3[0], e3[2], e3[3]);
-    p[2] = -det3(u[0], u[1], u[3], e2[0], e2[1], e2[3], e3[0], e3[1], e3[3]);
-    p[3] = det3(u[0], u[1], u[2], e2[0], e2[1], e2[2], e3[0], e3[1], e3[2]);
+    // the four 3x3 cofactors from the six 2x2 minors of (e2, e3)
+    const R m01 = e2[0] * e3[1] - e2[1] * e3[0], m02 = e2[0] * e3[2] - e2[2] * e3[0];
+    const R m03 = e2[0] * e3[3] - e2[3] * e3[0], m12 = e2[1] * e3[2] - e2[2] * e3[1];
+    const R m13 = e2[1] * e3[3] - e2[3] * e3[1], m23 = e2[2] * e3[3] - e2[3] * e3[2];
+    p[0] = -(u[1] * m23 - u[2] * m13 + u[3] * m12);
+    p[1] = u[0] * m23 - u[2] * m03 + u[3] * m02;
+    p[2] = -(u[0] * m13 - u[1] * m03 + u[3] * m01);
+    p[3] = u[0] * m12 - u[1] * m02 + u[2] * m01;
     raise(k, p, e1);
 }
 
