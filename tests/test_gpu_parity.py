@@ -221,6 +221,18 @@ def test_render_polarized_uniform(ctx, oracle):
     _compare_render(ctx, oracle, _wl("c2_256_pol", 14))
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_render_polarized_sigma_cut(ctx, oracle, precision):
+    """A low sigma cut (0.01) leaves vacuum holes inside the emitting region,
+    so on most rays samples with and without a Stokes step alternate: the
+    transfer then takes the full-N transport into a Stokes step (a state not
+    packed by the previous sample) and unpacks a packed state before a sample
+    without one, besides the packed path (about 160 such transitions on this
+    12x12 image, counted with the oracle)."""
+    w = _wl("c2_256_pol", 12, plasma=dict(sigma_max=0.01))
+    _compare_render(ctx, oracle, w, precision=precision, tol=TOL_FP64 if precision == 0 else TOL_MIXED)
+
+
 def test_render_polarized_smr(ctx, oracle):
     _compare_render(ctx, oracle, _wl("c3_1024_smr", 11))
 
