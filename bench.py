@@ -285,6 +285,9 @@ def main():
     ap.add_argument("--tune-trials", type=int, default=14)
     ap.add_argument("--step-model", type=int, default=0, help="1: learned step proposals (trains the network first)")
     ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--freqs", type=int, default=0,
+                    help="single image: also time a K-frequency render from one geodesic pass (K frequencies "
+                         "evenly spaced in wavelength over 152-324 GHz, as for true-colour images)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -368,6 +371,36 @@ def main():
         "kernels": kern,
         "roofline": roof,
     }
+    if args.freqs > 1:
+        K = args.freqs
+        lam = [1.0 / 324e9 + (1.0 / 152e9 - 1.0 / 324e9) * k / (K - 1) for k in range(K)]
+        nus = [1.0 / v for v in lam]
+        outs = [(torch.empty(4, n, n, dtype=torch.float64, device="cuda"),
+                 torch.empty(blgpu.NAUX, n, n, dtype=torch.float64, device="cuda")) for _ in range(K)]
+
+        def mstep():
+            ctx.render_multifreq(w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"], nus,
+                                 precision=args.precision, outputs=outs)
+
+        mstep()
+        torch.cuda.synchronize()
+        log(f"multi-frequency warmup done ({K} frequencies)")
+        ctx.profile_enable(True)
+        ctx.profile_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            mstep()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mprof = ctx.profile_read()
+        ctx.profile_enable(False)
+        mms = (t1 - t0) * 1e3 / args.steps
+        out["multifreq"] = {"n_freq": K, "nu_hz": nus, "ms_per_render": mms, "ms_per_image": mms / K,
+                            "images_per_s": K / (mms / 1e3), "rays_per_s": K * rays / (mms / 1e3),
+                            "single_frequency_ms": ms, "speedup_vs_separate_renders": K * ms / mms,
+                            "kernels": kernel_table(mprof, args.steps)}
+        log("multi-frequency", out["multifreq"]["ms_per_render"], "ms per render of", K, "frequencies")
     if args.copy_probe:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)

@@ -232,6 +232,21 @@ bl_status bl_render_batch(bl_context *ctx, int32_t n_images, const bl_image_desc
                           const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
                           const bl_mode *mode, const bl_tuning *tuning);
 
+/* One camera at several frequencies (paper section 4, true-color images:
+   images at many frequencies for a fixed camera and fixed data; section 5:
+   tracing several images at once amortises the geodesic integration).  The
+   geodesics do not depend on the frequency (n = nu / den with den = -k_t or
+   -k.u), so each chunk of rays is traced once and the transfer runs once per
+   frequency on the same step records.  cam->nu_hz is ignored; nu_hz: host
+   [n_freq] frequencies (Hz, positive, finite), 1 <= n_freq <= 4096;
+   images_out, aux_out: host arrays of n_freq device pointers, each an
+   output as for bl_render.  Image f equals bl_render with
+   cam->nu_hz = nu_hz[f], aux maps included.  Uses the context's tuning. */
+bl_status bl_render_multifreq(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
+                              const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
+                              const bl_mode *mode, int32_t n_freq, const double *nu_hz,
+                              double *const *images_out, double *const *aux_out);
+
 /* Autotuner: times bl_render_batch of the given images (which it renders,
    into their outputs, several times) under a coordinate search over tile
    shape, transfer waves per CU, refill threshold, chunk size and image

@@ -122,6 +122,10 @@ def load():
     L.bl_render_batch.argtypes = [vp, i32, C.POINTER(bl_image_desc), C.POINTER(bl_integrator), vp,
                                   C.POINTER(bl_plasma), C.POINTER(bl_mode), C.POINTER(bl_tuning)]
     L.bl_render_batch.restype = C.c_int
+    L.bl_render_multifreq.argtypes = [vp, C.POINTER(bl_camera), C.POINTER(bl_spacetime), C.POINTER(bl_integrator),
+                                      vp, C.POINTER(bl_plasma), C.POINTER(bl_mode), i32, C.POINTER(C.c_double),
+                                      C.POINTER(vp), C.POINTER(vp)]
+    L.bl_render_multifreq.restype = C.c_int
     L.bl_set_tuning.argtypes = [vp, C.POINTER(bl_tuning)]
     L.bl_set_tuning.restype = C.c_int
     L.bl_get_tuning.argtypes = [vp, C.POINTER(bl_tuning)]
@@ -304,6 +308,20 @@ class Context:
         self._check(load().bl_render(self.handle, C.byref(c), C.byref(s), C.byref(g), grid.handle,
                                      C.byref(p), C.byref(m), _ptr(image), _ptr(aux)))
         return image, aux
+
+    def render_multifreq(self, cam, st, integ, grid, pl, nu_hz, precision=0, step_model=0, outputs=None):
+        """One camera at several frequencies from one geodesic pass; returns a
+        list of (image, aux) tensors, one per frequency (cam["nu_hz"] is
+        ignored)."""
+        n, k = int(cam["n"]), len(nu_hz)
+        outs = outputs if outputs is not None else [(self._empty(4, n, n), self._empty(NAUX, n, n)) for _ in range(k)]
+        c, s, g, p, m = camera(cam), spacetime(st), integrator(integ), plasma(pl), mode(precision, step_model)
+        nus = (C.c_double * k)(*[float(v) for v in nu_hz])
+        ims = (C.c_void_p * k)(*[im.data_ptr() for im, _ in outs])
+        axs = (C.c_void_p * k)(*[ax.data_ptr() for _, ax in outs])
+        self._check(load().bl_render_multifreq(self.handle, C.byref(c), C.byref(s), C.byref(g), grid.handle,
+                                               C.byref(p), C.byref(m), k, nus, ims, axs))
+        return outs
 
     def _batch_descs(self, images, outputs):
         """images: list of (camera dict, spacetime dict); outputs: list of

@@ -327,9 +327,12 @@ __device__ __forceinline__ void velocity_from_normal(const KS<R> &k, const R ut[
 // Initial state of pixel (i, j) of the plane-parallel camera (paper section
 // 2.1): x_pix = x_c + a H + b V, k^a = K^a, k^t the root of the null
 // condition g k k = 0 that is positive (the lesser positive one inside the
-// ergosphere); then k_mu = g_mu nu k^nu and the normalisation n.
+// ergosphere); then k_mu = g_mu nu k^nu.  The frequency normalisation is
+// n = nu / den with den = -k_t (frequency at infinity) or -k.u (at the
+// camera); den does not depend on nu, so one traced ray serves every
+// frequency.
 __device__ __forceinline__ void camera_pixel(const Frame &fr, const CamParams &cp, double a, int flat, int i, int j,
-                                             double y[8], double &n_norm) {
+                                             double y[8], double &den) {
     double N = (double)cp.n;
     double ap = ((double)i - 0.5 * N + 0.5) * cp.width / N;
     double bp = ((double)j - 0.5 * N + 0.5) * cp.width / N;
@@ -348,11 +351,11 @@ __device__ __forceinline__ void camera_pixel(const Frame &fr, const CamParams &c
     ku[3] = K3[2];
     lower(k, ku, y + 4);
     if (cp.freq_mode == 0) {
-        n_norm = cp.nu / (-y[4]);
+        den = -y[4];
     } else {
         double u[4];
         velocity_from_normal(k, fr.ut, u);
-        n_norm = cp.nu / (-(y[4] * u[0] + y[5] * u[1] + y[6] * u[2] + y[7] * u[3]));
+        den = -(y[4] * u[0] + y[5] * u[1] + y[6] * u[2] + y[7] * u[3]);
     }
 }
 

@@ -479,14 +479,14 @@ struct RayWalk {
 };
 
 template <typename R>
-__device__ __forceinline__ void begin_ray(RayWalk<R> &w, const double *rec, int n_acc, double kt, double n_norm,
+__device__ __forceinline__ void begin_ray(RayWalk<R> &w, const double *rec, int n_acc, double kt, double den,
                                           const TransferParams &tp) {
+    // n = nu / den (camera_pixel), so nu_cam / n = den
     w.rec = rec;
     w.kt = (R)kt;
-    w.n_norm = (R)n_norm;
-    double q = tp.nu_cam / n_norm;
+    w.n_norm = (R)(tp.nu_cam / den);
     w.L = (R)tp.L;
-    w.lj = (R)(tp.L * q * q * q);
+    w.lj = (R)(tp.L * den * den * den);
     // the last step sampled against the grid (stored with the final state);
     // the vacuum steps beyond it count one record each and are not walked
     const int last = (int)rec[(long long)n_acc * kRecDoubles + 23];
@@ -815,12 +815,12 @@ __device__ __forceinline__ void load_ray_end(RayWalk<R> &w, const R *e, const do
 template <bool POL, typename R>
 __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
                                              const TransferParams &tp, const double *rec, int n_acc, double kt,
-                                             double n_norm, const double upix[4], const double Hv[4],
+                                             double den, const double upix[4], const double Hv[4],
                                              TransferOut &o) {
     __shared__ QuartLds<R> s_q;
     const int lane = threadIdx.x;
     RayWalk<R> w;
-    begin_ray(w, rec, n_acc, kt, n_norm, tp);
+    begin_ray(w, rec, n_acc, kt, den, tp);
     while (w.st >= 0 || w.p >= 0) {
         if (w.p < 0) next_step(w, s_q, lane);
         piece<POL, R>(w, P, g, pp, s_q, lane);

@@ -153,10 +153,10 @@ __global__ void k_camera_rays(const ImgDev *__restrict__ imp, double *__restrict
     long long NN = (long long)cp.n * cp.n;
     long long pix = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (pix >= NN) return;
-    double y[8], n;
-    camera_pixel(im.fr, cp, im.a, im.flat, (int)(pix % cp.n), (int)(pix / cp.n), y, n);
+    double y[8], den;
+    camera_pixel(im.fr, cp, im.a, im.flat, (int)(pix % cp.n), (int)(pix / cp.n), y, den);
     for (int m = 0; m < 8; ++m) state_out[pix * 8 + m] = y[m];
-    norm_out[pix] = n;
+    norm_out[pix] = cp.nu / den;
 }
 
 __global__ void k_fill_int(int *p, int v, int n) {
@@ -203,8 +203,8 @@ __global__ void __launch_bounds__(64, 2) k_geodesic(GeoParams P, Batch B, long l
     const long long NN = (long long)im.cp.n * im.cp.n;
     const long long pix = (long long)pj * im.cp.n + pi;
     double *aux = im.aux;
-    double y8[8], n;
-    camera_pixel(im.fr, im.cp, Q.a, Q.flat, pi, pj, y8, n);
+    double y8[8], den;
+    camera_pixel(im.fr, im.cp, Q.a, Q.flat, pi, pj, y8, den);
     double y[7] = {y8[0], y8[1], y8[2], y8[3], y8[5], y8[6], y8[7]};
     double kt = y8[4];
     TraceOut o;
@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(64, 2) k_geodesic(GeoParams P, Batch B, long l
                     StepLog{nullptr, 0, nullptr}, &X, slot);
     if (WREC) {
         meta[2 * slot] = kt;
-        meta[2 * slot + 1] = n;
+        meta[2 * slot + 1] = den;
         if (o.status == kRayOverflow) {
             nacc_out[slot] = work_out[slot] = -1;
             int idx = atomicAdd(ovf_count, 1);
@@ -457,8 +457,8 @@ __global__ void __launch_bounds__(64) k_overflow(GeoParams P, Batch B, DevGrid g
         tl.nu_cam = im.cp.nu;
         const long long NN = (long long)im.cp.n * im.cp.n, pix = (long long)pj * im.cp.n + pi;
         double *aux = im.aux;
-        double y8[8], n;
-        camera_pixel(im.fr, im.cp, Q.a, Q.flat, pi, pj, y8, n);
+        double y8[8], den;
+        camera_pixel(im.fr, im.cp, Q.a, Q.flat, pi, pj, y8, den);
         double y[7] = {y8[0], y8[1], y8[2], y8[3], y8[5], y8[6], y8[7]};
         double kt = y8[4];
         TraceOut o;
@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(64) k_overflow(GeoParams P, Batch B, DevGrid g
         double upix[4];
         pixel_observer(im.fr, Q, r, upix);
         TransferOut t;
-        transfer_ray<POL, R>(Q, g, pp, tl, r, o.n_acc, kt, n, upix, im.fr.H, t);
+        transfer_ray<POL, R>(Q, g, pp, tl, r, o.n_acc, kt, den, upix, im.fr.H, t);
         write_pixel(t, NN, pix, im.image, aux);
     }
 }
@@ -506,8 +506,8 @@ __global__ void __launch_bounds__(256, 2) k_geodesic_learned(GeoParams P, Batch 
     }
     const ImgDev &im = B.imgs[img];
     const GeoParams Q = lane_params<BATCH>(P, im);
-    double y8[8] = {0, 0, 0, 0, -1, 0, 0, 0}, n = 1.0;
-    if (active) camera_pixel(im.fr, im.cp, Q.a, Q.flat, pi, pj, y8, n);
+    double y8[8] = {0, 0, 0, 0, -1, 0, 0, 0}, den = 1.0;
+    if (active) camera_pixel(im.fr, im.cp, Q.a, Q.flat, pi, pj, y8, den);
     double y[7] = {y8[0], y8[1], y8[2], y8[3], y8[5], y8[6], y8[7]};
     const double kt = y8[4];
     TraceOut o;
@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(256, 2) k_geodesic_learned(GeoParams P, Batch 
     double *aux = im.aux;
     if (WREC) {
         meta[2 * slot] = kt;
-        meta[2 * slot + 1] = n;
+        meta[2 * slot + 1] = den;
         if (o.status == kRayOverflow) {
             nacc_out[slot] = work_out[slot] = -1;
             int idx = atomicAdd(ovf_count, 1);
@@ -547,8 +547,8 @@ __global__ void __launch_bounds__(64) k_steplog(GeoParams P, Batch B, long long 
     int pi, pj;
     if (!ray_pixel(B, im.cp.n, gid - B.ray0[img], pi, pj)) return;
     const GeoParams Q = lane_params<true>(P, im);
-    double y8[8], n;
-    camera_pixel(im.fr, im.cp, Q.a, Q.flat, pi, pj, y8, n);
+    double y8[8], den;
+    camera_pixel(im.fr, im.cp, Q.a, Q.flat, pi, pj, y8, den);
     double y[7] = {y8[0], y8[1], y8[2], y8[3], y8[5], y8[6], y8[7]};
     TraceOut o;
     trace_ray<false, true>(Q, y, y8[4], nullptr, 0, o, lg);
@@ -1182,9 +1182,12 @@ long long image_rays(int n, const bl_tuning &t) {
 // Build and upload the image table (in placement order: given, or largest
 // first) and launch the camera-frame kernel.  Returns the batch view and the
 // total ray-id count.
+// Image table of n entries.  With shared_rays every entry describes the
+// same rays (the same camera at the frequencies of a multi-frequency render:
+// ray ids start at 0 for each and the render has one image's rays).
 bl_status upload_images(bl_context *ctx, int n, const bl_camera *const *cams, const bl_spacetime *const *sts,
                         double *const *images, double *const *auxs, const bl_tuning &t, Batch &B,
-                        long long &total) {
+                        long long &total, bool shared_rays = false) {
     std::vector<int> perm(n);
     for (int k = 0; k < n; ++k) perm[k] = k;
     if (t.order == 1)
@@ -1204,10 +1207,10 @@ bl_status upload_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         im.L = kG * sts[k]->mass_msun * kMsun / (kC * kC);
         im.image = images[k];
         im.aux = auxs[k];
-        im.ray0 = r;
+        im.ray0 = shared_rays ? 0 : r;
         im.nray = image_rays(cams[k]->n, t);
-        ctx->h_ray0[q] = r;
-        r += im.nray;
+        ctx->h_ray0[q] = im.ray0;
+        if (!shared_rays || q == 0) r += im.nray;
     }
     if (r >= (1LL << 31)) return fail(ctx, BL_E_UNSUPPORTED, "more than 2^31 - 1 ray ids in one render");
     bl_status s;
@@ -1220,7 +1223,7 @@ bl_status upload_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     HIPCHK(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
     B.imgs = ctx->d_imgs;
     B.ray0 = ctx->d_ray0;
-    B.n_img = n;
+    B.n_img = n;   // every entry gets its camera frame
     B.tw = t.tile_w;
     B.th = t.tile_h;
     B.pad = 0;
@@ -1229,6 +1232,7 @@ bl_status upload_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         hipLaunchKernelGGL(k_camera_frame, dim3((unsigned)n), dim3(64), 0, ctx->stream, B);
     }
     HIPCHK(ctx, hipGetLastError());
+    if (shared_rays) B.n_img = 1;   // the entries describe one image's rays
     total = r;
     return BL_OK;
 }
@@ -1260,12 +1264,19 @@ void launch_overflow(bl_context *ctx, const GeoParams &P, const Batch &B, const 
 // The render of n images (a batch of one for bl_render).  With batch = false
 // there is one image and the kernels take its parameters as wave-uniform
 // values.
+// With n_freq > 0 (one image, batch = false) the cameras cams[0..n_freq) are
+// one camera at the frequencies of a multi-frequency render: the geodesics
+// are traced once per chunk and the transfer runs once per frequency on the
+// same step records, each writing its own image and aux.
 bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, const bl_spacetime *const *sts,
                         double *const *images, double *const *auxs, const bl_integrator *integ, const bl_grid *grid,
-                        const bl_plasma *plasma, const bl_mode *mode, const bl_tuning &t, bool batch) {
+                        const bl_plasma *plasma, const bl_mode *mode, const bl_tuning &t, bool batch,
+                        int n_freq = 0) {
     bl_status s;
     if ((s = check_integrator(ctx, integ)) != BL_OK || (s = check_tuning(ctx, &t)) != BL_OK) return s;
-    for (int k = 0; k < n; ++k) {
+    if (n_freq > 0 && (n != 1 || batch)) return fail(ctx, BL_E_INVALID_ARG, "a multi-frequency render has one image");
+    const int n_tr = n_freq > 0 ? n_freq : 1;   // transfers per chunk
+    for (int k = 0; k < (n_freq > 0 ? n_freq : n); ++k) {
         if ((s = check_camera(ctx, cams[k])) != BL_OK || (s = check_spacetime(ctx, sts[k])) != BL_OK) return s;
         if (!images[k] || !auxs[k]) return fail(ctx, BL_E_INVALID_ARG, "image and aux outputs must be non-NULL");
     }
@@ -1285,7 +1296,8 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     if ((s = persistent_waves(ctx)) != BL_OK) return s;
     Batch B;
     long long total = 0;
-    if ((s = upload_images(ctx, n, cams, sts, images, auxs, t, B, total)) != BL_OK) return s;
+    if ((s = upload_images(ctx, n_freq > 0 ? n_freq : n, cams, sts, images, auxs, t, B, total, n_freq > 0)) != BL_OK)
+        return s;
     GeoParams P = geo_params(cams[0], sts[0], integ);
     record_layout(P, grid->g, integ, mixed);
     size_t rec_per_ray = (size_t)P.cap * kRecDoubles * sizeof(double);
@@ -1338,9 +1350,10 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     tp.L = kG * sts[0]->mass_msun * kMsun / (kC * kC);
     tp.nu_cam = cams[0]->nu_hz;
     long long nchunk = (total + chunk - 1) / chunk;
-    if ((s = ensure(ctx, &ctx->d_queue, ctx->queue_bytes, (size_t)nchunk * 2 * sizeof(int))) != BL_OK) return s;
-    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((2 * nchunk + 63) / 64)), dim3(64), 0, ctx->stream, ctx->d_queue, 0,
-                       (int)(2 * nchunk));
+    const long long nqueue = 2 * nchunk * n_tr;   // one counter (padded to two ints) per transfer launch
+    if ((s = ensure(ctx, &ctx->d_queue, ctx->queue_bytes, (size_t)nqueue * sizeof(int))) != BL_OK) return s;
+    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((nqueue + 63) / 64)), dim3(64), 0, ctx->stream, ctx->d_queue, 0,
+                       (int)nqueue);
     HIPCHK(ctx, hipGetLastError());
     const int kidx = 4 * (batch ? 1 : 0) + 2 * pp.polarized + (mixed ? 1 : 0);
     int per_cu = ctx->blocks_tr[kidx];
@@ -1387,33 +1400,55 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
                                ctx->d_order);
         }
         HIPCHK(ctx, hipGetLastError());
-        {
+        for (int f = 0; f < n_tr; ++f) {
+            // frequency f of a multi-frequency render: its image table entry
+            // (outputs, camera frequency) and its own queue counter
+            Batch Bf = B;
+            Bf.imgs = B.imgs + f;
+            TransferParams tpf = tp;
+            tpf.nu_cam = cams[f]->nu_hz;
             TimedLaunch tl(ctx, BL_K_TRANSFER);
-            int *q = ctx->d_queue + 2 * ichunk;
+            int *q = ctx->d_queue + 2 * (ichunk * n_tr + f);
             dim3 pg(std::min<int>(grd.x, resident));
             switch (kidx) {
-            case 0: launch_transfer<false, double, false>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
-            case 1: launch_transfer<false, float, false>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
-            case 2: launch_transfer<true, double, false>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
-            case 3: launch_transfer<true, float, false>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
-            case 4: launch_transfer<false, double, true>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
-            case 5: launch_transfer<false, float, true>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
-            case 6: launch_transfer<true, double, true>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
-            default: launch_transfer<true, float, true>(ctx, pg, P, B, grid->g, pp, tp, start, count, t.refill_min, q); break;
+            case 0: launch_transfer<false, double, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 1: launch_transfer<false, float, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 2: launch_transfer<true, double, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 3: launch_transfer<true, float, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 4: launch_transfer<false, double, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 5: launch_transfer<false, float, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 6: launch_transfer<true, double, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            default: launch_transfer<true, float, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
             }
+            HIPCHK(ctx, hipGetLastError());
+        }
+    }
+    for (int f = 0; f < n_tr; ++f) {
+        // rays longer than the extension slots are traced again per frequency
+        Batch Bf = B;
+        Bf.imgs = B.imgs + f;
+        TransferParams tpf = tp;
+        tpf.nu_cam = cams[f]->nu_hz;
+        TimedLaunch tl(ctx, BL_K_OVERFLOW);
+        switch (kidx & 3) {
+        case 0: launch_overflow<false, double>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 1: launch_overflow<false, float>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 2: launch_overflow<true, double>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        default: launch_overflow<true, float>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
         }
         HIPCHK(ctx, hipGetLastError());
     }
-    {
-        TimedLaunch tl(ctx, BL_K_OVERFLOW);
-        switch (kidx & 3) {
-        case 0: launch_overflow<false, double>(ctx, P, B, grid->g, pp, tp, big_cap); break;
-        case 1: launch_overflow<false, float>(ctx, P, B, grid->g, pp, tp, big_cap); break;
-        case 2: launch_overflow<true, double>(ctx, P, B, grid->g, pp, tp, big_cap); break;
-        default: launch_overflow<true, float>(ctx, P, B, grid->g, pp, tp, big_cap); break;
+    if (n_freq > 1) {
+        // the geodesic maps (dt, s, lambda and n_acc, n_rej, status) were
+        // written into the first frequency's aux
+        const size_t NN = (size_t)cams[0]->n * cams[0]->n;
+        for (int f = 1; f < n_freq; ++f) {
+            HIPCHK(ctx, hipMemcpyAsync(auxs[f] + BL_AUX_DT * NN, auxs[0] + BL_AUX_DT * NN, 3 * NN * sizeof(double),
+                                       hipMemcpyDeviceToDevice, ctx->stream));
+            HIPCHK(ctx, hipMemcpyAsync(auxs[f] + BL_AUX_NACC * NN, auxs[0] + BL_AUX_NACC * NN,
+                                       3 * NN * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
         }
     }
-    HIPCHK(ctx, hipGetLastError());
     return BL_OK;
 }
 
@@ -1653,6 +1688,26 @@ bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *s
     if (!ctx) return BL_E_INVALID_ARG;
     if (!cam || !st) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
     return render_images(ctx, 1, &cam, &st, &image_out, &aux_out, integ, grid, plasma, mode, ctx->tuning, false);
+}
+
+bl_status bl_render_multifreq(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
+                              const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
+                              const bl_mode *mode, int32_t n_freq, const double *nu_hz, double *const *images_out,
+                              double *const *aux_out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    if (!cam || !st || !nu_hz || !images_out || !aux_out) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
+    if (n_freq < 1 || n_freq > 4096) return fail(ctx, BL_E_INVALID_ARG, "need 1 <= n_freq <= 4096");
+    std::vector<bl_camera> cams(n_freq, *cam);
+    std::vector<const bl_camera *> cp(n_freq);
+    std::vector<const bl_spacetime *> sp(n_freq, st);
+    for (int f = 0; f < n_freq; ++f) {
+        if (!(nu_hz[f] > 0.0) || !std::isfinite(nu_hz[f]))
+            return fail(ctx, BL_E_INVALID_ARG, "frequencies must be positive and finite");
+        cams[f].nu_hz = nu_hz[f];
+        cp[f] = &cams[f];
+    }
+    return render_images(ctx, 1, cp.data(), sp.data(), images_out, aux_out, integ, grid, plasma, mode, ctx->tuning,
+                         false, n_freq);
 }
 
 bl_status bl_render_batch(bl_context *ctx, int32_t n_images, const bl_image_desc *images, const bl_integrator *integ,
