@@ -63,10 +63,24 @@ typedef struct {
     double rho_unit;        /* g cm^-3 per code density unit                */
 } or_grid;
 
+/* Data cuts (paper section 4, Data Cuts): a sample whose rho, n_e, p,
+   Theta_e, B, sigma, beta^-1 or Kerr-Schild r lies below its lower or above
+   its upper limit is vacuum, and with a plane cut so is every sample on one
+   side of the plane (x - x0).n = 0 (CKS x, y, z).  Limits of -inf / +inf
+   leave a quantity uncut.  Units: rho and p as in the grid (code units), n_e
+   in cm^-3, B in gauss, r in GM/c^2. */
+enum { OR_CUT_RHO, OR_CUT_NE, OR_CUT_P, OR_CUT_THETAE, OR_CUT_B, OR_CUT_SIGMA, OR_CUT_BETAINV, OR_CUT_R,
+       OR_NCUT };
+
 typedef struct {
     double mu, ne_ni, r_high, r_low, sigma_max;
     int32_t polarized;      /* 0: I only, 1: I,Q,U,V                        */
     int32_t interp;         /* 0: nearest cell, 1: trilinear within a block */
+    int32_t use_cuts;       /* 0: only sigma_max                            */
+    int32_t plane;          /* 0: no plane; +1: (x - x0).n < 0 is vacuum;
+                               -1: (x - x0).n > 0 is vacuum                 */
+    double cut_lo[OR_NCUT], cut_hi[OR_NCUT];
+    double plane_x0[3], plane_n[3];
 } or_plasma;
 
 /* ---- geometry (kerr.c) ---- */

@@ -8,6 +8,8 @@ so that this module shares nothing with the HIP path's binding.
 import ctypes as C
 import os
 
+import math
+
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -41,10 +43,16 @@ class Grid(C.Structure):
                 ("prims", C.POINTER(C.c_double)), ("rho_unit", C.c_double)]
 
 
+CUT_KEYS = ("rho", "ne", "p", "theta_e", "b", "sigma", "beta_inv", "r")
+
+
 class Plasma(C.Structure):
     _fields_ = [("mu", C.c_double), ("ne_ni", C.c_double), ("r_high", C.c_double),
                 ("r_low", C.c_double), ("sigma_max", C.c_double),
-                ("polarized", C.c_int32), ("interp", C.c_int32)]
+                ("polarized", C.c_int32), ("interp", C.c_int32),
+                ("use_cuts", C.c_int32), ("plane", C.c_int32),
+                ("cut_lo", C.c_double * 8), ("cut_hi", C.c_double * 8),
+                ("plane_x0", C.c_double * 3), ("plane_n", C.c_double * 3)]
 
 
 def _dp(a):
@@ -131,6 +139,20 @@ def plasma(d):
     p.r_high, p.r_low = d.get("r_high", 20.0), d.get("r_low", 1.0)
     p.sigma_max = d.get("sigma_max", 1.0)
     p.polarized, p.interp = int(d.get("polarized", 0)), int(d.get("interp", 1))
+    cuts = d.get("cuts")
+    for k in range(8):
+        p.cut_lo[k], p.cut_hi[k] = -math.inf, math.inf
+    if cuts:
+        # {"rho": (lo, hi), ..., "plane": {"side": +1 or -1, "origin": x0, "normal": n}}
+        p.use_cuts = 1
+        for k, name in enumerate(CUT_KEYS):
+            if name in cuts:
+                p.cut_lo[k], p.cut_hi[k] = float(cuts[name][0]), float(cuts[name][1])
+        if "plane" in cuts:
+            pl = cuts["plane"]
+            p.plane = int(pl["side"])
+            for i in range(3):
+                p.plane_x0[i], p.plane_n[i] = float(pl["origin"][i]), float(pl["normal"][i])
     return p
 
 

@@ -241,6 +241,12 @@ void or_tetrad(const double g[16], const double gi[16], const double u[4],
     }
 }
 
+/* a quantity outside its cut limits (section 4, Data Cuts) */
+static int cut_out(const or_plasma *pl, int k, double q)
+{
+    return q < pl->cut_lo[k] || q > pl->cut_hi[k];
+}
+
 void or_sample_point(const or_spacetime *st, const or_grid *gr, const or_plasma *pl,
                      const double y[8], double n_norm, double out[30])
 {
@@ -253,6 +259,13 @@ void or_sample_point(const or_spacetime *st, const or_grid *gr, const or_plasma 
     rho = prim[0];
     p = prim[1];
     if (!(rho > 0.0)) return;
+    if (pl->use_cuts) {
+        double d = 0.0;
+        if (cut_out(pl, OR_CUT_RHO, rho) || cut_out(pl, OR_CUT_P, p)) return;
+        if (cut_out(pl, OR_CUT_R, or_ks_radius(st->a, y[1], y[2], y[3]))) return;
+        for (i = 0; i < 3; ++i) d += (y[1 + i] - pl->plane_x0[i]) * pl->plane_n[i];
+        if ((pl->plane > 0 && d < 0.0) || (pl->plane < 0 && d > 0.0)) return;
+    }
     or_metric(st->a, st->flat, y, g, gi);
     /* fluid velocity from normal-frame components */
     for (i = 0; i < 3; ++i)
@@ -276,6 +289,10 @@ void or_sample_point(const or_spacetime *st, const or_grid *gr, const or_plasma 
     tr = (pl->r_high + binv * binv * pl->r_low) / (1.0 + binv * binv);
     thetae = pl->mu * M_PROTON / M_ELECTRON * (p / rho) * (pl->ne_ni + 1.0) / (pl->ne_ni + tr);
     Bg = sqrt(b2) * C_LIGHT * sqrt(4.0 * M_PI * gr->rho_unit);
+    if (pl->use_cuts && (cut_out(pl, OR_CUT_NE, ne) || cut_out(pl, OR_CUT_THETAE, thetae) ||
+                         cut_out(pl, OR_CUT_B, Bg) || cut_out(pl, OR_CUT_SIGMA, sigma) ||
+                         cut_out(pl, OR_CUT_BETAINV, binv)))
+        return;
     omega = 0.0;
     kb = 0.0;
     for (i = 0; i < 4; ++i) { omega -= y[4 + i] * u[i]; kb += y[4 + i] * b[i]; }
