@@ -232,6 +232,28 @@ bl_status bl_render_batch(bl_context *ctx, int32_t n_images, const bl_image_desc
                           const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
                           const bl_mode *mode, const bl_tuning *tuning);
 
+/* Data cuts (paper section 4, Data Cuts): a sample whose rho, n_e, p,
+   Theta_e, B, sigma, beta^-1 or Kerr-Schild r lies below its lower limit
+   ([0]) or above its upper limit ([1]) is vacuum, and with plane = +1 (-1)
+   so is every sample with (x - x0).n < 0 (> 0), x the CKS position (x, y, z).
+   -inf / +inf leave a quantity uncut.  Units: rho and p as in the grid
+   (code units), n_e in cm^-3, B in gauss, r in GM/c^2; sigma = b^2/rho and
+   beta^-1 = b^2/(2 p).  These act besides bl_plasma.sigma_max.  The limits
+   are compared in the arithmetic's own precision (FP32 in the mixed form), the
+   plane test in FP64. */
+typedef struct {
+    double rho[2], ne[2], p[2], theta_e[2], b[2], sigma[2], beta_inv[2], r[2];
+    int32_t plane;            /* 0: no plane cut; +1 or -1 as above           */
+    int32_t pad;
+    double plane_origin[3], plane_normal[3];
+} bl_cuts;
+
+/* Install data cuts for the context's following renders (all render entry
+   points and bl_eval_samples); NULL removes them.  The struct is copied.
+   BL_E_INVALID_ARG for NaN limits, a plane flag other than -1, 0, 1, or a
+   non-finite plane origin or normal. */
+bl_status bl_set_cuts(bl_context *ctx, const bl_cuts *cuts);
+
 /* One camera at several frequencies (paper section 4, true-color images:
    images at many frequencies for a fixed camera and fixed data; section 5:
    tracing several images at once amortises the geodesic integration).  The

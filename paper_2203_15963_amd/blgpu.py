@@ -6,6 +6,7 @@ enqueues on the torch stream given at context creation.  The binding refuses
 to work without the built library (there is no fallback path).
 """
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -60,6 +61,31 @@ class bl_tuning(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("transfer_waves_per_cu", C.c_int32),
                 ("refill_min", C.c_int32), ("chunk_rays", C.c_int64), ("order", C.c_int32),
                 ("reserved", C.c_int32)]
+
+
+class bl_cuts(C.Structure):
+    _fields_ = [("rho", C.c_double * 2), ("ne", C.c_double * 2), ("p", C.c_double * 2),
+                ("theta_e", C.c_double * 2), ("b", C.c_double * 2), ("sigma", C.c_double * 2),
+                ("beta_inv", C.c_double * 2), ("r", C.c_double * 2), ("plane", C.c_int32), ("pad", C.c_int32),
+                ("plane_origin", C.c_double * 3), ("plane_normal", C.c_double * 3)]
+
+
+CUT_KEYS = ("rho", "ne", "p", "theta_e", "b", "sigma", "beta_inv", "r")
+
+
+def cuts(d):
+    """bl_cuts from {"rho": (lo, hi), ..., "plane": {"side": +1 or -1,
+    "origin": x0, "normal": n}}; absent quantities are left uncut."""
+    c = bl_cuts()
+    for k in CUT_KEYS:
+        lo, hi = d.get(k, (-math.inf, math.inf))
+        getattr(c, k)[0], getattr(c, k)[1] = float(lo), float(hi)
+    if "plane" in d:
+        pl = d["plane"]
+        c.plane = int(pl["side"])
+        for i in range(3):
+            c.plane_origin[i], c.plane_normal[i] = float(pl["origin"][i]), float(pl["normal"][i])
+    return c
 
 
 class bl_image_desc(C.Structure):
@@ -126,6 +152,8 @@ def load():
                                       vp, C.POINTER(bl_plasma), C.POINTER(bl_mode), i32, C.POINTER(C.c_double),
                                       C.POINTER(vp), C.POINTER(vp)]
     L.bl_render_multifreq.restype = C.c_int
+    L.bl_set_cuts.argtypes = [vp, C.POINTER(bl_cuts)]
+    L.bl_set_cuts.restype = C.c_int
     L.bl_set_tuning.argtypes = [vp, C.POINTER(bl_tuning)]
     L.bl_set_tuning.restype = C.c_int
     L.bl_get_tuning.argtypes = [vp, C.POINTER(bl_tuning)]
@@ -351,6 +379,11 @@ class Context:
         self._check(load().bl_render_batch(self.handle, len(images), descs, C.byref(g), grid.handle, C.byref(p),
                                            C.byref(m), t))
         return outs
+
+    def set_cuts(self, d):
+        """Install data cuts (see cuts()) for the following renders; None
+        removes them."""
+        self._check(load().bl_set_cuts(self.handle, C.byref(cuts(d)) if d is not None else None))
 
     def set_tuning(self, d):
         t = tuning(d)

@@ -189,7 +189,23 @@ struct PlasmaParams {
     double ne_per_rho;   // rho_unit / (mu m_p) / (1 + 1/(n_e/n_i))
     double th_per_pr;    // mu m_p / m_e
     double gauss_per_b;  // c sqrt(4 pi rho_unit)
+    // data cuts (bl_cuts), read from device memory only when set, so that
+    // they take no scalar registers in the kernels' loops
+    int cuts;                      // 0: none set
+    const struct CutParams *cut;   // device copy of the limits
 };
+
+// Data-cut limits in the order rho, n_e, p, Theta_e, B, sigma, beta^-1, r
+// (FP64 and rounded to FP32 on the host), and the half-space plane.
+struct CutParams {
+    double lo[8], hi[8];
+    float lo_f[8], hi_f[8];
+    double x0[3], n[3];
+    int plane;   // 0: none; +1: (x - x0).n < 0 is vacuum; -1: (x - x0).n > 0 is vacuum
+    int pad;
+};
+constexpr int kCutRho = 0, kCutNe = 1, kCutP = 2, kCutThetaE = 3, kCutB = 4, kCutSigma = 5, kCutBetaInv = 6,
+              kCutR = 7;
 
 // One image of a render (a batch of one for bl_render): the camera frame
 // (filled on the device), camera and spacetime parameters, where its results

@@ -313,7 +313,17 @@ struct Sample {
 //   u^t = gamma/alpha, u^a = u~^a - gamma beta^a/alpha,
 //   b^t = B^a u_a, b^a = (B^a + b^t u^a)/u^t, sigma = b^2/rho,
 //   beta^-1 = b^2/(2p), nu_fl = n (-k.u), cos(theta_B) = k.b/((-k.u)|b|).
+// A quantity outside its cut limits (paper section 4, Data Cuts), compared
+// in the arithmetic's own precision.
 template <typename R>
+__device__ __forceinline__ bool cut_out(const CutParams &c, int k, R q) {
+    if constexpr (sizeof(R) == 4) return q < c.lo_f[k] || q > c.hi_f[k];
+    else return q < c.lo[k] || q > c.hi[k];
+}
+
+// CUTS: compiled with the data-cut checks (renders with cuts installed use
+// that instantiation, so the others carry no trace of them).
+template <typename R, bool CUTS = false>
 __device__ __forceinline__ void sample_point(double a, int flat, const DevGrid &g, const PlasmaParams &pp,
                                              const double yd[8], double n_norm, Sample<R> &s) {
     s.plasma = false;
@@ -344,6 +354,19 @@ __device__ __forceinline__ void sample_point(double a, int flat, const DevGrid &
     R tr = fdiv((R)pp.r_high + binv * binv * (R)pp.r_low, R(1) + binv * binv);
     R th = (R)pp.th_per_pr * fdiv(p, rho) * fdiv((R)(pp.ne_ni + 1.0), (R)pp.ne_ni + tr);
     R Bg = sqrt(b2) * (R)pp.gauss_per_b;
+    if (CUTS && pp.cuts) {
+        // an opaque copy of the pointer keeps the limit loads here: hoisted out
+        // of the transfer's loop they would hold scalar registers throughout
+        const CutParams *cp = pp.cut;
+        asm volatile("" : "+s"(cp));
+        const CutParams &c = *cp;
+        const double d = (yd[1] - c.x0[0]) * c.n[0] + (yd[2] - c.x0[1]) * c.n[1] + (yd[3] - c.x0[2]) * c.n[2];
+        if (cut_out<R>(c, kCutRho, rho) || cut_out<R>(c, kCutP, p) || cut_out<R>(c, kCutR, k.r) ||
+            cut_out<R>(c, kCutNe, ne) || cut_out<R>(c, kCutThetaE, th) || cut_out<R>(c, kCutB, Bg) ||
+            cut_out<R>(c, kCutSigma, s.sigma) || cut_out<R>(c, kCutBetaInv, binv) || (c.plane > 0 && d < 0.0) ||
+            (c.plane < 0 && d > 0.0))
+            return;
+    }
     R kc[4] = {(R)yd[4], (R)yd[5], (R)yd[6], (R)yd[7]};
     R omega = -(kc[0] * s.u[0] + kc[1] * s.u[1] + kc[2] * s.u[2] + kc[3] * s.u[3]);
     R kb = kc[0] * s.b[0] + kc[1] * s.b[1] + kc[2] * s.b[2] + kc[3] * s.b[3];

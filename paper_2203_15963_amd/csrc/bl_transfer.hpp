@@ -597,7 +597,7 @@ __device__ __forceinline__ void to_state_r(const R p6[kQC], R kt, R y[8]) {
 }
 
 // Process piece w.p of the open step.
-template <bool POL, typename R>
+template <bool POL, typename R, bool CUTS = false>
 __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
                                       const QuartLds<R> &s_q, int lane) {
     const int flat = P.flat;
@@ -624,7 +624,7 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
     w.p = p - 1;
     Sample<R> smp;
     smp.plasma = false;
-    if (w.inb) sample_point<R>(P.a, flat, g, pp, ys, (double)w.n_norm, smp);
+    if (w.inb) sample_point<R, CUTS>(P.a, flat, g, pp, ys, (double)w.n_norm, smp);
     R c[8];
     if (smp.plasma) {
         R lt = w.L * w.dl * smp.omega;
@@ -812,7 +812,7 @@ __device__ __forceinline__ void load_ray_end(RayWalk<R> &w, const R *e, const do
 }
 
 // Whole ray by one lane (used where rays are not interleaved).
-template <bool POL, typename R>
+template <bool POL, typename R, bool CUTS = false>
 __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
                                              const TransferParams &tp, const double *rec, int n_acc, double kt,
                                              double den, const double upix[4], const double Hv[4],
@@ -823,7 +823,7 @@ __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &
     begin_ray(w, rec, n_acc, kt, den, tp);
     while (w.st >= 0 || w.p >= 0) {
         if (w.p < 0) next_step(w, s_q, lane);
-        piece<POL, R>(w, P, g, pp, s_q, lane);
+        piece<POL, R, CUTS>(w, P, g, pp, s_q, lane);
     }
     finish_ray<POL, R>(w, P, upix, Hv, o);
 }

@@ -329,7 +329,7 @@ __global__ void __launch_bounds__(256) k_order_scatter(const int *__restrict__ w
 template <bool POL, typename R>
 constexpr int transfer_waves() { return sizeof(R) == 4 ? (POL ? 3 : 4) : (POL ? 1 : 2); }
 
-template <bool POL, typename R, bool BATCH>
+template <bool POL, typename R, bool BATCH, bool CUTS>
 __global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(GeoParams P, Batch B, DevGrid g,
                                                                              PlasmaParams pp, TransferParams tp,
                                                  long long start, int count, int refill_min,
@@ -402,7 +402,7 @@ __global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(Geo
                 next_step(w, s_q, lane);
             }
         }
-        if (slot >= 0) piece<POL, R>(w, Pl, g, pp, s_q, lane);
+        if (slot >= 0) piece<POL, R, CUTS>(w, Pl, g, pp, s_q, lane);
     }
 }
 
@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(64) k_finish(GeoParams P, Batch B, long long s
 
 // Rays queued by k_geodesic: one wave, each lane traces and transfers its
 // rays in turn with a private buffer of big_cap records.
-template <bool POL, typename R>
+template <bool POL, typename R, bool CUTS>
 __global__ void __launch_bounds__(64) k_overflow(GeoParams P, Batch B, DevGrid g, PlasmaParams pp, TransferParams tp,
                                                  const int *__restrict__ ovf_count, const int *__restrict__ ovf_list,
                                                  double *__restrict__ big_rec, int big_cap) {
@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(64) k_overflow(GeoParams P, Batch B, DevGrid g
         double upix[4];
         pixel_observer(im.fr, Q, r, upix);
         TransferOut t;
-        transfer_ray<POL, R>(Q, g, pp, tl, r, o.n_acc, kt, den, upix, im.fr.H, t);
+        transfer_ray<POL, R, CUTS>(Q, g, pp, tl, r, o.n_acc, kt, den, upix, im.fr.H, t);
         write_pixel(t, NN, pix, im.image, aux);
     }
 }
@@ -904,7 +904,7 @@ __global__ void k_eval_samples(double a, int flat, DevGrid g, PlasmaParams pp, l
     conn_k(a, flat, y, y + 4, G);
     for (int m = 0; m < 16; ++m) o[8 + m] = G[m];
     Sample<double> s;
-    sample_point<double>(a, flat, g, pp, y, norms[i], s);
+    sample_point<double, true>(a, flat, g, pp, y, norms[i], s);
     o[53] = s.sigma;
     if (!s.plasma) return;
     // invariants: j/nu^2, alpha nu, rho nu at the fluid-frame frequency
@@ -963,6 +963,9 @@ struct bl_context {
     u32x4 *d_step_pk = nullptr;
     float *d_step_tail = nullptr;
     bool has_step_model = false;
+    bl_cuts cuts{};          // data cuts for the following renders (bl_set_cuts)
+    bool has_cuts = false;
+    CutParams *d_cuts = nullptr;   // their device copy, uploaded with each render
     // network training workspace
     u32x4 *d_mlp_pk = nullptr;
     float *d_mlp_tail = nullptr;
@@ -1075,7 +1078,7 @@ GeoParams geo_params(const bl_camera *c, const bl_spacetime *st, const bl_integr
     return P;
 }
 
-PlasmaParams plasma_params(const bl_plasma *plasma, const DevGrid &g, double mass_msun) {
+PlasmaParams plasma_params(const bl_context *ctx, const bl_plasma *plasma, const DevGrid &g, double mass_msun) {
     PlasmaParams pp;
     pp.mu = plasma->mu;
     pp.ne_ni = plasma->ne_ni;
@@ -1088,7 +1091,35 @@ PlasmaParams plasma_params(const bl_plasma *plasma, const DevGrid &g, double mas
     pp.ne_per_rho = g.rho_unit / (pp.mu * kMp) / (1.0 + 1.0 / pp.ne_ni);
     pp.th_per_pr = pp.mu * kMp / kMe;
     pp.gauss_per_b = kC * sqrt(4.0 * kPi * g.rho_unit);
+    pp.cuts = ctx->has_cuts ? 1 : 0;
+    pp.cut = ctx->d_cuts;
     return pp;
+}
+
+// Device copy of the context's data cuts for the launches that follow on the
+// stream (the copy is ordered with them).
+bl_status upload_cuts(bl_context *ctx) {
+    if (!ctx->has_cuts) return BL_OK;
+    if (!ctx->d_cuts && hipMalloc((void **)&ctx->d_cuts, sizeof(CutParams)) != hipSuccess)
+        return fail(ctx, BL_E_OOM, "device allocation of the data cuts failed");
+    const bl_cuts &c = ctx->cuts;
+    CutParams h{};
+    const double *lims[8] = {c.rho, c.ne, c.p, c.theta_e, c.b, c.sigma, c.beta_inv, c.r};
+    for (int k = 0; k < 8; ++k) {
+        h.lo[k] = lims[k][0];
+        h.hi[k] = lims[k][1];
+        h.lo_f[k] = (float)h.lo[k];
+        h.hi_f[k] = (float)h.hi[k];
+    }
+    for (int i = 0; i < 3; ++i) {
+        h.x0[i] = c.plane_origin[i];
+        h.n[i] = c.plane_normal[i];
+    }
+    h.plane = c.plane;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_cuts, &h, sizeof(CutParams), hipMemcpyHostToDevice, ctx->stream));
+    // the host struct is a local: wait for the copy to have read it
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return BL_OK;
 }
 
 // What the geodesic kernels store with each record for the transfer: the grid
@@ -1144,14 +1175,14 @@ bl_status persistent_waves(bl_context *ctx) {
     if (ctx->cus > 0) return BL_OK;
     int cus = 0, b[8] = {0};
     HIPCHK(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[0], k_transfer<false, double, false>, 64, 0));
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[1], k_transfer<false, float, false>, 64, 0));
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[2], k_transfer<true, double, false>, 64, 0));
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[3], k_transfer<true, float, false>, 64, 0));
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[4], k_transfer<false, double, true>, 64, 0));
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[5], k_transfer<false, float, true>, 64, 0));
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[6], k_transfer<true, double, true>, 64, 0));
-    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[7], k_transfer<true, float, true>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[0], k_transfer<false, double, false, false>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[1], k_transfer<false, float, false, false>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[2], k_transfer<true, double, false, false>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[3], k_transfer<true, float, false, false>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[4], k_transfer<false, double, true, false>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[5], k_transfer<false, float, true, false>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[6], k_transfer<true, double, true, false>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[7], k_transfer<true, float, true, false>, 64, 0));
     for (int k = 0; k < 8; ++k) ctx->blocks_tr[k] = std::max(1, b[k]);
     ctx->cus = std::max(1, cus);
     return BL_OK;
@@ -1242,22 +1273,22 @@ bl_status upload_one(bl_context *ctx, const bl_camera *cam, const bl_spacetime *
     return upload_images(ctx, 1, &cam, &st, &image, &aux, t, B, total);
 }
 
-template <bool POL, typename R, bool BATCH>
+template <bool POL, typename R, bool BATCH, bool CUTS>
 void launch_transfer(bl_context *ctx, dim3 grd, const GeoParams &P, const Batch &B, const DevGrid &g,
                      const PlasmaParams &pp, const TransferParams &tp, long long start, int count, int refill,
                      int *q) {
     R *ends = reinterpret_cast<R *>(ctx->d_ends);
-    hipLaunchKernelGGL((k_transfer<POL, R, BATCH>), grd, dim3(64), 0, ctx->stream, P, B, g, pp, tp, start, count,
+    hipLaunchKernelGGL((k_transfer<POL, R, BATCH, CUTS>), grd, dim3(64), 0, ctx->stream, P, B, g, pp, tp, start, count,
                        refill, ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_order, ctx->ext, q, ends);
     if (POL)
         hipLaunchKernelGGL((k_finish<R, BATCH>), dim3((count + 63) / 64), dim3(64), 0, ctx->stream, P, B, start, count,
                            ctx->d_rec, ctx->d_nacc, ctx->ext, (const R *)ends);
 }
 
-template <bool POL, typename R>
+template <bool POL, typename R, bool CUTS>
 void launch_overflow(bl_context *ctx, const GeoParams &P, const Batch &B, const DevGrid &g, const PlasmaParams &pp,
                      const TransferParams &tp, int big_cap) {
-    hipLaunchKernelGGL((k_overflow<POL, R>), dim3(1), dim3(64), 0, ctx->stream, P, B, g, pp, tp, ctx->d_ovf_count,
+    hipLaunchKernelGGL((k_overflow<POL, R, CUTS>), dim3(1), dim3(64), 0, ctx->stream, P, B, g, pp, tp, ctx->d_ovf_count,
                        ctx->d_ovf_list, ctx->d_big, big_cap);
 }
 
@@ -1344,7 +1375,8 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         return s;
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, ctx->d_ovf_count, 0, 1);
     HIPCHK(ctx, hipGetLastError());
-    const PlasmaParams pp = plasma_params(plasma, grid->g, sts[0]->mass_msun);
+    if ((s = upload_cuts(ctx)) != BL_OK) return s;
+    const PlasmaParams pp = plasma_params(ctx, plasma, grid->g, sts[0]->mass_msun);
     TransferParams tp;
     tp.ds_max = integ->ds_max;
     tp.L = kG * sts[0]->mass_msun * kMsun / (kC * kC);
@@ -1410,15 +1442,24 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
             TimedLaunch tl(ctx, BL_K_TRANSFER);
             int *q = ctx->d_queue + 2 * (ichunk * n_tr + f);
             dim3 pg(std::min<int>(grd.x, resident));
-            switch (kidx) {
-            case 0: launch_transfer<false, double, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
-            case 1: launch_transfer<false, float, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
-            case 2: launch_transfer<true, double, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
-            case 3: launch_transfer<true, float, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
-            case 4: launch_transfer<false, double, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
-            case 5: launch_transfer<false, float, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
-            case 6: launch_transfer<true, double, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
-            default: launch_transfer<true, float, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            const int kc = kidx + (pp.cuts ? 8 : 0);
+            switch (kc) {
+            case 0: launch_transfer<false, double, false, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 1: launch_transfer<false, float, false, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 2: launch_transfer<true, double, false, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 3: launch_transfer<true, float, false, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 4: launch_transfer<false, double, true, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 5: launch_transfer<false, float, true, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 6: launch_transfer<true, double, true, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 7: launch_transfer<true, float, true, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 8: launch_transfer<false, double, false, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 9: launch_transfer<false, float, false, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 10: launch_transfer<true, double, false, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 11: launch_transfer<true, float, false, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 12: launch_transfer<false, double, true, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 13: launch_transfer<false, float, true, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 14: launch_transfer<true, double, true, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            default: launch_transfer<true, float, true, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
             }
             HIPCHK(ctx, hipGetLastError());
         }
@@ -1430,11 +1471,15 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         TransferParams tpf = tp;
         tpf.nu_cam = cams[f]->nu_hz;
         TimedLaunch tl(ctx, BL_K_OVERFLOW);
-        switch (kidx & 3) {
-        case 0: launch_overflow<false, double>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
-        case 1: launch_overflow<false, float>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
-        case 2: launch_overflow<true, double>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
-        default: launch_overflow<true, float>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        switch ((kidx & 3) + (pp.cuts ? 4 : 0)) {
+        case 0: launch_overflow<false, double, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 1: launch_overflow<false, float, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 2: launch_overflow<true, double, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 3: launch_overflow<true, float, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 4: launch_overflow<false, double, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 5: launch_overflow<false, float, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 6: launch_overflow<true, double, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        default: launch_overflow<true, float, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
         }
         HIPCHK(ctx, hipGetLastError());
     }
@@ -1538,6 +1583,7 @@ void bl_destroy(bl_context *ctx) {
     (void)hipFree(ctx->d_big);
     (void)hipFree(ctx->d_queue);
     (void)hipFree(ctx->d_ends);
+    (void)hipFree(ctx->d_cuts);
     delete ctx;
 }
 
@@ -1688,6 +1734,26 @@ bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *s
     if (!ctx) return BL_E_INVALID_ARG;
     if (!cam || !st) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
     return render_images(ctx, 1, &cam, &st, &image_out, &aux_out, integ, grid, plasma, mode, ctx->tuning, false);
+}
+
+bl_status bl_set_cuts(bl_context *ctx, const bl_cuts *cuts) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    if (!cuts) {
+        ctx->has_cuts = false;
+        return BL_OK;
+    }
+    const double *lims[8] = {cuts->rho, cuts->ne, cuts->p, cuts->theta_e, cuts->b, cuts->sigma, cuts->beta_inv,
+                             cuts->r};
+    for (int k = 0; k < 8; ++k)
+        if (std::isnan(lims[k][0]) || std::isnan(lims[k][1]))
+            return fail(ctx, BL_E_INVALID_ARG, "cut limits must not be NaN");
+    if (cuts->plane < -1 || cuts->plane > 1) return fail(ctx, BL_E_INVALID_ARG, "plane must be -1, 0 or 1");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(cuts->plane_origin[i]) || !std::isfinite(cuts->plane_normal[i]))
+            return fail(ctx, BL_E_INVALID_ARG, "plane origin and normal must be finite");
+    ctx->cuts = *cuts;
+    ctx->has_cuts = true;
+    return BL_OK;
 }
 
 bl_status bl_render_multifreq(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
@@ -2074,7 +2140,8 @@ bl_status bl_eval_samples(bl_context *ctx, const bl_spacetime *st, const bl_grid
     if (grid->g.dtype != 0) return fail(ctx, BL_E_UNSUPPORTED, "float32 grids need precision 1");
     if (n == 0) return BL_OK;
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    const PlasmaParams pp = plasma_params(plasma, grid->g, st->mass_msun);
+    if ((s = upload_cuts(ctx)) != BL_OK) return s;
+    const PlasmaParams pp = plasma_params(ctx, plasma, grid->g, st->mass_msun);
     hipLaunchKernelGGL(k_eval_samples, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, ctx->stream, st->a,
                        st->flat ? 1 : 0, grid->g, pp, (long long)n, states, norms, out);
     HIPCHK(ctx, hipGetLastError());

@@ -233,6 +233,76 @@ def test_render_polarized_sigma_cut(ctx, oracle, precision):
     _compare_render(ctx, oracle, w, precision=precision, tol=TOL_FP64 if precision == 0 else TOL_MIXED)
 
 
+def _cut_set(w):
+    """theta_e >= 3, 4 <= r <= 40 and the half of the grid on the camera's side
+    of the plane through the origin orthogonal to the line of sight."""
+    cam = w["camera"]
+    nrm = (math.sin(cam["theta"]) * math.cos(cam["phi"]), math.sin(cam["theta"]) * math.sin(cam["phi"]),
+           math.cos(cam["theta"]))
+    return {"theta_e": (3.0, math.inf), "r": (4.0, 40.0),
+            "plane": {"side": 1, "origin": (0.0, 0.0, 0.0), "normal": nrm}}
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_render_with_data_cuts(ctx, oracle, precision):
+    """Data cuts (paper section 4) installed with bl_set_cuts against the
+    oracle with the same cuts."""
+    w = _wl("c2_256_pol", 12)
+    cuts = _cut_set(w)
+    w["plasma"]["cuts"] = cuts
+    ctx.set_cuts(cuts)
+    try:
+        _compare_render(ctx, oracle, w, precision=precision, tol=TOL_FP64 if precision == 0 else TOL_MIXED)
+    finally:
+        ctx.set_cuts(None)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cuts_without_effect_reproduce_the_uncut_render(ctx, precision):
+    """Installed cuts with infinite limits run the cut instantiation of the
+    transfer kernels, whose results must equal the plain kernels' bit for bit
+    (the FP64 one sits at the edge of the register file)."""
+    w = _wl("c2_256_pol", 12)
+    gg = ctx.grid(_grid(w))
+    args = (w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"])
+    i0, a0 = ctx.render(*args, precision=precision)
+    ctx.set_cuts({k: (-math.inf, math.inf) for k in ("rho", "ne", "p", "theta_e", "b", "sigma", "beta_inv", "r")})
+    try:
+        i1, a1 = ctx.render(*args, precision=precision)
+    finally:
+        ctx.set_cuts(None)
+    torch.cuda.synchronize()
+    assert torch.equal(i0, i1) and torch.equal(a0, a1)
+
+
+def test_complementary_cuts_partition_the_samples(ctx):
+    """The two sides of a plane cut hold every plasma sample exactly once."""
+    w = _wl("c2_256_pol", 12)
+    gg = ctx.grid(_grid(w))
+    plane = _cut_set(w)["plane"]
+    args = (w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"])
+    _, a0 = ctx.render(*args)
+    halves = []
+    for side in (1, -1):
+        ctx.set_cuts({"plane": dict(plane, side=side)})
+        halves.append(ctx.render(*args)[1])
+    ctx.set_cuts(None)
+    _, a1 = ctx.render(*args)
+    torch.cuda.synchronize()
+    n0, nh = a0[8].cpu().numpy(), [h[8].cpu().numpy() for h in halves]
+    assert np.array_equal(nh[0] + nh[1], n0) and nh[0].sum() > 0 and nh[1].sum() > 0
+    assert torch.equal(a0, a1)   # removing the cuts restores the uncut render
+
+
+def test_set_cuts_rejects_bad_arguments(ctx):
+    from paper_2203_15963_amd import blgpu
+    with pytest.raises(blgpu.BlError):
+        ctx.set_cuts({"rho": (math.nan, 1.0)})
+    with pytest.raises(blgpu.BlError):
+        ctx.set_cuts({"plane": {"side": 2, "origin": (0, 0, 0), "normal": (1, 0, 0)}})
+    ctx.set_cuts(None)
+
+
 def test_render_polarized_smr(ctx, oracle):
     _compare_render(ctx, oracle, _wl("c3_1024_smr", 11))
 
