@@ -135,9 +135,10 @@ void   or_thermal_coeffs(double ne, double thetae, double B, double nu,
    out[8..11]  = ne, thetae, B_gauss, nu_fluid
    out[12..27] = tetrad e0..e3 (contravariant, 4 each)
    out[28]     = 1 if the point holds emitting plasma, else 0 (vacuum)
-   out[29]     = sigma                                                      */
+   out[29]     = sigma
+   out[30..32] = rho, p (code units) and beta^-1 = b^2/(2p) (plasma only)   */
 void   or_sample_point(const or_spacetime *st, const or_grid *gr, const or_plasma *pl,
-                       const double y[8], double n_norm, double out[30]);
+                       const double y[8], double n_norm, double out[33]);
 
 /* ---- transfer pieces (transfer.c) ---- */
 double or_unpol_segment(double I, double j, double alpha, double dl);
@@ -153,11 +154,20 @@ void   or_transport_rhs(double a, int flat, const double y[8],
 void   or_dense_quartic(const double y0[8], const double y1[8], const double f0[8],
                         const double f1[8], const double ym[8], double h, double theta,
                         double out[8]);
+/* Averaged quantities (paper section 4, Auxiliary Images): for q in rho, n_e,
+   p, Theta_e, B, sigma, beta^-1 (index k), avg[k] = <q>_lambda =
+   (1/lambda) int q dlambda over the plasma samples, avg[7 + k] = <q>_Ij =
+   int q j_I dlambda / int j_I dlambda (0 without emission), avg[14 + k] =
+   <q>_tau, the solution of d<q>/dtau = q - <q> from 0 at the source end,
+   advanced over a sample of depth dtau as <q> += (q - <q>)(1 - e^-dtau). */
+#define OR_NAVG 21
+
 /* Render the listed pixels (index = i + N*j).  image[p][4] holds I,Q,U,V
-   (I_nu units, erg s^-1 cm^-2 sr^-1 Hz^-1); aux[p][OR_NAUX].               */
+   (I_nu units, erg s^-1 cm^-2 sr^-1 Hz^-1); aux[p][OR_NAUX]; avg (or NULL)
+   [p][OR_NAVG] the averaged quantities.                                     */
 void   or_render_pixels(const or_camera *cam, const or_spacetime *st,
                         const or_integrator *in, const or_grid *gr,
                         const or_plasma *pl, int64_t n_pix, const int64_t *pix,
-                        double *image, double *aux, int n_threads);
+                        double *image, double *aux, double *avg, int n_threads);
 
 #endif

@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
 NAUX = 10
+NAVG = 21
 AUX_NAMES = ["dt", "s", "lambda", "tau", "I_j", "n_acc", "n_rej", "status", "n_samp", "n_rec"]
 ESCAPED, CAPTURED, MAXSTEPS, UNDERFLOW, NONFINITE = 1, 2, 3, 4, 5
 
@@ -98,7 +99,7 @@ def lib():
         L.or_ds_dlambda.argtypes = [d, i, P]
         L.or_render_pixels.argtypes = [C.POINTER(Camera), C.POINTER(Spacetime), C.POINTER(Integrator),
                                        C.POINTER(Grid), C.POINTER(Plasma), i64,
-                                       C.POINTER(C.c_int64), P, P, i]
+                                       C.POINTER(C.c_int64), P, P, P, i]
         L.or_dense_quartic.argtypes = [P, P, P, P, P, d, d, P]
         _LIB = L
     return _LIB
@@ -267,7 +268,7 @@ def thermal_coeffs(ne, thetae, B, nu, cos_theta, polarized=1):
 def sample_point(st, gr, pl, y, n_norm):
     gh, s, p = grid(gr), spacetime(st), plasma(pl)
     y = np.ascontiguousarray(y, dtype=np.float64)
-    out = np.zeros(30)
+    out = np.zeros(33)
     lib().or_sample_point(C.byref(s), C.byref(gh.s), C.byref(p), _dp(y), float(n_norm), _dp(out))
     return out
 
@@ -294,26 +295,31 @@ def transport_rhs(a, y, Nre, Nim, flat=0):
     return dR.reshape(4, 4), dI.reshape(4, 4)
 
 
-def render_pixels(cam, st, integ, gr, pl, pixels, n_threads=None):
-    """Render pixel indices (i + N j).  Returns image [n,4] and aux [n,NAUX]."""
+def render_pixels(cam, st, integ, gr, pl, pixels, n_threads=None, averages=False):
+    """Render pixel indices (i + N j).  Returns image [n,4] and aux [n,NAUX],
+    and with averages=True also the averaged quantities [n,NAVG]."""
     c, s, g, p = camera(cam), spacetime(st), integrator(integ), plasma(pl)
     gh = grid(gr)
     pix = np.ascontiguousarray(pixels, dtype=np.int64)
     img = np.zeros((len(pix), 4))
     aux = np.zeros((len(pix), NAUX))
+    avg = np.zeros((len(pix), NAVG)) if averages else None
     if n_threads is None:
         n_threads = os.cpu_count() or 1
     lib().or_render_pixels(C.byref(c), C.byref(s), C.byref(g), C.byref(gh.s), C.byref(p),
                            len(pix), pix.ctypes.data_as(C.POINTER(C.c_int64)),
-                           _dp(img), _dp(aux), int(n_threads))
-    return img, aux
+                           _dp(img), _dp(aux), _dp(avg) if averages else None, int(n_threads))
+    return (img, aux, avg) if averages else (img, aux)
 
 
-def render(cam, st, integ, gr, pl, n_threads=None):
-    """Whole image: returns image [4, N, N] and aux [NAUX, N, N] (row j, column i)."""
+def render(cam, st, integ, gr, pl, n_threads=None, averages=False):
+    """Whole image: returns image [4, N, N] and aux [NAUX, N, N] (row j, column
+    i), and with averages=True the averaged quantities [NAVG, N, N] (<q>_lambda,
+    <q>_Ij, <q>_tau for q in rho, n_e, p, Theta_e, B, sigma, beta^-1)."""
     n = int(cam["n"])
-    img, aux = render_pixels(cam, st, integ, gr, pl, np.arange(n * n), n_threads)
-    return img.T.reshape(4, n, n), aux.T.reshape(NAUX, n, n)
+    out = render_pixels(cam, st, integ, gr, pl, np.arange(n * n), n_threads, averages)
+    res = (out[0].T.reshape(4, n, n), out[1].T.reshape(NAUX, n, n))
+    return res + (out[2].T.reshape(NAVG, n, n),) if averages else res
 
 
 def dense_quartic(y0, y1, f0, f1, ym, h, theta):

@@ -248,13 +248,13 @@ static int cut_out(const or_plasma *pl, int k, double q)
 }
 
 void or_sample_point(const or_spacetime *st, const or_grid *gr, const or_plasma *pl,
-                     const double y[8], double n_norm, double out[30])
+                     const double y[8], double n_norm, double out[33])
 {
     double g[16], gi[16], prim[8], u[4], ul[4], b[4], bl[4], ku[4];
     double q = 0.0, gam, alpha, beta[3], bt, b2, rho, p, sigma, binv, ne, tr, thetae;
     double Bg, omega, nu_fl, kb, cth, co[8], e[4][4];
     int i, j;
-    memset(out, 0, 30 * sizeof(double));
+    memset(out, 0, 33 * sizeof(double));
     if (or_grid_sample(gr, pl->interp, y + 1, prim) < 0) return;
     rho = prim[0];
     p = prim[1];
@@ -302,6 +302,7 @@ void or_sample_point(const or_spacetime *st, const or_grid *gr, const or_plasma 
     for (i = 0; i < 3; ++i) out[i] = co[i] / (nu_fl * nu_fl);
     for (i = 3; i < 8; ++i) out[i] = co[i] * nu_fl;
     out[8] = ne; out[9] = thetae; out[10] = Bg; out[11] = nu_fl;
+    out[30] = rho; out[31] = p; out[32] = binv;
     for (i = 0; i < 4; ++i) {
         ku[i] = 0.0;
         for (j = 0; j < 4; ++j) ku[i] += gi[4 * i + j] * y[4 + j];

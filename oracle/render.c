@@ -190,10 +190,28 @@ static void stokes_to_n(double e[4][4], const double S[4], double Nre[16], doubl
         }
 }
 
+/* Running sums of the averaged quantities (section 4, Auxiliary Images) at a
+   plasma sample with outputs c of or_sample_point, affine length dl,
+   emission increment dj and depth dtau: sl[k] += q dl, sj[k] += q dj and
+   qt[k] += (q - qt[k])(1 - e^-dtau). */
+static void accumulate_averages(const double *c, double dl, double dj, double dtau,
+                                double sl[7], double sj[7], double qt[7])
+{
+    const double q[7] = {c[30], c[8], c[31], c[9], c[10], c[29], c[32]};
+    const double w = -expm1(-dtau);
+    int k;
+    for (k = 0; k < 7; ++k) {
+        sl[k] += q[k] * dl;
+        sj[k] += q[k] * dj;
+        qt[k] += (q[k] - qt[k]) * w;
+    }
+}
+
 static void render_one(const or_camera *cam, const or_spacetime *st, const or_integrator *in,
                        const or_grid *gr, const or_plasma *pl, int64_t pix,
-                       double img[4], double aux[OR_NAUX])
+                       double img[4], double aux[OR_NAUX], double *avg)
 {
+    double sl[7] = {0}, sj[7] = {0}, qt[7] = {0};
     int i = (int)(pix % cam->n), j = (int)(pix / cam->n);
     double y[8], n_norm, upix[4], Hv[4];
     double L = G_NEWTON * st->mass_msun * M_SUN / (C_LIGHT * C_LIGHT);
@@ -213,7 +231,7 @@ static void render_one(const or_camera *cam, const or_spacetime *st, const or_in
     if (!pl->polarized) {
         double I = 0.0;
         for (r = 0; r < n_rec; ++r) {
-            double c[30], dlp;
+            double c[33], dlp;
             if (!rec[r].in_box) continue;
             or_sample_point(st, gr, pl, rec[r].ys, n_norm, c);
             if (c[28] == 0.0) continue;
@@ -222,6 +240,7 @@ static void render_one(const or_camera *cam, const or_spacetime *st, const or_in
             I = or_unpol_segment(I, c[0], c[3], dlp);
             tau += c[3] * dlp;
             Ij += c[0] * dlp;
+            if (avg) accumulate_averages(c, rec[r].dl, c[0] * dlp, c[3] * dlp, sl, sj, qt);
         }
         img[0] = nu3 * I;
     } else {
@@ -231,7 +250,7 @@ static void render_one(const or_camera *cam, const or_spacetime *st, const or_in
         memset(Nre, 0, sizeof(Nre));
         memset(Nim, 0, sizeof(Nim));
         for (r = 0; r < n_rec; ++r) {
-            double c[30];
+            double c[33];
             int plasma = 0;
             if (rec[r].in_box) {
                 or_sample_point(st, gr, pl, rec[r].ys, n_norm, c);
@@ -249,6 +268,7 @@ static void render_one(const or_camera *cam, const or_spacetime *st, const or_in
                 n_samp++;
                 tau += c[3] * dlp;
                 Ij += c[0] * dlp;
+                if (avg) accumulate_averages(c, rec[r].dl, c[0] * dlp, c[3] * dlp, sl, sj, qt);
                 for (q = 0; q < 8; ++q)
                     if (c[q] != 0.0) break;
                 if (q == 8) continue;   /* all coefficients zero: identity */
@@ -277,6 +297,13 @@ static void render_one(const or_camera *cam, const or_spacetime *st, const or_in
             for (m = 0; m < 4; ++m) img[m] = nu3 * S[m];
         }
     }
+    if (avg) {
+        for (m = 0; m < 7; ++m) {
+            avg[m] = sl[m] / ray.lambda;
+            avg[7 + m] = Ij > 0.0 ? sj[m] / Ij : 0.0;
+            avg[14 + m] = qt[m];
+        }
+    }
     aux[OR_AUX_DT] = ray.dt;
     aux[OR_AUX_S] = ray.s;
     aux[OR_AUX_LAMBDA] = ray.lambda;
@@ -294,7 +321,7 @@ static void render_one(const or_camera *cam, const or_spacetime *st, const or_in
 typedef struct {
     const or_camera *cam; const or_spacetime *st; const or_integrator *in;
     const or_grid *gr; const or_plasma *pl;
-    int64_t n_pix; const int64_t *pix; double *image, *aux;
+    int64_t n_pix; const int64_t *pix; double *image, *aux, *avg;
     int64_t next;
     pthread_mutex_t lock;
 } job;
@@ -309,7 +336,7 @@ static void *worker(void *arg)
         pthread_mutex_unlock(&jb->lock);
         if (p >= jb->n_pix) break;
         render_one(jb->cam, jb->st, jb->in, jb->gr, jb->pl, jb->pix[p],
-                   jb->image + 4 * p, jb->aux + OR_NAUX * p);
+                   jb->image + 4 * p, jb->aux + OR_NAUX * p, jb->avg ? jb->avg + OR_NAVG * p : NULL);
     }
     return NULL;
 }
@@ -317,7 +344,7 @@ static void *worker(void *arg)
 void or_render_pixels(const or_camera *cam, const or_spacetime *st,
                       const or_integrator *in, const or_grid *gr,
                       const or_plasma *pl, int64_t n_pix, const int64_t *pix,
-                      double *image, double *aux, int n_threads)
+                      double *image, double *aux, double *avg, int n_threads)
 {
     job jb;
     pthread_t th[256];
@@ -325,7 +352,7 @@ void or_render_pixels(const or_camera *cam, const or_spacetime *st,
     if (n_threads < 1) n_threads = 1;
     if (n_threads > 256) n_threads = 256;
     jb.cam = cam; jb.st = st; jb.in = in; jb.gr = gr; jb.pl = pl;
-    jb.n_pix = n_pix; jb.pix = pix; jb.image = image; jb.aux = aux; jb.next = 0;
+    jb.n_pix = n_pix; jb.pix = pix; jb.image = image; jb.aux = aux; jb.avg = avg; jb.next = 0;
     pthread_mutex_init(&jb.lock, NULL);
     for (t = 0; t < n_threads; ++t) pthread_create(&th[t], NULL, worker, &jb);
     for (t = 0; t < n_threads; ++t) pthread_join(th[t], NULL);
