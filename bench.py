@@ -288,6 +288,8 @@ def main():
     ap.add_argument("--freqs", type=int, default=0,
                     help="single image: also time a K-frequency render from one geodesic pass (K frequencies "
                          "evenly spaced in wavelength over 152-324 GHz, as for true-colour images)")
+    ap.add_argument("--averages", action="store_true",
+                    help="single image: also time a render with the 21 averaged-quantity maps (bl_render_averages)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -401,6 +403,26 @@ def main():
                             "single_frequency_ms": ms, "speedup_vs_separate_renders": K * ms / mms,
                             "kernels": kernel_table(mprof, args.steps)}
         log("multi-frequency", out["multifreq"]["ms_per_render"], "ms per render of", K, "frequencies")
+    if args.averages:
+        def astep():
+            return ctx.render_averages(w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"],
+                                       precision=args.precision)
+
+        astep()
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        ctx.profile_read()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            astep()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        aprof = ctx.profile_read()
+        ctx.profile_enable(False)
+        ams = (t1 - t0) * 1e3 / args.steps
+        out["averages"] = {"ms_per_render": ams, "single_render_ms": ms, "extra_ms": ams - ms,
+                           "kernels": kernel_table(aprof, args.steps)}
+        log("averages", ams, "ms per render with the 21 maps")
     if args.copy_probe:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)

@@ -232,6 +232,21 @@ bl_status bl_render_batch(bl_context *ctx, int32_t n_images, const bl_image_desc
                           const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
                           const bl_mode *mode, const bl_tuning *tuning);
 
+/* Averaged quantities (paper section 4, Auxiliary Images): a render of one
+   image (as bl_render: image_out and aux_out) followed by a pass over the
+   same step records that writes avg_out, device [BL_NAVG][N][N] doubles:
+   for q = rho, n_e, p, Theta_e, B, sigma, beta^-1 (k = 0..6; units as for
+   bl_cuts), map k = <q>_lambda = (1/lambda) int q dlambda over the plasma
+   samples (lambda the aux map of that name), map 7 + k = <q>_Ij =
+   int q j_I dlambda / int j_I dlambda (0 without emission), map 14 + k =
+   <q>_tau, the solution of d<q>/dtau = q - <q> from 0 at the source end,
+   advanced over a sample of depth dtau as <q> += (q - <q>)(1 - e^-dtau).
+   Data cuts apply.  The image and aux equal those of bl_render. */
+#define BL_NAVG 21
+bl_status bl_render_averages(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
+                             const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
+                             const bl_mode *mode, double *image_out, double *aux_out, double *avg_out);
+
 /* Data cuts (paper section 4, Data Cuts): a sample whose rho, n_e, p,
    Theta_e, B, sigma, beta^-1 or Kerr-Schild r lies below its lower limit
    ([0]) or above its upper limit ([1]) is vacuum, and with plane = +1 (-1)

@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libblgpu.so")
 ABI_VERSION = 1
 NAUX = 10
+NAVG = 21
 NKERNEL = 4
 KERNEL_NAMES = ["setup", "geodesic", "transfer", "overflow"]
 NSAMPLE_OUT = 64
@@ -152,6 +153,9 @@ def load():
                                       vp, C.POINTER(bl_plasma), C.POINTER(bl_mode), i32, C.POINTER(C.c_double),
                                       C.POINTER(vp), C.POINTER(vp)]
     L.bl_render_multifreq.restype = C.c_int
+    L.bl_render_averages.argtypes = [vp, C.POINTER(bl_camera), C.POINTER(bl_spacetime), C.POINTER(bl_integrator),
+                                     vp, C.POINTER(bl_plasma), C.POINTER(bl_mode), vp, vp, vp]
+    L.bl_render_averages.restype = C.c_int
     L.bl_set_cuts.argtypes = [vp, C.POINTER(bl_cuts)]
     L.bl_set_cuts.restype = C.c_int
     L.bl_set_tuning.argtypes = [vp, C.POINTER(bl_tuning)]
@@ -336,6 +340,16 @@ class Context:
         self._check(load().bl_render(self.handle, C.byref(c), C.byref(s), C.byref(g), grid.handle,
                                      C.byref(p), C.byref(m), _ptr(image), _ptr(aux)))
         return image, aux
+
+    def render_averages(self, cam, st, integ, grid, pl, precision=0, step_model=0):
+        """Render one image and its averaged quantities; returns (image, aux,
+        avg [NAVG, N, N])."""
+        n = int(cam["n"])
+        image, aux, avg = self._empty(4, n, n), self._empty(NAUX, n, n), self._empty(NAVG, n, n)
+        c, s, g, p, m = camera(cam), spacetime(st), integrator(integ), plasma(pl), mode(precision, step_model)
+        self._check(load().bl_render_averages(self.handle, C.byref(c), C.byref(s), C.byref(g), grid.handle,
+                                              C.byref(p), C.byref(m), _ptr(image), _ptr(aux), _ptr(avg)))
+        return image, aux, avg
 
     def render_multifreq(self, cam, st, integ, grid, pl, nu_hz, precision=0, step_model=0, outputs=None):
         """One camera at several frequencies from one geodesic pass; returns a

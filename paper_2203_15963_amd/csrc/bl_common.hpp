@@ -217,6 +217,7 @@ struct ImgDev {
     double L;            // GM/c^2 in cm
     double *image;       // [4][n][n]
     double *aux;         // [naux][n][n]
+    double *avg;         // [21][n][n] averaged quantities (their own render pass), or null
     long long ray0;      // first global ray id
     long long nray;      // ray ids owned: n^2, or whole pixel tiles
     int flat, pad;

@@ -306,6 +306,7 @@ struct Sample {
     R u[4], b[4];         // fluid 4-velocity and magnetic 4-vector (contravariant)
     R omega;              // -k.u for the unnormalised k
     R ne, th, B, nu_fl, sigma;
+    R rho, p, binv;       // density and pressure (code units), beta^-1
 };
 
 // Plasma state and fluid-frame coefficients at state y = (x^mu, k_mu) for a
@@ -378,6 +379,9 @@ __device__ __forceinline__ void sample_point(double a, int flat, const DevGrid &
     s.th = th;
     s.B = Bg;
     s.nu_fl = nu;
+    s.rho = rho;
+    s.p = p;
+    s.binv = binv;
     s.plasma = true;
 }
 

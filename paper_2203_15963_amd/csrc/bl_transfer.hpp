@@ -476,6 +476,9 @@ struct RayWalk {
     int nsamp, nrec;
     R pys[kQC], pyb[kQC];   // previous piece: sample and boundary (x, y, z, k_x, k_y, k_z)
     Coh<R> N;
+    // averaged quantities (their own pass): for q = rho, n_e, p, Theta_e, B,
+    // sigma, beta^-1, the sums of q dlambda and q dI_j and the tau-relaxed <q>
+    R av_l[7], av_j[7], av_t[7];
 };
 
 template <typename R>
@@ -501,6 +504,8 @@ __device__ __forceinline__ void begin_ray(RayWalk<R> &w, const double *rec, int 
     w.I = w.tau = w.Ij = w.tau_c = w.Ij_c = R(0);
     w.nsamp = 0;
     w.nrec = n_acc - 1 - last;
+#pragma unroll
+    for (int m = 0; m < 7; ++m) w.av_l[m] = w.av_j[m] = w.av_t[m] = R(0);
 #pragma unroll
     for (int m = 0; m < 10; ++m) w.N.r[m] = R(0);
 #pragma unroll
@@ -596,8 +601,24 @@ __device__ __forceinline__ void to_state_r(const R p6[kQC], R kt, R y[8]) {
     y[4] = kt; y[5] = p6[3]; y[6] = p6[4]; y[7] = p6[5];
 }
 
-// Process piece w.p of the open step.
-template <bool POL, typename R, bool CUTS = false>
+// Averaged quantities at a plasma sample (paper section 4, Auxiliary
+// Images): sums of q dlambda and q dI_j, and <q>_tau relaxed towards q over
+// the sample's depth dtau, <q> += (q - <q>)(1 - e^-dtau).
+template <typename R>
+__device__ __forceinline__ void accumulate_averages(RayWalk<R> &w, const Sample<R> &smp, R dl, R dj, R dtau) {
+    const R q[7] = {smp.rho, smp.ne, smp.p, smp.th, smp.B, smp.sigma, smp.binv};
+    const R wt = -fexpm1(-dtau);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        w.av_l[k] += q[k] * dl;
+        w.av_j[k] += q[k] * dj;
+        w.av_t[k] += (q[k] - w.av_t[k]) * wt;
+    }
+}
+
+// Process piece w.p of the open step (AVG: the unpolarized walk of the
+// averages pass).
+template <bool POL, typename R, bool CUTS = false, bool AVG = false>
 __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
                                       const QuartLds<R> &s_q, int lane) {
     const int flat = P.flat;
@@ -640,6 +661,7 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
             w.I = unpol_segment<R>(w.I, c[0], c[3]);
             csum(w.tau, w.tau_c, c[3]);
             csum(w.Ij, w.Ij_c, c[0]);
+            if constexpr (AVG) accumulate_averages(w, smp, w.dl, c[0], c[3]);
         }
         return;
     }
@@ -811,21 +833,38 @@ __device__ __forceinline__ void load_ray_end(RayWalk<R> &w, const R *e, const do
     w.fresh = as_int(e[29]) != 0;
 }
 
+// The 21 averaged-quantity maps of a finished ray of the averages pass:
+// <q>_lambda = sum q dlambda / lambda (lambda the ray's affine length),
+// <q>_Ij = sum q dI_j / I_j (0 without emission), <q>_tau.
+template <typename R>
+__device__ __forceinline__ void write_averages(const RayWalk<R> &w, double lambda, long long NN, long long pix,
+                                               double *avg) {
+    const double Ij = (double)w.Ij;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        avg[k * NN + pix] = (double)w.av_l[k] / lambda;
+        avg[(7 + k) * NN + pix] = Ij > 0.0 ? (double)w.av_j[k] / Ij : 0.0;
+        avg[(14 + k) * NN + pix] = (double)w.av_t[k];
+    }
+}
+
 // Whole ray by one lane (used where rays are not interleaved).
-template <bool POL, typename R, bool CUTS = false>
+template <bool POL, typename R, bool CUTS = false, bool AVG = false>
 __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
                                              const TransferParams &tp, const double *rec, int n_acc, double kt,
                                              double den, const double upix[4], const double Hv[4],
-                                             TransferOut &o) {
+                                             TransferOut &o, double *avg = nullptr, double lambda = 0.0,
+                                             long long NN = 0, long long pix = 0) {
     __shared__ QuartLds<R> s_q;
     const int lane = threadIdx.x;
     RayWalk<R> w;
     begin_ray(w, rec, n_acc, kt, den, tp);
     while (w.st >= 0 || w.p >= 0) {
         if (w.p < 0) next_step(w, s_q, lane);
-        piece<POL, R, CUTS>(w, P, g, pp, s_q, lane);
+        piece<POL, R, CUTS, AVG>(w, P, g, pp, s_q, lane);
     }
     finish_ray<POL, R>(w, P, upix, Hv, o);
+    if constexpr (AVG) write_averages(w, lambda, NN, pix, avg);
 }
 
 }  // namespace bl

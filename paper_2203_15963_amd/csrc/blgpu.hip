@@ -329,7 +329,7 @@ __global__ void __launch_bounds__(256) k_order_scatter(const int *__restrict__ w
 template <bool POL, typename R>
 constexpr int transfer_waves() { return sizeof(R) == 4 ? (POL ? 3 : 4) : (POL ? 1 : 2); }
 
-template <bool POL, typename R, bool BATCH, bool CUTS>
+template <bool POL, typename R, bool BATCH, bool CUTS, bool AVG = false>
 __global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(GeoParams P, Batch B, DevGrid g,
                                                                              PlasmaParams pp, TransferParams tp,
                                                  long long start, int count, int refill_min,
@@ -396,13 +396,15 @@ __global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(Geo
                 pixel_observer(im.fr, Pl, w.rec, upix);
                 TransferOut t;
                 finish_ray<POL, R>(w, Pl, upix, im.fr.H, t);
-                write_pixel(t, (long long)im.cp.n * im.cp.n, (long long)pj * im.cp.n + pi, im.image, im.aux);
+                const long long NN = (long long)im.cp.n * im.cp.n, pix = (long long)pj * im.cp.n + pi;
+                if constexpr (AVG) write_averages(w, im.aux[BL_AUX_LAMBDA * NN + pix], NN, pix, im.avg);
+                else write_pixel(t, NN, pix, im.image, im.aux);
                 slot = -1;
             } else {
                 next_step(w, s_q, lane);
             }
         }
-        if (slot >= 0) piece<POL, R, CUTS>(w, Pl, g, pp, s_q, lane);
+        if (slot >= 0) piece<POL, R, CUTS, AVG>(w, Pl, g, pp, s_q, lane);
     }
 }
 
@@ -437,7 +439,7 @@ __global__ void __launch_bounds__(64) k_finish(GeoParams P, Batch B, long long s
 
 // Rays queued by k_geodesic: one wave, each lane traces and transfers its
 // rays in turn with a private buffer of big_cap records.
-template <bool POL, typename R, bool CUTS>
+template <bool POL, typename R, bool CUTS, bool AVG = false>
 __global__ void __launch_bounds__(64) k_overflow(GeoParams P, Batch B, DevGrid g, PlasmaParams pp, TransferParams tp,
                                                  const int *__restrict__ ovf_count, const int *__restrict__ ovf_list,
                                                  double *__restrict__ big_rec, int big_cap) {
@@ -463,17 +465,22 @@ __global__ void __launch_bounds__(64) k_overflow(GeoParams P, Batch B, DevGrid g
         double kt = y8[4];
         TraceOut o;
         trace_ray<true>(Q, y, kt, r, big_cap, o);
-        aux[BL_AUX_DT * NN + pix] = o.dt;
-        aux[BL_AUX_S * NN + pix] = o.s;
-        aux[BL_AUX_LAMBDA * NN + pix] = o.lambda;
-        aux[BL_AUX_NACC * NN + pix] = (double)o.n_acc;
-        aux[BL_AUX_NREJ * NN + pix] = (double)o.n_rej;
-        aux[BL_AUX_STATUS * NN + pix] = (double)o.status;
         double upix[4];
         pixel_observer(im.fr, Q, r, upix);
         TransferOut t;
-        transfer_ray<POL, R, CUTS>(Q, g, pp, tl, r, o.n_acc, kt, den, upix, im.fr.H, t);
-        write_pixel(t, NN, pix, im.image, aux);
+        if constexpr (AVG) {
+            transfer_ray<POL, R, CUTS, true>(Q, g, pp, tl, r, o.n_acc, kt, den, upix, im.fr.H, t, im.avg, o.lambda,
+                                             NN, pix);
+        } else {
+            aux[BL_AUX_DT * NN + pix] = o.dt;
+            aux[BL_AUX_S * NN + pix] = o.s;
+            aux[BL_AUX_LAMBDA * NN + pix] = o.lambda;
+            aux[BL_AUX_NACC * NN + pix] = (double)o.n_acc;
+            aux[BL_AUX_NREJ * NN + pix] = (double)o.n_rej;
+            aux[BL_AUX_STATUS * NN + pix] = (double)o.status;
+            transfer_ray<POL, R, CUTS>(Q, g, pp, tl, r, o.n_acc, kt, den, upix, im.fr.H, t);
+            write_pixel(t, NN, pix, im.image, aux);
+        }
     }
 }
 
@@ -1218,7 +1225,7 @@ long long image_rays(int n, const bl_tuning &t) {
 // ray ids start at 0 for each and the render has one image's rays).
 bl_status upload_images(bl_context *ctx, int n, const bl_camera *const *cams, const bl_spacetime *const *sts,
                         double *const *images, double *const *auxs, const bl_tuning &t, Batch &B,
-                        long long &total, bool shared_rays = false) {
+                        long long &total, bool shared_rays = false, double *const *avgs = nullptr) {
     std::vector<int> perm(n);
     for (int k = 0; k < n; ++k) perm[k] = k;
     if (t.order == 1)
@@ -1238,6 +1245,7 @@ bl_status upload_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         im.L = kG * sts[k]->mass_msun * kMsun / (kC * kC);
         im.image = images[k];
         im.aux = auxs[k];
+        im.avg = avgs ? avgs[k] : nullptr;
         im.ray0 = shared_rays ? 0 : r;
         im.nray = image_rays(cams[k]->n, t);
         ctx->h_ray0[q] = im.ray0;
@@ -1273,22 +1281,22 @@ bl_status upload_one(bl_context *ctx, const bl_camera *cam, const bl_spacetime *
     return upload_images(ctx, 1, &cam, &st, &image, &aux, t, B, total);
 }
 
-template <bool POL, typename R, bool BATCH, bool CUTS>
+template <bool POL, typename R, bool BATCH, bool CUTS, bool AVG = false>
 void launch_transfer(bl_context *ctx, dim3 grd, const GeoParams &P, const Batch &B, const DevGrid &g,
                      const PlasmaParams &pp, const TransferParams &tp, long long start, int count, int refill,
                      int *q) {
     R *ends = reinterpret_cast<R *>(ctx->d_ends);
-    hipLaunchKernelGGL((k_transfer<POL, R, BATCH, CUTS>), grd, dim3(64), 0, ctx->stream, P, B, g, pp, tp, start, count,
+    hipLaunchKernelGGL((k_transfer<POL, R, BATCH, CUTS, AVG>), grd, dim3(64), 0, ctx->stream, P, B, g, pp, tp, start, count,
                        refill, ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_order, ctx->ext, q, ends);
     if (POL)
         hipLaunchKernelGGL((k_finish<R, BATCH>), dim3((count + 63) / 64), dim3(64), 0, ctx->stream, P, B, start, count,
                            ctx->d_rec, ctx->d_nacc, ctx->ext, (const R *)ends);
 }
 
-template <bool POL, typename R, bool CUTS>
+template <bool POL, typename R, bool CUTS, bool AVG = false>
 void launch_overflow(bl_context *ctx, const GeoParams &P, const Batch &B, const DevGrid &g, const PlasmaParams &pp,
                      const TransferParams &tp, int big_cap) {
-    hipLaunchKernelGGL((k_overflow<POL, R, CUTS>), dim3(1), dim3(64), 0, ctx->stream, P, B, g, pp, tp, ctx->d_ovf_count,
+    hipLaunchKernelGGL((k_overflow<POL, R, CUTS, AVG>), dim3(1), dim3(64), 0, ctx->stream, P, B, g, pp, tp, ctx->d_ovf_count,
                        ctx->d_ovf_list, ctx->d_big, big_cap);
 }
 
@@ -1302,11 +1310,13 @@ void launch_overflow(bl_context *ctx, const GeoParams &P, const Batch &B, const 
 bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, const bl_spacetime *const *sts,
                         double *const *images, double *const *auxs, const bl_integrator *integ, const bl_grid *grid,
                         const bl_plasma *plasma, const bl_mode *mode, const bl_tuning &t, bool batch,
-                        int n_freq = 0) {
+                        int n_freq = 0, double *avg = nullptr) {
     bl_status s;
     if ((s = check_integrator(ctx, integ)) != BL_OK || (s = check_tuning(ctx, &t)) != BL_OK) return s;
     if (n_freq > 0 && (n != 1 || batch)) return fail(ctx, BL_E_INVALID_ARG, "a multi-frequency render has one image");
+    if (avg && (n != 1 || batch || n_freq > 0)) return fail(ctx, BL_E_INVALID_ARG, "averages are for one image");
     const int n_tr = n_freq > 0 ? n_freq : 1;   // transfers per chunk
+    const int n_q = n_tr + (avg ? 1 : 0);        // queue counters per chunk (the averages pass has its own)
     for (int k = 0; k < (n_freq > 0 ? n_freq : n); ++k) {
         if ((s = check_camera(ctx, cams[k])) != BL_OK || (s = check_spacetime(ctx, sts[k])) != BL_OK) return s;
         if (!images[k] || !auxs[k]) return fail(ctx, BL_E_INVALID_ARG, "image and aux outputs must be non-NULL");
@@ -1327,7 +1337,8 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     if ((s = persistent_waves(ctx)) != BL_OK) return s;
     Batch B;
     long long total = 0;
-    if ((s = upload_images(ctx, n_freq > 0 ? n_freq : n, cams, sts, images, auxs, t, B, total, n_freq > 0)) != BL_OK)
+    if ((s = upload_images(ctx, n_freq > 0 ? n_freq : n, cams, sts, images, auxs, t, B, total, n_freq > 0,
+                           avg ? &avg : nullptr)) != BL_OK)
         return s;
     GeoParams P = geo_params(cams[0], sts[0], integ);
     record_layout(P, grid->g, integ, mixed);
@@ -1382,7 +1393,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     tp.L = kG * sts[0]->mass_msun * kMsun / (kC * kC);
     tp.nu_cam = cams[0]->nu_hz;
     long long nchunk = (total + chunk - 1) / chunk;
-    const long long nqueue = 2 * nchunk * n_tr;   // one counter (padded to two ints) per transfer launch
+    const long long nqueue = 2 * nchunk * n_q;   // one counter (padded to two ints) per transfer launch
     if ((s = ensure(ctx, &ctx->d_queue, ctx->queue_bytes, (size_t)nqueue * sizeof(int))) != BL_OK) return s;
     hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((nqueue + 63) / 64)), dim3(64), 0, ctx->stream, ctx->d_queue, 0,
                        (int)nqueue);
@@ -1440,7 +1451,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
             TransferParams tpf = tp;
             tpf.nu_cam = cams[f]->nu_hz;
             TimedLaunch tl(ctx, BL_K_TRANSFER);
-            int *q = ctx->d_queue + 2 * (ichunk * n_tr + f);
+            int *q = ctx->d_queue + 2 * (ichunk * n_q + f);
             dim3 pg(std::min<int>(grd.x, resident));
             const int kc = kidx + (pp.cuts ? 8 : 0);
             switch (kc) {
@@ -1463,6 +1474,34 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
             }
             HIPCHK(ctx, hipGetLastError());
         }
+        if (avg) {
+            // the averages pass: the unpolarized walk over the same records
+            // (j_I and alpha_I are those of the polarized coefficients)
+            PlasmaParams pa = pp;
+            pa.polarized = 0;
+            TimedLaunch tl(ctx, BL_K_TRANSFER);
+            int *q = ctx->d_queue + 2 * (ichunk * n_q + n_tr);
+            dim3 pg(std::min<int>(grd.x, ctx->blocks_tr[mixed ? 1 : 0] * ctx->cus));
+            switch ((mixed ? 1 : 0) + (pp.cuts ? 2 : 0)) {
+            case 0: launch_transfer<false, double, false, false, true>(ctx, pg, P, B, grid->g, pa, tp, start, count, t.refill_min, q); break;
+            case 1: launch_transfer<false, float, false, false, true>(ctx, pg, P, B, grid->g, pa, tp, start, count, t.refill_min, q); break;
+            case 2: launch_transfer<false, double, false, true, true>(ctx, pg, P, B, grid->g, pa, tp, start, count, t.refill_min, q); break;
+            default: launch_transfer<false, float, false, true, true>(ctx, pg, P, B, grid->g, pa, tp, start, count, t.refill_min, q); break;
+            }
+            HIPCHK(ctx, hipGetLastError());
+        }
+    }
+    if (avg) {
+        PlasmaParams pa = pp;
+        pa.polarized = 0;
+        TimedLaunch tl(ctx, BL_K_OVERFLOW);
+        switch ((mixed ? 1 : 0) + (pp.cuts ? 2 : 0)) {
+        case 0: launch_overflow<false, double, false, true>(ctx, P, B, grid->g, pa, tp, big_cap); break;
+        case 1: launch_overflow<false, float, false, true>(ctx, P, B, grid->g, pa, tp, big_cap); break;
+        case 2: launch_overflow<false, double, true, true>(ctx, P, B, grid->g, pa, tp, big_cap); break;
+        default: launch_overflow<false, float, true, true>(ctx, P, B, grid->g, pa, tp, big_cap); break;
+        }
+        HIPCHK(ctx, hipGetLastError());
     }
     for (int f = 0; f < n_tr; ++f) {
         // rays longer than the extension slots are traced again per frequency
@@ -1734,6 +1773,15 @@ bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *s
     if (!ctx) return BL_E_INVALID_ARG;
     if (!cam || !st) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
     return render_images(ctx, 1, &cam, &st, &image_out, &aux_out, integ, grid, plasma, mode, ctx->tuning, false);
+}
+
+bl_status bl_render_averages(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
+                             const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
+                             const bl_mode *mode, double *image_out, double *aux_out, double *avg_out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    if (!cam || !st || !avg_out) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
+    return render_images(ctx, 1, &cam, &st, &image_out, &aux_out, integ, grid, plasma, mode, ctx->tuning, false, 0,
+                         avg_out);
 }
 
 bl_status bl_set_cuts(bl_context *ctx, const bl_cuts *cuts) {
