@@ -290,6 +290,9 @@ def main():
                          "evenly spaced in wavelength over 152-324 GHz, as for true-colour images)")
     ap.add_argument("--averages", action="store_true",
                     help="single image: also time a render with the 21 averaged-quantity maps (bl_render_averages)")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="single image: also time an adaptive render of the same camera (root N/4 in 8x8 blocks, "
+                         "two refinement levels up to N, absolute-gradient criterion)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -423,6 +426,37 @@ def main():
         out["averages"] = {"ms_per_render": ams, "single_render_ms": ms, "extra_ms": ams - ms,
                            "kernels": kernel_table(aprof, args.steps)}
         log("averages", ams, "ms per render with the 21 maps")
+    if args.adaptive:
+        n = int(w["camera"]["n"])
+        cam0 = dict(w["camera"], n=n // 4)
+        i0, _ = ctx.render(cam0, w["spacetime"], w["integrator"], gg, w["plasma"], precision=args.precision)
+        thr = 0.02 * float(i0[0].max())
+        ad = dict(block=8, max_level=2, frac=5 / 64, thr=[None, thr, None, None, None])
+
+        def adstep():
+            return ctx.render_adaptive(cam0, w["spacetime"], w["integrator"], gg, w["plasma"], ad,
+                                       precision=args.precision)
+
+        counts = [len(l[0]) for l in adstep()]
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        ctx.profile_read()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            adstep()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dprof = ctx.profile_read()
+        ctx.profile_enable(False)
+        dms = (t1 - t0) * 1e3 / args.steps
+        arays = 64 * sum(counts)
+        out["adaptive"] = {"root_n": n // 4, "block": 8, "max_level": 2, "finest_n": n,
+                           "criterion": "|grad I|_abs > 0.02 max(I_root) in at least 5 of a block's 64 pixels",
+                           "threshold": thr, "blocks_per_level": counts, "rays": arays,
+                           "ms_per_render": dms, "rays_per_s": arays / (dms / 1e3),
+                           "uniform_finest_ms": ms, "uniform_finest_rays": n * n,
+                           "speedup_vs_uniform_finest": ms / dms, "kernels": kernel_table(dprof, args.steps)}
+        log("adaptive", dms, "ms per render,", arays, "rays, blocks per level", counts)
     if args.copy_probe:
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)

@@ -247,6 +247,56 @@ bl_status bl_render_averages(bl_context *ctx, const bl_camera *cam, const bl_spa
                              const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
                              const bl_mode *mode, double *image_out, double *aux_out, double *avg_out);
 
+/* Adaptive ray tracing (paper section 4, Adaptive Ray Tracing).  A pixel is
+   a square of the image plane sampled at its centre.  Level 0 is the camera's
+   N x N image cut into blocks of B x B pixels; a block that refines is
+   replaced at the next level by four blocks of B x B pixels of half the size,
+   so a level-l block (bx, by) holds pixels bx B .. bx B + B - 1 (columns) and
+   by B .. by B + B - 1 (rows) of an N 2^l image of the same camera width, and
+   each of its pixels equals that pixel of bl_render at N 2^l.  A block of a
+   level below max_level refines if its centre lies in a region (closed
+   rectangle x0 <= x <= x1, y0 <= y <= y1 in image-plane coordinates, units of
+   M, the axes of the pixel columns and rows, origin at the image centre)
+   whose minimum level exceeds the block's level, or if, for an enabled
+   criterion c, at least frac B^2 of its pixels have a value above thr[c].
+   The criteria act on Stokes I (image units) of the block's own pixels:
+   c = 0: I; 1: (Di^2 + Dj^2)^1/2 with Di = (I[i+1] - I[i-1]) / 2;
+   2: the same with Di = 2 (I[i+1] - I[i-1]) / (I[i-1] + 2 I[i] + I[i+1]);
+   3: |Di + Dj| with Di = I[i-1] - 2 I[i] + I[i+1]; 4: the same divided by
+   (I[i-1] + 2 I[i] + I[i+1]) / 4 (Dj alike along the column).  At block
+   edges the gradient takes the one-sided two-point difference (relative:
+   over the pair's mean) and the Laplacian the second difference of the
+   nearest interior pixel; along a direction of one pixel (two for the
+   Laplacian) the difference is 0; a relative difference whose weighted sum
+   is 0 is 0. */
+#define BL_ADAPT_MAX_REGIONS 8
+typedef struct {
+    int32_t block_n;          /* B: pixels per block side; divides cam->n     */
+    int32_t max_level;        /* highest level (0: root only); n 2^max_level
+                                 <= 2^20                                      */
+    int32_t use[5];           /* criteria on (1) or off (0), order as above   */
+    int32_t n_regions;        /* 0 .. BL_ADAPT_MAX_REGIONS                    */
+    double thr[5];            /* thresholds of the criteria (not NaN if used) */
+    double frac;              /* critical fraction of a block's pixels, (0, 1] */
+    double region[BL_ADAPT_MAX_REGIONS][5]; /* x0, x1, y0, y1, minimum level   */
+} bl_adaptive;
+
+/* The adaptive render.  Outputs for up to max_blocks blocks over all levels,
+   in level order; the blocks of level 0 row by row, those of level l + 1 in
+   the order of their parents, each parent's four children as (2bx, 2by),
+   (2bx+1, 2by), (2bx, 2by+1), (2bx+1, 2by+1).  blocks_out: device
+   [max_blocks][3] int32 (level, bx, by); image_out: device
+   [max_blocks][4][B][B] doubles (as bl_render's image, per block);
+   aux_out: device [max_blocks][BL_NAUX][B][B] doubles; level_counts_out:
+   host [max_level + 1], blocks per level (0 past the last level reached).
+   Returns when the outputs are complete.  BL_E_UNSUPPORTED if a level's
+   blocks would pass max_blocks (the levels before it are complete),
+   BL_E_INVALID_ARG for a bad parameter. */
+bl_status bl_render_adaptive(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
+                             const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
+                             const bl_mode *mode, const bl_adaptive *adaptive, int32_t max_blocks,
+                             int32_t *blocks_out, double *image_out, double *aux_out, int32_t *level_counts_out);
+
 /* Data cuts (paper section 4, Data Cuts): a sample whose rho, n_e, p,
    Theta_e, B, sigma, beta^-1 or Kerr-Schild r lies below its lower limit
    ([0]) or above its upper limit ([1]) is vacuum, and with plane = +1 (-1)

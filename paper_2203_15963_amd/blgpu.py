@@ -71,6 +71,34 @@ class bl_cuts(C.Structure):
                 ("plane_origin", C.c_double * 3), ("plane_normal", C.c_double * 3)]
 
 
+ADAPT_MAX_REGIONS = 8
+ADAPT_CRITERIA = ("value", "grad_abs", "grad_rel", "lap_abs", "lap_rel")
+
+
+class bl_adaptive(C.Structure):
+    _fields_ = [("block_n", C.c_int32), ("max_level", C.c_int32), ("use", C.c_int32 * 5), ("n_regions", C.c_int32),
+                ("thr", C.c_double * 5), ("frac", C.c_double), ("region", (C.c_double * 5) * ADAPT_MAX_REGIONS)]
+
+
+def adaptive(d):
+    """bl_adaptive from {"block": B, "max_level": L, "frac": f, "thr": [5
+    thresholds, None = off] (or criterion name -> threshold), "regions":
+    [(x0, x1, y0, y1, min_level), ...]}."""
+    a = bl_adaptive()
+    a.block_n, a.max_level, a.frac = int(d["block"]), int(d["max_level"]), float(d.get("frac", 1.0))
+    thr = d.get("thr", [None] * 5)
+    if isinstance(thr, dict):
+        thr = [thr.get(k) for k in ADAPT_CRITERIA]
+    for c, v in enumerate(thr):
+        a.use[c], a.thr[c] = (0, 0.0) if v is None else (1, float(v))
+    regs = d.get("regions", [])
+    a.n_regions = len(regs)
+    for r, g in enumerate(regs[:ADAPT_MAX_REGIONS]):
+        for q in range(5):
+            a.region[r][q] = float(g[q])
+    return a
+
+
 CUT_KEYS = ("rho", "ne", "p", "theta_e", "b", "sigma", "beta_inv", "r")
 
 
@@ -156,6 +184,10 @@ def load():
     L.bl_render_averages.argtypes = [vp, C.POINTER(bl_camera), C.POINTER(bl_spacetime), C.POINTER(bl_integrator),
                                      vp, C.POINTER(bl_plasma), C.POINTER(bl_mode), vp, vp, vp]
     L.bl_render_averages.restype = C.c_int
+    L.bl_render_adaptive.argtypes = [vp, C.POINTER(bl_camera), C.POINTER(bl_spacetime), C.POINTER(bl_integrator),
+                                     vp, C.POINTER(bl_plasma), C.POINTER(bl_mode), C.POINTER(bl_adaptive), C.c_int32,
+                                     vp, vp, vp, C.POINTER(C.c_int32)]
+    L.bl_render_adaptive.restype = C.c_int
     L.bl_set_cuts.argtypes = [vp, C.POINTER(bl_cuts)]
     L.bl_set_cuts.restype = C.c_int
     L.bl_set_tuning.argtypes = [vp, C.POINTER(bl_tuning)]
@@ -350,6 +382,32 @@ class Context:
         self._check(load().bl_render_averages(self.handle, C.byref(c), C.byref(s), C.byref(g), grid.handle,
                                               C.byref(p), C.byref(m), _ptr(image), _ptr(aux), _ptr(avg)))
         return image, aux, avg
+
+    def render_adaptive(self, cam, st, integ, grid, pl, ad, max_blocks=None, precision=0, step_model=0):
+        """Adaptive render; returns a list over the levels reached of (blocks
+        [n][3] int32 (level, bx, by), image [n][4][B][B], aux [n][NAUX][B][B]),
+        device tensors viewing one allocation of max_blocks blocks (default:
+        every block of every level)."""
+        import torch
+        b, lmax = int(ad["block"]), int(ad["max_level"])
+        if max_blocks is None:
+            max_blocks = sum((int(cam["n"]) // b) ** 2 * 4 ** l for l in range(lmax + 1))
+        blocks = torch.empty(max_blocks, 3, dtype=torch.int32, device=self.device)
+        image, aux = self._empty(max_blocks, 4, b, b), self._empty(max_blocks, NAUX, b, b)
+        counts = (C.c_int32 * (lmax + 1))()
+        c, s, g, p, m = camera(cam), spacetime(st), integrator(integ), plasma(pl), mode(precision, step_model)
+        a = adaptive(ad)
+        self._check(load().bl_render_adaptive(self.handle, C.byref(c), C.byref(s), C.byref(g), grid.handle,
+                                              C.byref(p), C.byref(m), C.byref(a), int(max_blocks), _ptr(blocks),
+                                              _ptr(image), _ptr(aux), counts))
+        out, off = [], 0
+        for l in range(lmax + 1):
+            n = counts[l]
+            if n == 0:
+                break
+            out.append((blocks[off:off + n], image[off:off + n], aux[off:off + n]))
+            off += n
+        return out
 
     def render_multifreq(self, cam, st, integ, grid, pl, nu_hz, precision=0, step_model=0, outputs=None):
         """One camera at several frequencies from one geodesic pass; returns a

@@ -149,6 +149,10 @@ struct Frame {
 struct CamParams {
     double r, theta, phi, u_normal[3], k_cov[3], width, psi, nu;
     int n, freq_mode;
+    // the pixels rendered are pixels (i0 .. i0 + n - 1, j0 .. j0 + n - 1) of
+    // an nf x nf image of the same width (nf = n, i0 = j0 = 0 for a whole
+    // image; a block of an adaptive level otherwise)
+    int nf, i0, j0, pad_c;
 };
 
 struct GeoParams {

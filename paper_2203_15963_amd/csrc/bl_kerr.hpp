@@ -333,9 +333,9 @@ __device__ __forceinline__ void velocity_from_normal(const KS<R> &k, const R ut[
 // frequency.
 __device__ __forceinline__ void camera_pixel(const Frame &fr, const CamParams &cp, double a, int flat, int i, int j,
                                              double y[8], double &den) {
-    double N = (double)cp.n;
-    double ap = ((double)i - 0.5 * N + 0.5) * cp.width / N;
-    double bp = ((double)j - 0.5 * N + 0.5) * cp.width / N;
+    double N = (double)cp.nf;
+    double ap = ((double)(i + cp.i0) - 0.5 * N + 0.5) * cp.width / N;
+    double bp = ((double)(j + cp.j0) - 0.5 * N + 0.5) * cp.width / N;
 #pragma unroll
     for (int m = 0; m < 4; ++m) y[m] = fr.xc[m] + (ap * fr.H[m] + bp * fr.V[m]);
     KS<double> k = ks_point(a, flat, y[1], y[2], y[3]);

@@ -973,6 +973,8 @@ struct bl_context {
     bl_cuts cuts{};          // data cuts for the following renders (bl_set_cuts)
     bool has_cuts = false;
     CutParams *d_cuts = nullptr;   // their device copy, uploaded with each render
+    int *d_refine = nullptr;       // refinement flags of an adaptive level
+    size_t refine_bytes = 0;
     // network training workspace
     u32x4 *d_mlp_pk = nullptr;
     float *d_mlp_tail = nullptr;
@@ -999,6 +1001,103 @@ struct bl_grid {
     DevGrid g{};
     double *d_table = nullptr;
 };
+
+// ---------------------------------------------------------------- adaptive
+// Refinement criteria of one block of an adaptive level (paper section 4,
+// Adaptive Ray Tracing), on Stokes I of the block's B x B pixels alone:
+// central differences inside the block, one-sided ones at its edges (the
+// gradient: the two-point difference; the Laplacian: the second difference
+// of the nearest interior pixel), none along a direction of one pixel (two
+// for the Laplacian); the relative forms divide by the 1-2-1 weighted sum
+// (the pair sum / 2 for a one-sided gradient) and are 0 where that is 0.
+// Evaluated without contraction so that a decision depends only on the
+// intensities and the thresholds.
+struct RefineParams {
+    int b, level, n_root, n_regions;
+    int use[5], pad;
+    double thr[5];
+    double frac, width;
+    double region[8][5];   // x0, x1, y0, y1, minimum level
+};
+
+__device__ double crit_grad(const double *v, int stride, int n, int k, bool rel) {
+#pragma clang fp contract(off)
+    if (n < 2) return 0.0;
+    if (k > 0 && k < n - 1) {
+        const double a = v[(k - 1) * stride], b = v[k * stride], c = v[(k + 1) * stride];
+        if (rel) {
+            const double sw = a + 2.0 * b + c;
+            return sw == 0.0 ? 0.0 : 2.0 * (c - a) / sw;
+        }
+        return 0.5 * (c - a);
+    }
+    const double lo = k == 0 ? v[0] : v[(n - 2) * stride], hi = k == 0 ? v[stride] : v[(n - 1) * stride];
+    if (rel) {
+        const double sw = lo + hi;
+        return sw == 0.0 ? 0.0 : 2.0 * (hi - lo) / sw;
+    }
+    return hi - lo;
+}
+
+__device__ double crit_lap(const double *v, int stride, int n, int k, bool rel) {
+#pragma clang fp contract(off)
+    if (n < 3) return 0.0;
+    const int m = k < 1 ? 1 : (k > n - 2 ? n - 2 : k);
+    const double a = v[(m - 1) * stride], b = v[m * stride], c = v[(m + 1) * stride];
+    const double d2 = a - 2.0 * b + c;
+    if (rel) {
+        const double sw = a + 2.0 * b + c;
+        return sw == 0.0 ? 0.0 : 4.0 * d2 / sw;
+    }
+    return d2;
+}
+
+// One wave per block: flags[k] = 1 if block k of the level refines.
+// blocks: [n_blocks][3] (level, bx, by); img: the level's images, block k at
+// img + k 4 B^2, Stokes I first.  Launched with exactly n_blocks groups.
+__global__ void __launch_bounds__(64) k_refine(RefineParams rp, const int *__restrict__ blocks,
+                                               const double *__restrict__ img, int n_blocks,
+                                               int *__restrict__ flags) {
+#pragma clang fp contract(off)
+    const int k = blockIdx.x;
+    if (k >= n_blocks) return;
+    const int lane = threadIdx.x, b = rp.b, bb = b * b;
+    const double *I = img + (size_t)k * 4 * bb;
+    int cnt[5] = {0, 0, 0, 0, 0};
+    for (int p = lane; p < bb; p += 64) {
+        const int j = p / b, i = p - j * b;
+        const double *row = I + (size_t)j * b, *col = I + i;
+        double v[5];
+        v[0] = I[p];
+        double gi = crit_grad(row, 1, b, i, false), gj = crit_grad(col, b, b, j, false);
+        v[1] = sqrt(gi * gi + gj * gj);
+        gi = crit_grad(row, 1, b, i, true);
+        gj = crit_grad(col, b, b, j, true);
+        v[2] = sqrt(gi * gi + gj * gj);
+        v[3] = fabs(crit_lap(row, 1, b, i, false) + crit_lap(col, b, b, j, false));
+        v[4] = fabs(crit_lap(row, 1, b, i, true) + crit_lap(col, b, b, j, true));
+#pragma unroll
+        for (int c = 0; c < 5; ++c) cnt[c] += (rp.use[c] && v[c] > rp.thr[c]) ? 1 : 0;
+    }
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) cnt[c] += __shfl_xor(cnt[c], o);
+    if (lane != 0) return;
+    bool ref = false;
+    const double need = rp.frac * (double)bb;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) ref = ref || (rp.use[c] && (double)cnt[c] >= need);
+    const int bx = blocks[3 * k + 1], by = blocks[3 * k + 2];
+    const double nl = (double)rp.n_root * (double)(1LL << rp.level);
+    const double cx = ((double)bx * b + 0.5 * b - 0.5 * nl) * rp.width / nl;
+    const double cy = ((double)by * b + 0.5 * b - 0.5 * nl) * rp.width / nl;
+    for (int r = 0; r < rp.n_regions; ++r) {
+        const double *g = rp.region[r];
+        if (g[0] <= cx && cx <= g[1] && g[2] <= cy && cy <= g[3] && (double)rp.level < g[4]) ref = true;
+    }
+    flags[k] = ref ? 1 : 0;
+}
 
 namespace {
 
@@ -1055,6 +1154,8 @@ CamParams cam_params(const bl_camera *c) {
     p.psi = c->psi;
     p.nu = c->nu_hz;
     p.n = c->n;
+    p.nf = c->n;
+    p.i0 = p.j0 = p.pad_c = 0;
     p.freq_mode = c->freq_mode;
     return p;
 }
@@ -1225,7 +1326,8 @@ long long image_rays(int n, const bl_tuning &t) {
 // ray ids start at 0 for each and the render has one image's rays).
 bl_status upload_images(bl_context *ctx, int n, const bl_camera *const *cams, const bl_spacetime *const *sts,
                         double *const *images, double *const *auxs, const bl_tuning &t, Batch &B,
-                        long long &total, bool shared_rays = false, double *const *avgs = nullptr) {
+                        long long &total, bool shared_rays = false, double *const *avgs = nullptr,
+                        const int *sub = nullptr) {
     std::vector<int> perm(n);
     for (int k = 0; k < n; ++k) perm[k] = k;
     if (t.order == 1)
@@ -1239,6 +1341,11 @@ bl_status upload_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         const int k = perm[q];
         ImgDev &im = ctx->h_imgs[q];
         im.cp = cam_params(cams[k]);
+        if (sub) {   // a block of a finer image: (nf, i0, j0) per image
+            im.cp.nf = sub[3 * k];
+            im.cp.i0 = sub[3 * k + 1];
+            im.cp.j0 = sub[3 * k + 2];
+        }
         im.a = sts[k]->a;
         im.r_in = sts[k]->r_in;
         im.flat = sts[k]->flat ? 1 : 0;
@@ -1310,7 +1417,7 @@ void launch_overflow(bl_context *ctx, const GeoParams &P, const Batch &B, const 
 bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, const bl_spacetime *const *sts,
                         double *const *images, double *const *auxs, const bl_integrator *integ, const bl_grid *grid,
                         const bl_plasma *plasma, const bl_mode *mode, const bl_tuning &t, bool batch,
-                        int n_freq = 0, double *avg = nullptr) {
+                        int n_freq = 0, double *avg = nullptr, const int *sub = nullptr) {
     bl_status s;
     if ((s = check_integrator(ctx, integ)) != BL_OK || (s = check_tuning(ctx, &t)) != BL_OK) return s;
     if (n_freq > 0 && (n != 1 || batch)) return fail(ctx, BL_E_INVALID_ARG, "a multi-frequency render has one image");
@@ -1338,7 +1445,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     Batch B;
     long long total = 0;
     if ((s = upload_images(ctx, n_freq > 0 ? n_freq : n, cams, sts, images, auxs, t, B, total, n_freq > 0,
-                           avg ? &avg : nullptr)) != BL_OK)
+                           avg ? &avg : nullptr, sub)) != BL_OK)
         return s;
     GeoParams P = geo_params(cams[0], sts[0], integ);
     record_layout(P, grid->g, integ, mixed);
@@ -1536,6 +1643,101 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     return BL_OK;
 }
 
+// Adaptive render: the root level's blocks, then level by level the children
+// of the blocks the criteria flag, each level as one batched render of its
+// blocks (every block a B x B sub-image of the level's N 2^l image).
+bl_status adaptive_impl(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st, const bl_integrator *integ,
+                        const bl_grid *grid, const bl_plasma *plasma, const bl_mode *mode, const bl_adaptive *ad,
+                        int32_t max_blocks, int32_t *blocks_out, double *image_out, double *aux_out,
+                        int32_t *counts_out) {
+    bl_status s;
+    if ((s = check_camera(ctx, cam)) != BL_OK) return s;
+    const int B = ad->block_n, N = cam->n;
+    if (B < 1 || N % B != 0) return fail(ctx, BL_E_INVALID_ARG, "block_n must divide the camera's n");
+    if (ad->max_level < 0 || ad->max_level > 20 || ((long long)N << ad->max_level) > (1LL << 20))
+        return fail(ctx, BL_E_INVALID_ARG, "need 0 <= max_level and n 2^max_level <= 2^20");
+    if (ad->n_regions < 0 || ad->n_regions > BL_ADAPT_MAX_REGIONS)
+        return fail(ctx, BL_E_INVALID_ARG, "n_regions must be 0 .. BL_ADAPT_MAX_REGIONS");
+    if (!(ad->frac > 0.0 && ad->frac <= 1.0)) return fail(ctx, BL_E_INVALID_ARG, "frac must lie in (0, 1]");
+    for (int c = 0; c < 5; ++c) {
+        if (ad->use[c] != 0 && ad->use[c] != 1) return fail(ctx, BL_E_INVALID_ARG, "use[] entries must be 0 or 1");
+        if (ad->use[c] && std::isnan(ad->thr[c])) return fail(ctx, BL_E_INVALID_ARG, "NaN threshold");
+    }
+    for (int r = 0; r < ad->n_regions; ++r)
+        for (int q = 0; q < 5; ++q)
+            if (std::isnan(ad->region[r][q])) return fail(ctx, BL_E_INVALID_ARG, "NaN region bound");
+    if (max_blocks < 1 || !blocks_out || !image_out || !aux_out || !counts_out)
+        return fail(ctx, BL_E_INVALID_ARG, "need max_blocks >= 1 and non-NULL outputs");
+    for (int l = 0; l <= ad->max_level; ++l) counts_out[l] = 0;
+    bl_tuning t = ctx->tuning;
+    if (t.tile_w > 0 && (B % t.tile_w != 0 || B % t.tile_h != 0)) t.tile_w = t.tile_h = 0;   // row-major blocks
+    RefineParams rp{};
+    rp.b = B;
+    rp.n_root = N;
+    rp.n_regions = ad->n_regions;
+    for (int c = 0; c < 5; ++c) {
+        rp.use[c] = ad->use[c];
+        rp.thr[c] = ad->thr[c];
+    }
+    rp.frac = ad->frac;
+    rp.width = cam->width;
+    for (int r = 0; r < ad->n_regions; ++r)
+        for (int q = 0; q < 5; ++q) rp.region[r][q] = ad->region[r][q];
+    std::vector<int> blk;
+    for (int by = 0; by < N / B; ++by)
+        for (int bx = 0; bx < N / B; ++bx) blk.insert(blk.end(), {0, bx, by});
+    const size_t img_sz = (size_t)4 * B * B, aux_sz = (size_t)BL_NAUX * B * B;
+    long long off = 0;
+    for (int level = 0; level <= ad->max_level && !blk.empty(); ++level) {
+        const int nl = (int)(blk.size() / 3);
+        if (off + nl > max_blocks)
+            return fail(ctx, BL_E_UNSUPPORTED, "max_blocks is too small for level " + std::to_string(level));
+        std::vector<bl_camera> cams(nl, *cam);
+        std::vector<const bl_camera *> cp(nl);
+        std::vector<const bl_spacetime *> sp(nl, st);
+        std::vector<double *> ims(nl), axs(nl);
+        std::vector<int> sub(3 * (size_t)nl);
+        for (int k = 0; k < nl; ++k) {
+            cams[k].n = B;
+            cp[k] = &cams[k];
+            ims[k] = image_out + (size_t)(off + k) * img_sz;
+            axs[k] = aux_out + (size_t)(off + k) * aux_sz;
+            sub[3 * k] = N << level;
+            sub[3 * k + 1] = blk[3 * k + 1] * B;
+            sub[3 * k + 2] = blk[3 * k + 2] * B;
+        }
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        HIPCHK(ctx, hipMemcpyAsync(blocks_out + 3 * off, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice,
+                                   ctx->stream));
+        if ((s = render_images(ctx, nl, cp.data(), sp.data(), ims.data(), axs.data(), integ, grid, plasma, mode, t,
+                               true, 0, nullptr, sub.data())) != BL_OK)
+            return s;
+        counts_out[level] = nl;
+        if (level < ad->max_level) {
+            if ((s = ensure(ctx, &ctx->d_refine, ctx->refine_bytes, (size_t)nl * sizeof(int))) != BL_OK) return s;
+            rp.level = level;
+            hipLaunchKernelGGL(k_refine, dim3((unsigned)nl), dim3(64), 0, ctx->stream, rp,
+                               (const int *)(blocks_out + 3 * off), (const double *)ims[0], nl, ctx->d_refine);
+            HIPCHK(ctx, hipGetLastError());
+            std::vector<int> flags(nl);
+            HIPCHK(ctx, hipMemcpyAsync(flags.data(), ctx->d_refine, (size_t)nl * sizeof(int), hipMemcpyDeviceToHost,
+                                       ctx->stream));
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+            std::vector<int> next;
+            for (int k = 0; k < nl; ++k)
+                if (flags[k])
+                    for (int dy = 0; dy < 2; ++dy)
+                        for (int dx = 0; dx < 2; ++dx)
+                            next.insert(next.end(), {level + 1, 2 * blk[3 * k + 1] + dx, 2 * blk[3 * k + 2] + dy});
+            blk.swap(next);
+        } else {
+            HIPCHK(ctx, hipStreamSynchronize(ctx->stream));   // the host block list was read by the copy
+        }
+        off += nl;
+    }
+    return BL_OK;
+}
+
 bl_status render_batch_impl(bl_context *ctx, int32_t n_images, const bl_image_desc *images,
                             const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
                             const bl_mode *mode, const bl_tuning &t) {
@@ -1623,6 +1825,7 @@ void bl_destroy(bl_context *ctx) {
     (void)hipFree(ctx->d_queue);
     (void)hipFree(ctx->d_ends);
     (void)hipFree(ctx->d_cuts);
+    (void)hipFree(ctx->d_refine);
     delete ctx;
 }
 
@@ -1782,6 +1985,16 @@ bl_status bl_render_averages(bl_context *ctx, const bl_camera *cam, const bl_spa
     if (!cam || !st || !avg_out) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
     return render_images(ctx, 1, &cam, &st, &image_out, &aux_out, integ, grid, plasma, mode, ctx->tuning, false, 0,
                          avg_out);
+}
+
+bl_status bl_render_adaptive(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
+                             const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
+                             const bl_mode *mode, const bl_adaptive *adaptive, int32_t max_blocks,
+                             int32_t *blocks_out, double *image_out, double *aux_out, int32_t *level_counts_out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    if (!cam || !st || !adaptive) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
+    return adaptive_impl(ctx, cam, st, integ, grid, plasma, mode, adaptive, max_blocks, blocks_out, image_out, aux_out,
+                         level_counts_out);
 }
 
 bl_status bl_set_cuts(bl_context *ctx, const bl_cuts *cuts) {

@@ -30,7 +30,8 @@ def test_header_declares_entry_points():
     for n in ["bl_abi_version", "bl_create", "bl_destroy", "bl_last_error", "bl_grid_create",
               "bl_grid_destroy", "bl_camera_rays", "bl_trace_geodesics", "bl_render", "bl_eval_samples",
               "bl_profile_enable", "bl_profile_read", "bl_render_batch", "bl_set_tuning", "bl_get_tuning",
-              "bl_autotune", "bl_render_multifreq", "bl_set_cuts", "bl_render_averages"]:
+              "bl_autotune", "bl_render_multifreq", "bl_set_cuts", "bl_render_averages",
+              "bl_render_adaptive"]:
         assert n in names
 
 
@@ -52,11 +53,12 @@ def test_struct_layouts_match_header():
     import tempfile
     from paper_2203_15963_amd import blgpu
     src = '#include <stdio.h>\n#include <stddef.h>\n#include "blgpu.h"\n' \
-          'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu",' \
+          'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu",' \
           'sizeof(bl_camera),sizeof(bl_spacetime),sizeof(bl_integrator),sizeof(bl_grid_desc),' \
           'sizeof(bl_plasma),sizeof(bl_mode),sizeof(bl_tuning),sizeof(bl_image_desc),' \
           'offsetof(bl_tuning,chunk_rays),offsetof(bl_image_desc,image_out),' \
-          'sizeof(bl_cuts),offsetof(bl_cuts,plane_origin));return 0;}\n'
+          'sizeof(bl_cuts),offsetof(bl_cuts,plane_origin),sizeof(bl_adaptive),offsetof(bl_adaptive,thr),' \
+          'offsetof(bl_adaptive,region));return 0;}\n'
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
         open(c, "w").write(src)
@@ -67,7 +69,8 @@ def test_struct_layouts_match_header():
                                        blgpu.bl_grid_desc, blgpu.bl_plasma, blgpu.bl_mode, blgpu.bl_tuning,
                                        blgpu.bl_image_desc)]
     mine += [blgpu.bl_tuning.chunk_rays.offset, blgpu.bl_image_desc.image_out.offset,
-             ctypes.sizeof(blgpu.bl_cuts), blgpu.bl_cuts.plane_origin.offset]
+             ctypes.sizeof(blgpu.bl_cuts), blgpu.bl_cuts.plane_origin.offset, ctypes.sizeof(blgpu.bl_adaptive),
+             blgpu.bl_adaptive.thr.offset, blgpu.bl_adaptive.region.offset]
     assert sizes == mine
 
 
