@@ -223,3 +223,42 @@ def test_edge_cases(ctx):
         with pytest.raises(blgpu.BlError) as e:
             ctx.render_adaptive(*args, bad, max_blocks=64, precision=1)
         assert e.value.status == -1
+
+
+def test_bench_configuration_sampled(ctx, oracle):
+    """The adaptive configuration the benchmark times (1024² SMR workload,
+    root 256² in 8² blocks, two levels, absolute-gradient criterion at 2 % of
+    the root's peak in 5 of 64 pixels, mixed form, FP32 grid) against the
+    FP64 oracle on sampled pixels of every level, read through the block
+    geometry (a level-l pixel is pixel (bx 8 + i, by 8 + j) of the 256 2^l
+    image)."""
+    from paper_2203_15963_amd import synth
+    w = synth.workload("c3_1024_smr", n=1024)
+    g = synth.make_grid(w["grid_args"])
+    g32 = dict(g, prims=g["prims"].astype(np.float32))
+    g64r = dict(g, prims=g32["prims"].astype(np.float64))
+    gg = ctx.grid(g32)
+    cam0 = dict(w["camera"], n=256)
+    i0, _ = ctx.render(cam0, w["spacetime"], w["integrator"], gg, w["plasma"], precision=1)
+    ad = dict(block=8, max_level=2, frac=5 / 64, thr=[None, 0.02 * float(i0[0].max()), None, None, None])
+    levels = ctx.render_adaptive(cam0, w["spacetime"], w["integrator"], gg, w["plasma"], ad, precision=1)
+    torch.cuda.synchronize()
+    _say("bench configuration: blocks per level", [len(l[0]) for l in levels])
+    assert len(levels) == 3
+    rng = np.random.default_rng(21)
+    for level, (blk, img, aux) in enumerate(levels):
+        nl = 256 << level
+        bl, ig, ag = blk.cpu().numpy(), img.cpu().numpy(), aux.cpu().numpy()
+        ks = rng.choice(len(bl), size=min(12, len(bl)), replace=False)
+        ij = rng.integers(0, 8, size=(len(ks), 2))
+        pix = [(bl[k, 1] * 8 + i) + nl * (bl[k, 2] * 8 + j) for k, (i, j) in zip(ks, ij)]
+        io, ao = oracle.render_pixels(dict(cam0, n=nl), w["spacetime"], w["integrator"], g64r, w["plasma"], pix)
+        gi = np.array([ig[k, :, j, i] for k, (i, j) in zip(ks, ij)])
+        ga = np.array([ag[k, :, j, i] for k, (i, j) in zip(ks, ij)])
+        match = (ga[:, 5] == ao[:, 5]) & (ga[:, 6] == ao[:, 6])
+        den = np.maximum(np.abs(io[:, 0]), 1e-3 * float(np.abs(ig[:, 0]).max()))
+        e = (np.abs(gi - io) / den[:, None]).max(axis=1)
+        _say("level", level, "sampled E_pix(matched)", e[match].max() if match.any() else 0.0,
+             "mismatched", int((~match).sum()), "of", len(pix))
+        assert (~match).sum() <= 1
+        assert e[match].max() <= 1e-4
