@@ -1706,12 +1706,13 @@ bl_status adaptive_impl(bl_context *ctx, const bl_camera *cam, const bl_spacetim
             sub[3 * k + 1] = blk[3 * k + 1] * B;
             sub[3 * k + 2] = blk[3 * k + 2] * B;
         }
-        HIPCHK(ctx, hipSetDevice(ctx->device));
-        HIPCHK(ctx, hipMemcpyAsync(blocks_out + 3 * off, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice,
-                                   ctx->stream));
         if ((s = render_images(ctx, nl, cp.data(), sp.data(), ims.data(), axs.data(), integ, grid, plasma, mode, t,
                                true, 0, nullptr, sub.data())) != BL_OK)
             return s;
+        // the level's block list; blk stays alive until the stream has
+        // passed this copy (synchronised below on every path)
+        HIPCHK(ctx, hipMemcpyAsync(blocks_out + 3 * off, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice,
+                                   ctx->stream));
         counts_out[level] = nl;
         if (level < ad->max_level) {
             if ((s = ensure(ctx, &ctx->d_refine, ctx->refine_bytes, (size_t)nl * sizeof(int))) != BL_OK) return s;
