@@ -326,11 +326,11 @@ __global__ void __launch_bounds__(256) k_order_scatter(const int *__restrict__ w
 // Resident waves per SIMD the transfer kernels are compiled for (the register
 // budget: 168 VGPRs for three, 128 for four, 256 for two); the polarized FP64
 // kernel keeps the compiler's choice (one).
-template <bool POL, typename R>
-constexpr int transfer_waves() { return sizeof(R) == 4 ? (POL ? 3 : 4) : (POL ? 1 : 2); }
+template <bool POL, typename R, bool AVG>
+constexpr int transfer_waves() { return sizeof(R) == 4 ? (POL || AVG ? 3 : 4) : (POL ? 1 : 2); }
 
 template <bool POL, typename R, bool BATCH, bool CUTS, bool AVG = false>
-__global__ void __launch_bounds__(64, (transfer_waves<POL, R>())) k_transfer(GeoParams P, Batch B, DevGrid g,
+__global__ void __launch_bounds__(64, (transfer_waves<POL, R, AVG>())) k_transfer(GeoParams P, Batch B, DevGrid g,
                                                                              PlasmaParams pp, TransferParams tp,
                                                  long long start, int count, int refill_min,
                                                  const double *__restrict__ rec, const double *__restrict__ meta,
@@ -964,8 +964,9 @@ struct bl_context {
     char *d_ends = nullptr;              // polarized rays' end states, kRayEnd reals per ray slot
     size_t ends_bytes = 0;
     int cus = 0;
-    int blocks_tr[8] = {0};              // resident waves per CU of k_transfer<pol, R, batch>:
-                                         // [4 batch + 2 pol + (R == float)]
+    int blocks_tr[10] = {0};              // resident waves per CU of k_transfer<pol, R, batch>:
+                                         // [4 batch + 2 pol + (R == float)]; [8 + (R == float)]:
+                                         // the averages instantiation
     // step-proposal network installed by bl_set_step_model (packed form)
     u32x4 *d_step_pk = nullptr;
     float *d_step_tail = nullptr;
@@ -1281,7 +1282,7 @@ struct TimedLaunch {
 // Waves per CU of each persistent transfer kernel that fit at once.
 bl_status persistent_waves(bl_context *ctx) {
     if (ctx->cus > 0) return BL_OK;
-    int cus = 0, b[8] = {0};
+    int cus = 0, b[10] = {0};
     HIPCHK(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
     HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[0], k_transfer<false, double, false, false>, 64, 0));
     HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[1], k_transfer<false, float, false, false>, 64, 0));
@@ -1291,7 +1292,9 @@ bl_status persistent_waves(bl_context *ctx) {
     HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[5], k_transfer<false, float, true, false>, 64, 0));
     HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[6], k_transfer<true, double, true, false>, 64, 0));
     HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[7], k_transfer<true, float, true, false>, 64, 0));
-    for (int k = 0; k < 8; ++k) ctx->blocks_tr[k] = std::max(1, b[k]);
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[8], k_transfer<false, double, false, false, true>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[9], k_transfer<false, float, false, false, true>, 64, 0));
+    for (int k = 0; k < 10; ++k) ctx->blocks_tr[k] = std::max(1, b[k]);
     ctx->cus = std::max(1, cus);
     return BL_OK;
 }
@@ -1588,7 +1591,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
             pa.polarized = 0;
             TimedLaunch tl(ctx, BL_K_TRANSFER);
             int *q = ctx->d_queue + 2 * (ichunk * n_q + n_tr);
-            dim3 pg(std::min<int>(grd.x, ctx->blocks_tr[mixed ? 1 : 0] * ctx->cus));
+            dim3 pg(std::min<int>(grd.x, ctx->blocks_tr[mixed ? 9 : 8] * ctx->cus));
             switch ((mixed ? 1 : 0) + (pp.cuts ? 2 : 0)) {
             case 0: launch_transfer<false, double, false, false, true>(ctx, pg, P, B, grid->g, pa, tp, start, count, t.refill_min, q); break;
             case 1: launch_transfer<false, float, false, false, true>(ctx, pg, P, B, grid->g, pa, tp, start, count, t.refill_min, q); break;
