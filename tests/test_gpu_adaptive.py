@@ -262,3 +262,41 @@ def test_bench_configuration_sampled(ctx, oracle):
              "mismatched", int((~match).sum()), "of", len(pix))
         assert (~match).sum() <= 1
         assert e[match].max() <= 1e-4
+
+
+def test_adaptive_with_data_cuts(ctx):
+    """Data cuts set on the context act on every level: each block equals the
+    same pixels of a cut bl_render at that level's resolution."""
+    w, g, gg = _setup(ctx, "c2_256_pol", 8)
+    ctx.set_cuts({"sigma": (float("-inf"), 0.05), "r": (4.0, float("inf"))})
+    try:
+        ad = dict(block=4, max_level=2, frac=1.0, regions=[(-1e9, 0.0, -1e9, 1e9, 5)])
+        levels = ctx.render_adaptive(w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"], ad, precision=1)
+        torch.cuda.synchronize()
+        _say("cuts: blocks per level", [len(l[0]) for l in levels])
+        assert [len(l[0]) for l in levels] == [4, 8, 32]
+        _check_against_uniform(ctx, w, gg, levels, 4, 1)
+    finally:
+        ctx.set_cuts(None)
+
+
+def test_adaptive_polarized_fp64_matches_oracle(ctx, oracle):
+    from oracle import adaptive as A
+    w, g, gg = _setup(ctx, "c2_256_pol", 8)
+    # (with B = 2 the Laplacian criteria are 0 by the edge rule: use the gradient)
+    ad = dict(block=2, max_level=1, frac=0.5, thr=[None, _root_threshold(ctx, w, gg, A.GRAD_ABS, 2, 0), None, None,
+                                                    None])
+    levels = ctx.render_adaptive(w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"], ad, precision=0)
+    torch.cuda.synchronize()
+    ol = A.render_adaptive(w["camera"], w["spacetime"], w["integrator"], g, w["plasma"], ad)
+    _say("polarized: gpu blocks", [len(l[0]) for l in levels], "oracle blocks", [len(l[0]) for l in ol])
+    assert len(levels) == len(ol) == 2
+    for (blk, img, aux), (oblk, oimg, oaux) in zip(levels, ol):
+        assert np.array_equal(blk.cpu().numpy(), oblk)
+        ig, ag = img.cpu().numpy(), aux.cpu().numpy()
+        match = (ag[:, 5] == oaux[:, 5]) & (ag[:, 6] == oaux[:, 6])
+        assert match.mean() >= 0.98
+        den = np.maximum(np.abs(oimg[:, 0]), 1e-3 * np.abs(oimg[:, 0]).max())
+        e = (np.abs(ig - oimg) / den[:, None]).max(axis=1)
+        _say("polarized level", int(blk[0, 0]), "E_pix(matched)", e[match].max())
+        assert e[match].max() <= TOL_FP64
