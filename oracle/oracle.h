@@ -117,6 +117,13 @@ typedef struct {
 int    or_trace(const or_camera *cam, const or_spacetime *st, const or_integrator *in,
                 const double y0[8], or_ray *ray);
 void   or_ray_free(or_ray *ray);
+/* Trace pixel (i,j) and log every trial step (at most cap of them) into
+   trials_out as OR_TRIAL_LOG doubles each: state at the trial's start y[8],
+   trial step h, error norm eps, accepted (1) or rejected (0).  Returns the
+   number of trials; info[8] as for or_trace_pixel.                         */
+#define OR_TRIAL_LOG 11
+int64_t or_trace_trials(const or_camera *cam, const or_spacetime *st, const or_integrator *in,
+                        int i, int j, double *trials_out, int64_t cap, double info[8]);
 /* Trace pixel (i,j) and copy at most max_steps accepted step records
    (25 doubles each) into steps_out.  Returns n_acc; fills info[8] =
    n_acc, n_rej, status, lambda, s, dt, r_end, 0 and y_end[8].             */

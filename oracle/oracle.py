@@ -85,6 +85,9 @@ def lib():
         L.or_trace_pixel.restype = i64
         L.or_trace_pixel.argtypes = [C.POINTER(Camera), C.POINTER(Spacetime), C.POINTER(Integrator),
                                      i, i, P, i64, P, P]
+        L.or_trace_trials.restype = i64
+        L.or_trace_trials.argtypes = [C.POINTER(Camera), C.POINTER(Spacetime), C.POINTER(Integrator),
+                                      i, i, P, i64, P]
         L.or_grid_sample.restype = i
         L.or_grid_sample.argtypes = [C.POINTER(Grid), i, P, P]
         L.or_bessel_k_scaled.restype = d
@@ -245,6 +248,19 @@ def trace_pixel(cam, st, integ, i, j, max_records=200000):
     return {"steps": steps[:n].copy(), "n_acc": int(info[0]), "n_rej": int(info[1]),
             "status": int(info[2]), "lambda": info[3], "s": info[4], "dt": info[5],
             "r_end": info[6], "n_norm": info[7], "y_end": yend}
+
+
+def trace_trials(cam, st, integ, i, j, max_trials=200000):
+    """Every trial step of pixel (i, j): rows of the state at the trial's
+    start y[8], the trial step h, its error norm eps and accepted (1) or
+    rejected (0)."""
+    c, s, g = camera(cam), spacetime(st), integrator(integ)
+    log = np.zeros((max_trials, 11))
+    info = np.zeros(8)
+    n = lib().or_trace_trials(C.byref(c), C.byref(s), C.byref(g), int(i), int(j), _dp(log), max_trials,
+                              _dp(info))
+    return {"trials": log[:min(n, max_trials)].copy(), "n_acc": int(info[0]), "n_rej": int(info[1]),
+            "status": int(info[2])}
 
 
 def grid_sample(gr, x, interp=1):

@@ -110,8 +110,12 @@ static int finite8(const double y[8])
     return 1;
 }
 
-int or_trace(const or_camera *cam, const or_spacetime *st, const or_integrator *in,
-             const double ystart[8], or_ray *ray)
+/* The integration of one ray.  With tlog non-NULL every trial step is also
+   logged (up to tcap of them; *tn receives the number of trials) as
+   OR_TRIAL_LOG doubles: the state at the start of the trial y[8], the trial
+   step h, its error norm eps and 1 if it was accepted, else 0. */
+static int trace_impl(const or_camera *cam, const or_spacetime *st, const or_integrator *in,
+                      const double ystart[8], or_ray *ray, double *tlog, int64_t tcap, int64_t *tn)
 {
     double c[7], A[7][7], b5[7], b4[7], bm[7];
     double y[8], k[7][8], ys[8], y5[8], ym[8], err[8];
@@ -165,6 +169,16 @@ int or_trace(const or_camera *cam, const or_spacetime *st, const or_integrator *
             }
             if (bad || !finite8(y5)) { ray->status = OR_NONFINITE; break; }
         }
+        if (tlog) {
+            int64_t t = ray->n_acc + ray->n_rej;
+            if (t < tcap) {
+                double *q = tlog + OR_TRIAL_LOG * t;
+                memcpy(q, y, 8 * sizeof(double));
+                q[8] = h;
+                q[9] = eps;
+                q[10] = eps <= 1.0 ? 1.0 : 0.0;
+            }
+        }
         if (eps <= 1.0) {
             double fac, r_new;
             push_step(ray, y, ym, y5, h);
@@ -191,7 +205,31 @@ int or_trace(const or_camera *cam, const or_spacetime *st, const or_integrator *
     memcpy(ray->y_end, y, sizeof(y));
     ray->lambda = fabs(lambda);
     ray->dt = ystart[0] - y[0];
+    if (tn) *tn = ray->n_acc + ray->n_rej;
     return ray->status;
+}
+
+int or_trace(const or_camera *cam, const or_spacetime *st, const or_integrator *in,
+             const double ystart[8], or_ray *ray)
+{
+    return trace_impl(cam, st, in, ystart, ray, NULL, 0, NULL);
+}
+
+int64_t or_trace_trials(const or_camera *cam, const or_spacetime *st, const or_integrator *in,
+                        int i, int j, double *trials_out, int64_t cap, double info[8])
+{
+    or_ray ray;
+    double y[8], n;
+    int64_t nt = 0;
+    memset(&ray, 0, sizeof(ray));
+    or_camera_ray(cam, st, i, j, y, &n);
+    trace_impl(cam, st, in, y, &ray, trials_out, cap, &nt);
+    info[0] = (double)ray.n_acc; info[1] = (double)ray.n_rej; info[2] = ray.status;
+    info[3] = ray.lambda; info[4] = ray.s; info[5] = ray.dt;
+    info[6] = or_ks_radius(st->a, ray.y_end[1], ray.y_end[2], ray.y_end[3]);
+    info[7] = n;
+    or_ray_free(&ray);
+    return nt;
 }
 
 int64_t or_trace_pixel(const or_camera *cam, const or_spacetime *st,

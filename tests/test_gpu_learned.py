@@ -81,9 +81,21 @@ def test_forward_backward_matches_oracle(ctx, n):
     assert ey <= 2e-3
     assert abs(loss - lo) <= 2e-3 * lo
     assert eg <= 5e-3 and max(eb.values()) <= 2e-2
-    # and the exact (unrounded) FP64 gradient is close: the BF16 operands cost percent-level accuracy
+    # Against the exact (unrounded) FP64 gradient, block by block: the GPU's
+    # distance may not exceed what rounding the matrix-core operands to BF16
+    # explains -- the distance of the BF16-emulating oracle from the exact
+    # gradient -- by more than half again, plus 1e-3 of the block for the
+    # FP32 accumulation.  (BF16 keeps 8 significant bits: each rounded operand
+    # is off by up to 2^-9 relative, so a block's gradient moves by a few
+    # tenths of a percent; the bound follows the measured emulation instead of
+    # a worst case.)
     _, _, g64 = M.loss_and_grad(m.astype(np.float64), X[:, :11].astype(np.float64), X[:, 11].astype(np.float64))
-    assert np.linalg.norm(g - g64) <= 0.05 * np.linalg.norm(g64)
+    for k, (a, b) in blocks.items():
+        n64 = np.linalg.norm(g64[a:b])
+        d_gpu = np.linalg.norm(g[a:b] - g64[a:b])
+        d_emu = np.linalg.norm(go[a:b] - g64[a:b])
+        _say("block", k, "GPU vs exact", d_gpu / n64, "BF16 emulation vs exact", d_emu / n64)
+        assert d_gpu <= 1.5 * d_emu + 1e-3 * n64, k
 
 
 def test_steplog_is_consistent(ctx):

@@ -77,6 +77,30 @@ def test_zero_field_and_high_frequency_limit(oracle):
         assert oracle.thermal_coeffs(ne, th, B, nu, c)[0] == pytest.approx(ref, rel=0.05)
 
 
+def test_faraday_rotativity_cold_plasma_limit(oracle):
+    """As Theta_e -> 0 the thermal Faraday rotativity must reduce to the
+    cold-plasma one, rho_V = omega_p^2 omega_B cos(theta) / (c omega^2): the
+    plane of polarization turns by d chi / ds = rho_V / 2 =
+    2 pi e^3 n B cos(theta) / (m^2 c^2 omega^2) (Rybicki & Lightman, Faraday
+    rotation in a cold magnetized plasma).  The relativistic corrections of
+    the fit (the Bessel ratio and the X correction) are O(Theta_e)."""
+    for ne, B, nu, c in [(1e6, 10.0, 230e9, 0.6), (3e4, 80.0, 86e9, -0.3), (1e7, 2.0, 690e9, 0.95)]:
+        omega = 2 * math.pi * nu
+        chi_rate = 2 * math.pi * Q_E ** 3 * ne * B * c / (M_E ** 2 * C_LIGHT ** 2 * omega ** 2)
+        wp2 = 4 * math.pi * ne * Q_E ** 2 / M_E
+        wb = Q_E * B / (M_E * C_LIGHT)
+        cold = wp2 * wb * c / (C_LIGHT * omega ** 2)
+        assert cold == pytest.approx(2 * chi_rate, rel=1e-12)
+        prev = None
+        for th in [3e-3, 1e-3, 3e-4]:
+            rv = oracle.thermal_coeffs(ne, th, B, nu, c)[7]
+            assert abs(rv / cold - 1.0) <= 3.0 * th, (th, rv / cold)
+            # hotter electrons rotate less (relativistic suppression)
+            if prev is not None:
+                assert abs(rv) > abs(prev)
+            prev = rv
+
+
 # ------------------------------------------------------------------ grid
 def _block_grid(nb_cells=(6, 5, 4), bounds=(-3, 3, -2, 3, -1, 1), f=None):
     nx, ny, nz = nb_cells
