@@ -16,45 +16,64 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X published vector peaks: FP64 256 CU x 2.4 GHz x 128 FLOP/clk; FP32
-# 157.3 TFLOP/s counts packed dual FP32 (this build issues unpacked FP32,
-# whose ceiling equals the FP64 one, so the combined bound below is generous
-# to the hardware and the reported fraction conservative).
-FP64_PEAK_TFLOPS = 78.6
-FP32_PEAK_TFLOPS = 157.3
+# MI355X vector ALU peak: 256 CU x 2.4 GHz x 4 SIMD x 16 lanes x 2 (FMA) =
+# 78.6 TFLOP/s for FP64 and for unpacked FP32 alike.  The published FP32
+# figure of 157.3 TFLOP/s counts packed dual FP32 (v_pk_fma_f32), which this
+# build disables (-packed-fp32-ops), so 78.6 is the attainable ceiling of both
+# arithmetic types here.  Transcendental-unit instructions are counted as one
+# operation although they issue at a quarter of the rate, which makes the
+# ceiling generous to the hardware.
+VALU_PEAK_TFLOPS = 78.6
+PUBLISHED_FP32_TFLOPS = 157.3
 
-# Floating-point operations per unit of work of the 1024^2 SMR polarized
-# workload, measured on divergence-free launches (paper_2203_15963_amd/opcount.py:
+# Floating-point operations per unit of work, measured on divergence-free
+# launches (paper_2203_15963_amd/opcount.py: 64 copies of one ray per wave,
 # FMA = 2, add/mul/transcendental = 1, non-negative least squares over 48
-# directions).  These are the work of the method per unit and stay fixed when
-# the kernels get faster.  Keys: precision -> kernel -> arithmetic type -> unit;
-# units: trial = DP trial steps, acc = accepted steps, samp = plasma samples,
-# rec = transport records (pieces), ray = rays.
+# directions): the work the kernels do per unit with every lane useful.  Valid
+# only for the kernel sources and flags they were measured on (hash "src").
+# Keys: precision -> kernel -> arithmetic type -> unit; units: trial = DP trial
+# steps, acc = accepted steps, samp = plasma samples, rec = transport records
+# (pieces), ray = rays.
 OPS_PER_UNIT = {
-    0: {"geodesic": {"F64": {"trial": 2175.0, "acc": 286.0, "ray": 486.0}, "F32": {}},
-        "transfer": {"F64": {"samp": 4324.5, "rec": 497.3, "acc": 484.0, "ray": 6353.5}, "F32": {}}},
-    1: {"geodesic": {"F64": {"trial": 2175.0, "acc": 286.0, "ray": 486.0}, "F32": {}},
-        "transfer": {"F64": {"samp": 92.9, "rec": 170.9, "acc": 323.6, "ray": 0.0},
-                     "F32": {"samp": 3156.4, "rec": 360.5, "acc": 58.5, "ray": 69597.5}}},
+    "src": "7941c341a8156869",
+    0: {"geodesic": {"F64": {"trial": 1291.6, "acc": 287.4, "ray": 1055.3}, "F32": {"trial": 11.0, "ray": 7.0}},
+        "transfer": {"F64": {"samp": 2713.6, "rec": 366.8, "acc": 52.3, "ray": 36328.8}, "F32": {}}},
+    1: {"geodesic": {"F64": {"trial": 1216.5, "acc": 424.2, "ray": 5321.1}, "F32": {"trial": 11.0, "ray": 7.0}},
+        "transfer": {"F64": {"samp": 16.0, "rec": 30.8}, "F32": {"samp": 1448.5, "rec": 353.4, "ray": 50633.5}}},
 }
 
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE passes over this benchmark (KiB per dispatch, scaled by what the
-# same counters read for a 1 GiB device copy: x2.0 and x1.0), valid only for
-# the kernel sources they were taken on (hash over csrc/ and include/).
-TRAFFIC = {
-    (1, "transfer"): {"bytes": 2.0 * (1.42026e7 + 203937.0) * 1024 + 1.0 * (137996.0 + 65536.0) * 1024, "src": "d036044345837dcb"},
+# Counter passes over this benchmark (rocprofv3), per launch of a kernel, for
+# the sources whose hash is "src": issued floating-point operations
+# (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_{F32,F64} x 64 lanes, FMA = 2: masked
+# lanes included), VALU lane activity (SQ_THREAD_CYCLES_VALU over 64 x
+# SQ_ACTIVE_INST_VALU) and HBM bytes (FETCH_SIZE and WRITE_SIZE in KiB per
+# dispatch, scaled by what the same counters read for a 1 GiB device copy:
+# x2.0 and x1.0).  Keys: (precision, kernel class).
+COUNTERS = {
+    "src": "7941c341a8156869",
+    (1, "transfer"): {"issued_f64": 4.63e10, "issued_f32": 1.517e12, "lane_activity": 0.851,
+                      "bytes": 2.0 * (1.42026e7 + 203937.0) * 1024 + 1.0 * (137996.0 + 65536.0) * 1024,
+                      # units of work of that launch (1024^2 SMR image, auxiliary maps)
+                      "units": {"trial": 85456054.0, "acc": 72527214.0, "samp": 682634999.0, "rec": 734227814.0,
+                                "ray": 1048576.0}},
 }
 
 
 def source_hash():
+    """Hash over the kernel sources (comments and blank space removed, so
+    that only code changes count) and the library's build flags."""
     import hashlib
+    import re
     h = hashlib.sha256()
-    for d in (os.path.join(ROOT, "paper_2203_15963_amd", "csrc"), os.path.join(ROOT, "include")):
-        for f in sorted(os.listdir(d)):
-            if f.endswith((".hip", ".hpp", ".h")):
-                with open(os.path.join(d, f), "rb") as fh:
-                    h.update(f.encode() + b"\0" + fh.read())
+    d = os.path.join(ROOT, "paper_2203_15963_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".h")):
+            with open(os.path.join(d, f)) as fh:
+                code = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
+            code = re.sub(r"//[^\n]*", " ", code)
+            h.update(f.encode() + b"\0" + " ".join(code.split()).encode())
+    from paper_2203_15963_amd import build as libbuild
+    h.update(" ".join(libbuild.FLAGS[:-2]).encode())
     return h.hexdigest()[:16]
 
 
@@ -62,9 +81,24 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, grid, budget_s=15.0, seed=0):
-    """The CPU oracle on a random pixel sample of the same workload, timed for
-    about budget_s seconds on the host cores; returns rays/s."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(w, grid, budget_s=20.0, seed=0):
+    """The CPU oracle timed on random pixel samples of the same workload: a
+    short calibration, then three runs on every host core this process may
+    use (their median is the value) and one run on one thread, each sized to
+    about a quarter of budget_s.  Returns the baseline record and the oracle's
+    pixels (ids, image rows, aux rows) for the accuracy check."""
     import numpy as np
     from oracle import oracle as O
     try:
@@ -74,35 +108,90 @@ def cpu_baseline(w, grid, budget_s=15.0, seed=0):
     n = int(w["camera"]["n"])
     rng = np.random.default_rng(seed)
     gh = O.grid(grid)
-    done, t_used, batch = 0, 0.0, max(16, cores * 4)
-    while t_used < budget_s:
-        pix = rng.choice(n * n, size=batch, replace=False)
+    pix_all, io_all, ao_all = [], [], []
+
+    def timed(m, threads):
+        pix = rng.choice(n * n, size=min(m, n * n), replace=False)
         t0 = time.perf_counter()
-        O.render_pixels(w["camera"], w["spacetime"], w["integrator"], gh, w["plasma"], pix, n_threads=cores)
+        io, ao = O.render_pixels(w["camera"], w["spacetime"], w["integrator"], gh, w["plasma"], pix,
+                                 n_threads=threads)
         dt = time.perf_counter() - t0
-        done += batch
-        t_used += dt
-        if dt < budget_s / 8:
-            batch *= 2
-    return {"value": done / t_used, "unit": "rays/s", "cores": cores, "kind": "oracle",
-            "sample": f"{done} random pixels of the same {n}x{n} image (seed {seed}), {t_used:.1f} s"}
+        pix_all.append(pix)
+        io_all.append(io)
+        ao_all.append(ao)
+        return len(pix) / dt, dt, len(pix)
+
+    rate, _, _ = timed(4 * cores, cores)
+    per_run = budget_s / 4.0
+    runs, secs, npx = [], 0.0, 0
+    for _ in range(3):
+        r, dt, m = timed(max(cores, int(rate * per_run)), cores)
+        runs.append(r)
+        secs += dt
+        npx += m
+        rate = r
+    r1, dt1, m1 = timed(max(4, int(rate / cores * per_run)), 1)
+    value = float(np.median(runs))
+    rec = {"value": value, "unit": "rays/s", "cores": cores, "kind": "oracle", "cpu": cpu_model(),
+           "runs": runs, "one_thread": {"value": r1, "pixels": m1, "seconds": dt1},
+           "sample": f"3 runs of {npx // 3} random pixels of the same {n}x{n} image on {cores} threads "
+                     f"(median), {secs:.1f} s; one run of {m1} pixels on 1 thread, {dt1:.1f} s"}
+    return rec, np.concatenate(pix_all), np.concatenate(io_all), np.concatenate(ao_all)
+
+
+def accuracy(img, aux, pix, io, ao, tol):
+    """Error of the timed GPU image against the FP64 oracle on the oracle's
+    pixels: E_pix = max over Stokes of |X_gpu - X_oracle| / max(I_oracle,
+    1e-3 max I) per pixel (max I over the GPU image), its distribution, the
+    relative error of the sample's total flux and the pixels whose accepted or
+    rejected step counts differ from the oracle's."""
+    import numpy as np
+    pix, first = np.unique(pix, return_index=True)
+    io, ao = io[first], ao[first]
+    ig = img.reshape(4, -1)[:, pix].T
+    ag = aux.reshape(aux.shape[0], -1)[:, pix].T
+    den = np.maximum(np.abs(io[:, 0]), 1e-3 * np.abs(img[0]).max())
+    e = (np.abs(ig - io) / den[:, None]).max(axis=1)
+    match = (ag[:, 5] == ao[:, 5]) & (ag[:, 6] == ao[:, 6])
+    return {"pixels": int(len(pix)), "E_pix_max": float(e.max()), "E_pix_p999": float(np.quantile(e, 0.999)),
+            "E_pix_p99": float(np.quantile(e, 0.99)), "E_pix_median": float(np.median(e)),
+            "E_pix_rms": float(np.sqrt(np.mean(e * e))),
+            "flux_rel_err": float(abs(ig[:, 0].sum() - io[:, 0].sum()) / abs(io[:, 0].sum())),
+            "step_count_mismatches": int((~match).sum()),
+            "E_pix_max_mismatched": float(e[~match].max()) if (~match).any() else None,
+            "tolerance": tol, "within_tolerance": bool(e.max() <= tol)}
 
 
 def roofline(precision, dom, kern, units):
-    model = OPS_PER_UNIT[precision][dom]
+    """Useful FLOP/s of the dominant kernel against the VALU ceiling, with the
+    counters' issued operations and HBM bytes beside it."""
+    lm = kern[dom]["avg_launch_ms"] / 1e3
     nl = max(1.0, kern[dom]["launches_per_step"])
-    ops = {t: sum(c * units[u] for u, c in model[t].items()) / nl for t in ("F64", "F32")}
-    t_min = ops["F64"] / (FP64_PEAK_TFLOPS * 1e12) + ops["F32"] / (FP32_PEAK_TFLOPS * 1e12)
-    per_launch = ops["F64"] + ops["F32"]
-    peak = per_launch / t_min / 1e12
-    achieved = per_launch / (kern[dom]["avg_launch_ms"] / 1e3) / 1e12
-    tr = TRAFFIC.get((precision, dom))
-    traffic = tr["bytes"] if tr is not None and tr["src"] == source_hash() else None
-    return {"bound": "alu", "kernel": "k_" + dom, "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic, "traffic_unit": "bytes/launch",
-            "ops_per_launch": {"f64": ops["F64"], "f32": ops["F32"]},
-            "peak_note": f"combined bound t >= F64/{FP64_PEAK_TFLOPS} + F32/{FP32_PEAK_TFLOPS} TFLOP/s",
-            "units_per_step": units}
+    src = source_hash()
+    out = {"bound": "alu", "kernel": "k_" + dom, "achieved": None, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": None, "traffic": None, "traffic_unit": "bytes/launch",
+           "peak_note": f"{VALU_PEAK_TFLOPS} TFLOP/s = 256 CU x 2.4 GHz x 128 FLOP/clk: FP64 and unpacked FP32 "
+                        f"(packed FP32, the published {PUBLISHED_FP32_TFLOPS}, is disabled in this build)",
+           "units_per_step": units, "source_hash": src}
+    if OPS_PER_UNIT["src"] == src:
+        model = OPS_PER_UNIT[precision][dom]
+        ops = {t: sum(c * units[u] for u, c in model[t].items()) / nl for t in ("F64", "F32")}
+        useful = ops["F64"] + ops["F32"]
+        out["achieved"] = useful / lm / 1e12
+        out["frac"] = out["achieved"] / VALU_PEAK_TFLOPS
+        out["ops_per_launch"] = {"f64": ops["F64"], "f32": ops["F32"]}
+    else:
+        out["stale"] = "per-unit operation counts were measured on other kernel sources"
+    cn = COUNTERS.get((precision, dom)) if COUNTERS["src"] == src else None
+    if cn is not None:
+        issued = cn["issued_f64"] + cn["issued_f32"]
+        out["issued"] = {"tflops": issued / lm / 1e12, "frac": issued / lm / 1e12 / VALU_PEAK_TFLOPS,
+                         "f64_per_launch": cn["issued_f64"], "f32_per_launch": cn["issued_f32"],
+                         "lane_activity": cn["lane_activity"]}
+        out["traffic"] = cn["bytes"]
+        if out["achieved"] is not None:
+            out["useful_over_issued"] = out["achieved"] / out["issued"]["tflops"]
+    return out
 
 
 def kernel_table(prof, steps):
@@ -278,7 +367,7 @@ def main():
     ap.add_argument("--grid-f64", action="store_true", help="keep the grid in FP64 in the mixed form")
     ap.add_argument("--n", type=int, default=None, help="override the image size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-autotune", action="store_true", help="batched workload: keep the default schedule")
     ap.add_argument("--autotune", action="store_true", help="single image: autotune the schedule first (untimed)")
     ap.add_argument("--tuning", default=None, help="schedule as JSON, e.g. '{\"tile_w\": 8, \"tile_h\": 8}'")
@@ -316,9 +405,15 @@ def main():
     n = int(w["camera"]["n"])
     log("generating grid", w["grid_args"])
     grid_f32 = args.precision == 1 and not args.grid_f64
-    grid = synth.make_grid(w["grid_args"], dtype=np.float32 if grid_f32 else np.float64)
+    # the FP64 cells are the oracle's input; the mixed form stores them rounded to FP32
+    grid64 = synth.make_grid(w["grid_args"], dtype=np.float64)
+    grid = dict(grid64, prims=grid64["prims"].astype(np.float32)) if grid_f32 else grid64
     ctx = blgpu.Context(0)
+    torch.cuda.synchronize()
+    te0 = time.perf_counter()
     gg = ctx.grid(grid)
+    torch.cuda.synchronize()
+    grid_ms = (time.perf_counter() - te0) * 1e3
     img = torch.empty(4, n, n, dtype=torch.float64, device="cuda")
     aux = torch.empty(blgpu.NAUX, n, n, dtype=torch.float64, device="cuda")
     log("grid resident:", grid["prims"].nbytes / 1e6, "MB;", len(grid["bounds"]), "blocks")
@@ -336,21 +431,29 @@ def main():
                    image=img, aux=aux)
 
     for k in range(args.warmup):
+        te0 = time.perf_counter()
         step()
         torch.cuda.synchronize()
+        if k == 0:
+            first_ms = (time.perf_counter() - te0) * 1e3
         log(f"warmup {k + 1}/{args.warmup} done")
     ctx.profile_enable(True)
     ctx.profile_read()
+    # per-step HIP events on the stream the library enqueues on (torch's current stream)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
+        evs[k][0].record()
         step()
+        evs[k][1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile_read()
     ctx.profile_enable(False)
     log("timed steps done", prof)
     ms = (t1 - t0) * 1e3 / args.steps
+    step_ms = sorted(a.elapsed_time(b) for a, b in evs)
     rays = n * n
     value = rays / (ms / 1e3)
 
@@ -372,6 +475,11 @@ def main():
                                f"{'polarized' if pol else 'unpolarized'}, {len(grid['bounds'])} blocks of "
                                f"{grid['prims'].shape[1]}^3 cells, f_abs=f_rel={w['integrator']['f_abs']}",
                    "precision": args.precision, "grid_dtype": "f32" if grid_f32 else "f64", "pixels": rays},
+        "step_ms": {"median": step_ms[len(step_ms) // 2], "min": step_ms[0], "max": step_ms[-1],
+                    "timer": "HIP events around each render on the library's stream"},
+        "end_to_end_ms": {"grid_create": grid_ms, "first_render": first_ms if args.warmup > 0 else None,
+                          "note": "host-to-device copy of the cells and bl_grid_create; the first render "
+                                  "includes the workspace allocation"},
         "tuning": ctx.get_tuning(),
         "kernels": kern,
         "roofline": roof,
@@ -466,7 +574,11 @@ def main():
         log("copy probe: 1 GiB read + 1 GiB written")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(w, grid, budget_s=args.cpu_budget)
+        img_np = img.cpu().numpy()
+        out["cpu_baseline"], pix, io, ao = cpu_baseline(w, grid64, budget_s=args.cpu_budget)
+        out["accuracy"] = accuracy(img_np, a, pix, io, ao, 1e-4 if args.precision == 1 else 1e-10)
+        out["accuracy"]["reference"] = "FP64 oracle on the FP64 cells, pixels of the CPU-baseline runs"
+        log("accuracy", out["accuracy"])
     print(json.dumps(out), flush=True)
 
 

@@ -6,7 +6,7 @@
  * For every camera pixel the library integrates a null geodesic of the Kerr
  * metric in Cartesian Kerr-Schild coordinates with adaptive Dormand-Prince
  * RK5(4) steps (paper section 2.2), samples GRMHD-like cell data on the ray
- * (section 2.4), evaluates thermal synchrotron coefficients (section 2.5) and
+ * (section 2.5), evaluates thermal synchrotron coefficients (section 2.6) and
  * integrates the unpolarized (section 2.3) or polarized (section 2.4,
  * Strang-split coordinate/plasma terms) transfer equation from source to
  * camera.  The camera is the plane-parallel camera of section 2.1.
@@ -49,7 +49,8 @@ typedef enum {
     BL_E_UNSUPPORTED = -4    /* a valid request this version does not support  */
 } bl_status;
 
-/* Auxiliary maps, each [N][N] doubles, in this order (paper section 4.5:
+/* Auxiliary maps, each [N][N] doubles, in this order (paper section 4.6,
+   Auxiliary Images:
    elapsed time, proper length, affine parameter, optical depth and
    integrated emissivity; plus step counts, status and sample counts). */
 #define BL_NAUX 10
@@ -112,7 +113,7 @@ typedef struct {
     int32_t pad;
 } bl_integrator;
 
-/* Block-structured fluid data (paper section 2.4): n_blocks logically
+/* Block-structured fluid data (paper section 2.5): n_blocks logically
    Cartesian blocks of bnx*bny*bnz cells; cell values are cell-centred. */
 typedef struct {
     int32_t n_blocks, bnx, bny, bnz;  /* every bn* >= 2                       */
@@ -130,7 +131,7 @@ typedef struct {
                                  of rho_unit c^2 and B of c sqrt(4 pi rho_unit) */
 } bl_grid_desc;
 
-/* Plasma model, paper section 2.5 (thermal electrons, R_high/R_low). */
+/* Plasma model, paper section 2.6 (thermal electrons, R_high/R_low). */
 typedef struct {
     double mu, ne_ni;         /* molecular weight, n_e/n_i                    */
     double r_high, r_low;     /* T_i/T_e prescription                         */
@@ -179,7 +180,7 @@ bl_status bl_camera_rays(bl_context *ctx, const bl_camera *cam, const bl_spaceti
 bl_status bl_trace_geodesics(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
                              const bl_integrator *integ, double *state_out, double *aux_out);
 
-/* Full image (paper sections 2.1-2.5): image_out device [4][N][N] doubles
+/* Full image (paper sections 2.1-2.6): image_out device [4][N][N] doubles
    (I, Q, U, V; Q, U, V zero when unpolarized); aux_out device
    [BL_NAUX][N][N].  Q > 0 means polarization along the vertical V, U > 0
    along the direction 45 degrees from V towards -H. */
@@ -232,7 +233,7 @@ bl_status bl_render_batch(bl_context *ctx, int32_t n_images, const bl_image_desc
                           const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
                           const bl_mode *mode, const bl_tuning *tuning);
 
-/* Averaged quantities (paper section 4, Auxiliary Images): a render of one
+/* Averaged quantities (paper section 4.6, Auxiliary Images): a render of one
    image (as bl_render: image_out and aux_out) followed by a pass over the
    same step records that writes avg_out, device [BL_NAVG][N][N] doubles:
    for q = rho, n_e, p, Theta_e, B, sigma, beta^-1 (k = 0..6; units as for
@@ -247,7 +248,7 @@ bl_status bl_render_averages(bl_context *ctx, const bl_camera *cam, const bl_spa
                              const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
                              const bl_mode *mode, double *image_out, double *aux_out, double *avg_out);
 
-/* Adaptive ray tracing (paper section 4, Adaptive Ray Tracing).  A pixel is
+/* Adaptive ray tracing (paper section 4.4, Adaptive Ray Tracing).  A pixel is
    a square of the image plane sampled at its centre.  Level 0 is the camera's
    N x N image cut into blocks of B x B pixels; a block that refines is
    replaced at the next level by four blocks of B x B pixels of half the size,
@@ -297,7 +298,7 @@ bl_status bl_render_adaptive(bl_context *ctx, const bl_camera *cam, const bl_spa
                              const bl_mode *mode, const bl_adaptive *adaptive, int32_t max_blocks,
                              int32_t *blocks_out, double *image_out, double *aux_out, int32_t *level_counts_out);
 
-/* Data cuts (paper section 4, Data Cuts): a sample whose rho, n_e, p,
+/* Data cuts (paper section 4.1, Data Cuts): a sample whose rho, n_e, p,
    Theta_e, B, sigma, beta^-1 or Kerr-Schild r lies below its lower limit
    ([0]) or above its upper limit ([1]) is vacuum, and with plane = +1 (-1)
    so is every sample with (x - x0).n < 0 (> 0), x the CKS position (x, y, z).
@@ -319,7 +320,7 @@ typedef struct {
    non-finite plane origin or normal. */
 bl_status bl_set_cuts(bl_context *ctx, const bl_cuts *cuts);
 
-/* One camera at several frequencies (paper section 4, true-color images:
+/* One camera at several frequencies (paper section 4.8, True-Color Images:
    images at many frequencies for a fixed camera and fixed data; section 5:
    tracing several images at once amortises the geodesic integration).  The
    geodesics do not depend on the frequency (n = nu / den with den = -k_t or
@@ -408,7 +409,7 @@ bl_status bl_mlp_forward_backward(bl_context *ctx, const float *model, const flo
    may free the model afterwards). */
 bl_status bl_set_step_model(bl_context *ctx, const float *model);
 
-/* Per-sample evaluation for checking (paper sections 2.2, 2.4, 2.5): for
+/* Per-sample evaluation for checking (paper sections 2.2, 2.5, 2.6): for
    states device [n][8] and norms device [n], writes out device [n][64]:
    [0..7]   geodesic right-hand side dy/dlambda,
    [8..23]  G^a_d = Gamma^a_cd k^c (row-major a, d),

@@ -1,4 +1,4 @@
-"""Adaptive ray tracing (paper section 4, Adaptive Ray Tracing): plain
+"""Adaptive ray tracing (paper section 4.4, Adaptive Ray Tracing): plain
 reference of the refinement criteria and of the level-by-level render.
 
 TEST INFRASTRUCTURE ONLY: imported by the test suite, never by the product

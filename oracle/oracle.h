@@ -63,7 +63,7 @@ typedef struct {
     double rho_unit;        /* g cm^-3 per code density unit                */
 } or_grid;
 
-/* Data cuts (paper section 4, Data Cuts): a sample whose rho, n_e, p,
+/* Data cuts (paper section 4.1, Data Cuts): a sample whose rho, n_e, p,
    Theta_e, B, sigma, beta^-1 or Kerr-Schild r lies below its lower or above
    its upper limit is vacuum, and with a plane cut so is every sample on one
    side of the plane (x - x0).n = 0 (CKS x, y, z).  Limits of -inf / +inf
@@ -161,7 +161,7 @@ void   or_transport_rhs(double a, int flat, const double y[8],
 void   or_dense_quartic(const double y0[8], const double y1[8], const double f0[8],
                         const double f1[8], const double ym[8], double h, double theta,
                         double out[8]);
-/* Averaged quantities (paper section 4, Auxiliary Images): for q in rho, n_e,
+/* Averaged quantities (paper section 4.6, Auxiliary Images): for q in rho, n_e,
    p, Theta_e, B, sigma, beta^-1 (index k), avg[k] = <q>_lambda =
    (1/lambda) int q dlambda over the plasma samples, avg[7 + k] = <q>_Ij =
    int q j_I dlambda / int j_I dlambda (0 without emission), avg[14 + k] =

@@ -241,7 +241,7 @@ void or_tetrad(const double g[16], const double gi[16], const double u[4],
     }
 }
 
-/* a quantity outside its cut limits (section 4, Data Cuts) */
+/* a quantity outside its cut limits (section 4.1, Data Cuts) */
 static int cut_out(const or_plasma *pl, int k, double q)
 {
     return q < pl->cut_lo[k] || q > pl->cut_hi[k];

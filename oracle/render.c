@@ -3,7 +3,7 @@
  * sampling of the accepted steps, transfer from source to camera.
  * TEST INFRASTRUCTURE ONLY (see oracle.h).
  *
- * Sampling (paper section 2.2, last paragraph; section 2.4): each accepted
+ * Sampling (paper section 2.2, last paragraph; section 2.5): each accepted
  * step is represented by its fourth-order midpoint; steps longer than the
  * proper-length limit are subdivided with the quartic through y0, y1, f0, f1
  * and y_mid.  Readings:
@@ -190,7 +190,7 @@ static void stokes_to_n(double e[4][4], const double S[4], double Nre[16], doubl
         }
 }
 
-/* Running sums of the averaged quantities (section 4, Auxiliary Images) at a
+/* Running sums of the averaged quantities (section 4.6, Auxiliary Images) at a
    plasma sample with outputs c of or_sample_point, affine length dl,
    emission increment dj and depth dtau: sl[k] += q dl, sj[k] += q dj and
    qt[k] += (q - qt[k])(1 - e^-dtau). */

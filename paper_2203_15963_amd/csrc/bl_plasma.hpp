@@ -1,10 +1,10 @@
 // bl_plasma.hpp -- grid sampling, plasma state, thermal synchrotron
 // coefficients and the fluid-frame tetrad on the device.
 //
-// Paper section 2.4 (Sampling): primitives rho, p, normal-frame velocity and
+// Paper section 2.5 (Sampling): primitives rho, p, normal-frame velocity and
 // B^a are interpolated, nearest-cell or trilinear within one block (blocks
 // carry no ghost zones, so corner indices are clamped to the block: values are
-// held constant within half a cell of a block face).  Section 2.5
+// held constant within half a cell of a block face).  Section 2.6
 // (Coefficients): n_e = rho/(mu m_p) (1 + 1/(n_e/n_i))^-1, T_i/T_e from
 // R_high/R_low and beta, sigma > sigma_max is vacuum, U coefficients vanish in
 // the rotated frame.  The thermal fitting formulas the paper takes from
@@ -310,11 +310,11 @@ struct Sample {
 };
 
 // Plasma state and fluid-frame coefficients at state y = (x^mu, k_mu) for a
-// ray of normalisation n (paper sections 2.4, 2.5):
+// ray of normalisation n (paper sections 2.5, 2.6):
 //   u^t = gamma/alpha, u^a = u~^a - gamma beta^a/alpha,
 //   b^t = B^a u_a, b^a = (B^a + b^t u^a)/u^t, sigma = b^2/rho,
 //   beta^-1 = b^2/(2p), nu_fl = n (-k.u), cos(theta_B) = k.b/((-k.u)|b|).
-// A quantity outside its cut limits (paper section 4, Data Cuts), compared
+// A quantity outside its cut limits (paper section 4.1, Data Cuts), compared
 // in the arithmetic's own precision.
 template <typename R>
 __device__ __forceinline__ bool cut_out(const CutParams &c, int k, R q) {

@@ -601,7 +601,7 @@ __device__ __forceinline__ void to_state_r(const R p6[kQC], R kt, R y[8]) {
     y[4] = kt; y[5] = p6[3]; y[6] = p6[4]; y[7] = p6[5];
 }
 
-// Averaged quantities at a plasma sample (paper section 4, Auxiliary
+// Averaged quantities at a plasma sample (paper section 4.6, Auxiliary
 // Images): sums of q dlambda and q dI_j, and <q>_tau relaxed towards q over
 // the sample's depth dtau, <q> += (q - <q>)(1 - e^-dtau).
 template <typename R>

@@ -1004,7 +1004,7 @@ struct bl_grid {
 };
 
 // ---------------------------------------------------------------- adaptive
-// Refinement criteria of one block of an adaptive level (paper section 4,
+// Refinement criteria of one block of an adaptive level (paper section 4.4,
 // Adaptive Ray Tracing), on Stokes I of the block's B x B pixels alone:
 // central differences inside the block, one-sided ones at its edges (the
 // gradient: the two-point difference; the Laplacian: the second difference

@@ -16,6 +16,11 @@ and non-negative least squares gives the per-unit figures.  An FMA counts as two
 operations; add, multiply and each transcendental-unit instruction (rcp,
 sqrt, exp, log, sin, ...) as one.
 
+The same counters over a benchmark run give the operations the kernels
+issued there (masked lanes included); `issued` summarises them per kernel
+together with the VALU lane activity and the HBM byte counters when those
+passes are given.
+
 Usage, on the GPU machine (the counter pass needs rocprofv3):
 
     rocprofv3 --pmc SQ_INSTS_VALU_ADD_F32 SQ_INSTS_VALU_MUL_F32 SQ_INSTS_VALU_FMA_F32 \
@@ -120,6 +125,34 @@ def fit(db, cases_json):
     return res
 
 
+def issued(dbs):
+    """Per kernel name: dispatches, issued FP64 / FP32 operations per dispatch
+    (instruction counters x 64 lanes, FMA = 2), VALU lane activity
+    (SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU)) and FETCH_SIZE /
+    WRITE_SIZE (KiB) per dispatch, from any number of counter databases."""
+    acc = {}
+    for db in dbs:
+        for d in _dispatch_counters(db):
+            e = acc.setdefault(d["kernel"], {})
+            for c, v in d["c"].items():
+                e.setdefault(c, []).append(v)
+    out = {}
+    for k, e in acc.items():
+        mean = {c: float(np.mean(v)) for c, v in e.items()}
+        r = {"dispatches": max(len(v) for v in e.values())}
+        if "SQ_INSTS_VALU_FMA_F64" in mean:
+            r["issued_f64"] = 64.0 * _flops(mean, "F64")
+            r["issued_f32"] = 64.0 * _flops(mean, "F32")
+        if "SQ_ACTIVE_INST_VALU" in mean and mean["SQ_ACTIVE_INST_VALU"] > 0:
+            r["lane_activity"] = mean["SQ_THREAD_CYCLES_VALU"] / (64.0 * mean["SQ_ACTIVE_INST_VALU"])
+            r["valu_insts"] = mean.get("SQ_INSTS_VALU")
+        for c in ("FETCH_SIZE", "WRITE_SIZE"):
+            if c in mean:
+                r[c] = mean[c]
+        out[k] = r
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -131,11 +164,15 @@ def main(argv=None):
     f = sub.add_parser("fit")
     f.add_argument("db")
     f.add_argument("cases")
+    s = sub.add_parser("issued")
+    s.add_argument("dbs", nargs="+")
     a = ap.parse_args(argv)
     if a.cmd == "run":
         run(a.workload, a.precision, a.n_dirs, a.out)
-    else:
+    elif a.cmd == "fit":
         print(json.dumps(fit(a.db, a.cases), indent=1))
+    else:
+        print(json.dumps(issued(a.dbs), indent=1))
 
 
 if __name__ == "__main__":

@@ -15,3 +15,44 @@ def test_more_than_one_gpu_is_refused():
     msg = (r.stdout + r.stderr).lower()
     assert "one gpu" in msg or "1 gpu" in msg or "single gpu" in msg, msg[-500:]
     assert '"metric"' not in r.stdout
+
+
+def _bench():
+    sys.path.insert(0, ROOT)
+    import bench
+    return bench
+
+
+def test_useful_operations_do_not_exceed_issued_ones():
+    """The per-unit counts (divergence-free launches) applied to the units of
+    the launch the counters were taken on give at most the operations that
+    launch issued (masked lanes add issued work, never remove it), and the
+    ratio is about the measured lane activity."""
+    b = _bench()
+    if b.OPS_PER_UNIT["src"] != b.COUNTERS["src"]:
+        return
+    for key, cn in b.COUNTERS.items():
+        if key == "src":
+            continue
+        prec, dom = key
+        model = b.OPS_PER_UNIT[prec][dom]
+        useful = sum(c * cn["units"][u] for t in ("F64", "F32") for u, c in model[t].items())
+        issued = cn["issued_f64"] + cn["issued_f32"]
+        assert useful <= issued, (key, useful, issued)
+        assert abs(useful / issued - cn["lane_activity"]) <= 0.05, (key, useful / issued, cn["lane_activity"])
+
+
+def test_roofline_fraction_is_bounded_by_the_ceiling():
+    """At the launch time that the issued operations fill the VALU ceiling
+    exactly, the reported (useful) fraction is at most 1."""
+    b = _bench()
+    src = b.source_hash()
+    if b.COUNTERS["src"] != src or b.OPS_PER_UNIT["src"] != src:
+        return
+    for key, cn in b.COUNTERS.items():
+        if key == "src":
+            continue
+        prec, dom = key
+        t_min = (cn["issued_f64"] + cn["issued_f32"]) / (b.VALU_PEAK_TFLOPS * 1e12)
+        r = b.roofline(prec, dom, {dom: {"avg_launch_ms": t_min * 1e3, "launches_per_step": 1.0}}, cn["units"])
+        assert r["frac"] <= 1.0 and abs(r["issued"]["frac"] - 1.0) < 1e-9

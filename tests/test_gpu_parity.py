@@ -245,7 +245,7 @@ def _cut_set(w):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_render_with_data_cuts(ctx, oracle, precision):
-    """Data cuts (paper section 4) installed with bl_set_cuts against the
+    """Data cuts (paper section 4.1) installed with bl_set_cuts against the
     oracle with the same cuts."""
     w = _wl("c2_256_pol", 12)
     cuts = _cut_set(w)

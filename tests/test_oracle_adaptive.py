@@ -1,4 +1,4 @@
-"""Pins of the oracle's adaptive ray tracing (paper section 4, Adaptive Ray
+"""Pins of the oracle's adaptive ray tracing (paper section 4.4, Adaptive Ray
 Tracing): the five refinement criteria against closed forms of smooth
 intensity fields (linear, quadratic, exponential), the edge rules, the
 critical-fraction and region rules at their boundaries, the level geometry

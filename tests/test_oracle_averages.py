@@ -1,4 +1,4 @@
-"""Pins of the oracle's averaged quantities (paper section 4, Auxiliary
+"""Pins of the oracle's averaged quantities (paper section 4.6, Auxiliary
 Images): <q>_lambda, <q>_Ij and <q>_tau for q = rho, n_e, p, Theta_e, B,
 sigma, beta^-1, on a uniform cube of plasma at rest in flat spacetime, where
 they have closed forms: along a ray q is constant, so <q>_Ij = q,

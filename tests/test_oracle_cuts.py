@@ -1,4 +1,4 @@
-"""Pins of the oracle's data cuts (paper section 4, Data Cuts): limits on
+"""Pins of the oracle's data cuts (paper section 4.1, Data Cuts): limits on
 rho, n_e, p, Theta_e, B, sigma, beta^-1 and r, and a half-space plane.
 
 - each limit acts on its own quantity: at a plasma sample, an upper limit just
