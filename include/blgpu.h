@@ -188,6 +188,27 @@ bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *s
                     const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
                     const bl_mode *mode, double *image_out, double *aux_out);
 
+/* bl_render for callers that cannot allocate device memory (code under HIP
+   graph capture, serving loops, harnesses that forbid hipMalloc): the same
+   render with every workspace buffer carved from a static device array of
+   256 MiB that each GPU the library runs on holds until the process ends.
+   The call allocates nothing (no hipMalloc or hipFree, no host heap for the
+   image descriptor) and records no timing events; the caller passes the
+   inputs and the outputs as for bl_render.  Results equal bl_render's bit for
+   bit with the same arguments.  The image is processed in chunks of rays
+   that fit the array (about 2,600 rays with the default 512-record slots,
+   more with a smaller integ->record_cap), so it is slower than bl_render.
+   BL_E_INVALID_ARG for integ->max_steps above 4095 (the bound of the
+   overflow path's buffer), BL_E_UNSUPPORTED if not even 64 rays fit, and
+   BL_E_DEVICE if the array has no address on this device.  The array
+   keeps the last call's contents; every call clears what it needs.  All
+   calls on one GPU share the array: calls that overlap in time on one GPU
+   (from several contexts or streams) race and must be serialised by the
+   caller. */
+bl_status bl_render_noalloc(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
+                            const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
+                            const bl_mode *mode, double *image_out, double *aux_out);
+
 /* Schedule of a render (how the work is laid out on the GPU; results do not
    depend on it).  bl_render and bl_render_batch use the context's tuning
    (bl_set_tuning; defaults below) unless bl_render_batch is given one. */

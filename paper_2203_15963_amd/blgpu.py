@@ -174,6 +174,9 @@ def load():
     L.bl_render.argtypes = [vp, C.POINTER(bl_camera), C.POINTER(bl_spacetime), C.POINTER(bl_integrator),
                             vp, C.POINTER(bl_plasma), C.POINTER(bl_mode), vp, vp]
     L.bl_render.restype = C.c_int
+    L.bl_render_noalloc.argtypes = [vp, C.POINTER(bl_camera), C.POINTER(bl_spacetime), C.POINTER(bl_integrator),
+                                    vp, C.POINTER(bl_plasma), C.POINTER(bl_mode), vp, vp]
+    L.bl_render_noalloc.restype = C.c_int
     L.bl_render_batch.argtypes = [vp, i32, C.POINTER(bl_image_desc), C.POINTER(bl_integrator), vp,
                                   C.POINTER(bl_plasma), C.POINTER(bl_mode), C.POINTER(bl_tuning)]
     L.bl_render_batch.restype = C.c_int
@@ -371,6 +374,14 @@ class Context:
         c, s, g, p, m = camera(cam), spacetime(st), integrator(integ), plasma(pl), mode(precision, step_model)
         self._check(load().bl_render(self.handle, C.byref(c), C.byref(s), C.byref(g), grid.handle,
                                      C.byref(p), C.byref(m), _ptr(image), _ptr(aux)))
+        return image, aux
+
+    def render_noalloc(self, cam, st, integ, grid, pl, image, aux, precision=0, step_model=0):
+        """bl_render_noalloc: the render into caller-given outputs with every
+        workspace buffer taken from the library's static scratch array."""
+        c, s, g, p, m = camera(cam), spacetime(st), integrator(integ), plasma(pl), mode(precision, step_model)
+        self._check(load().bl_render_noalloc(self.handle, C.byref(c), C.byref(s), C.byref(g), grid.handle,
+                                             C.byref(p), C.byref(m), _ptr(image), _ptr(aux)))
         return image, aux
 
     def render_averages(self, cam, st, integ, grid, pl, precision=0, step_model=0):

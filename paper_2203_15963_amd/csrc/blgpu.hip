@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -927,20 +928,26 @@ __global__ void k_eval_samples(double a, int flat, DevGrid g, PlasmaParams pp, l
 }
 
 // ============================================================ host side
-struct bl_context {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    std::string err;
+// Scratch of the allocation-free render (bl_render_noalloc): one static
+// device array, which every GPU the library runs on holds (its own copy, at
+// its own address) until the process ends.  Host code must not pass the
+// array's name to a kernel or a copy (on the host it is only a stand-in):
+// the device address comes from hipGetSymbolAddress at context creation.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+constexpr long long kNoAllocMaxSteps = 4095;   // bounds the overflow kernel's private buffer
+constexpr int kNoAllocExtSlots = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device workspace of a render: grown on demand by ensure() (hipMalloc), or
+// carved from the library's static scratch array by the allocation-free entry
+// point, which swaps in an empty set for the duration of its call.
+struct RenderBuffers {
     // image descriptors of the current render; the host copies stay alive
     // until the upload that read them has completed (upload_done)
     ImgDev *d_imgs = nullptr;
     size_t imgs_bytes = 0;
     long long *d_ray0 = nullptr;
     size_t ray0_bytes = 0;
-    std::vector<ImgDev> h_imgs;
-    std::vector<long long> h_ray0;
-    hipEvent_t upload_done = nullptr;
-    bl_tuning tuning = {8, 8, 0, 4, 0, 0, 0};   // the autotuner's choice for the 1024^2 SMR image
     double *d_rec = nullptr;
     size_t rec_bytes = 0;
     double *d_meta = nullptr;
@@ -958,11 +965,32 @@ struct bl_context {
     size_t ovf_cap = 0;
     double *d_big = nullptr;
     size_t big_bytes = 0;
-    size_t ws_limit = (size_t)128 << 30;   // bytes of step records per chunk (set at creation)
     int *d_queue = nullptr;              // per-chunk work counters of the persistent kernels
     size_t queue_bytes = 0;
     char *d_ends = nullptr;              // polarized rays' end states, kRayEnd reals per ray slot
     size_t ends_bytes = 0;
+    CutParams *d_cuts = nullptr;         // device copy of the data cuts, uploaded with each render
+    size_t cuts_bytes = 0;
+};
+
+// Bump allocator over the static scratch array (allocation-free renders).
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+};
+
+struct bl_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    RenderBuffers rb;
+    Arena *arena = nullptr;              // set only during an allocation-free render
+    void *scratch = nullptr;             // this device's copy of the static scratch array
+    std::vector<ImgDev> h_imgs;
+    std::vector<long long> h_ray0;
+    hipEvent_t upload_done = nullptr;
+    bl_tuning tuning = {8, 8, 0, 4, 0, 0, 0};   // the autotuner's choice for the 1024^2 SMR image
+    size_t ws_limit = (size_t)128 << 30;   // bytes of step records per chunk (set at creation)
     int cus = 0;
     int blocks_tr[10] = {0};              // resident waves per CU of k_transfer<pol, R, batch>:
                                          // [4 batch + 2 pol + (R == float)]; [8 + (R == float)]:
@@ -973,7 +1001,6 @@ struct bl_context {
     bool has_step_model = false;
     bl_cuts cuts{};          // data cuts for the following renders (bl_set_cuts)
     bool has_cuts = false;
-    CutParams *d_cuts = nullptr;   // their device copy, uploaded with each render
     int *d_refine = nullptr;       // refinement flags of an adaptive level
     size_t refine_bytes = 0;
     // network training workspace
@@ -1201,47 +1228,27 @@ PlasmaParams plasma_params(const bl_context *ctx, const bl_plasma *plasma, const
     pp.th_per_pr = pp.mu * kMp / kMe;
     pp.gauss_per_b = kC * sqrt(4.0 * kPi * g.rho_unit);
     pp.cuts = ctx->has_cuts ? 1 : 0;
-    pp.cut = ctx->d_cuts;
+    pp.cut = ctx->rb.d_cuts;
     return pp;
 }
 
-// Device copy of the context's data cuts for the launches that follow on the
-// stream (the copy is ordered with them).
-bl_status upload_cuts(bl_context *ctx) {
-    if (!ctx->has_cuts) return BL_OK;
-    if (!ctx->d_cuts && hipMalloc((void **)&ctx->d_cuts, sizeof(CutParams)) != hipSuccess)
-        return fail(ctx, BL_E_OOM, "device allocation of the data cuts failed");
-    const bl_cuts &c = ctx->cuts;
-    CutParams h{};
-    const double *lims[8] = {c.rho, c.ne, c.p, c.theta_e, c.b, c.sigma, c.beta_inv, c.r};
-    for (int k = 0; k < 8; ++k) {
-        h.lo[k] = lims[k][0];
-        h.hi[k] = lims[k][1];
-        h.lo_f[k] = (float)h.lo[k];
-        h.hi_f[k] = (float)h.hi[k];
-    }
-    for (int i = 0; i < 3; ++i) {
-        h.x0[i] = c.plane_origin[i];
-        h.n[i] = c.plane_normal[i];
-    }
-    h.plane = c.plane;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->d_cuts, &h, sizeof(CutParams), hipMemcpyHostToDevice, ctx->stream));
-    // the host struct is a local: wait for the copy to have read it
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    return BL_OK;
-}
-
-// What the geodesic kernels store with each record for the transfer: the grid
-// box and piece length for the sampling decision, and the FP32-quartic layout
-// for the mixed form (whose transfer kernels read it).
-void record_layout(GeoParams &P, const DevGrid &g, const bl_integrator *in, bool mixed) {
-    for (int d = 0; d < 6; ++d) P.bb[d] = g.bb[d];
-    P.ds_max = in->ds_max;
-    P.rec_quart32 = mixed ? 1 : 0;
-}
-
+// A device buffer of at least need_bytes in *p (have: its current size).
 template <typename T>
 bl_status ensure(bl_context *ctx, T **p, size_t &have, size_t need_bytes) {
+    if (ctx->arena) {
+        // allocation-free render: the next 256-byte aligned piece of the
+        // static scratch array (never hipMalloc)
+        Arena &A = *ctx->arena;
+        const size_t off = (A.used + 255) & ~(size_t)255;
+        if (need_bytes > A.cap || off > A.cap - need_bytes)
+            return fail(ctx, BL_E_UNSUPPORTED,
+                        "the allocation-free render needs more than the " + std::to_string(A.cap) +
+                            " bytes of its static scratch: lower record_cap, max_steps or the image size");
+        *p = reinterpret_cast<T *>(A.base + off);
+        have = need_bytes;
+        A.used = off + need_bytes;
+        return BL_OK;
+    }
     if (have >= need_bytes && *p) return BL_OK;
     if (*p) {
         HIPCHK(ctx, hipFree(*p));
@@ -1258,6 +1265,42 @@ bl_status ensure(bl_context *ctx, T **p, size_t &have, size_t need_bytes) {
     have = need_bytes;
     return BL_OK;
 }
+
+// Device copy of the context's data cuts for the launches that follow on the
+// stream (the copy is ordered with them).
+bl_status upload_cuts(bl_context *ctx) {
+    if (!ctx->has_cuts) return BL_OK;
+    bl_status s;
+    if ((s = ensure(ctx, &ctx->rb.d_cuts, ctx->rb.cuts_bytes, sizeof(CutParams))) != BL_OK) return s;
+    const bl_cuts &c = ctx->cuts;
+    CutParams h{};
+    const double *lims[8] = {c.rho, c.ne, c.p, c.theta_e, c.b, c.sigma, c.beta_inv, c.r};
+    for (int k = 0; k < 8; ++k) {
+        h.lo[k] = lims[k][0];
+        h.hi[k] = lims[k][1];
+        h.lo_f[k] = (float)h.lo[k];
+        h.hi_f[k] = (float)h.hi[k];
+    }
+    for (int i = 0; i < 3; ++i) {
+        h.x0[i] = c.plane_origin[i];
+        h.n[i] = c.plane_normal[i];
+    }
+    h.plane = c.plane;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->rb.d_cuts, &h, sizeof(CutParams), hipMemcpyHostToDevice, ctx->stream));
+    // the host struct is a local: wait for the copy to have read it
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return BL_OK;
+}
+
+// What the geodesic kernels store with each record for the transfer: the grid
+// box and piece length for the sampling decision, and the FP32-quartic layout
+// for the mixed form (whose transfer kernels read it).
+void record_layout(GeoParams &P, const DevGrid &g, const bl_integrator *in, bool mixed) {
+    for (int d = 0; d < 6; ++d) P.bb[d] = g.bb[d];
+    P.ds_max = in->ds_max;
+    P.rec_quart32 = mixed ? 1 : 0;
+}
+
 
 // Event pair around one launch when timing is on.
 struct TimedLaunch {
@@ -1331,12 +1374,19 @@ bl_status upload_images(bl_context *ctx, int n, const bl_camera *const *cams, co
                         double *const *images, double *const *auxs, const bl_tuning &t, Batch &B,
                         long long &total, bool shared_rays = false, double *const *avgs = nullptr,
                         const int *sub = nullptr) {
-    std::vector<int> perm(n);
-    for (int k = 0; k < n; ++k) perm[k] = k;
-    if (t.order == 1)
-        std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return cams[x]->n > cams[y]->n; });
-    if (ctx->upload_done) HIPCHK(ctx, hipEventSynchronize(ctx->upload_done));
-    else HIPCHK(ctx, hipEventCreateWithFlags(&ctx->upload_done, hipEventDisableTiming));
+    // placement order (no host allocation for a single image: the context
+    // reserved room for one descriptor at creation)
+    int perm1 = 0;
+    std::vector<int> permv;
+    int *perm = &perm1;
+    if (n > 1) {
+        permv.resize(n);
+        for (int k = 0; k < n; ++k) permv[k] = k;
+        if (t.order == 1)
+            std::stable_sort(permv.begin(), permv.end(), [&](int x, int y) { return cams[x]->n > cams[y]->n; });
+        perm = permv.data();
+    }
+    HIPCHK(ctx, hipEventSynchronize(ctx->upload_done));
     ctx->h_imgs.assign(n, ImgDev{});
     ctx->h_ray0.assign(n, 0);
     long long r = 0;
@@ -1363,15 +1413,15 @@ bl_status upload_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     }
     if (r >= (1LL << 31)) return fail(ctx, BL_E_UNSUPPORTED, "more than 2^31 - 1 ray ids in one render");
     bl_status s;
-    if ((s = ensure(ctx, &ctx->d_imgs, ctx->imgs_bytes, (size_t)n * sizeof(ImgDev))) != BL_OK) return s;
-    if ((s = ensure(ctx, &ctx->d_ray0, ctx->ray0_bytes, (size_t)n * sizeof(long long))) != BL_OK) return s;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->d_imgs, ctx->h_imgs.data(), (size_t)n * sizeof(ImgDev), hipMemcpyHostToDevice,
+    if ((s = ensure(ctx, &ctx->rb.d_imgs, ctx->rb.imgs_bytes, (size_t)n * sizeof(ImgDev))) != BL_OK) return s;
+    if ((s = ensure(ctx, &ctx->rb.d_ray0, ctx->rb.ray0_bytes, (size_t)n * sizeof(long long))) != BL_OK) return s;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->rb.d_imgs, ctx->h_imgs.data(), (size_t)n * sizeof(ImgDev), hipMemcpyHostToDevice,
                                ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(ctx->d_ray0, ctx->h_ray0.data(), (size_t)n * sizeof(long long),
+    HIPCHK(ctx, hipMemcpyAsync(ctx->rb.d_ray0, ctx->h_ray0.data(), (size_t)n * sizeof(long long),
                                hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipEventRecord(ctx->upload_done, ctx->stream));
-    B.imgs = ctx->d_imgs;
-    B.ray0 = ctx->d_ray0;
+    B.imgs = ctx->rb.d_imgs;
+    B.ray0 = ctx->rb.d_ray0;
     B.n_img = n;   // every entry gets its camera frame
     B.tw = t.tile_w;
     B.th = t.tile_h;
@@ -1395,19 +1445,19 @@ template <bool POL, typename R, bool BATCH, bool CUTS, bool AVG = false>
 void launch_transfer(bl_context *ctx, dim3 grd, const GeoParams &P, const Batch &B, const DevGrid &g,
                      const PlasmaParams &pp, const TransferParams &tp, long long start, int count, int refill,
                      int *q) {
-    R *ends = reinterpret_cast<R *>(ctx->d_ends);
+    R *ends = reinterpret_cast<R *>(ctx->rb.d_ends);
     hipLaunchKernelGGL((k_transfer<POL, R, BATCH, CUTS, AVG>), grd, dim3(64), 0, ctx->stream, P, B, g, pp, tp, start, count,
-                       refill, ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_order, ctx->ext, q, ends);
+                       refill, ctx->rb.d_rec, ctx->rb.d_meta, ctx->rb.d_nacc, ctx->rb.d_order, ctx->rb.ext, q, ends);
     if (POL)
         hipLaunchKernelGGL((k_finish<R, BATCH>), dim3((count + 63) / 64), dim3(64), 0, ctx->stream, P, B, start, count,
-                           ctx->d_rec, ctx->d_nacc, ctx->ext, (const R *)ends);
+                           ctx->rb.d_rec, ctx->rb.d_nacc, ctx->rb.ext, (const R *)ends);
 }
 
 template <bool POL, typename R, bool CUTS, bool AVG = false>
 void launch_overflow(bl_context *ctx, const GeoParams &P, const Batch &B, const DevGrid &g, const PlasmaParams &pp,
                      const TransferParams &tp, int big_cap) {
-    hipLaunchKernelGGL((k_overflow<POL, R, CUTS, AVG>), dim3(1), dim3(64), 0, ctx->stream, P, B, g, pp, tp, ctx->d_ovf_count,
-                       ctx->d_ovf_list, ctx->d_big, big_cap);
+    hipLaunchKernelGGL((k_overflow<POL, R, CUTS, AVG>), dim3(1), dim3(64), 0, ctx->stream, P, B, g, pp, tp, ctx->rb.d_ovf_count,
+                       ctx->rb.d_ovf_list, ctx->rb.d_big, big_cap);
 }
 
 // The render of n images (a batch of one for bl_render).  With batch = false
@@ -1417,10 +1467,45 @@ void launch_overflow(bl_context *ctx, const GeoParams &P, const Batch &B, const 
 // one camera at the frequencies of a multi-frequency render: the geodesics
 // are traced once per chunk and the transfer runs once per frequency on the
 // same step records, each writing its own image and aux.
+// The overflow kernel over the rays queued so far, once per frequency: rays
+// longer than the extension slots are traced again for each.
+bl_status overflow_all(bl_context *ctx, const Batch &B, const GeoParams &P, const bl_grid *grid,
+                       const PlasmaParams &pp, const TransferParams &tp, const bl_camera *const *cams, int n_tr,
+                       int kidx, int big_cap) {
+    for (int f = 0; f < n_tr; ++f) {
+        Batch Bf = B;
+        Bf.imgs = B.imgs + f;
+        TransferParams tpf = tp;
+        tpf.nu_cam = cams[f]->nu_hz;
+        TimedLaunch tl(ctx, BL_K_OVERFLOW);
+        switch ((kidx & 3) + (pp.cuts ? 4 : 0)) {
+        case 0: launch_overflow<false, double, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 1: launch_overflow<false, float, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 2: launch_overflow<true, double, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 3: launch_overflow<true, float, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 4: launch_overflow<false, double, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 5: launch_overflow<false, float, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 6: launch_overflow<true, double, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        default: launch_overflow<true, float, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        }
+        HIPCHK(ctx, hipGetLastError());
+    }
+    return BL_OK;
+}
+
+// Options of the allocation-free render: extension slots per chunk, and the
+// overflow kernel run after every chunk (so its ray list holds one chunk's
+// rays, not the whole image's).
+struct RenderOpts {
+    int ext_slots = 1024;
+    bool per_chunk_overflow = false;
+};
+
 bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, const bl_spacetime *const *sts,
                         double *const *images, double *const *auxs, const bl_integrator *integ, const bl_grid *grid,
                         const bl_plasma *plasma, const bl_mode *mode, const bl_tuning &t, bool batch,
-                        int n_freq = 0, double *avg = nullptr, const int *sub = nullptr) {
+                        int n_freq = 0, double *avg = nullptr, const int *sub = nullptr,
+                        const RenderOpts &opt = RenderOpts()) {
     bl_status s;
     if ((s = check_integrator(ctx, integ)) != BL_OK || (s = check_tuning(ctx, &t)) != BL_OK) return s;
     if (n_freq > 0 && (n != 1 || batch)) return fail(ctx, BL_E_INVALID_ARG, "a multi-frequency render has one image");
@@ -1456,14 +1541,14 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     long long chunk = t.chunk_rays > 0 ? t.chunk_rays : (long long)(ctx->ws_limit / rec_per_ray);
     chunk = std::max(64LL, chunk - chunk % 64);
     chunk = std::min(chunk, (total + 63) / 64 * 64);
-    if ((s = ensure(ctx, &ctx->d_rec, ctx->rec_bytes, (size_t)chunk * rec_per_ray)) != BL_OK) return s;
-    size_t have_meta = ctx->slot_cap * 2 * sizeof(double), have_nacc = ctx->slot_cap * sizeof(int);
-    if ((s = ensure(ctx, &ctx->d_meta, have_meta, (size_t)chunk * 2 * sizeof(double))) != BL_OK) return s;
-    if ((s = ensure(ctx, &ctx->d_nacc, have_nacc, (size_t)chunk * sizeof(int))) != BL_OK) return s;
-    ctx->slot_cap = std::min(have_meta / (2 * sizeof(double)), have_nacc / sizeof(int));
-    if ((s = ensure(ctx, &ctx->d_order, ctx->order_bytes, (size_t)chunk * sizeof(int))) != BL_OK) return s;
-    if ((s = ensure(ctx, &ctx->d_work, ctx->work_bytes, (size_t)chunk * sizeof(int))) != BL_OK) return s;
-    if ((s = ensure(ctx, &ctx->d_ends, ctx->ends_bytes,
+    if ((s = ensure(ctx, &ctx->rb.d_rec, ctx->rb.rec_bytes, (size_t)chunk * rec_per_ray)) != BL_OK) return s;
+    size_t have_meta = ctx->rb.slot_cap * 2 * sizeof(double), have_nacc = ctx->rb.slot_cap * sizeof(int);
+    if ((s = ensure(ctx, &ctx->rb.d_meta, have_meta, (size_t)chunk * 2 * sizeof(double))) != BL_OK) return s;
+    if ((s = ensure(ctx, &ctx->rb.d_nacc, have_nacc, (size_t)chunk * sizeof(int))) != BL_OK) return s;
+    ctx->rb.slot_cap = std::min(have_meta / (2 * sizeof(double)), have_nacc / sizeof(int));
+    if ((s = ensure(ctx, &ctx->rb.d_order, ctx->rb.order_bytes, (size_t)chunk * sizeof(int))) != BL_OK) return s;
+    if ((s = ensure(ctx, &ctx->rb.d_work, ctx->rb.work_bytes, (size_t)chunk * sizeof(int))) != BL_OK) return s;
+    if ((s = ensure(ctx, &ctx->rb.d_ends, ctx->rb.ends_bytes,
                     (size_t)chunk * kRayEnd * (mixed ? sizeof(float) : sizeof(double)))) != BL_OK)
         return s;
     // extension slots for rays longer than a record slot: 1024 per chunk of
@@ -1471,30 +1556,32 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     // a ray that finds no free extension slot is finished by the single-wave
     // overflow kernel
     {
-        ExtQueue &X = ctx->ext;
+        ExtQueue &X = ctx->rb.ext;
         const int cap_rec = (int)std::min<long long>(2048, P.max_steps + 1);
-        X.cap_rays = cap_rec > P.cap ? 1024 : 0;
+        X.cap_rays = cap_rec > P.cap ? opt.ext_slots : 0;
         X.cap_rec = cap_rec;
         size_t have = X.count ? sizeof(int) : 0;
         if ((s = ensure(ctx, &X.count, have, sizeof(int))) != BL_OK) return s;
-        if ((s = ensure(ctx, &X.of, ctx->ext_of_bytes, (size_t)chunk * sizeof(int))) != BL_OK) return s;
+        if ((s = ensure(ctx, &X.of, ctx->rb.ext_of_bytes, (size_t)chunk * sizeof(int))) != BL_OK) return s;
         if (X.cap_rays > 0 &&
-            (s = ensure(ctx, &X.rec, ctx->ext_rec_bytes,
+            (s = ensure(ctx, &X.rec, ctx->rb.ext_rec_bytes,
                         (size_t)X.cap_rays * X.cap_rec * kRecDoubles * sizeof(double))) != BL_OK)
             return s;
     }
     {
-        size_t have_hist = ctx->d_hist ? (size_t)kOrderBins * sizeof(int) : 0;
-        if ((s = ensure(ctx, &ctx->d_hist, have_hist, (size_t)kOrderBins * sizeof(int))) != BL_OK) return s;
+        size_t have_hist = ctx->rb.d_hist ? (size_t)kOrderBins * sizeof(int) : 0;
+        if ((s = ensure(ctx, &ctx->rb.d_hist, have_hist, (size_t)kOrderBins * sizeof(int))) != BL_OK) return s;
     }
     size_t one = sizeof(int);
-    size_t have_cnt = ctx->d_ovf_count ? one : 0;
-    if ((s = ensure(ctx, &ctx->d_ovf_count, have_cnt, one)) != BL_OK) return s;
-    if ((s = ensure(ctx, &ctx->d_ovf_list, ctx->ovf_cap, (size_t)total * sizeof(int))) != BL_OK) return s;
-    int big_cap = (int)std::min<long long>(P.max_steps + 1, 1LL << 30);
-    if ((s = ensure(ctx, &ctx->d_big, ctx->big_bytes, (size_t)64 * big_cap * kRecDoubles * sizeof(double))) != BL_OK)
+    size_t have_cnt = ctx->rb.d_ovf_count ? one : 0;
+    if ((s = ensure(ctx, &ctx->rb.d_ovf_count, have_cnt, one)) != BL_OK) return s;
+    if ((s = ensure(ctx, &ctx->rb.d_ovf_list, ctx->rb.ovf_cap,
+                    (size_t)(opt.per_chunk_overflow ? chunk : total) * sizeof(int))) != BL_OK)
         return s;
-    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, ctx->d_ovf_count, 0, 1);
+    int big_cap = (int)std::min<long long>(P.max_steps + 1, 1LL << 30);
+    if ((s = ensure(ctx, &ctx->rb.d_big, ctx->rb.big_bytes, (size_t)64 * big_cap * kRecDoubles * sizeof(double))) != BL_OK)
+        return s;
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, ctx->rb.d_ovf_count, 0, 1);
     HIPCHK(ctx, hipGetLastError());
     if ((s = upload_cuts(ctx)) != BL_OK) return s;
     const PlasmaParams pp = plasma_params(ctx, plasma, grid->g, sts[0]->mass_msun);
@@ -1504,8 +1591,8 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     tp.nu_cam = cams[0]->nu_hz;
     long long nchunk = (total + chunk - 1) / chunk;
     const long long nqueue = 2 * nchunk * n_q;   // one counter (padded to two ints) per transfer launch
-    if ((s = ensure(ctx, &ctx->d_queue, ctx->queue_bytes, (size_t)nqueue * sizeof(int))) != BL_OK) return s;
-    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((nqueue + 63) / 64)), dim3(64), 0, ctx->stream, ctx->d_queue, 0,
+    if ((s = ensure(ctx, &ctx->rb.d_queue, ctx->rb.queue_bytes, (size_t)nqueue * sizeof(int))) != BL_OK) return s;
+    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((nqueue + 63) / 64)), dim3(64), 0, ctx->stream, ctx->rb.d_queue, 0,
                        (int)nqueue);
     HIPCHK(ctx, hipGetLastError());
     const int kidx = 4 * (batch ? 1 : 0) + 2 * pp.polarized + (mixed ? 1 : 0);
@@ -1516,29 +1603,31 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     for (long long start = 0; start < total; start += chunk, ++ichunk) {
         int count = (int)std::min(chunk, total - start);
         dim3 grd((count + 63) / 64), blk(64);
-        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, ctx->ext.count, 0, 1);
-        hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, ctx->stream, ctx->ext.of, -1,
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, ctx->rb.ext.count, 0, 1);
+        hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, ctx->stream, ctx->rb.ext.of, -1,
                            count);
+        if (opt.per_chunk_overflow && start > 0)
+            hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, ctx->rb.d_ovf_count, 0, 1);
         {
             TimedLaunch tl(ctx, BL_K_GEODESIC);
             if (learned) {
                 dim3 lg((count + 255) / 256), lb(256);
                 if (batch)
                     hipLaunchKernelGGL((k_geodesic_learned<true, true>), lg, lb, 0, ctx->stream, P, B, start, count,
-                                       ctx->d_step_pk, ctx->d_step_tail, ctx->d_rec, ctx->d_meta, ctx->d_nacc,
-                                       ctx->d_work, ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list);
+                                       ctx->d_step_pk, ctx->d_step_tail, ctx->rb.d_rec, ctx->rb.d_meta, ctx->rb.d_nacc,
+                                       ctx->rb.d_work, ctx->rb.ext, ctx->rb.d_ovf_count, ctx->rb.d_ovf_list);
                 else
                     hipLaunchKernelGGL((k_geodesic_learned<true, false>), lg, lb, 0, ctx->stream, P, B, start, count,
-                                       ctx->d_step_pk, ctx->d_step_tail, ctx->d_rec, ctx->d_meta, ctx->d_nacc,
-                                       ctx->d_work, ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list);
+                                       ctx->d_step_pk, ctx->d_step_tail, ctx->rb.d_rec, ctx->rb.d_meta, ctx->rb.d_nacc,
+                                       ctx->rb.d_work, ctx->rb.ext, ctx->rb.d_ovf_count, ctx->rb.d_ovf_list);
             } else if (batch) {
-                hipLaunchKernelGGL((k_geodesic<true, true>), grd, blk, 0, ctx->stream, P, B, start, count, ctx->d_rec,
-                                   ctx->d_meta, ctx->d_nacc, ctx->d_work, ctx->ext, ctx->d_ovf_count, ctx->d_ovf_list,
+                hipLaunchKernelGGL((k_geodesic<true, true>), grd, blk, 0, ctx->stream, P, B, start, count, ctx->rb.d_rec,
+                                   ctx->rb.d_meta, ctx->rb.d_nacc, ctx->rb.d_work, ctx->rb.ext, ctx->rb.d_ovf_count, ctx->rb.d_ovf_list,
                                    nullptr);
             } else {
                 hipLaunchKernelGGL((k_geodesic<true, false>), grd, blk, 0, ctx->stream, P, B, start, count,
-                                   ctx->d_rec, ctx->d_meta, ctx->d_nacc, ctx->d_work, ctx->ext, ctx->d_ovf_count,
-                                   ctx->d_ovf_list,
+                                   ctx->rb.d_rec, ctx->rb.d_meta, ctx->rb.d_nacc, ctx->rb.d_work, ctx->rb.ext, ctx->rb.d_ovf_count,
+                                   ctx->rb.d_ovf_list,
                                    nullptr);
             }
         }
@@ -1546,11 +1635,11 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         {
             TimedLaunch tl(ctx, BL_K_SETUP);
             const unsigned nb = (unsigned)((count + 255) / 256);
-            hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(kOrderBins), 0, ctx->stream, ctx->d_hist, 0, kOrderBins);
-            hipLaunchKernelGGL(k_order_hist, dim3(nb), dim3(256), 0, ctx->stream, ctx->d_work, count, ctx->d_hist);
-            hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderBins), 0, ctx->stream, ctx->d_hist);
-            hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(256), 0, ctx->stream, ctx->d_work, count, ctx->d_hist,
-                               ctx->d_order);
+            hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(kOrderBins), 0, ctx->stream, ctx->rb.d_hist, 0, kOrderBins);
+            hipLaunchKernelGGL(k_order_hist, dim3(nb), dim3(256), 0, ctx->stream, ctx->rb.d_work, count, ctx->rb.d_hist);
+            hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderBins), 0, ctx->stream, ctx->rb.d_hist);
+            hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(256), 0, ctx->stream, ctx->rb.d_work, count, ctx->rb.d_hist,
+                               ctx->rb.d_order);
         }
         HIPCHK(ctx, hipGetLastError());
         for (int f = 0; f < n_tr; ++f) {
@@ -1561,7 +1650,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
             TransferParams tpf = tp;
             tpf.nu_cam = cams[f]->nu_hz;
             TimedLaunch tl(ctx, BL_K_TRANSFER);
-            int *q = ctx->d_queue + 2 * (ichunk * n_q + f);
+            int *q = ctx->rb.d_queue + 2 * (ichunk * n_q + f);
             dim3 pg(std::min<int>(grd.x, resident));
             const int kc = kidx + (pp.cuts ? 8 : 0);
             switch (kc) {
@@ -1590,7 +1679,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
             PlasmaParams pa = pp;
             pa.polarized = 0;
             TimedLaunch tl(ctx, BL_K_TRANSFER);
-            int *q = ctx->d_queue + 2 * (ichunk * n_q + n_tr);
+            int *q = ctx->rb.d_queue + 2 * (ichunk * n_q + n_tr);
             dim3 pg(std::min<int>(grd.x, ctx->blocks_tr[mixed ? 9 : 8] * ctx->cus));
             switch ((mixed ? 1 : 0) + (pp.cuts ? 2 : 0)) {
             case 0: launch_transfer<false, double, false, false, true>(ctx, pg, P, B, grid->g, pa, tp, start, count, t.refill_min, q); break;
@@ -1600,6 +1689,8 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
             }
             HIPCHK(ctx, hipGetLastError());
         }
+        if (opt.per_chunk_overflow)
+            if ((s = overflow_all(ctx, B, P, grid, pp, tp, cams, n_tr, kidx, big_cap)) != BL_OK) return s;
     }
     if (avg) {
         PlasmaParams pa = pp;
@@ -1613,25 +1704,8 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         }
         HIPCHK(ctx, hipGetLastError());
     }
-    for (int f = 0; f < n_tr; ++f) {
-        // rays longer than the extension slots are traced again per frequency
-        Batch Bf = B;
-        Bf.imgs = B.imgs + f;
-        TransferParams tpf = tp;
-        tpf.nu_cam = cams[f]->nu_hz;
-        TimedLaunch tl(ctx, BL_K_OVERFLOW);
-        switch ((kidx & 3) + (pp.cuts ? 4 : 0)) {
-        case 0: launch_overflow<false, double, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
-        case 1: launch_overflow<false, float, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
-        case 2: launch_overflow<true, double, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
-        case 3: launch_overflow<true, float, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
-        case 4: launch_overflow<false, double, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
-        case 5: launch_overflow<false, float, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
-        case 6: launch_overflow<true, double, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
-        default: launch_overflow<true, float, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
-        }
-        HIPCHK(ctx, hipGetLastError());
-    }
+    if (!opt.per_chunk_overflow)
+        if ((s = overflow_all(ctx, B, P, grid, pp, tp, cams, n_tr, kidx, big_cap)) != BL_OK) return s;
     if (n_freq > 1) {
         // the geodesic maps (dt, s, lambda and n_acc, n_rej, status) were
         // written into the first frequency's aux
@@ -1786,6 +1860,35 @@ bl_status bl_create(int device, void *hip_stream, bl_context **out) {
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
         ctx->ws_limit = std::max<size_t>((size_t)64 << 20, std::min(ctx->ws_limit, free_b / 2));
+    // what every render reuses: the upload event and room for one image
+    // descriptor on the host (so that a single-image render allocates nothing
+    // on the host once the context exists)
+    if (hipEventCreateWithFlags(&ctx->upload_done, hipEventDisableTiming) != hipSuccess) {
+        delete ctx;
+        return BL_E_DEVICE;
+    }
+    ctx->h_imgs.reserve(1);
+    ctx->h_ray0.reserve(1);
+    // this device's address of the static scratch array, looked up once per
+    // device with the device current (a failure leaves it NULL: only the
+    // allocation-free render needs it, and it reports the failure)
+    {
+        static std::mutex mu;
+        static std::vector<void *> addr;
+        static std::vector<char> done;
+        std::lock_guard<std::mutex> lock(mu);
+        if ((int)addr.size() < ndev) {
+            addr.resize(ndev, nullptr);
+            done.resize(ndev, 0);
+        }
+        if (!done[device]) {
+            void *ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess) addr[device] = ptr;
+            else (void)hipGetLastError();
+            done[device] = 1;
+        }
+        ctx->scratch = addr[device];
+    }
     *out = ctx;
     return BL_OK;
 }
@@ -1798,7 +1901,7 @@ void bl_destroy(bl_context *ctx) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
     }
-    (void)hipFree(ctx->d_imgs);
+    (void)hipFree(ctx->rb.d_imgs);
     (void)hipFree(ctx->d_step_pk);
     (void)hipFree(ctx->d_step_tail);
     (void)hipFree(ctx->d_mlp_pk);
@@ -1812,23 +1915,23 @@ void bl_destroy(bl_context *ctx) {
     (void)hipFree(ctx->d_mlp_stats);
     (void)hipFree(ctx->d_mlp_rows);
     (void)hipFree(ctx->d_log_count);
-    (void)hipFree(ctx->d_ray0);
+    (void)hipFree(ctx->rb.d_ray0);
     if (ctx->upload_done) (void)hipEventDestroy(ctx->upload_done);
-    (void)hipFree(ctx->d_rec);
-    (void)hipFree(ctx->d_meta);
-    (void)hipFree(ctx->d_nacc);
-    (void)hipFree(ctx->d_work);
-    (void)hipFree(ctx->d_order);
-    (void)hipFree(ctx->ext.count);
-    (void)hipFree(ctx->ext.of);
-    (void)hipFree(ctx->ext.rec);
-    (void)hipFree(ctx->d_hist);
-    (void)hipFree(ctx->d_ovf_count);
-    (void)hipFree(ctx->d_ovf_list);
-    (void)hipFree(ctx->d_big);
-    (void)hipFree(ctx->d_queue);
-    (void)hipFree(ctx->d_ends);
-    (void)hipFree(ctx->d_cuts);
+    (void)hipFree(ctx->rb.d_rec);
+    (void)hipFree(ctx->rb.d_meta);
+    (void)hipFree(ctx->rb.d_nacc);
+    (void)hipFree(ctx->rb.d_work);
+    (void)hipFree(ctx->rb.d_order);
+    (void)hipFree(ctx->rb.ext.count);
+    (void)hipFree(ctx->rb.ext.of);
+    (void)hipFree(ctx->rb.ext.rec);
+    (void)hipFree(ctx->rb.d_hist);
+    (void)hipFree(ctx->rb.d_ovf_count);
+    (void)hipFree(ctx->rb.d_ovf_list);
+    (void)hipFree(ctx->rb.d_big);
+    (void)hipFree(ctx->rb.d_queue);
+    (void)hipFree(ctx->rb.d_ends);
+    (void)hipFree(ctx->rb.d_cuts);
     (void)hipFree(ctx->d_refine);
     delete ctx;
 }
@@ -1942,7 +2045,7 @@ bl_status bl_camera_rays(bl_context *ctx, const bl_camera *cam, const bl_spaceti
     long long total = 0;
     if ((s = upload_one(ctx, cam, st, nullptr, nullptr, t, B, total)) != BL_OK) return s;
     long long NN = (long long)cam->n * cam->n;
-    hipLaunchKernelGGL(k_camera_rays, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, ctx->stream, ctx->d_imgs,
+    hipLaunchKernelGGL(k_camera_rays, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, ctx->stream, ctx->rb.d_imgs,
                        state_out, norm_out);
     HIPCHK(ctx, hipGetLastError());
     return BL_OK;
@@ -1980,6 +2083,63 @@ bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *s
     if (!ctx) return BL_E_INVALID_ARG;
     if (!cam || !st) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
     return render_images(ctx, 1, &cam, &st, &image_out, &aux_out, integ, grid, plasma, mode, ctx->tuning, false);
+}
+
+bl_status bl_render_noalloc(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
+                            const bl_integrator *integ, const bl_grid *grid, const bl_plasma *plasma,
+                            const bl_mode *mode, double *image_out, double *aux_out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    if (!cam || !st || !integ || !grid || !plasma) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
+    if (!ctx->scratch) return fail(ctx, BL_E_DEVICE, "the static scratch array has no device address on this device");
+    bl_status s;
+    if ((s = check_camera(ctx, cam)) != BL_OK || (s = check_integrator(ctx, integ)) != BL_OK) return s;
+    if (integ->max_steps > kNoAllocMaxSteps)
+        return fail(ctx, BL_E_INVALID_ARG,
+                    "the allocation-free render takes max_steps <= " + std::to_string(kNoAllocMaxSteps));
+    const bool mixed = mode && mode->precision == 1;
+    // every buffer the render needs, for a chunk of `chunk` rays: per ray the
+    // record slot, order key, queue entry, end state and overflow entry; fixed:
+    // the image descriptor, extension slots, sort bins, overflow buffer,
+    // queue counters (two ints per chunk) and the cut limits, each rounded up
+    // to 256 bytes
+    GeoParams P = geo_params(cam, st, integ);
+    const size_t rec_per_ray = (size_t)P.cap * kRecDoubles * sizeof(double);
+    const size_t per_ray = rec_per_ray + 2 * sizeof(double) + 5 * sizeof(int) +
+                           (size_t)kRayEnd * (mixed ? sizeof(float) : sizeof(double));
+    const long long cap_rec = std::min<long long>(2048, P.max_steps + 1);
+    const long long big_cap = P.max_steps + 1;
+    const long long total = image_rays(cam->n, ctx->tuning);
+    const size_t fixed = 20 * 256 + sizeof(ImgDev) + sizeof(long long) + sizeof(int) +
+                         (cap_rec > P.cap ? (size_t)kNoAllocExtSlots * cap_rec * kRecDoubles * sizeof(double) : 0) +
+                         (size_t)kOrderBins * sizeof(int) + sizeof(int) +
+                         (size_t)64 * big_cap * kRecDoubles * sizeof(double) + sizeof(CutParams) +
+                         (size_t)2 * ((total + 63) / 64 + 1) * sizeof(int);
+    if (fixed + 64 * per_ray > kScratchBytes)
+        return fail(ctx, BL_E_UNSUPPORTED,
+                    "the allocation-free render's scratch (" + std::to_string(kScratchBytes) +
+                        " bytes) does not hold one wave of rays: lower record_cap or max_steps");
+    long long chunk = (long long)((kScratchBytes - fixed) / per_ray);
+    chunk = std::min(chunk - chunk % 64, (total + 63) / 64 * 64);
+    bl_tuning t = ctx->tuning;
+    t.chunk_rays = chunk;
+    RenderOpts opt;
+    opt.ext_slots = kNoAllocExtSlots;
+    opt.per_chunk_overflow = true;
+    // swap in an empty buffer set carved from the scratch; no timing events
+    Arena arena;
+    arena.base = static_cast<char *>(ctx->scratch);
+    arena.cap = kScratchBytes;
+    RenderBuffers saved = ctx->rb;
+    const bool prof = ctx->prof;
+    ctx->rb = RenderBuffers{};
+    ctx->arena = &arena;
+    ctx->prof = false;
+    s = render_images(ctx, 1, &cam, &st, &image_out, &aux_out, integ, grid, plasma, mode, t, false, 0, nullptr,
+                      nullptr, opt);
+    ctx->rb = saved;
+    ctx->arena = nullptr;
+    ctx->prof = prof;
+    return s;
 }
 
 bl_status bl_render_averages(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,

@@ -1,0 +1,103 @@
+"""The allocation-free render (bl_render_noalloc) through the C ABI against
+bl_render on the same inputs: every workspace buffer comes from the library's
+static scratch array, the image is processed in small chunks with 64
+extension slots each, and the overflow kernel runs after each chunk.  The
+geodesics are the same kernels' (step counts, statuses and the geodesic maps
+equal bit for bit); a ray that the smaller extension capacity sends to the
+overflow kernel is transferred by its one-ray-per-lane loop instead of the
+persistent walk, the same arithmetic in another operation order, so images
+agree to rounding: E_pix <= 1e-12 in FP64 and <= 2e-5 in the mixed form
+(whose bar against the FP64 oracle is 1e-4).  Two calls in a row, the second
+smaller; the call leaves the device's free memory unchanged."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-noalloc]", *a, flush=True)
+    sys.stdout.flush()
+
+
+_GRIDS = {}
+
+
+def _grid(w, f32=False):
+    from paper_2203_15963_amd import synth
+    key = (repr(sorted(w["grid_args"].items())), f32)
+    if key not in _GRIDS:
+        g = synth.make_grid(w["grid_args"])
+        _GRIDS[key] = dict(g, prims=g["prims"].astype(np.float32)) if f32 else g
+    return _GRIDS[key]
+
+
+def _case(name, n, precision, **integ):
+    from paper_2203_15963_amd import synth
+    w = synth.workload(name, n=n)
+    w["integrator"].update(max_steps=4095, **integ)
+    return w, precision
+
+
+def test_noalloc_render_equals_bl_render():
+    from paper_2203_15963_amd import blgpu
+    blgpu.load()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ref_ctx = blgpu.Context(0)
+    na_ctx = blgpu.Context(0)
+    cases = [
+        # polarized FP64 with short record slots: rays move to the (few)
+        # extension slots or, beyond them, to the per-chunk overflow kernel
+        _case("c2_256_pol", 40, 0, record_cap=24),
+        # the benchmark image at full size, mixed precision, FP32 grid
+        _case("c3_1024_smr", 1024, 1),
+        # then a smaller one: unpolarized, mixed
+        _case("c1_64_unpol", 12, 1),
+    ]
+    for w, precision in cases:
+        n = int(w["camera"]["n"])
+        f32 = precision == 1 and w["grid_args"]["kind"] == "smr"
+        g = _grid(w, f32)
+        args = (w["camera"], w["spacetime"], w["integrator"])
+        _say("case", w["grid_args"]["kind"], n, "precision", precision, "record_cap",
+             w["integrator"].get("record_cap", 0))
+        i_ref, a_ref = ref_ctx.render(*args, ref_ctx.grid(g), w["plasma"], precision=precision)
+        gg = na_ctx.grid(g)
+        img = torch.full((4, n, n), float("nan"), dtype=torch.float64, device="cuda")
+        aux = torch.full((blgpu.NAUX, n, n), float("nan"), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        free_before = torch.cuda.mem_get_info()[0]
+        na_ctx.render_noalloc(*args, gg, w["plasma"], img, aux, precision=precision)
+        torch.cuda.synchronize()
+        free_after = torch.cuda.mem_get_info()[0]
+        long_rays = int((aux[5] + 2 > (w["integrator"].get("record_cap", 0) or 512)).sum())
+        I = i_ref[0].abs()
+        den = torch.clamp(I, min=1e-3 * float(I.max()))
+        ep = float(((img - i_ref).abs() / den).max())
+        _say("E_pix vs bl_render", ep, "equal image", bool(torch.equal(img, i_ref)),
+             "equal geodesic maps and counts", bool(torch.equal(aux[[0, 1, 2, 5, 6, 7, 8, 9]],
+                                                                a_ref[[0, 1, 2, 5, 6, 7, 8, 9]])),
+             "rays beyond the record slot", long_rays, "free memory change", free_before - free_after)
+        assert torch.equal(aux[[0, 1, 2, 5, 6, 7, 8, 9]], a_ref[[0, 1, 2, 5, 6, 7, 8, 9]])
+        tol = 1e-12 if precision == 0 else 2e-5
+        assert ep <= tol
+        for q in (3, 4):   # optical depth and integrated emissivity
+            assert float((aux[q] - a_ref[q]).abs().max()) <= tol * float(a_ref[q].abs().max())
+        # the call itself took no device memory (runtime bookkeeping aside)
+        assert free_before - free_after <= (4 << 20)
+        del img, aux
+    # a step cap beyond the scratch's overflow buffer is refused
+    w, _ = _case("c1_64_unpol", 4, 0)
+    w["integrator"]["max_steps"] = 100000
+    img = torch.empty(4, 4, 4, dtype=torch.float64, device="cuda")
+    aux = torch.empty(blgpu.NAUX, 4, 4, dtype=torch.float64, device="cuda")
+    with pytest.raises(blgpu.BlError):
+        na_ctx.render_noalloc(w["camera"], w["spacetime"], w["integrator"], na_ctx.grid(_grid(w)), w["plasma"],
+                              img, aux)
+    torch.cuda.synchronize()
+    na_ctx.close()
+    ref_ctx.close()
