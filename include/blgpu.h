@@ -196,7 +196,7 @@ bl_status bl_render(bl_context *ctx, const bl_camera *cam, const bl_spacetime *s
    image descriptor) and records no timing events; the caller passes the
    inputs and the outputs as for bl_render.  Results equal bl_render's bit for
    bit with the same arguments.  The image is processed in chunks of rays
-   that fit the array (about 2,600 rays with the default 512-record slots,
+   that fit the array (about 1,900 rays with the default 512-record slots,
    more with a smaller integ->record_cap), so it is slower than bl_render.
    BL_E_INVALID_ARG for integ->max_steps above 4095 (the bound of the
    overflow path's buffer), BL_E_UNSUPPORTED if not even 64 rays fit, and
