@@ -291,7 +291,8 @@ def run_learned(args):
     w = synth.workload(args.workload, n=args.n)
     n = int(w["camera"]["n"])
     grid_f32 = args.precision == 1 and not args.grid_f64
-    grid = synth.make_grid(w["grid_args"], dtype=np.float32 if grid_f32 else np.float64)
+    grid64 = synth.make_grid(w["grid_args"], dtype=np.float64)
+    grid = dict(grid64, prims=grid64["prims"].astype(np.float32)) if grid_f32 else grid64
     ctx = blgpu.Context(0)
     gg = ctx.grid(grid)
     t0 = time.perf_counter()
@@ -335,6 +336,24 @@ def run_learned(args):
     diff = {"E_pix": float((np.abs(il - ip) / den).max()),
             "L1_I": float(np.abs(il[0] - ip[0]).sum() / np.abs(ip[0]).sum())}
 
+    vs_oracle = None
+    if not args.no_cpu_baseline:
+        # equal image accuracy: both images against a converged FP64 oracle
+        # (sampling limit ds_max/4) on sampled pixels
+        from oracle import oracle as O
+        rng = np.random.default_rng(5)
+        pix = rng.choice(n * n, size=min(n * n, 192), replace=False)
+        fine = dict(w["integrator"], ds_max=w["integrator"]["ds_max"] / 4)
+        log("converged oracle on", len(pix), "pixels ...")
+        iref, _ = O.render_pixels(w["camera"], w["spacetime"], fine, O.grid(grid64), w["plasma"], pix)
+        floor = 1e-3 * np.abs(ip[0]).max()
+        den = np.maximum(np.abs(iref[:, 0]), floor)
+        vs_oracle = {"reference": f"FP64 oracle with ds_max/4 on {len(pix)} random pixels (FP64 cells)"}
+        for name, im in (("learned", il), ("plain", ip)):
+            x = im.reshape(4, -1)[:, pix].T
+            vs_oracle[name] = {"E_pix": float((np.abs(x - iref) / den[:, None]).max()),
+                               "L1_I": float(np.abs(x[:, 0] - iref[:, 0]).sum() / np.abs(iref[:, 0]).sum())}
+
     def summary(r):
         return {"rays_per_s": n * n / (r["ms"] / 1e3), "ms_per_step": r["ms"],
                 "rejected_fraction": r["rej"] / (r["acc"] + r["rej"]), "accepted_per_ray": r["acc"],
@@ -353,6 +372,7 @@ def run_learned(args):
         "learned": summary(res[1]), "plain": summary(res[0]),
         "speedup_vs_plain": res[0]["ms"] / res[1]["ms"],
         "image_difference_learned_vs_plain": diff,
+        "image_error_vs_converged_oracle": vs_oracle,
         "training": {"logged_steps": n_steps, "epochs": args.epochs, "seconds": t_train,
                      "loss_train_heldout": losses.tolist()},
         "kernels": res[1]["kern"],

@@ -1,0 +1,179 @@
+"""Parity of the HIP path with the FP64 oracle at the workloads' full sizes
+and for the camera cases of the paper's section 2.1 (Camera Definition) that
+the benchmark does not exercise: a camera on the polar axis, a camera rotated
+about its line of sight, a moving camera and the frequency fixed at the
+camera.  Full images where the oracle finishes in seconds, sampled pixels
+otherwise; FP64 images to E_pix <= 1e-10 and the mixed form to 1e-4, every
+sampled pixel with the oracle's step counts."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-10
+TOL_MIXED = 1e-4
+
+
+def _say(*a):
+    print("[gpu-fullsize]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2203_15963_amd import blgpu
+    blgpu.load()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = blgpu.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+_GRIDS = {}
+
+
+def _grid(grid_args):
+    from paper_2203_15963_amd import synth
+    key = repr(sorted(grid_args.items()))
+    if key not in _GRIDS:
+        _GRIDS[key] = synth.make_grid(grid_args)
+    return _GRIDS[key]
+
+
+def _wl(name, n, **over):
+    from paper_2203_15963_amd import synth
+    w = synth.workload(name, n=n)
+    for k, v in over.items():
+        w[k].update(v)
+    return w
+
+
+def _epix_rows(ig, io, floor):
+    den = np.maximum(np.abs(io[:, 0]), floor)
+    return (np.abs(ig - io) / den[:, None]).max(axis=1)
+
+
+def _check(tag, ig, ag, io, ao, floor, tol):
+    """E_pix of sampled rows; every row's step counts and status must equal
+    the oracle's (listed if not)."""
+    e = _epix_rows(ig, io, floor)
+    bad = np.flatnonzero((ag[:, 5] != ao[:, 5]) | (ag[:, 6] != ao[:, 6]) | (ag[:, 7] != ao[:, 7]))
+    _say(tag, "pixels", len(e), "E_pix max", float(e.max()), "median", float(np.median(e)),
+         "step-count mismatches", [(int(b), ag[b, 5:8].tolist(), ao[b, 5:8].tolist()) for b in bad[:10]])
+    assert len(bad) == 0
+    assert e.max() <= tol
+    return e
+
+
+def _render_and_sample(ctx, oracle, w, pix, precision=0, grid_f32=False):
+    g = _grid(w["grid_args"])
+    if grid_f32:
+        g32 = dict(g, prims=g["prims"].astype(np.float32))
+        gg = ctx.grid(g32)
+        g = dict(g, prims=g32["prims"].astype(np.float64))
+    else:
+        gg = ctx.grid(g)
+    img, aux = ctx.render(w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"], precision=precision)
+    torch.cuda.synchronize()
+    img, aux = img.cpu().numpy(), aux.cpu().numpy()
+    io, ao = oracle.render_pixels(w["camera"], w["spacetime"], w["integrator"], g, w["plasma"], pix)
+    return img, aux, img.reshape(4, -1)[:, pix].T, aux.reshape(10, -1)[:, pix].T, io, ao
+
+
+def test_c1_full_image(ctx, oracle):
+    """The 64^2 unpolarized FP64 workload, every pixel."""
+    w = _wl("c1_64_unpol", 64)
+    pix = np.arange(64 * 64)
+    img, aux, ig, ag, io, ao = _render_and_sample(ctx, oracle, w, pix)
+    e = _check("c1 64^2 full", ig, ag, io, ao, 1e-3 * np.abs(io[:, 0]).max(), TOL_FP64)
+    # the auxiliary maps of every pixel
+    for q in (0, 1, 2):
+        assert np.abs(ag[:, q] - ao[:, q]).max() <= 1e-9 * (1 + np.abs(ao[:, q]).max())
+    for q in (3, 4):
+        assert np.abs(ag[:, q] - ao[:, q]).max() <= TOL_FP64 * np.abs(ao[:, q]).max()
+    assert np.array_equal(ag[:, 8], ao[:, 8]) and np.array_equal(ag[:, 9], ao[:, 9])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c2_full_size_sampled(ctx, oracle, precision):
+    """The 256^2 polarized workload at full size: 320 random pixels, the
+    corners and the centre."""
+    w = _wl("c2_256_pol", 256)
+    rng = np.random.default_rng(21 + precision)
+    pix = np.concatenate([rng.choice(256 * 256, size=320, replace=False), [0, 255, 256 * 128 + 128, 256 * 256 - 1]])
+    img, aux, ig, ag, io, ao = _render_and_sample(ctx, oracle, w, pix, precision=precision,
+                                                  grid_f32=precision == 1)
+    _check(f"c2 256^2 precision {precision}", ig, ag, io, ao, 1e-3 * np.abs(img[0]).max(),
+           TOL_FP64 if precision == 0 else TOL_MIXED)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_c4_batch_full_size_sampled(ctx, oracle, precision):
+    """The 64-image batch of uneven sizes (64^2 to 512^2, 3.8 M rays),
+    frequencies, inclinations and spins in one batched render (the
+    benchmark's batched form is mixed with an FP32 grid), against the oracle
+    on five pixels of every image."""
+    from paper_2203_15963_amd import synth
+    bw = synth.batch_workload()
+    g = _grid(bw["grid_args"])
+    if precision == 1:
+        g32 = dict(g, prims=g["prims"].astype(np.float32))
+        gg = ctx.grid(g32)
+        go = dict(g, prims=g32["prims"].astype(np.float64))
+    else:
+        gg, go = ctx.grid(g), g
+    outs = ctx.render_batch(bw["images"], bw["integrator"], gg, bw["plasma"], precision=precision)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(31)
+    worst = 0.0
+    for k, (cam, st) in enumerate(bw["images"]):
+        n = int(cam["n"])
+        img, aux = outs[k][0].cpu().numpy(), outs[k][1].cpu().numpy()
+        pix = np.concatenate([rng.choice(n * n, size=4, replace=False), [(n // 2) * n + n // 2]])
+        io, ao = oracle.render_pixels(cam, st, bw["integrator"], go, bw["plasma"], pix)
+        ig, ag = img.reshape(4, -1)[:, pix].T, aux.reshape(10, -1)[:, pix].T
+        e = _check(f"batch image {k} n={n} a={st['a']} theta={math.degrees(cam['theta']):.0f} "
+                   f"nu={cam['nu_hz'] / 1e9:.0f}GHz", ig, ag, io, ao, 1e-3 * np.abs(img[0]).max(),
+                   TOL_FP64 if precision == 0 else TOL_MIXED)
+        worst = max(worst, float(e.max()))
+    _say("batch precision", precision, "worst E_pix over 64 images", worst)
+
+
+def _camera_case(ctx, oracle, cam_over, n=12, precision=0):
+    w = _wl("c2_256_pol", n, camera=cam_over)
+    pix = np.arange(n * n)
+    img, aux, ig, ag, io, ao = _render_and_sample(ctx, oracle, w, pix, precision=precision,
+                                                  grid_f32=precision == 1)
+    assert (io[:, 0] > 0).sum() > n * n // 4, "the case must see plasma"
+    _check(f"camera {cam_over} precision {precision}", ig, ag, io, ao, 1e-3 * np.abs(io[:, 0]).max(),
+           TOL_FP64 if precision == 0 else TOL_MIXED)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_camera_on_the_polar_axis(ctx, oracle, precision):
+    """theta = 0: the camera's vertical comes from the y direction instead of
+    z (the frame's special case); the face-on view of the disk."""
+    _camera_case(ctx, oracle, {"theta": 0.0}, precision=precision)
+
+
+def test_camera_rotated_about_its_axis(ctx, oracle):
+    """psi != 0 turns the image-plane axes (and the Stokes Q, U reference)."""
+    _camera_case(ctx, oracle, {"theta": math.radians(60.0), "psi": 0.7})
+
+
+def test_moving_camera(ctx, oracle):
+    """A camera with a normal-frame velocity u^p = (-0.1, 0.02, 0.05)
+    (spherical components): aberration moves the rays and the Doppler factor
+    scales the frequencies."""
+    _camera_case(ctx, oracle, {"u_normal": (-0.1, 0.02, 0.05)})
+
+
+def test_frequency_at_the_camera(ctx, oracle):
+    """freq_mode 1: nu is the frequency measured by the (moving) camera."""
+    _camera_case(ctx, oracle, {"u_normal": (0.05, -0.03, 0.0), "freq_mode": 1})

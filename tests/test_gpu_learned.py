@@ -186,3 +186,47 @@ def test_learned_render_equal_accuracy(ctx, oracle, trained, name, n, precision)
     assert e_l <= 2.0 * e_p + 1e-3
     # what the network gains: fewer rejected trial steps than the plain controller
     assert rej_l < rej_p
+
+
+def test_learned_full_size_sampled(ctx, oracle, trained):
+    """The benchmark image (1024^2 SMR polarized, mixed form, FP32 grid) with
+    learned proposals against the plain controller, on 96 sampled pixels and
+    the centre: against a converged oracle (sampling limit ds_max/4, FP64,
+    on the same float-rounded cells) the learned image is as accurate as the
+    plain one; the fates of the sampled rays equal the oracle's, and the
+    network lowers the rejected-step rate over the whole image."""
+    from paper_2203_15963_amd import synth
+    ctx.set_step_model(trained[0])
+    w = synth.workload("c3_1024_smr", n=1024)
+    g = _grid(w)
+    g32 = dict(g, prims=g["prims"].astype(np.float32))
+    gg = ctx.grid(g32)
+    go = dict(g, prims=g32["prims"].astype(np.float64))
+    args = (w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"])
+    il, al = ctx.render(*args, precision=1, step_model=1)
+    ip, ap = ctx.render(*args, precision=1)
+    torch.cuda.synchronize()
+    il, al, ip, ap = il.cpu().numpy(), al.cpu().numpy(), ip.cpu().numpy(), ap.cpu().numpy()
+    rng = np.random.default_rng(41)
+    pix = np.concatenate([rng.choice(1024 * 1024, size=96, replace=False), [512 * 1024 + 512]])
+    fine = dict(w["integrator"], ds_max=w["integrator"]["ds_max"] / 4)
+    iref, aref = oracle.render_pixels(w["camera"], w["spacetime"], fine, go, w["plasma"], pix)
+    floor = 1e-3 * np.abs(ip[0]).max()
+
+    def errs(img):
+        x = img.reshape(4, -1)[:, pix].T
+        den = np.maximum(np.abs(iref[:, 0]), floor)
+        return float((np.abs(x - iref) / den[:, None]).max()), float(np.abs(x[:, 0] - iref[:, 0]).sum()
+                                                                        / np.abs(iref[:, 0]).sum())
+
+    e_l, l1_l = errs(il)
+    e_p, l1_p = errs(ip)
+    rej_l = al[6].sum() / (al[5].sum() + al[6].sum())
+    rej_p = ap[6].sum() / (ap[5].sum() + ap[6].sum())
+    _say("1024^2 learned vs converged oracle: E_pix", e_l, "L1", l1_l, "| plain: E_pix", e_p, "L1", l1_p,
+         "| rejected fraction learned", rej_l, "plain", rej_p,
+         "| trial steps per ray learned", float((al[5] + al[6]).mean()), "plain", float((ap[5] + ap[6]).mean()))
+    assert np.array_equal(al.reshape(10, -1)[7, pix], aref[:, 7])
+    assert l1_l <= 1.5 * l1_p + 1e-4
+    assert e_l <= 2.0 * e_p + 1e-3
+    assert rej_l < rej_p

@@ -64,7 +64,17 @@ def epix(img_g, img_o, counts_match):
     return e[counts_match].max() if counts_match.any() else 0.0, e
 
 
-def _compare_render(ctx, oracle, w, pixels=None, precision=0, tol=TOL_FP64, max_mismatch=0.02, grid_f32=False):
+def _mismatches(ag, ao, where):
+    """Pixels whose accepted or rejected step counts (or status) differ from
+    the oracle's, each with what differs."""
+    bad = []
+    for idx in np.flatnonzero((ag[:, 5] != ao[:, 5]) | (ag[:, 6] != ao[:, 6]) | (ag[:, 7] != ao[:, 7])):
+        bad.append((int(where[idx]), {"n_acc": (ag[idx, 5], ao[idx, 5]), "n_rej": (ag[idx, 6], ao[idx, 6]),
+                                      "status": (ag[idx, 7], ao[idx, 7])}))
+    return bad
+
+
+def _compare_render(ctx, oracle, w, pixels=None, precision=0, tol=TOL_FP64, max_mismatch=0, grid_f32=False):
     g = _grid(w)
     n = int(w["camera"]["n"])
     _say("render", w["camera"]["n"], w["plasma"]["polarized"], w["grid_args"].get("kind"), "precision", precision,
@@ -83,10 +93,14 @@ def _compare_render(ctx, oracle, w, pixels=None, precision=0, tol=TOL_FP64, max_
         io, ao = oracle.render(w["camera"], w["spacetime"], w["integrator"], g, w["plasma"])
         match = (ao[5] == aux[5]) & (ao[6] == aux[6])
         ep, e = epix(img, io, match)
-        _say("E_pix(matched)", ep, "mismatched", int((~match).sum()), "of", n * n,
-             "max E_pix(all)", e.max())
+        bad = _mismatches(aux.reshape(10, -1).T, ao.reshape(10, -1).T, np.arange(n * n))
+        _say("E_pix(matched)", ep, "mismatched", len(bad), "of", n * n, "max E_pix(all)", e.max(),
+             "mismatched pixels:", [(p, float(e.reshape(-1)[p]), c) for p, c in bad[:10]])
         assert ep <= tol
-        assert (~match).sum() <= max(1, max_mismatch * n * n)
+        # pixels whose step counts differ (a decision flipped by rounding) are
+        # listed above; their number is bounded by max_mismatch (0 unless a
+        # test states otherwise)
+        assert len(bad) <= max_mismatch * n * n
         # geodesic auxiliary maps on matched pixels
         for q in (0, 1, 2):
             assert np.abs(aux[q] - ao[q])[match].max() <= 1e-9 * (1 + np.abs(ao[q]).max())
@@ -109,10 +123,11 @@ def _compare_render(ctx, oracle, w, pixels=None, precision=0, tol=TOL_FP64, max_
     full_max = np.abs(img[0]).max()
     den = np.maximum(np.abs(io[:, 0]), 1e-3 * full_max)
     e = (np.abs(ig - io) / den[:, None]).max(axis=1)
-    _say("sampled E_pix(matched)", e[match].max() if match.any() else 0, "mismatched", int((~match).sum()),
-         "of", len(pix))
+    bad = _mismatches(ag, ao, pix)
+    _say("sampled E_pix(matched)", e[match].max() if match.any() else 0, "mismatched", len(bad),
+         "of", len(pix), "mismatched pixels:", [(p, c) for p, c in bad[:10]])
     assert e[match].max() <= tol
-    assert (~match).sum() <= max(1, max_mismatch * len(pix))
+    assert len(bad) <= max_mismatch * len(pix)
     return img, aux, io, ao
 
 
@@ -149,7 +164,7 @@ def test_geodesics_match_oracle(ctx, oracle):
         assert abs(aux[1, j, i] - t["s"]) <= 1e-10 * t["s"]
         assert abs(aux[0, j, i] - t["dt"]) <= 1e-10 * t["dt"]
     _say("geodesic count mismatches", mism)
-    assert mism <= 0.02 * n * n
+    assert mism == 0
 
 
 def test_samples_match_oracle(ctx, oracle):
@@ -398,7 +413,7 @@ def test_render_mixed_fp32_grid(ctx, oracle):
     match = (ao[5] == aux[5]) & (ao[6] == aux[6])
     ep, e = epix(img, io, match)
     _say("mixed fp32 grid E_pix", ep, "matched", int(match.sum()))
-    assert ep <= TOL_MIXED and match.sum() >= 0.98 * n * n
+    assert ep <= TOL_MIXED and match.sum() == n * n
 
 
 def test_full_size_sampled_mixed(ctx, oracle):
@@ -450,7 +465,7 @@ def test_batch_matches_single_and_oracle(ctx, oracle):
         _say("batch image", k, "n", cam["n"], "a", st["a"], "nu", cam["nu_hz"], "E vs single", e_self,
              "E vs oracle", e_or, "mismatched", int((~match).sum()))
         assert e_self <= 1e-13
-        assert e_or <= TOL_FP64 and (~match).sum() <= max(1, 0.02 * match.size)
+        assert e_or <= TOL_FP64 and (~match).sum() == 0
 
 
 def test_batch_mixed_matches_oracle(ctx, oracle):
@@ -468,7 +483,7 @@ def test_batch_mixed_matches_oracle(ctx, oracle):
         match = (ao[5] == ab[5]) & (ao[6] == ab[6])
         e = epix(ib, io, match)[0]
         _say("mixed batch image", k, "n", cam["n"], "E", e)
-        assert e <= TOL_MIXED and (~match).sum() <= max(1, 0.02 * match.size)
+        assert e <= TOL_MIXED and (~match).sum() == 0
 
 
 def test_schedule_does_not_change_results(ctx):
