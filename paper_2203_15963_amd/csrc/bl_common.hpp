@@ -22,8 +22,8 @@ constexpr double kEulerGamma = 0.57721566490153286061;
 // Exponential, logarithm and cube root for smooth fitting-formula terms: the
 // hardware transcendental unit in FP32 (relative error a few 1e-7 times the
 // argument's magnitude for exp, far inside the mixed form's tolerance); in
-// FP64 the exponentials below (about one ulp) and the library logarithm and
-// cube root.
+// FP64 the branch-free exponential and logarithm below (a few ulp), whose
+// straight-line code lets independent evaluations interleave.
 __device__ __forceinline__ float fexp(float x) { return __expf(x); }
 // e^x in FP64: x = k ln2 + r with the reduction in two parts (Cody and Waite;
 // ln2_hi has eleven trailing zero bits, so k ln2_hi is exact), e^r from its
@@ -52,9 +52,7 @@ __device__ __forceinline__ double fexp(double x) {
     return ldexp(fma(r, od, ev), (int)k);
 }
 __device__ __forceinline__ float flog(float x) { return __logf(x); }
-__device__ __forceinline__ double flog(double x) { return log(x); }
 __device__ __forceinline__ float fcbrt(float x) { return __expf(__logf(x) * (1.0f / 3.0f)); }   // x > 0
-__device__ __forceinline__ double fcbrt(double x) { return cbrt(x); }
 // e^x - 1 with relative accuracy near zero: in FP32 the Taylor polynomial
 // through x^8/8! for |x| < 0.35 (truncation below 1e-9 relative), the hardware
 // exponential minus one elsewhere.
@@ -111,13 +109,42 @@ __device__ __forceinline__ double rsqrt_r(double x) {
 // refined reciprocal (within about two ulp)
 __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double fdiv(double a, double b) { return a * rcp_nr(b); }
-// cos for arguments of moderate size: the hardware unit in FP32, the library in FP64
+// ln x in FP64, branch free: x = m 2^e with m in [sqrt(1/2), sqrt(2)) from
+// the hardware mantissa/exponent split, ln m = 2 atanh(s) with
+// s = (m - 1)/(m + 1), |s| <= 0.1716, from its series 2 s (1 + s^2/3 + ... +
+// s^20/21) (truncation below 1e-17 relative; even and odd parts in s^4 side by
+// side), and e ln 2 added with ln 2 in two parts (the high part has eleven
+// trailing zero bits): within a few ulp, also near x = 1.  x <= 0 gives -inf
+// (x = 0) or NaN.
+__device__ __forceinline__ double flog(double x) {
+    int e = __builtin_amdgcn_frexp_exp(x);         // x = mant 2^e, mant in [1/2, 1)
+    double m = __builtin_amdgcn_frexp_mant(x);
+    const bool lo = m < 0x1.6a09e667f3bcdp-1;     // sqrt(1/2)
+    m = lo ? 2.0 * m : m;
+    e = lo ? e - 1 : e;
+    const double s = (m - 1.0) * rcp_nr(m + 1.0);
+    const double z = s * s, z2 = z * z;
+    double ev = 1.0 / 21.0, od = 1.0 / 19.0;       // coefficients 1/(2j+1) of z^j
+    ev = fma(ev, z2, 1.0 / 17.0);
+    od = fma(od, z2, 1.0 / 15.0);
+    ev = fma(ev, z2, 1.0 / 13.0);
+    od = fma(od, z2, 1.0 / 11.0);
+    ev = fma(ev, z2, 1.0 / 9.0);
+    od = fma(od, z2, 1.0 / 7.0);
+    ev = fma(ev, z2, 1.0 / 5.0);
+    od = fma(od, z2, 1.0 / 3.0);
+    ev = fma(ev, z2, 1.0);
+    const double lnm = 2.0 * s * fma(od, z, ev);
+    const double de = (double)e;
+    const double r = fma(de, 0x1.62e42fefa3800p-1, fma(de, 5.497923018708371e-14, lnm));
+    return x > 0.0 ? (__builtin_isinf(x) ? x : r) : (x == 0.0 ? -__builtin_inf() : __builtin_nan(""));
+}
+// cos for arguments of moderate size: the hardware unit in FP32; in FP64
+// from fsincos below
 __device__ __forceinline__ float fcos(float x) { return __cosf(x); }
-__device__ __forceinline__ double fcos(double x) { return cos(x); }
 // sin and cos: in FP32 the argument is reduced by 2 pi in two parts (Cody and
 // Waite; 6.28125 has eight significant bits, so n * 6.28125 is exact for the
-// argument sizes met here) and the hardware unit evaluates on [-pi, pi]; in
-// FP64 the library function
+// argument sizes met here) and the hardware unit evaluates on [-pi, pi]
 __device__ __forceinline__ void fsincos(float x, float &s, float &c) {
     const float n = rintf(x * 0.15915494309189535f);
     float r = fmaf(-n, 6.28125f, x);
@@ -125,10 +152,39 @@ __device__ __forceinline__ void fsincos(float x, float &s, float &c) {
     s = __sinf(r);
     c = __cosf(r);
 }
-__device__ __forceinline__ void fsincos(double x, double &s, double &c) { sincos(x, &s, &c); }
+// In FP64, branch free: x = k pi/2 + r with the reduction in three parts
+// (Cody and Waite; the first two parts of pi/2 carry 33 significant bits, so
+// k times them is exact for |k| < 2^20, i.e. |x| below about 1.6e6, the
+// range met here), sin r and cos r on |r| <= pi/4 from their Taylor
+// polynomials through r^15/15! and r^16/16! (truncation below 1e-16
+// relative), and the quadrant of k choosing signs and order: within a few ulp.
+__device__ __forceinline__ void fsincos(double x, double &s, double &c) {
+    const double k = rint(x * 0x1.45f306dc9c883p-1);   // 2/pi
+    double r = fma(-k, 0x1.921fb54400000p+0, x);
+    r = fma(-k, 0x1.0b4611a600000p-34, r);
+    r = fma(-k, 0x1.3198a2e037073p-69, r);
+    const double u = r * r;
+    double ps = rfact(15), pc = fma(rfact(16), -u, rfact(14));
+#pragma unroll
+    for (int j = 13; j >= 1; j -= 2) {
+        ps = fma(ps, -u, rfact(j));
+        pc = fma(pc, -u, rfact(j - 1));
+    }
+    const double sr = r * ps;   // sin r = r (1 - r^2/3! + ...), cos r = 1 - r^2/2! + ...
+    const double cr = pc;
+    const int q = (int)(((long long)k) & 3);
+    const double sq = (q & 1) ? cr : sr, cq = (q & 1) ? sr : cr;
+    s = (q & 2) ? -sq : sq;
+    c = ((q + 1) & 2) ? -cq : cq;
+}
+__device__ __forceinline__ double fcos(double x) {
+    double s, c;
+    fsincos(x, s, c);
+    return c;
+}
 // ln(1 + x) for x >= 0 where only absolute accuracy is needed
 __device__ __forceinline__ float flog1p_abs(float x) { return __logf(1.0f + x); }
-__device__ __forceinline__ double flog1p_abs(double x) { return log1p(x); }
+__device__ __forceinline__ double flog1p_abs(double x) { return flog(1.0 + x); }
 
 // per-ray status codes (blgpu.h bl_ray_status); kRayOverflow is internal:
 // the ray needs more step records than the fast path keeps.
