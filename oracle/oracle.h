@@ -81,6 +81,15 @@ typedef struct {
                                -1: (x - x0).n > 0 is vacuum                 */
     double cut_lo[OR_NCUT], cut_hi[OR_NCUT];
     double plane_x0[3], plane_n[3];
+    /* electron populations (paper sections 2.6, 4.5): fractions of n_e in
+       the thermal, power-law and kappa distributions (non-negative, summing
+       to 1), power-law index and cutoffs, kappa index and width */
+    double frac[3];
+    double pl_p, pl_gmin, pl_gmax, kappa, kappa_w;
+    /* filled by or_nonthermal_prepare from the parameters above:
+       power law: (p-1)/(gmin^(1-p) - gmax^(1-p)); kappa: the normalisation A,
+       the moments <gamma^-2/3>, <gamma^-5/3> of the normalised distribution */
+    double pl_norm, kap_norm, kap_m23, kap_m53;
 } or_plasma;
 
 /* ---- geometry (kerr.c) ---- */
@@ -137,6 +146,15 @@ int    or_grid_sample(const or_grid *gr, int interp, const double x[3], double p
 double or_bessel_k_scaled(int n, double x);   /* e^x K_n(x) */
 void   or_thermal_coeffs(double ne, double thetae, double B, double nu,
                          double cos_theta, int polarized, double out[8]);
+/* Nonthermal populations (plasma.c): or_nonthermal_prepare fills the
+   distribution constants of pl; or_nonthermal_coeffs gives the fluid-frame
+   coefficients (as or_thermal_coeffs) of n_e electrons in distribution kind
+   (1: power law, 2: kappa).  or_kappa_integral is the integral over gamma of
+   gamma^s dn/dgamma / (n_e A) for the kappa distribution (s = 0 gives 1/A). */
+void   or_nonthermal_prepare(or_plasma *pl);
+double or_kappa_integral(double kappa, double w, double s);
+void   or_nonthermal_coeffs(int kind, const or_plasma *pl, double ne, double B, double nu,
+                            double cos_theta, int polarized, double out[8]);
 /* Everything at one sample point: state y[8], normalisation n.
    out[0..7]   = jI, jQ, jV, aI, aQ, aV, rQ, rV  (invariant: j/nu^2, a*nu)
    out[8..11]  = ne, thetae, B_gauss, nu_fluid

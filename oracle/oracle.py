@@ -53,7 +53,11 @@ class Plasma(C.Structure):
                 ("polarized", C.c_int32), ("interp", C.c_int32),
                 ("use_cuts", C.c_int32), ("plane", C.c_int32),
                 ("cut_lo", C.c_double * 8), ("cut_hi", C.c_double * 8),
-                ("plane_x0", C.c_double * 3), ("plane_n", C.c_double * 3)]
+                ("plane_x0", C.c_double * 3), ("plane_n", C.c_double * 3),
+                ("frac", C.c_double * 3), ("pl_p", C.c_double), ("pl_gmin", C.c_double),
+                ("pl_gmax", C.c_double), ("kappa", C.c_double), ("kappa_w", C.c_double),
+                ("pl_norm", C.c_double), ("kap_norm", C.c_double), ("kap_m23", C.c_double),
+                ("kap_m53", C.c_double)]
 
 
 def _dp(a):
@@ -93,6 +97,10 @@ def lib():
         L.or_bessel_k_scaled.restype = d
         L.or_bessel_k_scaled.argtypes = [i, d]
         L.or_thermal_coeffs.argtypes = [d, d, d, d, d, i, P]
+        L.or_nonthermal_prepare.argtypes = [C.POINTER(Plasma)]
+        L.or_kappa_integral.restype = d
+        L.or_kappa_integral.argtypes = [d, d, d]
+        L.or_nonthermal_coeffs.argtypes = [i, C.POINTER(Plasma), d, d, d, d, i, P]
         L.or_sample_point.argtypes = [C.POINTER(Spacetime), C.POINTER(Grid), C.POINTER(Plasma), P, d, P]
         L.or_unpol_segment.restype = d
         L.or_unpol_segment.argtypes = [d, d, d, d]
@@ -157,6 +165,15 @@ def plasma(d):
             p.plane = int(pl["side"])
             for i in range(3):
                 p.plane_x0[i], p.plane_n[i] = float(pl["origin"][i]), float(pl["normal"][i])
+    # electron populations: fractions (thermal, power law, kappa) and parameters
+    # (defaults: the paper's p = 3, gamma 4..1000, kappa = 4, w = 1/2)
+    fr = d.get("fractions", (1.0, 0.0, 0.0))
+    for k in range(3):
+        p.frac[k] = float(fr[k])
+    p.pl_p, p.pl_gmin, p.pl_gmax = d.get("pl_p", 3.0), d.get("pl_gamma_min", 4.0), d.get("pl_gamma_max", 1000.0)
+    p.kappa, p.kappa_w = d.get("kappa", 4.0), d.get("kappa_w", 0.5)
+    if p.frac[1] > 0 or p.frac[2] > 0:
+        lib().or_nonthermal_prepare(C.byref(p))
     return p
 
 
@@ -279,6 +296,19 @@ def thermal_coeffs(ne, thetae, B, nu, cos_theta, polarized=1):
     out = np.zeros(8)
     lib().or_thermal_coeffs(ne, thetae, B, nu, cos_theta, int(polarized), _dp(out))
     return out
+
+
+def nonthermal_coeffs(kind, pl, ne, B, nu, cos_theta, polarized=1):
+    """Fluid-frame coefficients of n_e electrons in population kind (1: power
+    law, 2: kappa) with the parameters of plasma dict pl."""
+    out = np.zeros(8)
+    p = plasma(dict(pl, fractions=(0.0, 1.0, 0.0) if kind == 1 else (0.0, 0.0, 1.0)))
+    lib().or_nonthermal_coeffs(int(kind), C.byref(p), ne, B, nu, cos_theta, int(polarized), _dp(out))
+    return out
+
+
+def kappa_integral(kappa, w, s):
+    return lib().or_kappa_integral(kappa, w, s)
 
 
 def sample_point(st, gr, pl, y, n_norm):
