@@ -39,14 +39,17 @@
 extern "C" {
 #endif
 
-#define BLGPU_ABI_VERSION 1
+#define BLGPU_ABI_VERSION 2
 
 typedef enum {
     BL_OK = 0,
     BL_E_INVALID_ARG = -1,   /* a pointer, size or parameter is invalid       */
     BL_E_DEVICE = -2,        /* a HIP runtime call failed                      */
     BL_E_OOM = -3,           /* device memory for the workspace is exhausted   */
-    BL_E_UNSUPPORTED = -4    /* a valid request this version does not support  */
+    BL_E_UNSUPPORTED = -4,   /* a valid request this version does not support  */
+    BL_E_STATE = -5          /* the call needs state the context does not hold
+                                (no step network installed, a grid of another
+                                context)                                      */
 } bl_status;
 
 /* Auxiliary maps, each [N][N] doubles, in this order (paper section 4.6,
@@ -87,6 +90,9 @@ typedef struct {
     int32_t n;                /* N: pixels per side (1 .. 16384)              */
     int32_t freq_mode;        /* 0: nu at infinity (-n k_t = nu);
                                  1: nu at the camera (-n k.u = nu)            */
+    int32_t kind;             /* 0: plane-parallel camera (the only kind built;
+                                 others give BL_E_UNSUPPORTED)                */
+    int32_t pad;
     double psi;               /* rotation of the camera about its axis        */
     double nu_hz;             /* observing frequency (Hz)                     */
 } bl_camera;
@@ -131,13 +137,28 @@ typedef struct {
                                  of rho_unit c^2 and B of c sqrt(4 pi rho_unit) */
 } bl_grid_desc;
 
-/* Plasma model, paper section 2.6 (thermal electrons, R_high/R_low). */
+/* Plasma model, paper section 2.6 (thermal electrons, R_high/R_low) and
+   section 4.5 (nonthermal electrons): n_e is shared by thermal, power-law
+   and kappa populations in the given fractions, whose coefficients add.  The
+   nonthermal populations' coefficients are ultrarelativistic synchrotron
+   ones: for the power law the closed forms of gamma_min^2 << X << gamma_max^2
+   (X = nu/(nu_c sin theta), nu_c = e B/(2 pi m_e c)); for the kappa
+   distribution its exact low- and high-frequency asymptotes joined by a
+   bridge; their circular and rotative coefficients are zero.  Renders with a
+   nonthermal population take the general constant-coefficient Stokes step
+   (no Kirchhoff relation) and are single-image renders without data cuts or
+   averages (else BL_E_UNSUPPORTED). */
 typedef struct {
     double mu, ne_ni;         /* molecular weight, n_e/n_i                    */
     double r_high, r_low;     /* T_i/T_e prescription                         */
     double sigma_max;         /* sigma above this is vacuum                   */
     int32_t polarized;        /* 0: I only (eq. unpolarized); 1: I,Q,U,V      */
     int32_t interp;           /* 0: nearest cell; 1: trilinear within a block */
+    double fractions[3];      /* of n_e: thermal, power law, kappa; >= 0,
+                                 summing to 1 (all 0: thermal only)           */
+    double pl_p;              /* power-law index p > 1                        */
+    double pl_gamma_min, pl_gamma_max;  /* cutoffs, 1 <= min < max < inf      */
+    double kappa, kappa_w;    /* kappa index (>= 2.5) and width w > 0         */
 } bl_plasma;
 
 typedef struct {

@@ -13,14 +13,14 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libblgpu.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
 NAUX = 10
 NAVG = 21
 NKERNEL = 4
 KERNEL_NAMES = ["setup", "geodesic", "transfer", "overflow"]
 NSAMPLE_OUT = 64
 AUX_NAMES = ["dt", "s", "lambda", "tau", "I_j", "n_acc", "n_rej", "status", "n_samp", "n_rec"]
-STATUS = {"OK": 0, "E_INVALID_ARG": -1, "E_DEVICE": -2, "E_OOM": -3, "E_UNSUPPORTED": -4}
+STATUS = {"OK": 0, "E_INVALID_ARG": -1, "E_DEVICE": -2, "E_OOM": -3, "E_UNSUPPORTED": -4, "E_STATE": -5}
 _STATUS_NAME = {v: k for k, v in STATUS.items()}
 
 
@@ -28,7 +28,7 @@ class bl_camera(C.Structure):
     _fields_ = [("r", C.c_double), ("theta", C.c_double), ("phi", C.c_double),
                 ("u_normal", C.c_double * 3), ("k_cov", C.c_double * 3),
                 ("width", C.c_double), ("n", C.c_int32), ("freq_mode", C.c_int32),
-                ("psi", C.c_double), ("nu_hz", C.c_double)]
+                ("kind", C.c_int32), ("pad", C.c_int32), ("psi", C.c_double), ("nu_hz", C.c_double)]
 
 
 class bl_spacetime(C.Structure):
@@ -51,7 +51,9 @@ class bl_grid_desc(C.Structure):
 class bl_plasma(C.Structure):
     _fields_ = [("mu", C.c_double), ("ne_ni", C.c_double), ("r_high", C.c_double),
                 ("r_low", C.c_double), ("sigma_max", C.c_double), ("polarized", C.c_int32),
-                ("interp", C.c_int32)]
+                ("interp", C.c_int32), ("fractions", C.c_double * 3), ("pl_p", C.c_double),
+                ("pl_gamma_min", C.c_double), ("pl_gamma_max", C.c_double), ("kappa", C.c_double),
+                ("kappa_w", C.c_double)]
 
 
 class bl_mode(C.Structure):
@@ -233,6 +235,7 @@ def camera(d):
         c.k_cov[k] = d.get("k_cov", (1.0, 0.0, 0.0))[k]
     c.width, c.n = d["width"], int(d["n"])
     c.freq_mode = int(d.get("freq_mode", 0))
+    c.kind = int(d.get("kind", 0))
     c.psi, c.nu_hz = d.get("psi", 0.0), d.get("nu_hz", 230e9)
     return c
 
@@ -259,6 +262,14 @@ def plasma(d):
     p.r_high, p.r_low = d.get("r_high", 20.0), d.get("r_low", 1.0)
     p.sigma_max = d.get("sigma_max", 1.0)
     p.polarized, p.interp = int(d.get("polarized", 0)), int(d.get("interp", 1))
+    # electron populations: fractions (thermal, power law, kappa) and parameters
+    # (defaults: the paper's p = 3, gamma 4..1000, kappa = 4, w = 1/2)
+    fr = d.get("fractions", (1.0, 0.0, 0.0))
+    for k in range(3):
+        p.fractions[k] = float(fr[k])
+    p.pl_p, p.pl_gamma_min = d.get("pl_p", 3.0), d.get("pl_gamma_min", 4.0)
+    p.pl_gamma_max = d.get("pl_gamma_max", 1000.0)
+    p.kappa, p.kappa_w = d.get("kappa", 4.0), d.get("kappa_w", 0.5)
     return p
 
 

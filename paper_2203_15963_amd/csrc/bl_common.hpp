@@ -253,6 +253,28 @@ struct PlasmaParams {
     // they take no scalar registers in the kernels' loops
     int cuts;                      // 0: none set
     const struct CutParams *cut;   // device copy of the limits
+    // nonthermal electron populations (read by the kernels compiled for them)
+    int nonthermal;                // 0: thermal electrons only
+    const struct NthParams *nth;   // device copy of their constants
+};
+
+// Electron populations (paper sections 2.6 and 4.5): fractions of n_e in the
+// thermal, power-law and kappa distributions, and per nonthermal population
+// (index 0: power law, 1: kappa) the constants of its synchrotron
+// coefficients, formed on the host.  With X = nu/(nu_c sin theta) and
+// nu_c = e B/(2 pi m c), in units of n_e e^2 nu_c/c (emissivities) and
+// n_e e^2/(nu m c) (absorptivities):
+//   power-law terms  jI = hj sin X^ej, jQ = hjq jI, aI = ha X^ea, aQ = haq aI
+//   (the whole coefficient of the power law; the high-frequency asymptote of
+//   the kappa distribution, whose tail is a power law);
+//   kappa low-frequency asymptotes  jI = lj sin X^(1/3), aI = la X^(-2/3),
+//   jQ, aQ half of them, joined to the high-frequency ones as
+//   (low^-b + high^-b)^(-1/b) with b = 1/2 (jI, jQ, aQ) and 3/7 (aI).
+// The constant factors are stored as natural logarithms (l* fields).
+struct NthParams {
+    double frac[3];
+    double lhj[2], ej[2], lhjq[2], lha[2], ea[2], lhaq[2];
+    double llj, lla;
 };
 
 // Data-cut limits in the order rho, n_e, p, Theta_e, B, sigma, beta^-1, r

@@ -297,6 +297,59 @@ __device__ __forceinline__ void thermal_coeffs(R ne, R th, R B, R nu, R cth, int
     out[7] = R(2) * base * rb * inu * r0 * cth * gX;
 }
 
+// ------------------------------------------------ nonthermal populations
+// Synchrotron coefficients of the power-law and kappa electrons (paper
+// sections 2.6 and 4.5; constants in NthParams), added to out.  The circular
+// and rotative coefficients of these populations are zero.  The powers of X
+// come from one logarithm; a bridge (low^-b + high^-b)^(-1/b) is evaluated
+// on the logarithms of its two terms, scaled by the smaller one.
+template <typename R>
+__device__ __forceinline__ R nth_bridge(R ll, R lh, R b) {   // ll, lh: logs of low, high
+    const R m = fmin(ll, lh);
+    return fexp(m - flog(fexp(-b * (ll - m)) + fexp(-b * (lh - m))) * fdiv(R(1), b));
+}
+
+template <typename R>
+__device__ __forceinline__ void nonthermal_coeffs(const NthParams &q, R ne, R B, R nu, R cth, int polarized,
+                                                  R out[8]) {
+    cth = fmin(R(1), fmax(R(-1), cth));
+    const R sth = sqrt(R(1) - cth * cth);
+    if (!(ne > R(0)) || !(B > R(0)) || !(sth > R(0))) return;
+    const R nuc = R(kNuB) * B;
+    const R lX = flog(fdiv(nu, nuc * sth));
+    const R lsth = flog(sth);
+    const R jn = ne * R(kQe * kQe / kC) * nuc;             // n_e e^2 nu_c / c
+    const R an = fdiv(ne * R(kQe * kQe / (kMe * kC)), nu);   // n_e e^2 / (nu m c)
+    for (int k = 0; k < 2; ++k) {
+        const R f = (R)q.frac[1 + k];
+        if (!(f > R(0))) continue;
+        // power-law terms, as logarithms
+        const R lhj = (R)q.lhj[k] + lsth + (R)q.ej[k] * lX;
+        const R lha = (R)q.lha[k] + (R)q.ea[k] * lX;
+        R jI, jQ, aI, aQ;
+        if (k == 0) {
+            jI = fexp(lhj);
+            aI = fexp(lha);
+            jQ = fexp(lhj + (R)q.lhjq[k]);
+            aQ = fexp(lha + (R)q.lhaq[k]);
+        } else {
+            const R llj = (R)q.llj + lsth + lX * R(1.0 / 3.0);
+            const R lla = (R)q.lla - lX * R(2.0 / 3.0);
+            const R ln2 = R(0.6931471805599453);
+            jI = nth_bridge(llj, lhj, R(0.5));
+            aI = nth_bridge(lla, lha, R(3.0 / 7.0));
+            jQ = nth_bridge(llj - ln2, lhj + (R)q.lhjq[k], R(0.5));
+            aQ = nth_bridge(lla - ln2, lha + (R)q.lhaq[k], R(0.5));
+        }
+        out[0] += f * jn * jI;
+        out[3] += f * an * aI;
+        if (polarized) {
+            out[1] += f * jn * jQ;
+            out[4] += f * an * aQ;
+        }
+    }
+}
+
 // -------------------------------------------------------------- plasma
 template <typename R>
 struct Sample {
@@ -323,8 +376,9 @@ __device__ __forceinline__ bool cut_out(const CutParams &c, int k, R q) {
 }
 
 // CUTS: compiled with the data-cut checks (renders with cuts installed use
-// that instantiation, so the others carry no trace of them).
-template <typename R, bool CUTS = false>
+// that instantiation, so the others carry no trace of them); NTH: with the
+// nonthermal electron populations (likewise).
+template <typename R, bool CUTS = false, bool NTH = false>
 __device__ __forceinline__ void sample_point(double a, int flat, const DevGrid &g, const PlasmaParams &pp,
                                              const double yd[8], double n_norm, Sample<R> &s) {
     s.plasma = false;
@@ -373,7 +427,14 @@ __device__ __forceinline__ void sample_point(double a, int flat, const DevGrid &
     R kb = kc[0] * s.b[0] + kc[1] * s.b[1] + kc[2] * s.b[2] + kc[3] * s.b[3];
     R nu = (R)n_norm * omega;
     R cth = (b2 > R(0)) ? fdiv(kb, omega * sqrt(b2)) : R(0);
-    thermal_coeffs<R>(ne, th, Bg, nu, cth, pp.polarized, s.co);
+    if (NTH && pp.nonthermal) {
+        const NthParams *np = pp.nth;
+        asm volatile("" : "+s"(np));
+        thermal_coeffs<R>(ne * (R)np->frac[0], th, Bg, nu, cth, pp.polarized, s.co);
+        nonthermal_coeffs<R>(*np, ne, Bg, nu, cth, pp.polarized, s.co);
+    } else {
+        thermal_coeffs<R>(ne, th, Bg, nu, cth, pp.polarized, s.co);
+    }
     s.omega = omega;
     s.ne = ne;
     s.th = th;

@@ -408,6 +408,105 @@ __device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
     }
 }
 
+// The plasma substep for any source vector (nonthermal electrons: no
+// Kirchhoff relation between J and M): with the segment length folded into
+// the coefficients, dS/ds = J - M S over s in [0, 1] gives
+// S1 = e^-M S0 + int_0^1 e^-M(1-s) J ds, the upper block of the exponential of
+// the augmented matrix A = [[-M, J], [0, 0]].  Evaluated in FP64 in both
+// forms: A is scaled by 2^-k to a row-sum norm of at most 1/4, its Taylor
+// series summed through A^14/14! in Horner form on pairs (E, v) standing for
+// [[E, v], [0, 1]] (truncation below 1e-20), then squared k times.  With
+// aI >= 100 (the optical-depth cap of the unpolarized equation) S = M^-1 J.
+__device__ __forceinline__ void mat4_mul(const double A[16], const double B[16], double C[16]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            C[4 * i + j] = A[4 * i] * B[j] + A[4 * i + 1] * B[4 + j] + A[4 * i + 2] * B[8 + j] + A[4 * i + 3] * B[12 + j];
+}
+
+template <typename R>
+__device__ __forceinline__ void stokes_step_general(const R cr[8], R Sr[4]) {
+    const double aI = cr[3], aQ = cr[4], aV = cr[5], rQ = cr[6], rV = cr[7];
+    // M rows: (aI aQ 0 aV), (aQ aI rV 0), (0 -rV aI rQ), (aV 0 -rQ aI); aU, rU = 0
+    const double M[16] = {aI, aQ, 0.0, aV, aQ, aI, rV, 0.0, 0.0, -rV, aI, rQ, aV, 0.0, -rQ, aI};
+    const double J[4] = {(double)cr[0], (double)cr[1], 0.0, (double)cr[2]};
+    double S0[4] = {(double)Sr[0], (double)Sr[1], (double)Sr[2], (double)Sr[3]};
+    if (aI >= 100.0) {
+        // x = M^-1 J by the adjugate, from the 2x2 minors of the first two and
+        // of the last two rows (no indexed arrays, so nothing goes to scratch)
+        const double *m = M;
+        const double s0 = m[0] * m[5] - m[4] * m[1], s1 = m[0] * m[6] - m[4] * m[2];
+        const double s2 = m[0] * m[7] - m[4] * m[3], s3 = m[1] * m[6] - m[5] * m[2];
+        const double s4 = m[1] * m[7] - m[5] * m[3], s5 = m[2] * m[7] - m[6] * m[3];
+        const double c5 = m[10] * m[15] - m[14] * m[11], c4 = m[9] * m[15] - m[13] * m[11];
+        const double c3 = m[9] * m[14] - m[13] * m[10], c2 = m[8] * m[15] - m[12] * m[11];
+        const double c1 = m[8] * m[14] - m[12] * m[10], c0 = m[8] * m[13] - m[12] * m[9];
+        const double id = 1.0 / (s0 * c5 - s1 * c4 + s2 * c3 + s3 * c2 - s4 * c1 + s5 * c0);
+        // rows of adj(M)
+        const double a00 = m[5] * c5 - m[6] * c4 + m[7] * c3, a01 = -m[1] * c5 + m[2] * c4 - m[3] * c3;
+        const double a02 = m[13] * s5 - m[14] * s4 + m[15] * s3, a03 = -m[9] * s5 + m[10] * s4 - m[11] * s3;
+        const double a10 = -m[4] * c5 + m[6] * c2 - m[7] * c1, a11 = m[0] * c5 - m[2] * c2 + m[3] * c1;
+        const double a12 = -m[12] * s5 + m[14] * s2 - m[15] * s1, a13 = m[8] * s5 - m[10] * s2 + m[11] * s1;
+        const double a20 = m[4] * c4 - m[5] * c2 + m[7] * c0, a21 = -m[0] * c4 + m[1] * c2 - m[3] * c0;
+        const double a22 = m[12] * s4 - m[13] * s2 + m[15] * s0, a23 = -m[8] * s4 + m[9] * s2 - m[11] * s0;
+        const double a30 = -m[4] * c3 + m[5] * c1 - m[6] * c0, a31 = m[0] * c3 - m[1] * c1 + m[2] * c0;
+        const double a32 = -m[12] * s3 + m[13] * s1 - m[14] * s0, a33 = m[8] * s3 - m[9] * s1 + m[10] * s0;
+        Sr[0] = (R)((a00 * J[0] + a01 * J[1] + a02 * J[2] + a03 * J[3]) * id);
+        Sr[1] = (R)((a10 * J[0] + a11 * J[1] + a12 * J[2] + a13 * J[3]) * id);
+        Sr[2] = (R)((a20 * J[0] + a21 * J[1] + a22 * J[2] + a23 * J[3]) * id);
+        Sr[3] = (R)((a30 * J[0] + a31 * J[1] + a32 * J[2] + a33 * J[3]) * id);
+        return;
+    }
+    double nrm = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        nrm = fmax(nrm, fabs(M[4 * i]) + fabs(M[4 * i + 1]) + fabs(M[4 * i + 2]) + fabs(M[4 * i + 3]) + fabs(J[i]));
+    int k = 0;
+    while (nrm > 0.25) {
+        nrm *= 0.5;
+        ++k;
+    }
+    const double sc = ldexp(1.0, -k);
+    double B[16], b[4];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) B[m] = -M[m] * sc;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) b[m] = J[m] * sc;
+    // P = I + B/14; P = I + (B P)/i for i = 13 .. 1 (pairs (E, v))
+    double E[16], v[4];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) E[m] = ((m % 5) == 0 ? 1.0 : 0.0) + B[m] * (1.0 / 14.0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = b[m] * (1.0 / 14.0);
+    for (int i = 13; i >= 1; --i) {
+        double T[16], w[4];
+        mat4_mul(B, E, T);
+        const double ri = 1.0 / (double)i;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            w[r] = (B[4 * r] * v[0] + B[4 * r + 1] * v[1] + B[4 * r + 2] * v[2] + B[4 * r + 3] * v[3] + b[r]) * ri;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) E[m] = ((m % 5) == 0 ? 1.0 : 0.0) + T[m] * ri;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) v[m] = w[m];
+    }
+    for (int q = 0; q < k; ++q) {   // [[E, v], [0, 1]]^2 = [[E E, E v + v], [0, 1]]
+        double T[16], w[4];
+        mat4_mul(E, E, T);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            w[r] = E[4 * r] * v[0] + E[4 * r + 1] * v[1] + E[4 * r + 2] * v[2] + E[4 * r + 3] * v[3] + v[r];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) E[m] = T[m];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) v[m] = w[m];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        Sr[r] = (R)(E[4 * r] * S0[0] + E[4 * r + 1] * S0[1] + E[4 * r + 2] * S0[2] + E[4 * r + 3] * S0[3] + v[r]);
+}
+
 // unpolarized segment, eq. (unpolarized), with j and alpha carrying the length:
 // e^{-dtau} (I + (e^{dtau} - 1) j/dtau) written as I + (e^{-dtau} - 1) (I - j/dtau),
 // which cannot overflow in FP32 below the cut at 100 and keeps a thin
@@ -618,7 +717,7 @@ __device__ __forceinline__ void accumulate_averages(RayWalk<R> &w, const Sample<
 
 // Process piece w.p of the open step (AVG: the unpolarized walk of the
 // averages pass).
-template <bool POL, typename R, bool CUTS = false, bool AVG = false>
+template <bool POL, typename R, bool CUTS = false, bool AVG = false, bool NTH = false>
 __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
                                       const QuartLds<R> &s_q, int lane) {
     const int flat = P.flat;
@@ -645,7 +744,7 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
     w.p = p - 1;
     Sample<R> smp;
     smp.plasma = false;
-    if (w.inb) sample_point<R, CUTS>(P.a, flat, g, pp, ys, (double)w.n_norm, smp);
+    if (w.inb) sample_point<R, CUTS, NTH>(P.a, flat, g, pp, ys, (double)w.n_norm, smp);
     R c[8];
     if (smp.plasma) {
         R lt = w.L * w.dl * smp.omega;
@@ -719,7 +818,8 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
         }
     }
     if (stk) {
-        stokes_step(c, S);
+        if constexpr (NTH) stokes_step_general(c, S);
+        else stokes_step(c, S);
         pack_screen(e1, e2, S, w.N);
         w.fresh = true;
     }
@@ -849,7 +949,7 @@ __device__ __forceinline__ void write_averages(const RayWalk<R> &w, double lambd
 }
 
 // Whole ray by one lane (used where rays are not interleaved).
-template <bool POL, typename R, bool CUTS = false, bool AVG = false>
+template <bool POL, typename R, bool CUTS = false, bool AVG = false, bool NTH = false>
 __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &g, const PlasmaParams &pp,
                                              const TransferParams &tp, const double *rec, int n_acc, double kt,
                                              double den, const double upix[4], const double Hv[4],
@@ -861,7 +961,7 @@ __device__ __forceinline__ void transfer_ray(const GeoParams &P, const DevGrid &
     begin_ray(w, rec, n_acc, kt, den, tp);
     while (w.st >= 0 || w.p >= 0) {
         if (w.p < 0) next_step(w, s_q, lane);
-        piece<POL, R, CUTS, AVG>(w, P, g, pp, s_q, lane);
+        piece<POL, R, CUTS, AVG, NTH>(w, P, g, pp, s_q, lane);
     }
     finish_ray<POL, R>(w, P, upix, Hv, o);
     if constexpr (AVG) write_averages(w, lambda, NN, pix, avg);

@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(256) k_order_scatter(const int *__restrict__ w
 template <bool POL, typename R, bool AVG>
 constexpr int transfer_waves() { return sizeof(R) == 4 ? (POL || AVG ? 3 : 4) : (POL ? 1 : 2); }
 
-template <bool POL, typename R, bool BATCH, bool CUTS, bool AVG = false>
+template <bool POL, typename R, bool BATCH, bool CUTS, bool AVG = false, bool NTH = false>
 __global__ void __launch_bounds__(64, (transfer_waves<POL, R, AVG>())) k_transfer(GeoParams P, Batch B, DevGrid g,
                                                                              PlasmaParams pp, TransferParams tp,
                                                  long long start, int count, int refill_min,
@@ -405,7 +405,7 @@ __global__ void __launch_bounds__(64, (transfer_waves<POL, R, AVG>())) k_transfe
                 next_step(w, s_q, lane);
             }
         }
-        if (slot >= 0) piece<POL, R, CUTS, AVG>(w, Pl, g, pp, s_q, lane);
+        if (slot >= 0) piece<POL, R, CUTS, AVG, NTH>(w, Pl, g, pp, s_q, lane);
     }
 }
 
@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(64) k_finish(GeoParams P, Batch B, long long s
 
 // Rays queued by k_geodesic: one wave, each lane traces and transfers its
 // rays in turn with a private buffer of big_cap records.
-template <bool POL, typename R, bool CUTS, bool AVG = false>
+template <bool POL, typename R, bool CUTS, bool AVG = false, bool NTH = false>
 __global__ void __launch_bounds__(64) k_overflow(GeoParams P, Batch B, DevGrid g, PlasmaParams pp, TransferParams tp,
                                                  const int *__restrict__ ovf_count, const int *__restrict__ ovf_list,
                                                  double *__restrict__ big_rec, int big_cap) {
@@ -479,7 +479,7 @@ __global__ void __launch_bounds__(64) k_overflow(GeoParams P, Batch B, DevGrid g
             aux[BL_AUX_NACC * NN + pix] = (double)o.n_acc;
             aux[BL_AUX_NREJ * NN + pix] = (double)o.n_rej;
             aux[BL_AUX_STATUS * NN + pix] = (double)o.status;
-            transfer_ray<POL, R, CUTS>(Q, g, pp, tl, r, o.n_acc, kt, den, upix, im.fr.H, t);
+            transfer_ray<POL, R, CUTS, false, NTH>(Q, g, pp, tl, r, o.n_acc, kt, den, upix, im.fr.H, t);
             write_pixel(t, NN, pix, im.image, aux);
         }
     }
@@ -912,7 +912,7 @@ __global__ void k_eval_samples(double a, int flat, DevGrid g, PlasmaParams pp, l
     conn_k(a, flat, y, y + 4, G);
     for (int m = 0; m < 16; ++m) o[8 + m] = G[m];
     Sample<double> s;
-    sample_point<double, true>(a, flat, g, pp, y, norms[i], s);
+    sample_point<double, true, true>(a, flat, g, pp, y, norms[i], s);
     o[53] = s.sigma;
     if (!s.plasma) return;
     // invariants: j/nu^2, alpha nu, rho nu at the fluid-frame frequency
@@ -971,6 +971,8 @@ struct RenderBuffers {
     size_t ends_bytes = 0;
     CutParams *d_cuts = nullptr;         // device copy of the data cuts, uploaded with each render
     size_t cuts_bytes = 0;
+    NthParams *d_nth = nullptr;          // device copy of the nonthermal populations' constants
+    size_t nth_bytes = 0;
 };
 
 // Bump allocator over the static scratch array (allocation-free renders).
@@ -992,9 +994,10 @@ struct bl_context {
     bl_tuning tuning = {8, 8, 0, 4, 0, 0, 0};   // the autotuner's choice for the 1024^2 SMR image
     size_t ws_limit = (size_t)128 << 30;   // bytes of step records per chunk (set at creation)
     int cus = 0;
-    int blocks_tr[10] = {0};              // resident waves per CU of k_transfer<pol, R, batch>:
+    int blocks_tr[14] = {0};              // resident waves per CU of k_transfer<pol, R, batch>:
                                          // [4 batch + 2 pol + (R == float)]; [8 + (R == float)]:
-                                         // the averages instantiation
+                                         // the averages instantiation; [10 + 2 pol + (R == float)]:
+                                         // the nonthermal one
     // step-proposal network installed by bl_set_step_model (packed form)
     u32x4 *d_step_pk = nullptr;
     float *d_step_tail = nullptr;
@@ -1148,6 +1151,8 @@ bl_status check_camera(bl_context *ctx, const bl_camera *cam) {
     if (!(cam->width > 0.0) || !(cam->r > 0.0) || !(cam->nu_hz > 0.0))
         return fail(ctx, BL_E_INVALID_ARG, "camera width, r and nu_hz must be positive");
     if (cam->freq_mode != 0 && cam->freq_mode != 1) return fail(ctx, BL_E_INVALID_ARG, "freq_mode must be 0 or 1");
+    if (cam->kind != 0)
+        return fail(ctx, BL_E_UNSUPPORTED, "only the plane-parallel camera (kind 0) is built");
     return BL_OK;
 }
 
@@ -1229,6 +1234,8 @@ PlasmaParams plasma_params(const bl_context *ctx, const bl_plasma *plasma, const
     pp.gauss_per_b = kC * sqrt(4.0 * kPi * g.rho_unit);
     pp.cuts = ctx->has_cuts ? 1 : 0;
     pp.cut = ctx->rb.d_cuts;
+    pp.nonthermal = 0;
+    pp.nth = ctx->rb.d_nth;
     return pp;
 }
 
@@ -1292,6 +1299,82 @@ bl_status upload_cuts(bl_context *ctx) {
     return BL_OK;
 }
 
+// Electron populations of a plasma (paper sections 2.6 and 4.5): validation
+// and the fractions (all zero: thermal electrons only).
+bl_status nth_fractions(bl_context *ctx, const bl_plasma *pl, double fr[3]) {
+    fr[0] = pl->fractions[0];
+    fr[1] = pl->fractions[1];
+    fr[2] = pl->fractions[2];
+    if (fr[0] == 0.0 && fr[1] == 0.0 && fr[2] == 0.0) fr[0] = 1.0;
+    if (!(fr[0] >= 0.0) || !(fr[1] >= 0.0) || !(fr[2] >= 0.0) || !(fabs(fr[0] + fr[1] + fr[2] - 1.0) <= 1e-9))
+        return fail(ctx, BL_E_INVALID_ARG, "electron fractions must be non-negative and sum to 1");
+    if (fr[1] > 0.0 && !(pl->pl_p > 1.0 && pl->pl_gamma_min >= 1.0 && pl->pl_gamma_max > pl->pl_gamma_min &&
+                         std::isfinite(pl->pl_gamma_max)))
+        return fail(ctx, BL_E_INVALID_ARG, "power law needs p > 1 and 1 <= gamma_min < gamma_max < inf");
+    if (fr[2] > 0.0 && !(pl->kappa >= 2.5 && std::isfinite(pl->kappa) && pl->kappa_w > 0.0 &&
+                         std::isfinite(pl->kappa_w)))
+        return fail(ctx, BL_E_INVALID_ARG, "kappa distribution needs kappa >= 2.5 and w > 0");
+    return BL_OK;
+}
+
+// int_1^inf gamma^s gamma sqrt(gamma^2 - 1) (1 + (gamma - 1)/(kappa w))^-(kappa+1) dgamma
+// by the trapezoid rule in v = ln(gamma - 1) over [-80, 100] (the integrand
+// times e^v decays exponentially at both ends for kappa >= 2.5, s <= 0),
+// each term formed from its logarithm.
+double kappa_moment(double kap, double w, double s) {
+    const double h = 0.0025, kw = kap * w;
+    double sum = 0.0;
+    for (int i = 0; i <= 72000; ++i) {
+        const double v = -80.0 + i * h;
+        const double t = exp(v), lg = log1p(t);
+        const double lf = lg * (1.0 + s) + 0.5 * (v + log(2.0 + t)) - (kap + 1.0) * log1p(t / kw) + v;
+        sum += exp(lf);
+    }
+    return sum * h;
+}
+
+// The power-law terms of NthParams for dn/dgamma = n_e C gamma^-p.
+void nth_powerlaw_terms(NthParams &q, int k, double p, double C) {
+    q.lhj[k] = log(C) + 0.5 * p * log(3.0) - log(2.0 * (p + 1.0)) + lgamma((3.0 * p - 1.0) / 12.0) +
+               lgamma((3.0 * p + 19.0) / 12.0);
+    q.ej[k] = -0.5 * (p - 1.0);
+    q.lhjq[k] = log((p + 1.0) / (p + 7.0 / 3.0));
+    q.lha[k] = log(C) + 0.5 * (p + 1.0) * log(3.0) - log(4.0) + lgamma((3.0 * p + 2.0) / 12.0) +
+               lgamma((3.0 * p + 22.0) / 12.0);
+    q.ea[k] = -0.5 * (p + 2.0);
+    q.lhaq[k] = log((p + 2.0) / (p + 10.0 / 3.0));
+}
+
+// Device copy of the populations' constants for the launches that follow
+// (only when a nonthermal population is present).
+bl_status upload_nth(bl_context *ctx, const bl_plasma *pl, bool &active) {
+    double fr[3];
+    bl_status s;
+    if ((s = nth_fractions(ctx, pl, fr)) != BL_OK) return s;
+    active = fr[1] > 0.0 || fr[2] > 0.0;
+    if (!active) return BL_OK;
+    NthParams q{};
+    for (int k = 0; k < 3; ++k) q.frac[k] = fr[k];
+    if (fr[1] > 0.0) {
+        const double p = pl->pl_p;
+        nth_powerlaw_terms(q, 0, p, (p - 1.0) / (pow(pl->pl_gamma_min, 1.0 - p) - pow(pl->pl_gamma_max, 1.0 - p)));
+    }
+    if (fr[2] > 0.0) {
+        const double kap = pl->kappa, w = pl->kappa_w, kw = kap * w;
+        const double z0 = kappa_moment(kap, w, 0.0);
+        nth_powerlaw_terms(q, 1, kap - 1.0, pow(kw, kap + 1.0) / z0);
+        // F(x) ~ (4 pi/(sqrt3 Gamma(1/3))) (x/2)^1/3 for small x, x/2 = X/(3 gamma^2)
+        const double g13 = tgamma(1.0 / 3.0);
+        q.llj = log(2.0 * kPi / g13) - log(3.0) / 3.0 + log(kappa_moment(kap, w, -2.0 / 3.0) / z0);
+        q.lla = log(4.0 * kPi / (3.0 * g13)) - log(3.0) / 3.0 + log(kappa_moment(kap, w, -5.0 / 3.0) / z0);
+    }
+    if ((s = ensure(ctx, &ctx->rb.d_nth, ctx->rb.nth_bytes, sizeof(NthParams))) != BL_OK) return s;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->rb.d_nth, &q, sizeof(NthParams), hipMemcpyHostToDevice, ctx->stream));
+    // the host struct is a local: wait for the copy to have read it
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return BL_OK;
+}
+
 // What the geodesic kernels store with each record for the transfer: the grid
 // box and piece length for the sampling decision, and the FP32-quartic layout
 // for the mixed form (whose transfer kernels read it).
@@ -1325,7 +1408,7 @@ struct TimedLaunch {
 // Waves per CU of each persistent transfer kernel that fit at once.
 bl_status persistent_waves(bl_context *ctx) {
     if (ctx->cus > 0) return BL_OK;
-    int cus = 0, b[10] = {0};
+    int cus = 0, b[14] = {0};
     HIPCHK(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
     HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[0], k_transfer<false, double, false, false>, 64, 0));
     HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[1], k_transfer<false, float, false, false>, 64, 0));
@@ -1337,7 +1420,11 @@ bl_status persistent_waves(bl_context *ctx) {
     HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[7], k_transfer<true, float, true, false>, 64, 0));
     HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[8], k_transfer<false, double, false, false, true>, 64, 0));
     HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[9], k_transfer<false, float, false, false, true>, 64, 0));
-    for (int k = 0; k < 10; ++k) ctx->blocks_tr[k] = std::max(1, b[k]);
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[10], k_transfer<false, double, false, false, false, true>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[11], k_transfer<false, float, false, false, false, true>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[12], k_transfer<true, double, false, false, false, true>, 64, 0));
+    HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[13], k_transfer<true, float, false, false, false, true>, 64, 0));
+    for (int k = 0; k < 14; ++k) ctx->blocks_tr[k] = std::max(1, b[k]);
     ctx->cus = std::max(1, cus);
     return BL_OK;
 }
@@ -1441,22 +1528,22 @@ bl_status upload_one(bl_context *ctx, const bl_camera *cam, const bl_spacetime *
     return upload_images(ctx, 1, &cam, &st, &image, &aux, t, B, total);
 }
 
-template <bool POL, typename R, bool BATCH, bool CUTS, bool AVG = false>
+template <bool POL, typename R, bool BATCH, bool CUTS, bool AVG = false, bool NTH = false>
 void launch_transfer(bl_context *ctx, dim3 grd, const GeoParams &P, const Batch &B, const DevGrid &g,
                      const PlasmaParams &pp, const TransferParams &tp, long long start, int count, int refill,
                      int *q) {
     R *ends = reinterpret_cast<R *>(ctx->rb.d_ends);
-    hipLaunchKernelGGL((k_transfer<POL, R, BATCH, CUTS, AVG>), grd, dim3(64), 0, ctx->stream, P, B, g, pp, tp, start, count,
+    hipLaunchKernelGGL((k_transfer<POL, R, BATCH, CUTS, AVG, NTH>), grd, dim3(64), 0, ctx->stream, P, B, g, pp, tp, start, count,
                        refill, ctx->rb.d_rec, ctx->rb.d_meta, ctx->rb.d_nacc, ctx->rb.d_order, ctx->rb.ext, q, ends);
     if (POL)
         hipLaunchKernelGGL((k_finish<R, BATCH>), dim3((count + 63) / 64), dim3(64), 0, ctx->stream, P, B, start, count,
                            ctx->rb.d_rec, ctx->rb.d_nacc, ctx->rb.ext, (const R *)ends);
 }
 
-template <bool POL, typename R, bool CUTS, bool AVG = false>
+template <bool POL, typename R, bool CUTS, bool AVG = false, bool NTH = false>
 void launch_overflow(bl_context *ctx, const GeoParams &P, const Batch &B, const DevGrid &g, const PlasmaParams &pp,
                      const TransferParams &tp, int big_cap) {
-    hipLaunchKernelGGL((k_overflow<POL, R, CUTS, AVG>), dim3(1), dim3(64), 0, ctx->stream, P, B, g, pp, tp, ctx->rb.d_ovf_count,
+    hipLaunchKernelGGL((k_overflow<POL, R, CUTS, AVG, NTH>), dim3(1), dim3(64), 0, ctx->stream, P, B, g, pp, tp, ctx->rb.d_ovf_count,
                        ctx->rb.d_ovf_list, ctx->rb.d_big, big_cap);
 }
 
@@ -1478,7 +1565,11 @@ bl_status overflow_all(bl_context *ctx, const Batch &B, const GeoParams &P, cons
         TransferParams tpf = tp;
         tpf.nu_cam = cams[f]->nu_hz;
         TimedLaunch tl(ctx, BL_K_OVERFLOW);
-        switch ((kidx & 3) + (pp.cuts ? 4 : 0)) {
+        switch ((kidx & 3) + (pp.nonthermal ? 8 : (pp.cuts ? 4 : 0))) {
+        case 8: launch_overflow<false, double, false, false, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 9: launch_overflow<false, float, false, false, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 10: launch_overflow<true, double, false, false, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
+        case 11: launch_overflow<true, float, false, false, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
         case 0: launch_overflow<false, double, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
         case 1: launch_overflow<false, float, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
         case 2: launch_overflow<true, double, false>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
@@ -1523,7 +1614,8 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         return fail(ctx, BL_E_INVALID_ARG, "step_model must be 0 (controller) or 1 (learned)");
     const bool learned = mode && mode->step_model == 1;
     if (learned && !ctx->has_step_model)
-        return fail(ctx, BL_E_INVALID_ARG, "step_model 1 needs a network installed with bl_set_step_model");
+        return fail(ctx, BL_E_STATE, "step_model 1 needs a network installed with bl_set_step_model");
+    if (grid && grid->ctx != ctx) return fail(ctx, BL_E_STATE, "the grid belongs to another context");
     const bool mixed = mode && mode->precision == 1;
     if (grid->g.dtype != 0 && !mixed) return fail(ctx, BL_E_UNSUPPORTED, "float32 grids need precision 1");
     if (!(plasma->mu > 0.0) || !(plasma->ne_ni > 0.0) || !(plasma->sigma_max >= 0.0))
@@ -1584,7 +1676,13 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, ctx->rb.d_ovf_count, 0, 1);
     HIPCHK(ctx, hipGetLastError());
     if ((s = upload_cuts(ctx)) != BL_OK) return s;
-    const PlasmaParams pp = plasma_params(ctx, plasma, grid->g, sts[0]->mass_msun);
+    bool nth = false;
+    if ((s = upload_nth(ctx, plasma, nth)) != BL_OK) return s;
+    if (nth && (batch || ctx->has_cuts || avg))
+        return fail(ctx, BL_E_UNSUPPORTED,
+                    "nonthermal electrons are rendered by single-image renders without data cuts or averages");
+    PlasmaParams pp = plasma_params(ctx, plasma, grid->g, sts[0]->mass_msun);
+    pp.nonthermal = nth ? 1 : 0;
     TransferParams tp;
     tp.ds_max = integ->ds_max;
     tp.L = kG * sts[0]->mass_msun * kMsun / (kC * kC);
@@ -1596,7 +1694,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
                        (int)nqueue);
     HIPCHK(ctx, hipGetLastError());
     const int kidx = 4 * (batch ? 1 : 0) + 2 * pp.polarized + (mixed ? 1 : 0);
-    int per_cu = ctx->blocks_tr[kidx];
+    int per_cu = ctx->blocks_tr[nth ? 10 + 2 * pp.polarized + (mixed ? 1 : 0) : kidx];
     if (t.transfer_waves_per_cu > 0) per_cu = std::min(per_cu, t.transfer_waves_per_cu);
     const int resident = per_cu * ctx->cus;
     long long ichunk = 0;
@@ -1652,8 +1750,12 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
             TimedLaunch tl(ctx, BL_K_TRANSFER);
             int *q = ctx->rb.d_queue + 2 * (ichunk * n_q + f);
             dim3 pg(std::min<int>(grd.x, resident));
-            const int kc = kidx + (pp.cuts ? 8 : 0);
+            const int kc = nth ? 16 + kidx : kidx + (pp.cuts ? 8 : 0);
             switch (kc) {
+            case 16: launch_transfer<false, double, false, false, false, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 17: launch_transfer<false, float, false, false, false, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 18: launch_transfer<true, double, false, false, false, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
+            case 19: launch_transfer<true, float, false, false, false, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
             case 0: launch_transfer<false, double, false, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
             case 1: launch_transfer<false, float, false, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
             case 2: launch_transfer<true, double, false, false>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
@@ -2566,7 +2668,10 @@ bl_status bl_eval_samples(bl_context *ctx, const bl_spacetime *st, const bl_grid
     if (n == 0) return BL_OK;
     HIPCHK(ctx, hipSetDevice(ctx->device));
     if ((s = upload_cuts(ctx)) != BL_OK) return s;
-    const PlasmaParams pp = plasma_params(ctx, plasma, grid->g, st->mass_msun);
+    bool nth = false;
+    if ((s = upload_nth(ctx, plasma, nth)) != BL_OK) return s;
+    PlasmaParams pp = plasma_params(ctx, plasma, grid->g, st->mass_msun);
+    pp.nonthermal = nth ? 1 : 0;
     hipLaunchKernelGGL(k_eval_samples, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, ctx->stream, st->a,
                        st->flat ? 1 : 0, grid->g, pp, (long long)n, states, norms, out);
     HIPCHK(ctx, hipGetLastError());
