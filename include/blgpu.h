@@ -377,6 +377,27 @@ bl_status bl_render_multifreq(bl_context *ctx, const bl_camera *cam, const bl_sp
                               const bl_mode *mode, int32_t n_freq, const double *nu_hz,
                               double *const *images_out, double *const *aux_out);
 
+/* One camera and one set of geodesics, several plasma models (paper
+   section 5: an imaging study varies the frequency and the electron model of
+   a snapshot for a fixed camera; section 4.8: images at several frequencies
+   for fixed camera and data).  Neither the frequency nor the plasma enters
+   the geodesic equation, so each chunk of rays is traced once and the
+   transfer runs once per output on the same step records, each with its own
+   frequency and its own bl_plasma: electron temperature prescription
+   (R_high, R_low), sigma_max, mu, ne/ni, polarized or not, interpolation and
+   electron populations may all differ between outputs.  nu_hz: host
+   [n_out] frequencies (Hz, positive, finite) or NULL for cam->nu_hz in every
+   output; plasmas: host [n_out] structs, read during the call;
+   1 <= n_out <= 4096; images_out, aux_out: host arrays of n_out device
+   pointers, each an output as for bl_render.  Output f equals bl_render
+   with cam->nu_hz = nu_hz[f] and plasmas[f], aux maps included.  The
+   restrictions of bl_render apply per output (nonthermal populations
+   without data cuts: BL_E_UNSUPPORTED).  Uses the context's tuning. */
+bl_status bl_render_models(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st,
+                           const bl_integrator *integ, const bl_grid *grid, int32_t n_out,
+                           const double *nu_hz, const bl_plasma *plasmas, const bl_mode *mode,
+                           double *const *images_out, double *const *aux_out);
+
 /* Autotuner: times bl_render_batch of the given images (which it renders,
    into their outputs, several times) under a coordinate search over tile
    shape, transfer waves per CU, refill threshold, chunk size and image

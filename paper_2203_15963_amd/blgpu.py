@@ -186,6 +186,10 @@ def load():
                                       vp, C.POINTER(bl_plasma), C.POINTER(bl_mode), i32, C.POINTER(C.c_double),
                                       C.POINTER(vp), C.POINTER(vp)]
     L.bl_render_multifreq.restype = C.c_int
+    L.bl_render_models.argtypes = [vp, C.POINTER(bl_camera), C.POINTER(bl_spacetime), C.POINTER(bl_integrator),
+                                   vp, i32, C.POINTER(C.c_double), C.POINTER(bl_plasma), C.POINTER(bl_mode),
+                                   C.POINTER(vp), C.POINTER(vp)]
+    L.bl_render_models.restype = C.c_int
     L.bl_render_averages.argtypes = [vp, C.POINTER(bl_camera), C.POINTER(bl_spacetime), C.POINTER(bl_integrator),
                                      vp, C.POINTER(bl_plasma), C.POINTER(bl_mode), vp, vp, vp]
     L.bl_render_averages.restype = C.c_int
@@ -443,6 +447,23 @@ class Context:
         axs = (C.c_void_p * k)(*[ax.data_ptr() for _, ax in outs])
         self._check(load().bl_render_multifreq(self.handle, C.byref(c), C.byref(s), C.byref(g), grid.handle,
                                                C.byref(p), C.byref(m), k, nus, ims, axs))
+        return outs
+
+    def render_models(self, cam, st, integ, grid, plasmas, nu_hz=None, precision=0, step_model=0, outputs=None):
+        """One camera, one geodesic pass, one output per plasma model (list of
+        plasma dicts) at nu_hz[k] (or cam["nu_hz"] for all when None);
+        returns a list of (image, aux) tensors."""
+        n, k = int(cam["n"]), len(plasmas)
+        if nu_hz is not None and len(nu_hz) != k:
+            raise ValueError("one frequency per plasma model")
+        outs = outputs if outputs is not None else [(self._empty(4, n, n), self._empty(NAUX, n, n)) for _ in range(k)]
+        c, s, g, m = camera(cam), spacetime(st), integrator(integ), mode(precision, step_model)
+        pls = (bl_plasma * k)(*[plasma(p) for p in plasmas])
+        nus = None if nu_hz is None else (C.c_double * k)(*[float(v) for v in nu_hz])
+        ims = (C.c_void_p * k)(*[im.data_ptr() for im, _ in outs])
+        axs = (C.c_void_p * k)(*[ax.data_ptr() for _, ax in outs])
+        self._check(load().bl_render_models(self.handle, C.byref(c), C.byref(s), C.byref(g), grid.handle, k, nus,
+                                            pls, C.byref(m), ims, axs))
         return outs
 
     def _batch_descs(self, images, outputs):

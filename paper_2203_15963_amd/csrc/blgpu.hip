@@ -1345,15 +1345,15 @@ void nth_powerlaw_terms(NthParams &q, int k, double p, double C) {
     q.lhaq[k] = log((p + 2.0) / (p + 10.0 / 3.0));
 }
 
-// Device copy of the populations' constants for the launches that follow
-// (only when a nonthermal population is present).
-bl_status upload_nth(bl_context *ctx, const bl_plasma *pl, bool &active) {
+// Host constants of a plasma's electron populations; active: a nonthermal
+// population is present.
+bl_status nth_params(bl_context *ctx, const bl_plasma *pl, NthParams &q, bool &active) {
     double fr[3];
     bl_status s;
     if ((s = nth_fractions(ctx, pl, fr)) != BL_OK) return s;
     active = fr[1] > 0.0 || fr[2] > 0.0;
+    q = NthParams{};
     if (!active) return BL_OK;
-    NthParams q{};
     for (int k = 0; k < 3; ++k) q.frac[k] = fr[k];
     if (fr[1] > 0.0) {
         const double p = pl->pl_p;
@@ -1368,10 +1368,35 @@ bl_status upload_nth(bl_context *ctx, const bl_plasma *pl, bool &active) {
         q.llj = log(2.0 * kPi / g13) - log(3.0) / 3.0 + log(kappa_moment(kap, w, -2.0 / 3.0) / z0);
         q.lla = log(4.0 * kPi / (3.0 * g13)) - log(3.0) / 3.0 + log(kappa_moment(kap, w, -5.0 / 3.0) / z0);
     }
-    if ((s = ensure(ctx, &ctx->rb.d_nth, ctx->rb.nth_bytes, sizeof(NthParams))) != BL_OK) return s;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->rb.d_nth, &q, sizeof(NthParams), hipMemcpyHostToDevice, ctx->stream));
-    // the host struct is a local: wait for the copy to have read it
+    return BL_OK;
+}
+
+// Device copies of the populations' constants of n plasmas for the launches
+// that follow, one slot each (uploaded only when one of them has a nonthermal
+// population), and each plasma's PlasmaParams pointed at its slot.
+bl_status upload_nth(bl_context *ctx, int n, const bl_plasma *const *pls, PlasmaParams *pps) {
+    // no host allocation for one plasma (the allocation-free render)
+    NthParams q1{};
+    std::vector<NthParams> qv;
+    NthParams *q = &q1;
+    if (n > 1) {
+        qv.resize(n);
+        q = qv.data();
+    }
+    bool any = false;
+    bl_status s;
+    for (int f = 0; f < n; ++f) {
+        bool a = false;
+        if ((s = nth_params(ctx, pls[f], q[f], a)) != BL_OK) return s;
+        pps[f].nonthermal = a ? 1 : 0;
+        any = any || a;
+    }
+    if (!any) return BL_OK;
+    if ((s = ensure(ctx, &ctx->rb.d_nth, ctx->rb.nth_bytes, (size_t)n * sizeof(NthParams))) != BL_OK) return s;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->rb.d_nth, q, (size_t)n * sizeof(NthParams), hipMemcpyHostToDevice, ctx->stream));
+    // the host structs are locals: wait for the copy to have read them
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int f = 0; f < n; ++f) pps[f].nth = ctx->rb.d_nth + f;
     return BL_OK;
 }
 
@@ -1554,18 +1579,19 @@ void launch_overflow(bl_context *ctx, const GeoParams &P, const Batch &B, const 
 // one camera at the frequencies of a multi-frequency render: the geodesics
 // are traced once per chunk and the transfer runs once per frequency on the
 // same step records, each writing its own image and aux.
-// The overflow kernel over the rays queued so far, once per frequency: rays
-// longer than the extension slots are traced again for each.
+// The overflow kernel over the rays queued so far, once per output (frequency
+// and plasma): rays longer than the extension slots are traced again for each.
 bl_status overflow_all(bl_context *ctx, const Batch &B, const GeoParams &P, const bl_grid *grid,
-                       const PlasmaParams &pp, const TransferParams &tp, const bl_camera *const *cams, int n_tr,
-                       int kidx, int big_cap) {
+                       const PlasmaParams *pps, const TransferParams &tp, const bl_camera *const *cams, int n_tr,
+                       bool mixed, int big_cap) {
     for (int f = 0; f < n_tr; ++f) {
         Batch Bf = B;
         Bf.imgs = B.imgs + f;
         TransferParams tpf = tp;
         tpf.nu_cam = cams[f]->nu_hz;
+        const PlasmaParams &pp = pps[f];
         TimedLaunch tl(ctx, BL_K_OVERFLOW);
-        switch ((kidx & 3) + (pp.nonthermal ? 8 : (pp.cuts ? 4 : 0))) {
+        switch (2 * pp.polarized + (mixed ? 1 : 0) + (pp.nonthermal ? 8 : (pp.cuts ? 4 : 0))) {
         case 8: launch_overflow<false, double, false, false, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
         case 9: launch_overflow<false, float, false, false, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
         case 10: launch_overflow<true, double, false, false, true>(ctx, P, Bf, grid->g, pp, tpf, big_cap); break;
@@ -1596,7 +1622,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
                         double *const *images, double *const *auxs, const bl_integrator *integ, const bl_grid *grid,
                         const bl_plasma *plasma, const bl_mode *mode, const bl_tuning &t, bool batch,
                         int n_freq = 0, double *avg = nullptr, const int *sub = nullptr,
-                        const RenderOpts &opt = RenderOpts()) {
+                        const RenderOpts &opt = RenderOpts(), const bl_plasma *const *tr_plasmas = nullptr) {
     bl_status s;
     if ((s = check_integrator(ctx, integ)) != BL_OK || (s = check_tuning(ctx, &t)) != BL_OK) return s;
     if (n_freq > 0 && (n != 1 || batch)) return fail(ctx, BL_E_INVALID_ARG, "a multi-frequency render has one image");
@@ -1608,6 +1634,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         if (!images[k] || !auxs[k]) return fail(ctx, BL_E_INVALID_ARG, "image and aux outputs must be non-NULL");
     }
     if (!grid || !plasma) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
+    if (tr_plasmas && n_freq < 1) return fail(ctx, BL_E_INVALID_ARG, "per-output plasmas need a multi-output render");
     if (mode && (mode->precision < 0 || mode->precision > 1))
         return fail(ctx, BL_E_INVALID_ARG, "precision must be 0 (FP64) or 1 (mixed)");
     if (mode && (mode->step_model < 0 || mode->step_model > 1))
@@ -1618,8 +1645,16 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     if (grid && grid->ctx != ctx) return fail(ctx, BL_E_STATE, "the grid belongs to another context");
     const bool mixed = mode && mode->precision == 1;
     if (grid->g.dtype != 0 && !mixed) return fail(ctx, BL_E_UNSUPPORTED, "float32 grids need precision 1");
-    if (!(plasma->mu > 0.0) || !(plasma->ne_ni > 0.0) || !(plasma->sigma_max >= 0.0))
-        return fail(ctx, BL_E_INVALID_ARG, "plasma mu, ne_ni must be positive and sigma_max >= 0");
+    // the plasma of each output (the same one unless the caller gives one per
+    // output of a multi-output render)
+    const bl_plasma *pl1 = plasma;
+    const bl_plasma *const *pls = tr_plasmas ? tr_plasmas : &pl1;
+    for (int f = 0; f < (tr_plasmas ? n_tr : 1); ++f) {
+        const bl_plasma *pl = pls[f];
+        if (!pl) return fail(ctx, BL_E_INVALID_ARG, "NULL plasma");
+        if (!(pl->mu > 0.0) || !(pl->ne_ni > 0.0) || !(pl->sigma_max >= 0.0))
+            return fail(ctx, BL_E_INVALID_ARG, "plasma mu, ne_ni must be positive and sigma_max >= 0");
+    }
     HIPCHK(ctx, hipSetDevice(ctx->device));
     if ((s = persistent_waves(ctx)) != BL_OK) return s;
     Batch B;
@@ -1676,13 +1711,27 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, ctx->stream, ctx->rb.d_ovf_count, 0, 1);
     HIPCHK(ctx, hipGetLastError());
     if ((s = upload_cuts(ctx)) != BL_OK) return s;
+    // each output's plasma constants (no host allocation for one output)
+    PlasmaParams pp1;
+    std::vector<PlasmaParams> ppv;
+    PlasmaParams *pps = &pp1;
+    if (tr_plasmas && n_tr > 1) {
+        ppv.resize(n_tr);
+        pps = ppv.data();
+    }
+    const int n_pl = tr_plasmas ? n_tr : 1;
+    for (int f = 0; f < n_pl; ++f) pps[f] = plasma_params(ctx, pls[f], grid->g, sts[0]->mass_msun);
+    if ((s = upload_nth(ctx, n_pl, pls, pps)) != BL_OK) return s;
     bool nth = false;
-    if ((s = upload_nth(ctx, plasma, nth)) != BL_OK) return s;
+    for (int f = 0; f < n_pl; ++f) nth = nth || pps[f].nonthermal;
     if (nth && (batch || ctx->has_cuts || avg))
         return fail(ctx, BL_E_UNSUPPORTED,
                     "nonthermal electrons are rendered by single-image renders without data cuts or averages");
-    PlasmaParams pp = plasma_params(ctx, plasma, grid->g, sts[0]->mass_msun);
-    pp.nonthermal = nth ? 1 : 0;
+    if (!tr_plasmas && n_tr > 1) {
+        ppv.assign(n_tr, pp1);
+        pps = ppv.data();
+    }
+    const PlasmaParams &pp = pps[0];
     TransferParams tp;
     tp.ds_max = integ->ds_max;
     tp.L = kG * sts[0]->mass_msun * kMsun / (kC * kC);
@@ -1693,10 +1742,18 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((nqueue + 63) / 64)), dim3(64), 0, ctx->stream, ctx->rb.d_queue, 0,
                        (int)nqueue);
     HIPCHK(ctx, hipGetLastError());
-    const int kidx = 4 * (batch ? 1 : 0) + 2 * pp.polarized + (mixed ? 1 : 0);
-    int per_cu = ctx->blocks_tr[nth ? 10 + 2 * pp.polarized + (mixed ? 1 : 0) : kidx];
-    if (t.transfer_waves_per_cu > 0) per_cu = std::min(per_cu, t.transfer_waves_per_cu);
-    const int resident = per_cu * ctx->cus;
+    // the transfer kernel of a plasma (its index in the launch switch) and
+    // the waves of it that fit at once
+    auto kernel_of = [&](const PlasmaParams &q) {
+        const int k = 4 * (batch ? 1 : 0) + 2 * q.polarized + (mixed ? 1 : 0);
+        return q.nonthermal ? 16 + k : k + (q.cuts ? 8 : 0);
+    };
+    auto resident_of = [&](const PlasmaParams &q) {
+        const int k = 2 * q.polarized + (mixed ? 1 : 0);
+        int per_cu = ctx->blocks_tr[q.nonthermal ? 10 + k : 4 * (batch ? 1 : 0) + k];
+        if (t.transfer_waves_per_cu > 0) per_cu = std::min(per_cu, t.transfer_waves_per_cu);
+        return per_cu * ctx->cus;
+    };
     long long ichunk = 0;
     for (long long start = 0; start < total; start += chunk, ++ichunk) {
         int count = (int)std::min(chunk, total - start);
@@ -1741,17 +1798,17 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         }
         HIPCHK(ctx, hipGetLastError());
         for (int f = 0; f < n_tr; ++f) {
-            // frequency f of a multi-frequency render: its image table entry
-            // (outputs, camera frequency) and its own queue counter
+            // output f of a multi-output render: its image table entry
+            // (outputs, camera frequency), its plasma and its own queue counter
             Batch Bf = B;
             Bf.imgs = B.imgs + f;
             TransferParams tpf = tp;
             tpf.nu_cam = cams[f]->nu_hz;
+            const PlasmaParams &pp = pps[f];
             TimedLaunch tl(ctx, BL_K_TRANSFER);
             int *q = ctx->rb.d_queue + 2 * (ichunk * n_q + f);
-            dim3 pg(std::min<int>(grd.x, resident));
-            const int kc = nth ? 16 + kidx : kidx + (pp.cuts ? 8 : 0);
-            switch (kc) {
+            dim3 pg(std::min<int>(grd.x, resident_of(pp)));
+            switch (kernel_of(pp)) {
             case 16: launch_transfer<false, double, false, false, false, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
             case 17: launch_transfer<false, float, false, false, false, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
             case 18: launch_transfer<true, double, false, false, false, true>(ctx, pg, P, Bf, grid->g, pp, tpf, start, count, t.refill_min, q); break;
@@ -1792,7 +1849,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
             HIPCHK(ctx, hipGetLastError());
         }
         if (opt.per_chunk_overflow)
-            if ((s = overflow_all(ctx, B, P, grid, pp, tp, cams, n_tr, kidx, big_cap)) != BL_OK) return s;
+            if ((s = overflow_all(ctx, B, P, grid, pps, tp, cams, n_tr, mixed, big_cap)) != BL_OK) return s;
     }
     if (avg) {
         PlasmaParams pa = pp;
@@ -1807,7 +1864,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         HIPCHK(ctx, hipGetLastError());
     }
     if (!opt.per_chunk_overflow)
-        if ((s = overflow_all(ctx, B, P, grid, pp, tp, cams, n_tr, kidx, big_cap)) != BL_OK) return s;
+        if ((s = overflow_all(ctx, B, P, grid, pps, tp, cams, n_tr, mixed, big_cap)) != BL_OK) return s;
     if (n_freq > 1) {
         // the geodesic maps (dt, s, lambda and n_acc, n_rej, status) were
         // written into the first frequency's aux
@@ -2303,6 +2360,29 @@ bl_status bl_render_multifreq(bl_context *ctx, const bl_camera *cam, const bl_sp
                          false, n_freq);
 }
 
+bl_status bl_render_models(bl_context *ctx, const bl_camera *cam, const bl_spacetime *st, const bl_integrator *integ,
+                          const bl_grid *grid, int32_t n_out, const double *nu_hz, const bl_plasma *plasmas,
+                          const bl_mode *mode, double *const *images_out, double *const *aux_out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    if (!cam || !st || !plasmas || !images_out || !aux_out) return fail(ctx, BL_E_INVALID_ARG, "NULL argument");
+    if (n_out < 1 || n_out > 4096) return fail(ctx, BL_E_INVALID_ARG, "need 1 <= n_out <= 4096");
+    std::vector<bl_camera> cams(n_out, *cam);
+    std::vector<const bl_camera *> cp(n_out);
+    std::vector<const bl_spacetime *> sp(n_out, st);
+    std::vector<const bl_plasma *> pl(n_out);
+    for (int f = 0; f < n_out; ++f) {
+        if (nu_hz) {
+            if (!(nu_hz[f] > 0.0) || !std::isfinite(nu_hz[f]))
+                return fail(ctx, BL_E_INVALID_ARG, "frequencies must be positive and finite");
+            cams[f].nu_hz = nu_hz[f];
+        }
+        cp[f] = &cams[f];
+        pl[f] = &plasmas[f];
+    }
+    return render_images(ctx, 1, cp.data(), sp.data(), images_out, aux_out, integ, grid, &plasmas[0], mode,
+                         ctx->tuning, false, n_out, nullptr, nullptr, RenderOpts(), pl.data());
+}
+
 bl_status bl_render_batch(bl_context *ctx, int32_t n_images, const bl_image_desc *images, const bl_integrator *integ,
                           const bl_grid *grid, const bl_plasma *plasma, const bl_mode *mode,
                           const bl_tuning *tuning) {
@@ -2668,10 +2748,8 @@ bl_status bl_eval_samples(bl_context *ctx, const bl_spacetime *st, const bl_grid
     if (n == 0) return BL_OK;
     HIPCHK(ctx, hipSetDevice(ctx->device));
     if ((s = upload_cuts(ctx)) != BL_OK) return s;
-    bool nth = false;
-    if ((s = upload_nth(ctx, plasma, nth)) != BL_OK) return s;
     PlasmaParams pp = plasma_params(ctx, plasma, grid->g, st->mass_msun);
-    pp.nonthermal = nth ? 1 : 0;
+    if ((s = upload_nth(ctx, 1, &plasma, &pp)) != BL_OK) return s;
     hipLaunchKernelGGL(k_eval_samples, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, ctx->stream, st->a,
                        st->flat ? 1 : 0, grid->g, pp, (long long)n, states, norms, out);
     HIPCHK(ctx, hipGetLastError());
