@@ -35,9 +35,9 @@ PUBLISHED_FP32_TFLOPS = 157.3
 # steps, acc = accepted steps, samp = plasma samples, rec = transport records
 # (pieces), ray = rays.
 OPS_PER_UNIT = {
-    "src": "947152047fe23941",
+    "src": "e4b1cca3f039ce1d",
     0: {"geodesic": {"F64": {"trial": 1291.6, "acc": 287.4, "ray": 1055.3}, "F32": {"trial": 11.0, "ray": 7.0}},
-        "transfer": {"F64": {"samp": 2713.6, "rec": 366.8, "acc": 52.3, "ray": 36328.8}, "F32": {}}},
+        "transfer": {"F64": {"samp": 2508.6, "rec": 366.8, "acc": 52.3, "ray": 36328.8}, "F32": {}}},
     1: {"geodesic": {"F64": {"trial": 1216.5, "acc": 424.2, "ray": 5321.1}, "F32": {"trial": 11.0, "ray": 7.0}},
         "transfer": {"F64": {"samp": 16.0, "rec": 30.8}, "F32": {"samp": 1448.5, "rec": 353.4, "ray": 50633.5}}},
 }
@@ -46,16 +46,21 @@ OPS_PER_UNIT = {
 # the sources whose hash is "src": issued floating-point operations
 # (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_{F32,F64} x 64 lanes, FMA = 2: masked
 # lanes included), VALU lane activity (SQ_THREAD_CYCLES_VALU over 64 x
-# SQ_ACTIVE_INST_VALU) and HBM bytes (FETCH_SIZE and WRITE_SIZE in KiB per
-# dispatch, scaled by what the same counters read for a 1 GiB device copy:
-# x2.0 and x1.0).  Keys: (precision, kernel class).
+# SQ_ACTIVE_INST_VALU) and HBM bytes of the transfer and the k_finish launch
+# that follows it (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by
+# what the same counters read for a 1 GiB device copy: x2.0 and x1.0).  Keys:
+# (precision, kernel class).
+_UNITS_1024_SMR = {"trial": 85456054.0, "acc": 72527214.0, "samp": 682634999.0, "rec": 734227814.0,
+                   "ray": 1048576.0}
 COUNTERS = {
-    "src": "947152047fe23941",
-    (1, "transfer"): {"issued_f64": 4.63e10, "issued_f32": 1.517e12, "lane_activity": 0.851,
-                      "bytes": 2.0 * (1.42026e7 + 203937.0) * 1024 + 1.0 * (137996.0 + 65536.0) * 1024,
+    "src": "e4b1cca3f039ce1d",
+    (1, "transfer"): {"issued_f64": 4.635e+10, "issued_f32": 1.519e+12, "lane_activity": 0.851,
+                      "bytes": 2.0 * (14467622.7 + 203250.1) * 1024 + 1.0 * (137996.4 + 65536.0) * 1024,
                       # units of work of that launch (1024^2 SMR image, auxiliary maps)
-                      "units": {"trial": 85456054.0, "acc": 72527214.0, "samp": 682634999.0, "rec": 734227814.0,
-                                "ray": 1048576.0}},
+                      "units": _UNITS_1024_SMR},
+    (0, "transfer"): {"issued_f64": 2.434e+12, "issued_f32": 0, "lane_activity": 0.778,
+                      "bytes": 2.0 * (16779272.9 + 266632.6) * 1024 + 1.0 * (269212.7 + 65536.0) * 1024,
+                      "units": _UNITS_1024_SMR},
 }
 
 
