@@ -177,3 +177,26 @@ def test_moving_camera(ctx, oracle):
 def test_frequency_at_the_camera(ctx, oracle):
     """freq_mode 1: nu is the frequency measured by the (moving) camera."""
     _camera_case(ctx, oracle, {"u_normal": (0.05, -0.03, 0.0), "freq_mode": 1})
+
+
+def test_largest_image_in_chunks(ctx, oracle):
+    """A 4096^2 image of the SMR workload (16.8 M rays): more rays than one
+    chunk of the default step-record workspace holds, so the render runs as
+    several chunks, each traced, ordered and transferred in turn.  Mixed form
+    with an FP32 grid, 60 sampled pixels (corners and centre among them)
+    against the oracle with equal step counts."""
+    w = _wl("c3_1024_smr", 4096)
+    n = 4096
+    rng = np.random.default_rng(41)
+    pix = np.concatenate([rng.choice(n * n, size=56, replace=False), [0, n - 1, (n // 2) * n + n // 2, n * n - 1]])
+    ctx.profile_enable(True)
+    try:
+        ctx.profile_read()
+        img, aux, ig, ag, io, ao = _render_and_sample(ctx, oracle, w, pix, precision=1, grid_f32=True)
+        prof = ctx.profile_read()
+    finally:
+        ctx.profile_enable(False)
+    _say("4096^2 geodesic launches (chunks)", prof["geodesic"][1], "transfer launches", prof["transfer"][1])
+    assert prof["geodesic"][1] > 1
+    _check("c3 4096^2 mixed", ig, ag, io, ao, 1e-3 * np.abs(img[0]).max(), TOL_MIXED)
+    assert np.isfinite(img).all()
