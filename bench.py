@@ -408,6 +408,12 @@ def main():
     ap.add_argument("--freqs", type=int, default=0,
                     help="single image: also time a K-frequency render from one geodesic pass (K frequencies "
                          "evenly spaced in wavelength over 152-324 GHz, as for true-colour images)")
+    ap.add_argument("--models", type=int, default=0,
+                    help="single image: also time K electron-temperature models (R_high from 1 to 160, evenly "
+                         "spaced in log) rendered from one geodesic pass (bl_render_models)")
+    ap.add_argument("--nonthermal", action="store_true",
+                    help="single image: also time a render with thermal, power-law and kappa electrons in equal "
+                         "thirds (p = 3, gamma 4..1000; kappa = 4, w = 1/2)")
     ap.add_argument("--averages", action="store_true",
                     help="single image: also time a render with the 21 averaged-quantity maps (bl_render_averages)")
     ap.add_argument("--adaptive", action="store_true",
@@ -545,6 +551,55 @@ def main():
                             "single_frequency_ms": ms, "speedup_vs_separate_renders": K * ms / mms,
                             "kernels": kernel_table(mprof, args.steps)}
         log("multi-frequency", out["multifreq"]["ms_per_render"], "ms per render of", K, "frequencies")
+    if args.models > 1:
+        K = args.models
+        rhs = [math.exp(math.log(160.0) * k / (K - 1)) for k in range(K)]
+        pls = [dict(w["plasma"], r_high=rh) for rh in rhs]
+        outs = [(torch.empty(4, n, n, dtype=torch.float64, device="cuda"),
+                 torch.empty(blgpu.NAUX, n, n, dtype=torch.float64, device="cuda")) for _ in range(K)]
+
+        def mdstep():
+            ctx.render_models(w["camera"], w["spacetime"], w["integrator"], gg, pls, precision=args.precision,
+                              outputs=outs)
+
+        mdstep()
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        ctx.profile_read()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            mdstep()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mdprof = ctx.profile_read()
+        ctx.profile_enable(False)
+        mdms = (t1 - t0) * 1e3 / args.steps
+        out["models"] = {"n_models": K, "r_high": rhs, "ms_per_render": mdms, "ms_per_image": mdms / K,
+                         "rays_per_s": K * rays / (mdms / 1e3), "single_model_ms": ms,
+                         "speedup_vs_separate_renders": K * ms / mdms, "kernels": kernel_table(mdprof, args.steps)}
+        log("models", mdms, "ms per render of", K, "electron models")
+    if args.nonthermal:
+        pl_nt = dict(w["plasma"], fractions=(1 / 3, 1 / 3, 1 / 3))
+
+        def ntstep():
+            return ctx.render(w["camera"], w["spacetime"], w["integrator"], gg, pl_nt, precision=args.precision)
+
+        ntstep()
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        ctx.profile_read()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            ntstep()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ntprof = ctx.profile_read()
+        ctx.profile_enable(False)
+        ntms = (t1 - t0) * 1e3 / args.steps
+        out["nonthermal"] = {"fractions": [1 / 3, 1 / 3, 1 / 3], "ms_per_render": ntms,
+                             "rays_per_s": rays / (ntms / 1e3), "thermal_render_ms": ms,
+                             "kernels": kernel_table(ntprof, args.steps)}
+        log("nonthermal", ntms, "ms per render (equal thirds)")
     if args.averages:
         def astep():
             return ctx.render_averages(w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"],

@@ -1945,8 +1945,14 @@ bl_status adaptive_impl(bl_context *ctx, const bl_camera *cam, const bl_spacetim
         if ((s = render_images(ctx, nl, cp.data(), sp.data(), ims.data(), axs.data(), integ, grid, plasma, mode, t,
                                true, 0, nullptr, sub.data())) != BL_OK)
             return s;
-        // the level's block list; blk stays alive until the stream has
-        // passed this copy (synchronised below on every path)
+        // the level's block list; blk must stay alive until the stream has
+        // passed this copy: the guard waits for the stream on every return
+        // (the error returns included) and blk is only replaced after the
+        // synchronisations below
+        struct StreamWait {
+            hipStream_t st;
+            ~StreamWait() { (void)hipStreamSynchronize(st); }
+        } wait_copy{ctx->stream};
         HIPCHK(ctx, hipMemcpyAsync(blocks_out + 3 * off, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice,
                                    ctx->stream));
         counts_out[level] = nl;
