@@ -36,10 +36,11 @@ def _grid(w, f32=False):
     return _GRIDS[key]
 
 
-def _case(name, n, precision, **integ):
+def _case(name, n, precision, plasma=None, **integ):
     from paper_2203_15963_amd import synth
     w = synth.workload(name, n=n)
     w["integrator"].update(max_steps=4095, **integ)
+    w["plasma"].update(plasma or {})
     return w, precision
 
 
@@ -55,6 +56,9 @@ def test_noalloc_render_equals_bl_render():
         _case("c2_256_pol", 40, 0, record_cap=24),
         # the benchmark image at full size, mixed precision, FP32 grid
         _case("c3_1024_smr", 1024, 1),
+        # a smaller one with nonthermal electrons (their constants also come
+        # from the scratch array), polarized FP64
+        _case("c2_256_pol", 16, 0, plasma=dict(fractions=(1 / 3, 1 / 3, 1 / 3))),
         # then a smaller one: unpolarized, mixed
         _case("c1_64_unpol", 12, 1),
     ]
