@@ -485,6 +485,21 @@ bl_status bl_eval_samples(bl_context *ctx, const bl_spacetime *st, const bl_grid
                           const bl_plasma *plasma, int64_t n, const double *states,
                           const double *norms, double *out);
 
+/* The polarized plasma substep alone, for checking (paper section 2.4, the
+   constant-coefficient solution of the polarized transfer equation over one
+   segment): for coefficient sets coeffs device [n][8] = jI, jQ, jV, aI, aQ,
+   aV, rQ, rV (jU = aU = rU = 0: the frame's U axis is perpendicular to the
+   field; the segment length folded in, so the segment has unit length) and
+   Stokes vectors s0 device [n][4], writes S1 to s_out device [n][4].
+   precision 0: FP64, 1: FP32 (inputs rounded to FP32, results widened).
+   general 0: the thermal closed form of the image kernels, which assumes
+   Kirchhoff's law J = (jI/aI) M e_I and reads only jI of the emissivities;
+   general 1: the substep of the nonthermal kernels (any source vector).
+   aI >= 100 gives M^-1 J.  Asynchronous on the context's stream.
+   BL_E_INVALID_ARG for NULL pointers, n < 0 or flags other than 0 and 1. */
+bl_status bl_eval_stokes(bl_context *ctx, int32_t precision, int32_t general, int64_t n,
+                         const double *coeffs, const double *s0, double *s_out);
+
 /* Kernel timing with HIP events recorded around every launch on the context's
    stream (tracing aid; off by default).  Kernel classes: */
 #define BL_NKERNEL 4

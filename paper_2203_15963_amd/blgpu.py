@@ -220,6 +220,8 @@ def load():
     L.bl_set_step_model.restype = C.c_int
     L.bl_eval_samples.argtypes = [vp, C.POINTER(bl_spacetime), vp, C.POINTER(bl_plasma), i64, vp, vp, vp]
     L.bl_eval_samples.restype = C.c_int
+    L.bl_eval_stokes.argtypes = [vp, C.c_int32, C.c_int32, i64, vp, vp, vp]
+    L.bl_eval_stokes.restype = C.c_int
     L.bl_profile_enable.argtypes = [vp, C.c_int]
     L.bl_profile_enable.restype = C.c_int
     L.bl_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -573,6 +575,18 @@ class Context:
         nl = (C.c_int64 * NKERNEL)()
         self._check(load().bl_profile_read(self.handle, ms, nl))
         return {KERNEL_NAMES[k]: (ms[k], nl[k]) for k in range(NKERNEL)}
+
+    def eval_stokes(self, coeffs, s0, precision=0, general=0):
+        """bl_eval_stokes: one plasma substep per row of coeffs [n][8] from
+        s0 [n][4]; returns S1 [n][4]."""
+        import torch
+        coeffs = torch.as_tensor(coeffs, dtype=torch.float64, device=self.device).contiguous()
+        s0 = torch.as_tensor(s0, dtype=torch.float64, device=self.device).contiguous()
+        n = coeffs.shape[0]
+        out = self._empty(n, 4)
+        self._check(load().bl_eval_stokes(self.handle, int(precision), int(general), n, _ptr(coeffs), _ptr(s0),
+                                          _ptr(out)))
+        return out
 
     def eval_samples(self, st, grid, pl, states, norms):
         import torch

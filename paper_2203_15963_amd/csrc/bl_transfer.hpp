@@ -365,7 +365,9 @@ __device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
     }
     const R Th = L1s + L2s;
     const R em1 = fexpm1(-aI);
-    const R E = R(1) + em1;   // e^{-aI}
+    // e^{-aI}: 1 + expm1 for a thin step, the exponential itself for a thick
+    // one (1 + expm1 keeps only the absolute accuracy of numbers near 1)
+    const R E = aI <= R(1) ? R(1) + em1 : fexp(-aI);
     R cq, shq, shp, dc, ds, fp;   // cos L2 - 1, Sh(q), e^{-a} Sh(p), e^{-a} C[p,q], e^{-a} Sh[p,q], 1 - e^{-a} cosh L1
     if (Th <= R(1)) {
         // |p|, |q| <= 1: everything from the series; cos L2 = C(q)
@@ -389,12 +391,22 @@ __device__ __forceinline__ void stokes_step(const R c[8], R S[4]) {
         ds = (shp - E * shq) * iT;
         fp = R(-0.5) * (fexpm1(L1 - aI) + fexpm1(-L1 - aI));
     }
-    // e^{-a} cos L2 - 1 without forming e^{-a} cos L2 (a thin step's
-    // attenuation would otherwise be quantised to the spacing of numbers near 1)
-    const R ecm1 = em1 + E * cq, es = E * shq;
+    // a thin step as an increment, with e^{-a} cos L2 - 1 formed without
+    // e^{-a} cos L2 (its attenuation would otherwise be quantised to the
+    // spacing of numbers near 1); a thick one directly (an increment would
+    // lose a strongly attenuated S0 to cancellation)
+    const R es = E * shq;
+    if (aI <= R(1)) {
+        const R ecm1 = em1 + E * cq;
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
-        S[m] += ecm1 * S[m] + dc * (w2[m] + L2s * S[m]) - es * w1[m] - ds * (w3[m] + L2s * w1[m]);
+        for (int m = 0; m < 4; ++m)
+            S[m] += ecm1 * S[m] + dc * (w2[m] + L2s * S[m]) - es * w1[m] - ds * (w3[m] + L2s * w1[m]);
+    } else {
+        const R ec = E + E * cq;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            S[m] = ec * S[m] + dc * (w2[m] + L2s * S[m]) - es * w1[m] - ds * (w3[m] + L2s * w1[m]);
+    }
     if (Bnu > R(0)) {
         const R X = c[4] * c[7] - c[5] * c[6];
         const R den = R(0.5) * (al2 + rh2) + rt;
@@ -520,13 +532,10 @@ __device__ __forceinline__ void stokes_step_general(const R cr[8], R Sr[4]) {
 // E = (a X + b e^-a sin b)/(a^2 + b^2) and O = (X - a e^-a sin b / b)/(a^2 + b^2),
 // X = 1 - e^-a cos b = -expm1(-a) + 2 e^-a sin^2(b/2) (no cancellation).
 // Where a <= 1 and p - q <= 1 the series Phi J = sum_n (-M)^n J/(n+1)! (through
-// n = 14) is summed instead.  The propagator is the thermal step's; for
-// a > 1 it is applied directly (e^-a cos b S0 + ...) with e^-a from the
-// exponential, not as an increment of S0.  With a >= 100, S = M^-1 J (e^-a = 0
-// in FP32).  Checked in FP32 against the exponential of the augmented matrix
-// over 3e4 random coefficient sets (optical depths 1e-9 to 40, S0 up to 1e6
-// times J): within 3e-6 of I for rotation depths up to 30 rad per step, 7e-5 up
-// to 1e3 rad (the phase resolution of FP32).
+// n = 14) is summed instead.  The propagator is the thermal step's; for a > 1
+// it is applied directly (e^-a cos b S0 + ...) with e^-a from the
+// exponential, not as an increment of S0.  With a >= 100, S = M^-1 J (the
+// optical-depth cap), from (a - K') (a^2 - K'^2)^-1 on the same spectrum.
 template <typename R>
 __device__ __forceinline__ R phi_r(R y) {   // (1 - e^-y)/y
     if (fabs(y) < R(1e-6)) return R(1) - R(0.5) * y;
@@ -611,6 +620,17 @@ __device__ __forceinline__ void stokes_step_nth(const R c[8], R S[4]) {
     kprime(c, J, j1);
     kprime(c, j1, j2);
     kprime(c, j2, j3);
+    if (a >= R(100)) {
+        // M^-1 J = (a - K') g(K'^2) J with g(x) = 1/(a^2 - x) on {p, q}: g(q) =
+        // 1/(a^2 + L2^2), g[p,q] = g(p) g(q), a^2 - p = (a - L1)(a + L1) > 0
+        const R L1 = sqrt(L1s);
+        const R gq = fdiv(R(1), a * a + L2s);
+        const R gpq = gq * fdiv(R(1), (a - L1) * (a + L1));
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            S[m] = a * (gq * J[m] + gpq * (j2[m] + L2s * J[m])) - gq * j1[m] - gpq * (j3[m] + L2s * j1[m]);
+        return;
+    }
     const R L1 = sqrt(L1s), b = sqrt(L2s);
     const R pm = phi_r(a - L1), pp = phi_r(a + L1);
     const R Ep = R(0.5) * (pm + pp);

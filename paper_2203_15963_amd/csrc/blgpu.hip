@@ -927,6 +927,24 @@ __global__ void k_eval_samples(double a, int flat, DevGrid g, PlasmaParams pp, l
     o[52] = 1.0;
 }
 
+// The plasma substep alone, for checking: coefficient sets c [n][8] (jI, jQ,
+// jV, aI, aQ, aV, rQ, rV, the segment length folded in) and states S0
+// [n][4], in the arithmetic type R; GENERAL selects the substep of the
+// nonthermal kernels (any source vector) over the thermal closed form.
+template <typename R, bool GENERAL>
+__global__ void k_eval_stokes(long long n, const double *__restrict__ c8, const double *__restrict__ s4,
+                              double *__restrict__ out) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    R c[8], S[4];
+    for (int m = 0; m < 8; ++m) c[m] = (R)c8[i * 8 + m];
+    for (int m = 0; m < 4; ++m) S[m] = (R)s4[i * 4 + m];
+    if constexpr (!GENERAL) stokes_step(c, S);
+    else if constexpr (sizeof(R) == 4) stokes_step_nth(c, S);
+    else stokes_step_general(c, S);
+    for (int m = 0; m < 4; ++m) out[i * 4 + m] = (double)S[m];
+}
+
 // ============================================================ host side
 // Scratch of the allocation-free render (bl_render_noalloc): one static
 // device array, which every GPU the library runs on holds (its own copy, at
@@ -2758,6 +2776,26 @@ bl_status bl_eval_samples(bl_context *ctx, const bl_spacetime *st, const bl_grid
     if ((s = upload_nth(ctx, 1, &plasma, &pp)) != BL_OK) return s;
     hipLaunchKernelGGL(k_eval_samples, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, ctx->stream, st->a,
                        st->flat ? 1 : 0, grid->g, pp, (long long)n, states, norms, out);
+    HIPCHK(ctx, hipGetLastError());
+    return BL_OK;
+}
+
+bl_status bl_eval_stokes(bl_context *ctx, int32_t precision, int32_t general, int64_t n, const double *coeffs,
+                         const double *s0, double *s_out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    if (!coeffs || !s0 || !s_out || n < 0) return fail(ctx, BL_E_INVALID_ARG, "invalid argument");
+    if ((precision != 0 && precision != 1) || (general != 0 && general != 1))
+        return fail(ctx, BL_E_INVALID_ARG, "precision and general must be 0 or 1");
+    if (n == 0) return BL_OK;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const dim3 grd((unsigned)((n + 63) / 64)), blk(64);
+    const long long nn = (long long)n;
+    switch (2 * precision + general) {
+    case 0: hipLaunchKernelGGL((k_eval_stokes<double, false>), grd, blk, 0, ctx->stream, nn, coeffs, s0, s_out); break;
+    case 1: hipLaunchKernelGGL((k_eval_stokes<double, true>), grd, blk, 0, ctx->stream, nn, coeffs, s0, s_out); break;
+    case 2: hipLaunchKernelGGL((k_eval_stokes<float, false>), grd, blk, 0, ctx->stream, nn, coeffs, s0, s_out); break;
+    default: hipLaunchKernelGGL((k_eval_stokes<float, true>), grd, blk, 0, ctx->stream, nn, coeffs, s0, s_out); break;
+    }
     HIPCHK(ctx, hipGetLastError());
     return BL_OK;
 }
