@@ -164,9 +164,12 @@ typedef struct {
 typedef struct {
     int32_t precision;        /* 0: FP64 throughout; 1: FP64 geodesics with
                                  FP32 coefficients and transfer               */
-    int32_t step_model;       /* 0: the plain step-size controller; 1: learned
-                                 step proposals from the network installed
-                                 with bl_set_step_model                       */
+    int32_t step_model;       /* 0: the plain step-size controller; k in
+                                 1..64: learned step proposals from the
+                                 network installed with bl_set_step_model,
+                                 for the first step and after every k-th
+                                 accepted one (the plain controller proposes
+                                 after the others)                            */
 } bl_mode;
 
 /* ABI version of the loaded library (BLGPU_ABI_VERSION). */

@@ -221,6 +221,7 @@ struct GeoParams {
     int cap;           // step records per ray slot
     int n;             // pixels per side
     int rec_quart32;   // records carry the FP32 quartic of sampled steps (the mixed form)
+    int net_every;     // learned proposals: the network proposes after every net_every-th accepted step
     double bb[6];      // grid bounding box (x0, x1, y0, y1, z0, z1) for the sampling decision
     double ds_max;     // proper-length limit of a piece (0: no cut)
 };

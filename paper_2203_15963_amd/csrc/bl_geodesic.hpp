@@ -353,11 +353,12 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
     o.dt = t_pix - y[0];
 }
 
-// The same integration with learned step proposals: after every accepted
-// step (and for the first) the wave evaluates the step-proposal network for
-// its lanes and a lane tries h = -exp(net) (clamped to 0.2..10 times the last
-// accepted |h|; the plain controller's proposal if the output is not
-// finite).  The embedded error estimate still accepts or rejects each trial;
+// The same integration with learned step proposals: for the first step and
+// after every P.net_every-th accepted step the wave evaluates the
+// step-proposal network for its lanes and a lane tries h = -exp(net) (clamped
+// to 0.2..10 times the last accepted |h|; the plain controller's proposal if
+// the output is not finite); after the other accepted steps the plain
+// controller proposes.  The embedded error estimate still accepts or rejects each trial;
 // after a rejection the plain controller shrinks h for the retry.  The loop
 // runs wave-converged (every lane reaches the network call each iteration);
 // lanes with active = false only take part in it.
@@ -378,7 +379,7 @@ __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool activ
     double h_last = h, eps_last = 1.0;
     double lambda = 0.0, s = 0.0;
     int nacc = 0, nrej = 0, status = active ? kRunning : kEscaped, last_sampled = -1, pieces = 0, work = 0;
-    bool need = true;
+    bool need = true, no_grow = false;
     for (;;) {
         const bool run = status == kRunning;
         if (__ballot(run && need)) {
@@ -419,7 +420,13 @@ __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool activ
             s += ds;
             h_last = h;
             eps_last = eps;
-            need = true;
+            need = nacc % P.net_every == 0;
+            if (!need) {
+                double fac = grow_factor(eps);
+                if (no_grow) fac = fmin(fac, 1.0);
+                h *= fac;
+            }
+            no_grow = false;
 #pragma unroll
             for (int m = 0; m < 7; ++m) {
                 y[m] = y5[m];
@@ -432,6 +439,7 @@ __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool activ
         } else {
             ++nrej;
             h *= shrink_factor(eps);
+            no_grow = true;
         }
     }
     if (WREC && active && status != kRayOverflow) write_final(rec, nacc, y, k1, last_sampled);

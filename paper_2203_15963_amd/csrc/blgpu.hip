@@ -1232,6 +1232,7 @@ GeoParams geo_params(const bl_camera *c, const bl_spacetime *st, const bl_integr
     // no records are sampled unless a render sets the grid box, the piece
     // length and the record layout (record_layout)
     P.rec_quart32 = 0;
+    P.net_every = 1;
     for (int d = 0; d < 6; ++d) P.bb[d] = 0.0;
     P.ds_max = 0.0;
     return P;
@@ -1655,11 +1656,11 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
     if (tr_plasmas && n_freq < 1) return fail(ctx, BL_E_INVALID_ARG, "per-output plasmas need a multi-output render");
     if (mode && (mode->precision < 0 || mode->precision > 1))
         return fail(ctx, BL_E_INVALID_ARG, "precision must be 0 (FP64) or 1 (mixed)");
-    if (mode && (mode->step_model < 0 || mode->step_model > 1))
-        return fail(ctx, BL_E_INVALID_ARG, "step_model must be 0 (controller) or 1 (learned)");
-    const bool learned = mode && mode->step_model == 1;
+    if (mode && (mode->step_model < 0 || mode->step_model > 64))
+        return fail(ctx, BL_E_INVALID_ARG, "step_model must be 0 (controller) or 1..64 (learned)");
+    const bool learned = mode && mode->step_model >= 1;
     if (learned && !ctx->has_step_model)
-        return fail(ctx, BL_E_STATE, "step_model 1 needs a network installed with bl_set_step_model");
+        return fail(ctx, BL_E_STATE, "learned step proposals need a network installed with bl_set_step_model");
     if (grid && grid->ctx != ctx) return fail(ctx, BL_E_STATE, "the grid belongs to another context");
     const bool mixed = mode && mode->precision == 1;
     if (grid->g.dtype != 0 && !mixed) return fail(ctx, BL_E_UNSUPPORTED, "float32 grids need precision 1");
@@ -1682,6 +1683,7 @@ bl_status render_images(bl_context *ctx, int n, const bl_camera *const *cams, co
         return s;
     GeoParams P = geo_params(cams[0], sts[0], integ);
     record_layout(P, grid->g, integ, mixed);
+    if (learned) P.net_every = mode->step_model;
     size_t rec_per_ray = (size_t)P.cap * kRecDoubles * sizeof(double);
     long long chunk = t.chunk_rays > 0 ? t.chunk_rays : (long long)(ctx->ws_limit / rec_per_ray);
     chunk = std::max(64LL, chunk - chunk % 64);

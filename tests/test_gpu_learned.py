@@ -230,3 +230,35 @@ def test_learned_full_size_sampled(ctx, oracle, trained):
     assert l1_l <= 1.5 * l1_p + 1e-4
     assert e_l <= 2.0 * e_p + 1e-3
     assert rej_l < rej_p
+
+
+def test_network_every_k_steps(ctx, oracle, trained):
+    """step_model = k: the network proposes for the first step and after every
+    k-th accepted one, the plain controller after the others.  The image keeps
+    the plain form's accuracy against a converged oracle; k = 1 is the
+    every-step form; k beyond 64 is refused."""
+    from paper_2203_15963_amd import blgpu, synth
+    ctx.set_step_model(trained[0])
+    w = synth.workload("c2_256_pol", n=12)
+    g = _grid(w)
+    gg = ctx.grid(g)
+    args = (w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"])
+    fine = dict(w["integrator"], ds_max=w["integrator"]["ds_max"] / 4)
+    iref, _ = oracle.render(w["camera"], w["spacetime"], fine, g, w["plasma"])
+    ip, ap = ctx.render(*args)
+    e_p, l1_p = _errs(ip.cpu().numpy(), iref)
+    rej = {}
+    for k in (1, 4):
+        ik, ak = ctx.render(*args, step_model=k)
+        torch.cuda.synchronize()
+        ik, ak = ik.cpu().numpy(), ak.cpu().numpy()
+        e_k, l1_k = _errs(ik, iref)
+        rej[k] = ak[6].sum() / (ak[5].sum() + ak[6].sum())
+        _say("network every", k, "steps: E_pix", e_k, "L1", l1_k, "rejected fraction", rej[k],
+             "| plain E_pix", e_p, "L1", l1_p)
+        assert l1_k <= 1.5 * l1_p + 1e-4
+        assert e_k <= 2.0 * e_p + 1e-3
+    assert rej[1] <= rej[4]
+    with pytest.raises(blgpu.BlError):
+        ctx.render(*args, step_model=65)
+    torch.cuda.synchronize()
