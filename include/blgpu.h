@@ -167,9 +167,10 @@ typedef struct {
     int32_t step_model;       /* 0: the plain step-size controller; k in
                                  1..64: learned step proposals from the
                                  network installed with bl_set_step_model,
-                                 for the first step and after every k-th
-                                 accepted one (the plain controller proposes
-                                 after the others)                            */
+                                 for the first step and after an accepted
+                                 step whose trial count (accepted plus
+                                 rejected) is a multiple of k (the plain
+                                 controller proposes after the others)       */
 } bl_mode;
 
 /* ABI version of the loaded library (BLGPU_ABI_VERSION). */

@@ -354,11 +354,11 @@ __device__ __forceinline__ void trace_ray(const GeoParams &P, double y[7], doubl
 }
 
 // The same integration with learned step proposals: for the first step and
-// after every P.net_every-th accepted step the wave evaluates the
-// step-proposal network for its lanes and a lane tries h = -exp(net) (clamped
-// to 0.2..10 times the last accepted |h|; the plain controller's proposal if
-// the output is not finite); after the other accepted steps the plain
-// controller proposes.  The embedded error estimate still accepts or rejects each trial;
+// after an accepted step whose trial count is a multiple of P.net_every the
+// wave evaluates the step-proposal network for its lanes and a lane tries
+// h = -exp(net) (clamped to 0.2..10 times the last accepted |h|; the plain
+// controller's proposal if the output is not finite); after the other
+// accepted steps the plain controller proposes.  The embedded error estimate still accepts or rejects each trial;
 // after a rejection the plain controller shrinks h for the retry.  The loop
 // runs wave-converged (every lane reaches the network call each iteration);
 // lanes with active = false only take part in it.
@@ -420,7 +420,10 @@ __device__ __forceinline__ void trace_ray_learned(const GeoParams &P, bool activ
             s += ds;
             h_last = h;
             eps_last = eps;
-            need = nacc % P.net_every == 0;
+            // every running lane of the wave has made the same number of
+            // trials (one per loop pass), so this is a wave-wide choice and
+            // the network runs in one pass of net_every
+            need = (nacc + nrej) % P.net_every == 0;
             if (!need) {
                 double fac = grow_factor(eps);
                 if (no_grow) fac = fmin(fac, 1.0);
