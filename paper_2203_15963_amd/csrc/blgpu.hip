@@ -701,7 +701,7 @@ __global__ void __launch_bounds__(64) k_mlp_fwdbwd(const u32x4 *__restrict__ pk,
     __shared__ __attribute__((aligned(16))) unsigned short s_h1[64 * 64];       // BF16 h1, [unit][ray]
     __shared__ __attribute__((aligned(16))) unsigned short s_h2[64 * 64];
     __shared__ __attribute__((aligned(16))) unsigned short s_dz[64 * 64];       // BF16 dz of the current layer, [unit][ray]
-    __shared__ f32x4 s_z1[16 * 64], s_z2[16 * 64]; // pre-activations, [mt * 4 + nt][lane]
+    __shared__ f32x4 s_z1[16 * 64], s_z2[16 * 64], s_z3[16 * 64]; // pre-activations, [mt * 4 + nt][lane]
     const int lane = threadIdx.x, g = lane >> 4, j = lane & 15;
     const long long row = (long long)blockIdx.x * 64 + lane;
     const bool valid = row < n_rows;
@@ -710,13 +710,16 @@ __global__ void __launch_bounds__(64) k_mlp_fwdbwd(const u32x4 *__restrict__ pk,
         const long long idx = (long long)(((unsigned long long)mul * (unsigned long long)(offset + row) + (unsigned long long)add) %
                                           (unsigned long long)n_mod);
         const float *q = rec + idx * kLogRec;
+        #pragma unroll
         for (int m = 0; m < kMlpIn; ++m) x[m] = q[m];
         target = q[kMlpIn];
     } else {
+        #pragma unroll
         for (int m = 0; m < kMlpIn; ++m) x[m] = tail[kTMu + m];
     }
     // ---- forward
     stage_input(tail, x, s_stage, lane);
+    #pragma unroll
     for (int f = 0; f < 32; ++f)
         s_xt[f * 64 + lane] = f < kMlpIn ? (unsigned short)(pack2((x[f] - tail[kTMu + f]) * tail[kTISig + f], 0.0f) & 0xffffu) : 0;
     wave_lds_sync();
@@ -725,19 +728,26 @@ __global__ void __launch_bounds__(64) k_mlp_fwdbwd(const u32x4 *__restrict__ pk,
     f32x4 h[4][4];
     u32x4 bq[4][2];
     mm_layer<1>(pk + kPkL1, b1, h, lane);
+    #pragma unroll
     for (int L = 1; L <= 3; ++L) {
         const float *bias = tail + (L == 1 ? kTB1 : L == 2 ? kTB2 : kTB3);
+        #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float bb = bias[16 * mt + 4 * g + e];
+                #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) h[mt][nt][e] += bb;
             }
         if (L < 3) {
             f32x4 *zs = L == 1 ? s_z1 : s_z2;
             unsigned short *hs = L == 1 ? s_h1 : s_h2;
+            #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
+                #pragma unroll
                 for (int nt = 0; nt < 4; ++nt) {
                     zs[(mt * 4 + nt) * 64 + lane] = h[mt][nt];
+                    #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         h[mt][nt][e] = silu(h[mt][nt][e]);
                         hs[(16 * mt + 4 * g + e) * 64 + 16 * nt + j] = (unsigned short)(pack2(h[mt][nt][e], 0.0f) & 0xffffu);
@@ -747,14 +757,16 @@ __global__ void __launch_bounds__(64) k_mlp_fwdbwd(const u32x4 *__restrict__ pk,
             mm_layer<2>(pk + (L == 1 ? kPkL2 : kPkL3), bq, h, lane);
         }
     }
-    // h now holds z3; keep it and form h3
-    f32x4 z3[4][4], h3[4][4];
+    // h now holds z3: keep z3 in LDS (for the backward pass) and turn h into h3
+#pragma unroll
     for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-            z3[mt][nt] = h[mt][nt];
-            for (int e = 0; e < 4; ++e) h3[mt][nt][e] = silu(z3[mt][nt][e]);
+            s_z3[(mt * 4 + nt) * 64 + lane] = h[mt][nt];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) h[mt][nt][e] = silu(h[mt][nt][e]);
         }
-    const float y = out_layer(h3, tail, lane);
+    const float y = out_layer(h, tail, lane);
     if (valid && y_out) y_out[row] = y;
     const float diff = valid ? y - target : 0.0f;
     float lsum = diff * diff;
@@ -765,27 +777,34 @@ __global__ void __launch_bounds__(64) k_mlp_fwdbwd(const u32x4 *__restrict__ pk,
     // ---- backward
     const float dy = 2.0f * diff * inv_n;
     float dyn[4];
+    #pragma unroll
     for (int nt = 0; nt < 4; ++nt) dyn[nt] = __shfl(dy, 16 * nt + j);
     float db4 = dy;
     for (int o = 32; o > 0; o >>= 1) db4 += __shfl_xor(db4, o);
     if (lane == 0) gp[kB4] = db4;
-    // w4 and dz3
+    // w4 and dz3 (h holds h3, z3 comes back from LDS)
     f32x4 dz[4][4];
+#pragma unroll
     for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int u = 16 * mt + 4 * g + e;
             const float w = tail[kTW4 + u];
             float gw = 0.0f;
+#pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
-                gw += h3[mt][nt][e] * dyn[nt];
-                dz[mt][nt][e] = w * dyn[nt] * dsilu(z3[mt][nt][e]);
+                gw += h[mt][nt][e] * dyn[nt];
+                dz[mt][nt][e] = w * dyn[nt] * dsilu(s_z3[(mt * 4 + nt) * 64 + lane][e]);
             }
             for (int o = 1; o < 16; o <<= 1) gw += __shfl_xor(gw, o);
             if (j == 0) gp[kW4 + u] = gw;
         }
+    #pragma unroll
     for (int L = 3; L >= 1; --L) {
         // bias gradient: sum over the rays of dz
+        #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 float sb = dz[mt][0][e] + dz[mt][1][e] + dz[mt][2][e] + dz[mt][3][e];
                 for (int o = 1; o < 16; o <<= 1) sb += __shfl_xor(sb, o);
@@ -793,27 +812,39 @@ __global__ void __launch_bounds__(64) k_mlp_fwdbwd(const u32x4 *__restrict__ pk,
             }
         // weight gradient dW = dz h_prev^T (K = the 64 rays), through LDS
         wave_lds_sync();
+        #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
+                #pragma unroll
                 for (int e = 0; e < 4; ++e)
                     s_dz[(16 * mt + 4 * g + e) * 64 + 16 * nt + j] = (unsigned short)(pack2(dz[mt][nt][e], 0.0f) & 0xffffu);
         wave_lds_sync();
         const unsigned short *hp = L == 3 ? s_h2 : L == 2 ? s_h1 : s_xt;
         const int ntn = L == 1 ? 2 : 4;   // input features of layer 1: 32 (11 used)
         f32x4 gw[4][4];
+        #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
             for (int nt = 0; nt < ntn; ++nt) gw[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
             u32x4 bB[4];
+            #pragma unroll
             for (int nt = 0; nt < ntn; ++nt)
                 bB[nt] = *(const u32x4 *)(hp + (16 * nt + j) * 64 + 32 * kk + 8 * g);
+            #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 const u32x4 aA = *(const u32x4 *)(s_dz + (16 * mt + j) * 64 + 32 * kk + 8 * g);
+                #pragma unroll
                 for (int nt = 0; nt < ntn; ++nt) gw[mt][nt] = mma(aA, bB[nt], gw[mt][nt]);
             }
         }
+        #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
             for (int nt = 0; nt < ntn; ++nt)
+                #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int o = 16 * mt + 4 * g + e, i = 16 * nt + j;
                     if (L == 1) {
@@ -827,27 +858,49 @@ __global__ void __launch_bounds__(64) k_mlp_fwdbwd(const u32x4 *__restrict__ pk,
         to_bfrag(dz, bq);
         mm_layer<2>(pk + (L == 3 ? kPkB3 : kPkB2), bq, h, lane);
         const f32x4 *zs = L == 3 ? s_z2 : s_z1;
+        #pragma unroll
         for (int mt = 0; mt < 4; ++mt)
+            #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
                 const f32x4 zz = zs[(mt * 4 + nt) * 64 + lane];
+                #pragma unroll
                 for (int e = 0; e < 4; ++e) dz[mt][nt][e] = h[mt][nt][e] * dsilu(zz[e]);
             }
     }
 }
 
-// grad[p] = sum over tiles of the partials (fixed order); loss_acc[0] +=
-// the sum of the tile losses (one thread, launches in stream order).
-__global__ void k_mlp_reduce(const float *__restrict__ part, int n_tiles, float *__restrict__ grad,
-                             const float *__restrict__ loss_part, double *__restrict__ loss_acc, int want_grad) {
+// The gradient partials and losses of the tiles summed in two stages, each
+// in a fixed order: slice y of the grid sums tiles [kMlpSlice y,
+// kMlpSlice (y + 1)) into slice_sum[y] and slice_loss[y] (many threads at
+// once, instead of one thread per parameter walking every tile), then
+// grad[p] = the sum over the slices in order and loss_acc[0] += the sum of
+// the slice losses (launches in stream order).
+constexpr int kMlpSlice = 16;
+__global__ void k_mlp_reduce_slices(const float *__restrict__ part, const float *__restrict__ loss_part, int n_tiles,
+                                    int want_grad, double *__restrict__ slice_sum, double *__restrict__ slice_loss) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t0 = blockIdx.y * kMlpSlice, t1 = min(n_tiles, t0 + kMlpSlice);
+    if (p == 0) {
+        double l = 0.0;
+        for (int t = t0; t < t1; ++t) l += loss_part[t];
+        slice_loss[blockIdx.y] = l;
+    }
+    if (!want_grad || p >= kMlpNParam) return;
+    double s = 0.0;
+    for (int t = t0; t < t1; ++t) s += part[(long long)t * kMlpNParam + p];
+    slice_sum[(long long)blockIdx.y * kMlpNParam + p] = s;
+}
+__global__ void k_mlp_reduce(const double *__restrict__ slice_sum, const double *__restrict__ slice_loss,
+                             int n_slices, float *__restrict__ grad, double *__restrict__ loss_acc, int want_grad) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (want_grad && p < kMlpNParam) {
         double s = 0.0;
-        for (int t = 0; t < n_tiles; ++t) s += part[(long long)t * kMlpNParam + p];
+        for (int y = 0; y < n_slices; ++y) s += slice_sum[(long long)y * kMlpNParam + p];
         grad[p] = (float)s;
     }
     if (p == 0) {
         double l = 0.0;
-        for (int t = 0; t < n_tiles; ++t) l += loss_part[t];
+        for (int y = 0; y < n_slices; ++y) l += slice_loss[y];
         loss_acc[0] += l;
     }
 }
@@ -1029,6 +1082,10 @@ struct bl_context {
     float *d_mlp_tail = nullptr;
     float *d_mlp_gpart = nullptr;
     size_t mlp_gpart_bytes = 0;
+    double *d_mlp_slices = nullptr;   // per-slice gradient sums of a pass
+    size_t mlp_slices_bytes = 0;
+    double *d_mlp_sloss = nullptr;    // per-slice loss sums
+    size_t mlp_sloss_bytes = 0;
     float *d_mlp_lpart = nullptr;
     size_t mlp_lpart_bytes = 0;
     float *d_mlp_grad = nullptr, *d_mlp_m = nullptr, *d_mlp_v = nullptr;
@@ -2092,6 +2149,8 @@ void bl_destroy(bl_context *ctx) {
     (void)hipFree(ctx->d_mlp_pk);
     (void)hipFree(ctx->d_mlp_tail);
     (void)hipFree(ctx->d_mlp_gpart);
+    (void)hipFree(ctx->d_mlp_slices);
+    (void)hipFree(ctx->d_mlp_sloss);
     (void)hipFree(ctx->d_mlp_lpart);
     (void)hipFree(ctx->d_mlp_grad);
     (void)hipFree(ctx->d_mlp_m);
@@ -2560,6 +2619,11 @@ bl_status mlp_tiles(bl_context *ctx, long long tiles) {
     bl_status s;
     if ((s = ensure(ctx, &ctx->d_mlp_gpart, ctx->mlp_gpart_bytes, (size_t)tiles * kMlpNParam * sizeof(float))) != BL_OK)
         return s;
+    const long long slices = (tiles + kMlpSlice - 1) / kMlpSlice;
+    if ((s = ensure(ctx, &ctx->d_mlp_slices, ctx->mlp_slices_bytes, (size_t)slices * kMlpNParam * sizeof(double))) !=
+        BL_OK)
+        return s;
+    if ((s = ensure(ctx, &ctx->d_mlp_sloss, ctx->mlp_sloss_bytes, (size_t)slices * sizeof(double))) != BL_OK) return s;
     return ensure(ctx, &ctx->d_mlp_lpart, ctx->mlp_lpart_bytes, (size_t)tiles * sizeof(float));
 }
 
@@ -2577,8 +2641,12 @@ bl_status mlp_pass(bl_context *ctx, const float *records, long long n_rows, long
     hipLaunchKernelGGL(k_mlp_fwdbwd, dim3((unsigned)tiles), dim3(64), 0, ctx->stream, ctx->d_mlp_pk, ctx->d_mlp_tail,
                        records, n_rows, offset, mul, add, n_mod, inv_n, want_grad ? 1 : 0, ctx->d_mlp_gpart,
                        ctx->d_mlp_lpart, y_out);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpNParam + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_mlp_gpart,
-                       (int)tiles, ctx->d_mlp_grad, ctx->d_mlp_lpart, ctx->d_mlp_acc, want_grad ? 1 : 0);
+    const int slices = (int)((tiles + kMlpSlice - 1) / kMlpSlice);
+    hipLaunchKernelGGL(k_mlp_reduce_slices, dim3(want_grad ? (kMlpNParam + 255) / 256 : 1, (unsigned)slices), dim3(256),
+                       0, ctx->stream, ctx->d_mlp_gpart, ctx->d_mlp_lpart, (int)tiles, want_grad ? 1 : 0,
+                       ctx->d_mlp_slices, ctx->d_mlp_sloss);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kMlpNParam + 255) / 256), dim3(256), 0, ctx->stream, ctx->d_mlp_slices,
+                       ctx->d_mlp_sloss, slices, ctx->d_mlp_grad, ctx->d_mlp_acc, want_grad ? 1 : 0);
     HIPCHK(ctx, hipGetLastError());
     return BL_OK;
 }
