@@ -22,19 +22,30 @@
 namespace bl {
 
 // ---------------------------------------------------------------- lookup
-// Table entry of the block lattice cell holding x (half-open boxes, so faces
-// belong to the upper block), or nullptr outside the lattice.
-__device__ __forceinline__ const double *find_block(const DevGrid &g, const double x[3]) {
+// Index of the block lattice cell holding x (half-open boxes, so faces
+// belong to the upper block), or -1 outside the lattice.
+__device__ __forceinline__ long long lattice_cell(const DevGrid &g, const double x[3]) {
     int idx[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         double u = (x[d] - g.t0[d]) * g.itb[d];
-        if (!(u >= 0.0) || u >= (double)g.tn[d]) return nullptr;
+        if (!(u >= 0.0) || u >= (double)g.tn[d]) return -1;
         idx[d] = (int)floor(u);
-        if (idx[d] >= g.tn[d]) return nullptr;
+        if (idx[d] >= g.tn[d]) return -1;
     }
-    return g.table + 8 * (long long)((idx[2] * g.tn[1] + idx[1]) * g.tn[0] + idx[0]);
+    return (long long)((idx[2] * g.tn[1] + idx[1]) * g.tn[0] + idx[0]);
 }
+
+// The table entry of the lattice cell of the previous sample, kept by the
+// FP64 walk (one wave per SIMD, registers to spare): consecutive samples
+// mostly share a lattice cell (a cell is a block of the finest level), and
+// the entry's load is then one dependent round trip fewer.  Entries are a
+// function of the cell alone, so the choice of block is the table's.
+struct BlockCache {
+    long long cell;   // lattice cell of the entry held, -1: none
+    double o[3], is[3];
+    long long cb;
+};
 
 // Cells hold 8 primitives (32 or 64 contiguous bytes, 16-byte aligned) and
 // are read with 16-byte vector loads.
@@ -69,7 +80,8 @@ __device__ __forceinline__ void corner_weights(const R w[3], R wt[8]) {
 // used, so a lane waits for one round trip per group instead of one per
 // corner (G = 4 for the FP32 grid, 2 for the FP64 grid in the mixed form: 32
 // registers of cell data in flight either way; 4 for the FP64 grid in the
-// all-FP64 form, which runs one wave per SIMD and has round trips to hide).
+// all-FP64 form, and all 8 in its polarized walk, which runs one wave per SIMD
+// with registers to spare and has round trips to hide).
 template <int G, typename T, typename R>
 __device__ __forceinline__ void trilerp(const T *base, long long c0, long long sy, long long sz, const R w[3],
                                         R prim[8]) {
@@ -102,12 +114,34 @@ __device__ __forceinline__ void trilerp(const T *base, long long c0, long long s
 // have at least two cells per axis (checked when the grid is made), so the
 // clamped corner indices i0, i0 + 1 always lie inside the block and all eight
 // corners are read, those of weight zero included.
-template <typename R>
-__device__ __forceinline__ bool sample_grid(const DevGrid &g, int interp, const double x[3], R prim[8]) {
-    const double *e = find_block(g, x);
-    if (!e) return false;
+// WIDE: the one-wave-per-SIMD FP64 polarized walk (all eight corners at once,
+// block entry from bc when the lattice cell is the previous sample's).
+template <typename R, bool WIDE = false>
+__device__ __forceinline__ bool sample_grid(const DevGrid &g, int interp, const double x[3], R prim[8],
+                                            BlockCache *bc = nullptr) {
+    const long long cell = lattice_cell(g, x);
+    if (cell < 0) return false;
     double o[3], is[3];
-    const long long cb = block_meta(e, o, is);
+    long long cb;
+    if (WIDE && bc->cell == cell) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            o[d] = bc->o[d];
+            is[d] = bc->is[d];
+        }
+        cb = bc->cb;
+    } else {
+        cb = block_meta(g.table + 8 * cell, o, is);
+        if (WIDE) {
+            bc->cell = cell;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                bc->o[d] = o[d];
+                bc->is[d] = is[d];
+            }
+            bc->cb = cb;
+        }
+    }
     if (cb < 0) return false;
     const int nn[3] = {g.bnx, g.bny, g.bnz};
 #pragma unroll
@@ -156,7 +190,7 @@ __device__ __forceinline__ bool sample_grid(const DevGrid &g, int interp, const 
     if (g.dtype != 0)
         trilerp<4>((const float *)g.prims, c0, sy, sz, w, prim);
     else
-        trilerp<sizeof(R) == 8 ? 4 : 2>((const double *)g.prims, c0, sy, sz, w, prim);
+        trilerp<sizeof(R) == 8 ? (WIDE ? 8 : 4) : 2>((const double *)g.prims, c0, sy, sz, w, prim);
     return true;
 }
 
@@ -378,16 +412,17 @@ __device__ __forceinline__ bool cut_out(const CutParams &c, int k, R q) {
 // CUTS: compiled with the data-cut checks (renders with cuts installed use
 // that instantiation, so the others carry no trace of them); NTH: with the
 // nonthermal electron populations (likewise).
-template <typename R, bool CUTS = false, bool NTH = false>
+template <typename R, bool CUTS = false, bool NTH = false, bool WIDE = false>
 __device__ __forceinline__ void sample_point(double a, int flat, const DevGrid &g, const PlasmaParams &pp,
-                                             const double yd[8], double n_norm, Sample<R> &s) {
+                                             const double yd[8], double n_norm, Sample<R> &s,
+                                             BlockCache *bc = nullptr) {
     s.plasma = false;
     s.sigma = R(0);
     s.ne = s.th = s.B = s.nu_fl = s.omega = R(0);
 #pragma unroll
     for (int m = 0; m < 8; ++m) s.co[m] = R(0);
     R prim[8];
-    if (!sample_grid<R>(g, pp.interp, yd + 1, prim)) return;
+    if (!sample_grid<R, WIDE>(g, pp.interp, yd + 1, prim, bc)) return;
     R rho = prim[0], p = prim[1];
     if (!(rho > R(0))) return;
     s.k = ks_point<R>((R)a, flat, (R)yd[1], (R)yd[2], (R)yd[3]);

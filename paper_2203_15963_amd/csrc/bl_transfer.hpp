@@ -756,6 +756,7 @@ struct RayWalk {
     int nsamp, nrec;
     R pys[kQC], pyb[kQC];   // previous piece: sample and boundary (x, y, z, k_x, k_y, k_z)
     Coh<R> N;
+    BlockCache bc;       // the last block table entry (used by the FP64 polarized walk)
     // averaged quantities (their own pass): for q = rho, n_e, p, Theta_e, B,
     // sigma, beta^-1, the sums of q dlambda and q dI_j and the tau-relaxed <q>
     R av_l[7], av_j[7], av_t[7];
@@ -784,6 +785,7 @@ __device__ __forceinline__ void begin_ray(RayWalk<R> &w, const double *rec, int 
     w.I = w.tau = w.Ij = w.tau_c = w.Ij_c = R(0);
     w.nsamp = 0;
     w.nrec = n_acc - 1 - last;
+    w.bc.cell = -1;
 #pragma unroll
     for (int m = 0; m < 7; ++m) w.av_l[m] = w.av_j[m] = w.av_t[m] = R(0);
 #pragma unroll
@@ -925,7 +927,7 @@ __device__ __forceinline__ void piece(RayWalk<R> &w, const GeoParams &P, const D
     w.p = p - 1;
     Sample<R> smp;
     smp.plasma = false;
-    if (w.inb) sample_point<R, CUTS, NTH>(P.a, flat, g, pp, ys, (double)w.n_norm, smp);
+    if (w.inb) sample_point<R, CUTS, NTH, POL && sizeof(R) == 8>(P.a, flat, g, pp, ys, (double)w.n_norm, smp, &w.bc);
     R c[8];
     if (smp.plasma) {
         R lt = w.L * w.dl * smp.omega;
