@@ -489,6 +489,17 @@ bl_status bl_eval_samples(bl_context *ctx, const bl_spacetime *st, const bl_grid
                           const bl_plasma *plasma, int64_t n, const double *states,
                           const double *norms, double *out);
 
+/* The fluid-frame synchrotron coefficients alone, for checking (paper
+   section 2.6): for rows in device [n][5] = n_e (cm^-3), Theta_e, B (gauss),
+   nu (Hz), cos theta_B, writes out device [n][8] = jI, jQ, jV, aI, aQ, aV, rQ,
+   rV (CGS) of the electrons of plasma (its populations and polarized flag;
+   the other fields unused), in FP64 (precision 0) or FP32 (precision 1:
+   inputs rounded to FP32, results widened).  Asynchronous on the context's
+   stream.  BL_E_INVALID_ARG for NULL pointers, n < 0, another precision or
+   invalid populations. */
+bl_status bl_eval_coeffs(bl_context *ctx, int32_t precision, const bl_plasma *plasma, int64_t n,
+                         const double *in, double *out);
+
 /* The polarized plasma substep alone, for checking (paper section 2.4, the
    constant-coefficient solution of the polarized transfer equation over one
    segment): for coefficient sets coeffs device [n][8] = jI, jQ, jV, aI, aQ,

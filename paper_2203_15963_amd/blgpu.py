@@ -220,6 +220,8 @@ def load():
     L.bl_set_step_model.restype = C.c_int
     L.bl_eval_samples.argtypes = [vp, C.POINTER(bl_spacetime), vp, C.POINTER(bl_plasma), i64, vp, vp, vp]
     L.bl_eval_samples.restype = C.c_int
+    L.bl_eval_coeffs.argtypes = [vp, C.c_int32, C.POINTER(bl_plasma), i64, vp, vp]
+    L.bl_eval_coeffs.restype = C.c_int
     L.bl_eval_stokes.argtypes = [vp, C.c_int32, C.c_int32, i64, vp, vp, vp]
     L.bl_eval_stokes.restype = C.c_int
     L.bl_profile_enable.argtypes = [vp, C.c_int]
@@ -575,6 +577,17 @@ class Context:
         nl = (C.c_int64 * NKERNEL)()
         self._check(load().bl_profile_read(self.handle, ms, nl))
         return {KERNEL_NAMES[k]: (ms[k], nl[k]) for k in range(NKERNEL)}
+
+    def eval_coeffs(self, pl, rows, precision=0):
+        """bl_eval_coeffs: fluid-frame coefficients for rows [n][5] = n_e,
+        Theta_e, B, nu, cos theta_B; returns [n][8]."""
+        import torch
+        rows = torch.as_tensor(rows, dtype=torch.float64, device=self.device).contiguous()
+        n = rows.shape[0]
+        out = self._empty(n, 8)
+        p = plasma(pl)
+        self._check(load().bl_eval_coeffs(self.handle, int(precision), C.byref(p), n, _ptr(rows), _ptr(out)))
+        return out
 
     def eval_stokes(self, coeffs, s0, precision=0, general=0):
         """bl_eval_stokes: one plasma substep per row of coeffs [n][8] from

@@ -980,6 +980,25 @@ __global__ void k_eval_samples(double a, int flat, DevGrid g, PlasmaParams pp, l
     o[52] = 1.0;
 }
 
+// The fluid-frame coefficients alone, for checking: rows in [n][5] = n_e,
+// Theta_e, B (gauss), nu (Hz), cos theta_B; out [n][8], in the arithmetic
+// type R (thermal electrons, or the populations of nth when it is given).
+template <typename R>
+__global__ void k_eval_coeffs(long long n, const double *__restrict__ in, int polarized, const NthParams *nth,
+                              double *__restrict__ out) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double *r = in + i * 5;
+    R co[8];
+    if (nth) {
+        thermal_coeffs<R>((R)r[0] * (R)nth->frac[0], (R)r[1], (R)r[2], (R)r[3], (R)r[4], polarized, co);
+        nonthermal_coeffs<R>(*nth, (R)r[0], (R)r[2], (R)r[3], (R)r[4], polarized, co);
+    } else {
+        thermal_coeffs<R>((R)r[0], (R)r[1], (R)r[2], (R)r[3], (R)r[4], polarized, co);
+    }
+    for (int m = 0; m < 8; ++m) out[i * 8 + m] = (double)co[m];
+}
+
 // The plasma substep alone, for checking: coefficient sets c [n][8] (jI, jQ,
 // jV, aI, aQ, aV, rQ, rV, the segment length folded in) and states S0
 // [n][4], in the arithmetic type R; GENERAL selects the substep of the
@@ -2846,6 +2865,29 @@ bl_status bl_eval_samples(bl_context *ctx, const bl_spacetime *st, const bl_grid
     if ((s = upload_nth(ctx, 1, &plasma, &pp)) != BL_OK) return s;
     hipLaunchKernelGGL(k_eval_samples, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, ctx->stream, st->a,
                        st->flat ? 1 : 0, grid->g, pp, (long long)n, states, norms, out);
+    HIPCHK(ctx, hipGetLastError());
+    return BL_OK;
+}
+
+bl_status bl_eval_coeffs(bl_context *ctx, int32_t precision, const bl_plasma *plasma, int64_t n, const double *in,
+                         double *out) {
+    if (!ctx) return BL_E_INVALID_ARG;
+    if (!plasma || !in || !out || n < 0) return fail(ctx, BL_E_INVALID_ARG, "invalid argument");
+    if (precision != 0 && precision != 1) return fail(ctx, BL_E_INVALID_ARG, "precision must be 0 or 1");
+    if (n == 0) return BL_OK;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    PlasmaParams pp{};
+    pp.nonthermal = 0;
+    pp.nth = nullptr;
+    bl_status s;
+    if ((s = upload_nth(ctx, 1, &plasma, &pp)) != BL_OK) return s;
+    const NthParams *nth = pp.nonthermal ? pp.nth : nullptr;
+    const dim3 grd((unsigned)((n + 63) / 64)), blk(64);
+    const int pol = plasma->polarized ? 1 : 0;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_eval_coeffs<double>, grd, blk, 0, ctx->stream, (long long)n, in, pol, nth, out);
+    else
+        hipLaunchKernelGGL(k_eval_coeffs<float>, grd, blk, 0, ctx->stream, (long long)n, in, pol, nth, out);
     HIPCHK(ctx, hipGetLastError());
     return BL_OK;
 }

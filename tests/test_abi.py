@@ -29,7 +29,7 @@ def test_header_declares_entry_points():
     names = _declared()
     for n in ["bl_abi_version", "bl_create", "bl_destroy", "bl_last_error", "bl_grid_create",
               "bl_grid_destroy", "bl_camera_rays", "bl_trace_geodesics", "bl_render", "bl_eval_samples",
-              "bl_profile_enable", "bl_profile_read", "bl_eval_stokes", "bl_render_batch", "bl_set_tuning", "bl_get_tuning",
+              "bl_profile_enable", "bl_profile_read", "bl_eval_stokes", "bl_eval_coeffs", "bl_render_batch", "bl_set_tuning", "bl_get_tuning",
               "bl_autotune", "bl_render_multifreq", "bl_render_models", "bl_set_cuts", "bl_render_averages",
               "bl_render_adaptive"]:
         assert n in names
