@@ -109,6 +109,21 @@ __device__ __forceinline__ double rsqrt_r(double x) {
 // refined reciprocal (within about two ulp)
 __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double fdiv(double a, double b) { return a * rcp_nr(b); }
+// 1/x and 1/sqrt(x) for quantities whose rounding error compounds along a ray:
+// in FP32 the hardware estimates (whose errors of about an ulp lean to one
+// side) refined by one Newton step, y <- y + y (1 - x y) and
+// y <- y + y (1/2 - (x y / 2) y), each formed with fused multiply-adds; in
+// FP64 the refined reciprocal and reciprocal square root above.
+__device__ __forceinline__ float rcp_acc(float x) {
+    const float y = __builtin_amdgcn_rcpf(x);
+    return fmaf(fmaf(-x, y, 1.0f), y, y);
+}
+__device__ __forceinline__ double rcp_acc(double x) { return rcp_nr(x); }
+__device__ __forceinline__ float rsqrt_acc(float x) {
+    const float y = rsqrtf(x);
+    return fmaf(fmaf(-(0.5f * x * y), y, 0.5f), y, y);
+}
+__device__ __forceinline__ double rsqrt_acc(double x) { return rsqrt_r(x); }
 // ln x in FP64, branch free: x = m 2^e with m in [sqrt(1/2), sqrt(2)) from
 // the hardware mantissa/exponent split, ln m = 2 atanh(s) with
 // s = (m - 1)/(m + 1), |s| <= 0.1716, from its series 2 s (1 + s^2/3 + ... +

@@ -489,13 +489,19 @@ __device__ __forceinline__ void sample_point(double a, int flat, const DevGrid &
 // covariant e1 is p_a = -[abcd] u^b e2^c e3^d, formed here from the
 // contravariant vectors and raised once.  Returns the screen vectors e1, e2
 // contravariant and p = e1_a, q = e2_a covariant, and e3.
+// Every Stokes readout and repacking of the polarization state goes through
+// e1 and e2, so a scale error of their norms compounds over the samples of a
+// ray.  In FP32 the reciprocal of omega and the normalisation of e2 are
+// therefore refined (rcp_acc, rsqrt_acc), and e1, which inherits the rounding
+// of u, e2 and e3 through the cofactors, is normalised explicitly by
+// (p.e1)^-1/2.  In FP64 the construction is exact to rounding as it stands.
 template <typename R>
 __device__ __forceinline__ void screen_basis(const KS<R> &k, const R u[4], const R kc[4], const R w[4], R e1[4],
                                              R e2[4], R p[4], R q[4], R e3[4]) {
     R ku[4];
     raise(k, kc, ku);
     const R omega = -(kc[0] * u[0] + kc[1] * u[1] + kc[2] * u[2] + kc[3] * u[3]);
-    const R iom = fdiv(R(1), omega);
+    const R iom = sizeof(R) == 4 ? rcp_acc(omega) : fdiv(R(1), omega);
 #pragma unroll
     for (int m = 0; m < 4; ++m) e3[m] = (ku[m] - omega * u[m]) * iom;
     R t[4], nrm2 = R(0);
@@ -518,7 +524,7 @@ __device__ __forceinline__ void screen_basis(const KS<R> &k, const R u[4], const
         nrm2 = fabs(gdot(k, t, t));
         if (vv > R(0) && nrm2 > R(1e-20) * vv) break;
     }
-    const R inrm = rsqrt_r(nrm2);
+    const R inrm = sizeof(R) == 4 ? rsqrt_acc(nrm2) : rsqrt_r(nrm2);
 #pragma unroll
     for (int m = 0; m < 4; ++m) e2[m] = t[m] * inrm;
     lower(k, e2, q);
@@ -531,6 +537,14 @@ __device__ __forceinline__ void screen_basis(const KS<R> &k, const R u[4], const
     p[2] = -(u[0] * m13 - u[1] * m03 + u[3] * m01);
     p[3] = u[0] * m12 - u[1] * m02 + u[2] * m01;
     raise(k, p, e1);
+    if constexpr (sizeof(R) == 4) {
+        const R s1 = rsqrt_acc(fabs(p[0] * e1[0] + p[1] * e1[1] + p[2] * e1[2] + p[3] * e1[3]));
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            e1[m] *= s1;
+            p[m] *= s1;
+        }
+    }
 }
 
 // The whole tetrad (rows e0..e3, contravariant).
