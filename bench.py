@@ -35,11 +35,11 @@ PUBLISHED_FP32_TFLOPS = 157.3
 # steps, acc = accepted steps, samp = plasma samples, rec = transport records
 # (pieces), ray = rays.
 OPS_PER_UNIT = {
-    "src": "db1a7357e6791de8",
+    "src": "462cdab4655cc8ef",
     0: {"geodesic": {"F64": {"trial": 1291.6, "acc": 287.4, "ray": 1055.3}, "F32": {"trial": 11.0, "ray": 7.0}},
         "transfer": {"F64": {"samp": 2506.7, "rec": 366.8, "acc": 52.2, "ray": 36330.1}, "F32": {}}},
     1: {"geodesic": {"F64": {"trial": 1216.5, "acc": 424.2, "ray": 5321.1}, "F32": {"trial": 11.0, "ray": 7.0}},
-        "transfer": {"F64": {"samp": 16.0, "rec": 30.8}, "F32": {"samp": 1449.5, "rec": 353.4, "ray": 50633.5}}},
+        "transfer": {"F64": {"samp": 16.0, "rec": 30.8}, "F32": {"samp": 1481.5, "rec": 353.4, "ray": 50629.5}}},
 }
 
 # Counter passes over this benchmark (rocprofv3), per launch of a kernel, for
@@ -53,13 +53,13 @@ OPS_PER_UNIT = {
 _UNITS_1024_SMR = {"trial": 85456054.0, "acc": 72527214.0, "samp": 682634999.0, "rec": 734227814.0,
                    "ray": 1048576.0}
 COUNTERS = {
-    "src": "db1a7357e6791de8",
-    (1, "transfer"): {"issued_f64": 4.62e+10, "issued_f32": 1.515e+12, "lane_activity": 0.854,
-                      "bytes": 2.0 * (14092601.5 + 203402.8) * 1024 + 1.0 * (137999.8 + 65536.0) * 1024,
+    "src": "462cdab4655cc8ef",
+    (1, "transfer"): {"issued_f64": 4.608e+10, "issued_f32": 1.536e+12, "lane_activity": 0.855,
+                      "bytes": 2.0 * (14071833.3 + 203358.3) * 1024 + 1.0 * (138002.8 + 65536.0) * 1024,
                       # units of work of that launch (1024^2 SMR image, auxiliary maps)
                       "units": _UNITS_1024_SMR},
-    (0, "transfer"): {"issued_f64": 2.433e+12, "issued_f32": 0, "lane_activity": 0.781,
-                      "bytes": 2.0 * (16582221.4 + 266029.2) * 1024 + 1.0 * (269214.2 + 65536.0) * 1024,
+    (0, "transfer"): {"issued_f64": 2.427e+12, "issued_f32": 0, "lane_activity": 0.785,
+                      "bytes": 2.0 * (16733861.8 + 266234.6) * 1024 + 1.0 * (269202.7 + 65536.0) * 1024,
                       "units": _UNITS_1024_SMR},
 }
 
