@@ -243,3 +243,58 @@ def test_mixed_whole_image_against_fp64_form(ctx):
     assert np.percentile(e, 99.9) <= 3e-5
     assert abs(bias) <= 1e-5
     assert len(over) <= 4
+
+
+def _cut_set_for(w):
+    """theta_e >= 3, 4 <= r <= 40 and the half of the grid on the camera's
+    side of the plane through the origin orthogonal to the line of sight."""
+    cam = w["camera"]
+    nrm = (math.sin(cam["theta"]) * math.cos(cam["phi"]), math.sin(cam["theta"]) * math.sin(cam["phi"]),
+           math.cos(cam["theta"]))
+    return {"theta_e": (3.0, math.inf), "r": (4.0, 40.0),
+            "plane": {"side": 1, "origin": (0.0, 0.0, 0.0), "normal": nrm}}
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_data_cuts_full_size_sampled(ctx, oracle, precision):
+    """Data cuts (paper section 4.1) on the 1024^2 SMR image, whose FP64 cut
+    kernel is the most register-bound build of the library: 150 random
+    pixels and the centre against the oracle with the same cuts."""
+    w = _wl("c3_1024_smr", 1024)
+    cuts = _cut_set_for(w)
+    w["plasma"]["cuts"] = cuts
+    n = 1024
+    rng = np.random.default_rng(59 + precision)
+    pix = np.concatenate([rng.choice(n * n, size=150, replace=False), [(n // 2) * n + n // 2]])
+    ctx.set_cuts(cuts)
+    try:
+        img, aux, ig, ag, io, ao = _render_and_sample(ctx, oracle, w, pix, precision=precision,
+                                                      grid_f32=precision == 1)
+    finally:
+        ctx.set_cuts(None)
+    _check(f"c3 1024^2 cuts precision {precision}", ig, ag, io, ao, 1e-3 * np.abs(img[0]).max(),
+           TOL_FP64 if precision == 0 else TOL_MIXED)
+    assert np.abs(io[:, 0]).max() > 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_cut_kernels_full_size_equal_plain_kernels(ctx, precision):
+    """Cuts with infinite limits run the cut instantiations of the transfer
+    over the whole 1024^2 SMR image; their images and maps equal the plain
+    kernels' bit for bit."""
+    w = _wl("c3_1024_smr", 1024)
+    g = _grid(w["grid_args"])
+    if precision == 1:
+        g = dict(g, prims=g["prims"].astype(np.float32))
+    gg = ctx.grid(g)
+    args = (w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"])
+    i0, a0 = ctx.render(*args, precision=precision)
+    ctx.set_cuts({k: (-math.inf, math.inf) for k in ("rho", "ne", "p", "theta_e", "b", "sigma", "beta_inv", "r")})
+    try:
+        i1, a1 = ctx.render(*args, precision=precision)
+    finally:
+        ctx.set_cuts(None)
+    torch.cuda.synchronize()
+    gg.close()
+    _say("1024^2 cut kernel vs plain, precision", precision, "equal", bool(torch.equal(i0, i1)))
+    assert torch.equal(i0, i1) and torch.equal(a0, a1)
