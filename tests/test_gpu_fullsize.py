@@ -298,3 +298,24 @@ def test_cut_kernels_full_size_equal_plain_kernels(ctx, precision):
     gg.close()
     _say("1024^2 cut kernel vs plain, precision", precision, "equal", bool(torch.equal(i0, i1)))
     assert torch.equal(i0, i1) and torch.equal(a0, a1)
+
+
+def test_models_and_frequencies_full_size(ctx):
+    """Several electron models and frequencies from one geodesic pass over
+    the 1024^2 SMR image (mixed form, FP32 grid): each output equals the
+    single render of its plasma and frequency bit for bit."""
+    w = _wl("c3_1024_smr", 1024)
+    g = _grid(w["grid_args"])
+    gg = ctx.grid(dict(g, prims=g["prims"].astype(np.float32)))
+    pls = [w["plasma"], dict(w["plasma"], r_high=80.0, r_low=3.0),
+           dict(w["plasma"], fractions=(0.8, 0.1, 0.1))]
+    nus = [230e9, 345e9, 86e9]
+    args = (w["camera"], w["spacetime"], w["integrator"], gg)
+    outs = ctx.render_models(*args, pls, nus, precision=1)
+    for k, ((im, ax), pl, nu) in enumerate(zip(outs, pls, nus)):
+        im1, ax1 = ctx.render(dict(w["camera"], nu_hz=nu), w["spacetime"], w["integrator"], gg, pl, precision=1)
+        torch.cuda.synchronize()
+        _say("1024^2 model", k, "nu", nu, "equal to its single render", bool(torch.equal(im, im1)))
+        assert torch.equal(im, im1) and torch.equal(ax, ax1)
+        assert torch.isfinite(im).all() and float(im[0].max()) > 0
+    gg.close()
