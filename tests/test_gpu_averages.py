@@ -69,3 +69,44 @@ def test_averages_match_oracle(ctx, oracle, name, n, precision):
 
 def test_averages_with_cuts_match_oracle(ctx, oracle):
     _compare(ctx, oracle, "c2_256_pol", 10, 0, 1e-10, cuts={"theta_e": (3.0, math.inf), "r": (4.0, 40.0)})
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_averages_full_size_sampled(ctx, oracle, precision):
+    """The 21 averaged maps of the 1024^2 SMR image (the benchmark's
+    --averages configuration; FP32 grid in the mixed form) on 120 random
+    pixels against the oracle on the same cell values; the image and the
+    geodesic maps of the same call equal a plain render's bit for bit.  A
+    map's error is taken relative to its largest sampled value."""
+    from paper_2203_15963_amd import synth
+    w = synth.workload("c3_1024_smr", n=1024)
+    g = synth.make_grid(w["grid_args"])
+    if precision == 1:
+        g = dict(g, prims=g["prims"].astype(np.float32))
+    gg = ctx.grid(g)
+    args = (w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"])
+    im, ax, av = ctx.render_averages(*args, precision=precision)
+    i1, a1 = ctx.render(*args, precision=precision)
+    torch.cuda.synchronize()
+    assert torch.equal(im, i1) and torch.equal(ax, a1)
+    gg.close()
+    n = 1024
+    rng = np.random.default_rng(71 + precision)
+    pix = rng.choice(n * n, size=120, replace=False)
+    go = dict(g, prims=g["prims"].astype(np.float64))
+    io, ao, avo = oracle.render_pixels(w["camera"], w["spacetime"], w["integrator"], go, w["plasma"], pix,
+                                       averages=True)
+    a = ax.cpu().numpy().reshape(-1, n * n)[:, pix].T
+    v = av.cpu().numpy().reshape(21, n * n)[:, pix].T
+    assert np.array_equal(a[:, 5:8], ao[:, 5:8])
+    tol = 1e-10 if precision == 0 else 1e-4
+    worst = 0.0
+    for m in range(21):
+        scale = np.abs(avo[:, m]).max()
+        if scale == 0.0:
+            assert np.all(v[:, m] == 0.0), m
+            continue
+        e = np.abs(v[:, m] - avo[:, m]).max() / scale
+        worst = max(worst, e)
+        assert e <= tol, (m, e)
+    _say("c3_1024_smr 1024^2 sampled, precision", precision, "worst map error", worst)
