@@ -60,3 +60,34 @@ def test_roofline_fraction_is_bounded_by_the_ceiling():
         t_min = (cn["issued_f64"] + cn["issued_f32"]) / (b.VALU_PEAK_TFLOPS * 1e12)
         r = b.roofline(prec, dom, {dom: {"avg_launch_ms": t_min * 1e3, "launches_per_step": 1.0}}, cn["units"])
         assert r["frac"] <= 1.0 and abs(r["issued"]["frac"] - 1.0) < 1e-9
+
+
+def test_accuracy_metric_definition():
+    """E_pix per pixel = max over Stokes of |X_gpu - X_oracle| over
+    max(I_oracle, 1e-3 max I of the image); repeated pixels count once; step
+    count mismatches are counted and their E_pix reported apart."""
+    import numpy as np
+    import bench
+    n = 8
+    img = np.zeros((4, n * n))
+    img[0] = np.linspace(1.0, 2.0, n * n)            # max I = 2
+    aux = np.zeros((10, n * n))
+    aux[5], aux[6] = 50.0, 5.0
+    pix = np.array([3, 10, 10, 40])
+    io = img[:, pix].T.copy()
+    ao = aux[:, pix].T.copy()
+    io[0, 2] += 1e-3                                  # U off by 1e-3 on pixel 3
+    io[1, 0] = 1e-6                                   # a dark pixel: the floor 2e-3 applies
+    img[0, 10] = 1e-6 + 4e-9                          # ... with an error of 4e-9 in I
+    io[3, 0] *= 1.0 + 1e-5                            # pixel 40: I off by 1e-5 relative
+    ao[3, 6] = 6.0                                    # and a rejected-step mismatch
+    r = bench.accuracy(img.reshape(4, n, n), aux.reshape(10, n, n), pix, io, ao, 1e-4)
+    assert r["pixels"] == 3
+    e3 = 1e-3 / io[0, 0]
+    e10 = 4e-9 / 2e-3
+    e40 = abs(img[0, 40] - io[3, 0]) / io[3, 0]
+    assert abs(r["E_pix_max"] - e3) < 1e-12
+    assert abs(r["E_pix_median"] - e40) < 1e-12
+    assert r["step_count_mismatches"] == 1
+    assert abs(r["E_pix_max_mismatched"] - e40) < 1e-12
+    assert r["within_tolerance"] is False and e10 < 1e-5
