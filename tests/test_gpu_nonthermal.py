@@ -214,3 +214,29 @@ def test_boundary_refusals(ctx):
     img, aux = ctx.render(*args, w["plasma"])
     torch.cuda.synchronize()
     assert torch.isfinite(img).all()
+
+
+def test_mixed_full_size_sampled(ctx, oracle):
+    """The 1024^2 SMR image with the paper's equal thirds in the mixed form
+    (FP32 grid and the FP32 general Stokes step), 100 sampled pixels against
+    the oracle on the same cell values, to the mixed tolerance."""
+    from paper_2203_15963_amd import synth
+    w = _wl("c3_1024_smr", 1024, MIXES["thirds"])
+    g = _grid(w)
+    g32 = dict(g, prims=g["prims"].astype(np.float32))
+    gg = ctx.grid(g32)
+    img, aux = ctx.render(w["camera"], w["spacetime"], w["integrator"], gg, w["plasma"], precision=1)
+    torch.cuda.synchronize()
+    gg.close()
+    img, aux = img.cpu().numpy(), aux.cpu().numpy()
+    n = 1024
+    rng = np.random.default_rng(29)
+    pix = rng.choice(n * n, size=100, replace=False)
+    go = dict(g, prims=g32["prims"].astype(np.float64))
+    io, ao = oracle.render_pixels(w["camera"], w["spacetime"], w["integrator"], go, w["plasma"], pix)
+    ig, ag = img.reshape(4, -1)[:, pix].T, aux.reshape(10, -1)[:, pix].T
+    den = np.maximum(np.abs(io[:, 0]), 1e-3 * np.abs(img[0]).max())
+    e = (np.abs(ig - io) / den[:, None]).max(axis=1)
+    _say("1024^2 thirds mixed sampled E_pix", float(e.max()), "median", float(np.median(e)))
+    assert np.array_equal(ag[:, 5:8], ao[:, 5:8])
+    assert e.max() <= TOL_MIXED
