@@ -1,0 +1,137 @@
+"""The library's kernel source, built for the host and run one lane at a
+time under the host sanitizers (test infrastructure only: the library and
+its binding never use this build).
+
+tests/hostemu/shim stands in for the HIP runtime header: kernels become plain
+functions, a wave has a single lane (a ballot is that lane's predicate),
+device memory is host memory, and the hardware reciprocal, reciprocal square
+root and transcendental estimates become their exact definitions.  The kernel
+sources are copied with their empty `asm volatile` scheduling barriers (no
+operation, only register constraints of the GPU) removed, and
+tests/hostemu/emu.cpp drives the render as the library does: camera frame,
+the geodesic kernel for every ray, the persistent transfer kernel as one wave
+over all rays, the overflow kernel for rays that outgrow their slots, and the
+finishing kernel.
+
+Checked: the FP64 image equals the oracle to the FP64 parity tolerance and
+the mixed one to the mixed tolerance (with the host's exact functions in
+place of the hardware estimates), with the oracle's step counts; and the
+same runs are clean under AddressSanitizer with UndefinedBehaviorSanitizer
+(float-to-integer overflow included) and under MemorySanitizer (no
+uninitialised value reaches a branch, an address or an output), for the
+polarized FP64 and mixed forms, the unpolarized FP64 form, and with a record
+cap small enough to send rays through the extension slots and the overflow
+kernel.  What this cannot see: interactions between the 64 lanes of a wave
+and the GPU compiler's register allocation."""
+import ctypes as C
+import os
+import re
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CLANG = "/opt/rocm/lib/llvm/bin/clang++"
+SAN = {
+    "asan": ["-O1", "-fsanitize=address,undefined,float-cast-overflow", "-fno-sanitize-recover=all"],
+    "msan": ["-O1", "-fsanitize=memory", "-fsanitize-memory-track-origins=2", "-fno-omit-frame-pointer"],
+}
+ASM_BARRIER = re.compile(r'^(\s*)asm volatile\(""\s*:\s*"\+[vs]"\(\w+\)\);\s*(//.*)?$', re.M)
+
+pytestmark = pytest.mark.skipif(not os.path.exists(CLANG), reason="the ROCm host clang is not installed")
+
+
+def _sources(dst):
+    """Copy of the kernel sources without the GPU-only scheduling barriers."""
+    src = os.path.join(ROOT, "paper_2203_15963_amd", "csrc")
+    os.makedirs(dst, exist_ok=True)
+    removed = 0
+    for f in os.listdir(src):
+        if not f.endswith((".hip", ".hpp")):
+            continue
+        text = open(os.path.join(src, f)).read()
+        text, k = ASM_BARRIER.subn(r"\1/* scheduling barrier removed */", text)
+        removed += k
+        text = text.replace('#include "../../include/blgpu.h"', '#include "blgpu.h"')
+        assert "asm volatile" not in text, f
+        open(os.path.join(dst, f), "w").write(text)
+    return removed
+
+
+def _build(tmp, kind):
+    exe = os.path.join(tmp, "emu_" + kind)
+    cmd = [CLANG, "-std=c++17", "-g"] + SAN[kind] + [
+        "-I", os.path.join(ROOT, "tests", "hostemu", "shim"), "-I", os.path.join(ROOT, "include"),
+        "-I", os.path.join(tmp, "csrc"), "-o", exe, os.path.join(ROOT, "tests", "hostemu", "emu.cpp"), "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-4000:]
+    return exe
+
+
+def _workload(name, n, d):
+    sys.path.insert(0, ROOT)
+    from paper_2203_15963_amd import blgpu, synth
+    w = synth.workload(name, n=n)
+    g = synth.make_grid(w["grid_args"])
+    os.makedirs(d, exist_ok=True)
+    for s, fn in ((blgpu.camera(w["camera"]), "cam.bin"), (blgpu.spacetime(w["spacetime"]), "st.bin"),
+                  (blgpu.integrator(w["integrator"]), "integ.bin"), (blgpu.plasma(w["plasma"]), "plasma.bin")):
+        open(os.path.join(d, fn), "wb").write(C.string_at(C.addressof(s), C.sizeof(s)))
+    prims = np.ascontiguousarray(g["prims"], dtype=np.float64)
+    nb, bnz, bny, bnx, _ = prims.shape
+    open(os.path.join(d, "grid.txt"), "w").write(f"{nb} {bnx} {bny} {bnz} {g['rho_unit']!r}\n")
+    prims.tofile(os.path.join(d, "prims.bin"))
+    np.ascontiguousarray(g["bounds"], dtype=np.float64).tofile(os.path.join(d, "bounds.bin"))
+    return w, g
+
+
+@pytest.fixture(scope="module")
+def emu(tmp_path_factory):
+    tmp = str(tmp_path_factory.mktemp("hostemu"))
+    assert _sources(os.path.join(tmp, "csrc")) >= 1
+    with ThreadPoolExecutor(2) as ex:
+        exes = dict(zip(SAN, ex.map(lambda k: _build(tmp, k), SAN)))
+    return tmp, exes
+
+
+CASES = [  # workload, n, precision, polarized, record cap (0: default), extension slots
+    ("c2_256_pol", 12, 0, 1, 0, 16),
+    ("c2_256_pol", 12, 1, 1, 0, 16),
+    ("c2_256_pol", 8, 0, 1, 24, 3),
+    ("c3_1024_smr", 16, 0, 1, 0, 16),
+    ("c3_1024_smr", 16, 1, 1, 24, 3),
+    ("c1_64_unpol", 10, 0, 0, 0, 16),
+]
+
+
+@pytest.mark.parametrize("name,n,precision,pol,cap,ext", CASES)
+def test_kernels_on_the_host_match_oracle_and_are_sanitizer_clean(emu, oracle, name, n, precision, pol, cap, ext):
+    tmp, exes = emu
+    d = os.path.join(tmp, f"{name}_{n}_{precision}_{cap}")
+    w, g = _workload(name, n, d)
+    outs = {}
+    for kind, exe in exes.items():
+        env = dict(os.environ, MSAN_OPTIONS="halt_on_error=1", ASAN_OPTIONS="detect_leaks=0")
+        r = subprocess.run([exe, d, str(precision), str(pol), str(cap), str(ext)], capture_output=True, text=True,
+                           timeout=600, env=env)
+        print(f"[host-emulation] {kind}: {r.stdout.strip()}", flush=True)
+        assert r.returncode == 0, (kind, r.stderr[-4000:])
+        assert "Sanitizer" not in r.stderr and "runtime error" not in r.stderr, (kind, r.stderr[-4000:])
+        outs[kind] = np.fromfile(os.path.join(d, f"emu_out_{precision}.bin"), dtype=np.float64)
+    # both builds compute the same image
+    assert np.array_equal(outs["asan"], outs["msan"])
+    v = outs["asan"]
+    img, aux = v[:4 * n * n].reshape(4, n, n), v[4 * n * n:].reshape(10, n, n)
+    io, ao = oracle.render(w["camera"], w["spacetime"], w["integrator"], g, w["plasma"])
+    if not pol:
+        img = img.copy()
+        img[1:] = 0.0
+    I = io[0]
+    den = np.maximum(np.abs(I), 1e-3 * np.abs(I).max())
+    e = float((np.abs(img - io) / den).max())
+    print(f"[host-emulation] {name} {n}^2 precision {precision} cap {cap}: E_pix {e:.3e}", flush=True)
+    assert np.array_equal(aux[5:8], ao[5:8])
+    assert e <= (1e-10 if precision == 0 else 1e-4)
