@@ -4,6 +4,8 @@
 // rays (its refill, per-lane state machine and ray-end handoff), the overflow
 // kernel and the finishing kernel, for one image of a workload written by
 // tests/test_host_emulation.py.  Writes the image and its maps.
+// Data cuts (cuts.bin: a bl_cuts) and nonthermal populations (in the plasma)
+// select the transfer instantiations the library would launch for them.
 //   emu <dir> <precision 0|1> <polarized 0|1> [record cap] [extension slots]
 #include "blgpu.hip"
 #include <vector>
@@ -21,7 +23,14 @@ static void *readall(const char *dir, const char *fn, size_t *n) {
     *n = sz;
     return b;
 }
-template <bool POL, typename R>
+static bool has_file(const char *dir, const char *fn) {
+    char p[1024];
+    snprintf(p, sizeof p, "%s/%s", dir, fn);
+    FILE *f = fopen(p, "rb");
+    if (f) fclose(f);
+    return f != nullptr;
+}
+template <bool POL, typename R, bool CUTS, bool NTH>
 static void run(const char *dir, int precision, int cap_override, int ext_rays) {
     size_t sz;
     bl_camera cam; bl_spacetime st; bl_integrator integ; bl_plasma pl;
@@ -45,10 +54,19 @@ static void run(const char *dir, int precision, int cap_override, int ext_rays) 
     d.rho_unit = rho_unit;
     bl_grid *grid = nullptr;
     if (bl_grid_create(ctx, &d, &grid) != BL_OK) exit(7);
+    if (CUTS) {
+        bl_cuts cu;
+        b = readall(dir, "cuts.bin", &sz);
+        if (sz != sizeof cu) exit(4);
+        memcpy(&cu, b, sz);
+        free(b);
+        if (bl_set_cuts(ctx, &cu) != BL_OK || upload_cuts(ctx) != BL_OK) exit(9);
+    }
     PlasmaParams pps[1] = {plasma_params(ctx, &pl, grid->g, st.mass_msun)};
     const bl_plasma *pls[1] = {&pl};
     if (upload_nth(ctx, 1, pls, pps) != BL_OK) exit(8);
     const PlasmaParams pp = pps[0];
+    if ((pp.nonthermal != 0) != NTH || (pp.cuts != 0) != CUTS) { fprintf(stderr, "instantiation mismatch\n"); exit(10); }
     const int n = cam.n;
     std::vector<double> image(4 * (size_t)n * n, -7.0), aux((size_t)BL_NAUX * n * n, -7.0);
     ImgDev im{};
@@ -86,13 +104,13 @@ static void run(const char *dir, int precision, int cap_override, int ext_rays) 
     for (int s = 0; s < count; ++s) order[s] = s;
     std::vector<R> ends((size_t)count * kRayEnd);
     blockIdx.x = 0; threadIdx.x = 0;
-    k_transfer<POL, R, false, false, false, false>(P, B, grid->g, pp, tp, 0, count, 1, rec.data(), meta.data(),
+    k_transfer<POL, R, false, CUTS, false, NTH>(P, B, grid->g, pp, tp, 0, count, 1, rec.data(), meta.data(),
                                                   nacc.data(), order.data(), X, queue.data(), ends.data());
     if (ovf_count > 0) {
         const int big_cap = (int)std::min<long long>(P.max_steps + 1, 200000);
         std::vector<double> big((size_t)big_cap * kRecDoubles);
         blockDim.x = 1; threadIdx.x = 0;
-        k_overflow<POL, R, false, false, false>(P, B, grid->g, pp, tp, &ovf_count, ovf_list.data(), big.data(), big_cap);
+        k_overflow<POL, R, CUTS, false, NTH>(P, B, grid->g, pp, tp, &ovf_count, ovf_list.data(), big.data(), big_cap);
         blockDim.x = 64;
     }
     if (POL) {
@@ -112,11 +130,29 @@ static void run(const char *dir, int precision, int cap_override, int ext_rays) 
     bl_destroy(ctx);
     free(prims); free(bounds);
 }
+template <bool POL, typename R>
+static void run_form(const char *dir, int precision, int cap, int ext, bool cuts, bool nth) {
+    if (cuts) run<POL, R, true, false>(dir, precision, cap, ext);
+    else if (nth) run<POL, R, false, true>(dir, precision, cap, ext);
+    else run<POL, R, false, false>(dir, precision, cap, ext);
+}
 int main(int argc, char **argv) {
     const char *dir = argv[1];
     int precision = atoi(argv[2]), pol = atoi(argv[3]);
     int cap = argc > 4 ? atoi(argv[4]) : 0, ext = argc > 5 ? atoi(argv[5]) : 16;
-    if (precision == 0) { if (pol) run<true, double>(dir, 0, cap, ext); else run<false, double>(dir, 0, cap, ext); }
-    else { if (pol) run<true, float>(dir, 1, cap, ext); else run<false, float>(dir, 1, cap, ext); }
+    const bool cuts = has_file(dir, "cuts.bin");
+    size_t sz;
+    bl_plasma pl;
+    void *b = readall(dir, "plasma.bin", &sz);
+    memcpy(&pl, b, sizeof pl);
+    free(b);
+    const bool nth = pl.fractions[1] != 0.0 || pl.fractions[2] != 0.0;
+    if (precision == 0) {
+        if (pol) run_form<true, double>(dir, 0, cap, ext, cuts, nth);
+        else run_form<false, double>(dir, 0, cap, ext, cuts, nth);
+    } else {
+        if (pol) run_form<true, float>(dir, 1, cap, ext, cuts, nth);
+        else run_form<false, float>(dir, 1, cap, ext, cuts, nth);
+    }
     return 0;
 }

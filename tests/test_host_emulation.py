@@ -19,11 +19,12 @@ place of the hardware estimates), with the oracle's step counts; and the
 same runs are clean under AddressSanitizer with UndefinedBehaviorSanitizer
 (float-to-integer overflow included) and under MemorySanitizer (no
 uninitialised value reaches a branch, an address or an output), for the
-polarized FP64 and mixed forms, the unpolarized FP64 form, and with a record
-cap small enough to send rays through the extension slots and the overflow
-kernel.  What this cannot see: interactions between the 64 lanes of a wave
+polarized FP64 and mixed forms, the unpolarized FP64 form, the data-cut and
+nonthermal instantiations of the transfer, and with a record cap small
+enough to send rays through the extension slots and the overflow kernel.  What this cannot see: interactions between the 64 lanes of a wave
 and the GPU compiler's register allocation."""
 import ctypes as C
+import math
 import os
 import re
 import subprocess
@@ -71,12 +72,27 @@ def _build(tmp, kind):
     return exe
 
 
-def _workload(name, n, d):
+def _cut_set(w):
+    """theta_e >= 3, 4 <= r <= 40 and the camera's half of the grid."""
+    cam = w["camera"]
+    nrm = (math.sin(cam["theta"]) * math.cos(cam["phi"]), math.sin(cam["theta"]) * math.sin(cam["phi"]),
+           math.cos(cam["theta"]))
+    return {"theta_e": (3.0, math.inf), "r": (4.0, 40.0),
+            "plane": {"side": 1, "origin": (0.0, 0.0, 0.0), "normal": nrm}}
+
+
+def _workload(name, n, d, extra):
     sys.path.insert(0, ROOT)
     from paper_2203_15963_amd import blgpu, synth
     w = synth.workload(name, n=n)
     g = synth.make_grid(w["grid_args"])
     os.makedirs(d, exist_ok=True)
+    if extra == "cuts":
+        w["plasma"]["cuts"] = _cut_set(w)
+        c = blgpu.cuts(w["plasma"]["cuts"])
+        open(os.path.join(d, "cuts.bin"), "wb").write(C.string_at(C.addressof(c), C.sizeof(c)))
+    elif extra == "thirds":
+        w["plasma"]["fractions"] = (1 / 3, 1 / 3, 1 / 3)
     for s, fn in ((blgpu.camera(w["camera"]), "cam.bin"), (blgpu.spacetime(w["spacetime"]), "st.bin"),
                   (blgpu.integrator(w["integrator"]), "integ.bin"), (blgpu.plasma(w["plasma"]), "plasma.bin")):
         open(os.path.join(d, fn), "wb").write(C.string_at(C.addressof(s), C.sizeof(s)))
@@ -97,21 +113,26 @@ def emu(tmp_path_factory):
     return tmp, exes
 
 
-CASES = [  # workload, n, precision, polarized, record cap (0: default), extension slots
-    ("c2_256_pol", 12, 0, 1, 0, 16),
-    ("c2_256_pol", 12, 1, 1, 0, 16),
-    ("c2_256_pol", 8, 0, 1, 24, 3),
-    ("c3_1024_smr", 16, 0, 1, 0, 16),
-    ("c3_1024_smr", 16, 1, 1, 24, 3),
-    ("c1_64_unpol", 10, 0, 0, 0, 16),
+CASES = [  # workload, n, precision, polarized, record cap (0: default), extension slots, cuts / populations
+    ("c2_256_pol", 12, 0, 1, 0, 16, None),
+    ("c2_256_pol", 12, 1, 1, 0, 16, None),
+    ("c2_256_pol", 8, 0, 1, 24, 3, None),
+    ("c3_1024_smr", 16, 0, 1, 0, 16, None),
+    ("c3_1024_smr", 16, 1, 1, 24, 3, None),
+    ("c1_64_unpol", 10, 0, 0, 0, 16, None),
+    ("c2_256_pol", 10, 0, 1, 0, 16, "cuts"),
+    ("c2_256_pol", 10, 1, 1, 0, 16, "cuts"),
+    ("c2_256_pol", 10, 0, 1, 0, 16, "thirds"),
+    ("c2_256_pol", 10, 1, 1, 0, 16, "thirds"),
 ]
 
 
-@pytest.mark.parametrize("name,n,precision,pol,cap,ext", CASES)
-def test_kernels_on_the_host_match_oracle_and_are_sanitizer_clean(emu, oracle, name, n, precision, pol, cap, ext):
+@pytest.mark.parametrize("name,n,precision,pol,cap,ext,extra", CASES)
+def test_kernels_on_the_host_match_oracle_and_are_sanitizer_clean(emu, oracle, name, n, precision, pol, cap, ext,
+                                                                  extra):
     tmp, exes = emu
-    d = os.path.join(tmp, f"{name}_{n}_{precision}_{cap}")
-    w, g = _workload(name, n, d)
+    d = os.path.join(tmp, f"{name}_{n}_{precision}_{cap}_{extra}")
+    w, g = _workload(name, n, d, extra)
     outs = {}
     for kind, exe in exes.items():
         env = dict(os.environ, MSAN_OPTIONS="halt_on_error=1", ASAN_OPTIONS="detect_leaks=0")
@@ -132,6 +153,6 @@ def test_kernels_on_the_host_match_oracle_and_are_sanitizer_clean(emu, oracle, n
     I = io[0]
     den = np.maximum(np.abs(I), 1e-3 * np.abs(I).max())
     e = float((np.abs(img - io) / den).max())
-    print(f"[host-emulation] {name} {n}^2 precision {precision} cap {cap}: E_pix {e:.3e}", flush=True)
+    print(f"[host-emulation] {name} {n}^2 precision {precision} cap {cap} {extra or ''}: E_pix {e:.3e}", flush=True)
     assert np.array_equal(aux[5:8], ao[5:8])
     assert e <= (1e-10 if precision == 0 else 1e-4)
