@@ -21,8 +21,9 @@ same runs are clean under AddressSanitizer with UndefinedBehaviorSanitizer
 uninitialised value reaches a branch, an address or an output), for the
 polarized FP64 and mixed forms, the unpolarized FP64 form, the data-cut and
 nonthermal instantiations of the transfer, and with a record cap small
-enough to send rays through the extension slots and the overflow kernel.  What this cannot see: interactions between the 64 lanes of a wave
-and the GPU compiler's register allocation."""
+enough to send rays through the extension slots and the overflow kernel.
+What this cannot see: interactions between the 64 lanes of a wave and the
+GPU compiler's register allocation."""
 import ctypes as C
 import math
 import os
