@@ -1,14 +1,17 @@
 // Test-only host run of the library's render kernels (built against the
-// host stand-in for the HIP runtime): the camera frame, the geodesic kernel
+// host stand-in for the HIP runtime): the camera frames, the geodesic kernel
 // lane by lane, the persistent transfer kernel as a one-lane wave over all
 // rays (its refill, per-lane state machine and ray-end handoff), the overflow
-// kernel and the finishing kernel, for one image of a workload written by
-// tests/test_host_emulation.py.  Writes the image and its maps.
-// Data cuts (cuts.bin: a bl_cuts) and nonthermal populations (in the plasma)
-// select the transfer instantiations the library would launch for them.
+// kernel, the finishing kernel and, when asked, the averages pass, for one
+// image of a workload written by tests/test_host_emulation.py, or two images
+// as one batch.  Data cuts (cuts.bin: a bl_cuts), nonthermal populations (in
+// the plasma), a second image (cam2.bin, st2.bin) and the averages pass
+// (avg.flag) select the kernel instantiations the library launches for them.
+// Writes, per image, the image and its maps, then the averaged maps.
 //   emu <dir> <precision 0|1> <polarized 0|1> [record cap] [extension slots]
 #include "blgpu.hip"
 #include <vector>
+#include <xmmintrin.h>
 static void *readall(const char *dir, const char *fn, size_t *n) {
     char p[1024];
     snprintf(p, sizeof p, "%s/%s", dir, fn);
@@ -23,6 +26,14 @@ static void *readall(const char *dir, const char *fn, size_t *n) {
     *n = sz;
     return b;
 }
+template <typename T>
+static void readstruct(const char *dir, const char *fn, T &out) {
+    size_t sz;
+    void *b = readall(dir, fn, &sz);
+    if (sz != sizeof out) { fprintf(stderr, "%s: %zu bytes, expected %zu\n", fn, sz, sizeof out); exit(4); }
+    memcpy(&out, b, sz);
+    free(b);
+}
 static bool has_file(const char *dir, const char *fn) {
     char p[1024];
     snprintf(p, sizeof p, "%s/%s", dir, fn);
@@ -30,21 +41,25 @@ static bool has_file(const char *dir, const char *fn) {
     if (f) fclose(f);
     return f != nullptr;
 }
-template <bool POL, typename R, bool CUTS, bool NTH>
+template <bool POL, typename R, bool CUTS, bool NTH, bool BATCH, bool AVG>
 static void run(const char *dir, int precision, int cap_override, int ext_rays) {
-    size_t sz;
-    bl_camera cam; bl_spacetime st; bl_integrator integ; bl_plasma pl;
-    void *b;
-    b = readall(dir, "cam.bin", &sz); memcpy(&cam, b, sz); free(b);
-    b = readall(dir, "st.bin", &sz); memcpy(&st, b, sz); free(b);
-    b = readall(dir, "integ.bin", &sz); memcpy(&integ, b, sz); free(b);
-    b = readall(dir, "plasma.bin", &sz); memcpy(&pl, b, sz); free(b);
+    const int n_img = BATCH ? 2 : 1;
+    bl_camera cam[2]; bl_spacetime st[2]; bl_integrator integ; bl_plasma pl;
+    readstruct(dir, "cam.bin", cam[0]);
+    readstruct(dir, "st.bin", st[0]);
+    if (BATCH) {
+        readstruct(dir, "cam2.bin", cam[1]);
+        readstruct(dir, "st2.bin", st[1]);
+    }
+    readstruct(dir, "integ.bin", integ);
+    readstruct(dir, "plasma.bin", pl);
     char p[1024];
     snprintf(p, sizeof p, "%s/grid.txt", dir);
     FILE *f = fopen(p, "r");
     int nb, bnx, bny, bnz; double rho_unit;
     if (fscanf(f, "%d %d %d %d %lf", &nb, &bnx, &bny, &bnz, &rho_unit) != 5) exit(5);
     fclose(f);
+    size_t sz;
     double *prims = (double *)readall(dir, "prims.bin", &sz);
     double *bounds = (double *)readall(dir, "bounds.bin", &sz);
     bl_context *ctx = nullptr;
@@ -56,36 +71,43 @@ static void run(const char *dir, int precision, int cap_override, int ext_rays) 
     if (bl_grid_create(ctx, &d, &grid) != BL_OK) exit(7);
     if (CUTS) {
         bl_cuts cu;
-        b = readall(dir, "cuts.bin", &sz);
-        if (sz != sizeof cu) exit(4);
-        memcpy(&cu, b, sz);
-        free(b);
+        readstruct(dir, "cuts.bin", cu);
         if (bl_set_cuts(ctx, &cu) != BL_OK || upload_cuts(ctx) != BL_OK) exit(9);
     }
-    PlasmaParams pps[1] = {plasma_params(ctx, &pl, grid->g, st.mass_msun)};
+    PlasmaParams pps[1] = {plasma_params(ctx, &pl, grid->g, st[0].mass_msun)};
     const bl_plasma *pls[1] = {&pl};
     if (upload_nth(ctx, 1, pls, pps) != BL_OK) exit(8);
     const PlasmaParams pp = pps[0];
     if ((pp.nonthermal != 0) != NTH || (pp.cuts != 0) != CUTS) { fprintf(stderr, "instantiation mismatch\n"); exit(10); }
-    const int n = cam.n;
-    std::vector<double> image(4 * (size_t)n * n, -7.0), aux((size_t)BL_NAUX * n * n, -7.0);
-    ImgDev im{};
-    im.cp = cam_params(&cam);
-    im.a = st.a; im.r_in = st.r_in; im.flat = st.flat ? 1 : 0;
-    im.L = kG * st.mass_msun * kMsun / (kC * kC);
-    im.image = image.data(); im.aux = aux.data(); im.avg = nullptr;
-    const int tiles = (n + 7) / 8;
-    const int count = tiles * tiles * 64;
-    im.ray0 = 0; im.nray = count;
-    long long ray0 = 0;
-    Batch B; B.imgs = &im; B.ray0 = &ray0; B.n_img = 1; B.tw = 8; B.th = 8; B.pad = 0;
-    threadIdx.x = 0; blockIdx.x = 0;
-    k_camera_frame(B);
-    GeoParams P = geo_params(&cam, &st, &integ);
+    // images: row-major tiles of 8 x 8 pixels, one wave's worth of ray ids each
+    std::vector<std::vector<double>> image(n_img), aux(n_img), avg(n_img);
+    ImgDev im[2] = {};
+    long long ray0[2] = {0, 0};
+    long long count = 0;
+    for (int k = 0; k < n_img; ++k) {
+        const int n = cam[k].n, tiles = (n + 7) / 8;
+        image[k].assign(4 * (size_t)n * n, -7.0);
+        aux[k].assign((size_t)BL_NAUX * n * n, -7.0);
+        avg[k].assign(AVG ? 21 * (size_t)n * n : 1, -7.0);
+        im[k].cp = cam_params(&cam[k]);
+        im[k].a = st[k].a; im[k].r_in = st[k].r_in; im[k].flat = st[k].flat ? 1 : 0;
+        im[k].L = kG * st[k].mass_msun * kMsun / (kC * kC);
+        im[k].image = image[k].data(); im[k].aux = aux[k].data(); im[k].avg = AVG ? avg[k].data() : nullptr;
+        im[k].ray0 = ray0[k] = count;
+        im[k].nray = (long long)tiles * tiles * 64;
+        count += im[k].nray;
+    }
+    Batch B; B.imgs = im; B.ray0 = ray0; B.n_img = n_img; B.tw = 8; B.th = 8; B.pad = 0;
+    threadIdx.x = 0;
+    for (int k = 0; k < n_img; ++k) {
+        blockIdx.x = k;
+        k_camera_frame(B);
+    }
+    GeoParams P = geo_params(&cam[0], &st[0], &integ);
     record_layout(P, grid->g, &integ, precision == 1);
     if (cap_override > 0) P.cap = cap_override;
     TransferParams tp;
-    tp.ds_max = integ.ds_max; tp.L = im.L; tp.nu_cam = cam.nu_hz;
+    tp.ds_max = integ.ds_max; tp.L = im[0].L; tp.nu_cam = cam[0].nu_hz;
     std::vector<double> rec((size_t)count * P.cap * kRecDoubles), meta(2 * (size_t)count);
     std::vector<int> nacc(count), work(count), ovf_list(count), of(count, -1), order(count), queue(4, 0);
     int ovf_count = 0, ext_count = 0;
@@ -96,63 +118,80 @@ static void run(const char *dir, int precision, int cap_override, int ext_rays) 
     std::vector<double> xrec((size_t)std::max(1, X.cap_rays) * X.cap_rec * kRecDoubles);
     X.rec = xrec.data();
     blockDim.x = 64;
-    for (int s = 0; s < count; ++s) {
-        blockIdx.x = s / 64; threadIdx.x = s % 64;
-        k_geodesic<true, false>(P, B, 0, count, rec.data(), meta.data(), nacc.data(), work.data(), X, &ovf_count,
+    for (long long s = 0; s < count; ++s) {
+        blockIdx.x = (unsigned)(s / 64); threadIdx.x = (unsigned)(s % 64);
+        k_geodesic<true, BATCH>(P, B, 0, (int)count, rec.data(), meta.data(), nacc.data(), work.data(), X, &ovf_count,
                                 ovf_list.data(), nullptr);
     }
-    for (int s = 0; s < count; ++s) order[s] = s;
+    for (long long s = 0; s < count; ++s) order[s] = (int)s;
     std::vector<R> ends((size_t)count * kRayEnd);
     blockIdx.x = 0; threadIdx.x = 0;
-    k_transfer<POL, R, false, CUTS, false, NTH>(P, B, grid->g, pp, tp, 0, count, 1, rec.data(), meta.data(),
-                                                  nacc.data(), order.data(), X, queue.data(), ends.data());
+    k_transfer<POL, R, BATCH, CUTS, false, NTH>(P, B, grid->g, pp, tp, 0, (int)count, 1, rec.data(), meta.data(),
+                                                nacc.data(), order.data(), X, queue.data(), ends.data());
+    PlasmaParams pa = pp;
+    pa.polarized = 0;
+    if (AVG)   // the averages pass: the unpolarized walk over the same records
+        k_transfer<false, R, false, CUTS, true, false>(P, B, grid->g, pa, tp, 0, (int)count, 1, rec.data(), meta.data(),
+                                                       nacc.data(), order.data(), X, queue.data() + 2, ends.data());
     if (ovf_count > 0) {
         const int big_cap = (int)std::min<long long>(P.max_steps + 1, 200000);
         std::vector<double> big((size_t)big_cap * kRecDoubles);
         blockDim.x = 1; threadIdx.x = 0;
         k_overflow<POL, R, CUTS, false, NTH>(P, B, grid->g, pp, tp, &ovf_count, ovf_list.data(), big.data(), big_cap);
+        if (AVG)
+            k_overflow<false, R, CUTS, true, false>(P, B, grid->g, pa, tp, &ovf_count, ovf_list.data(), big.data(),
+                                                    big_cap);
         blockDim.x = 64;
     }
     if (POL) {
-        for (int s = 0; s < count; ++s) {
-            blockIdx.x = s / 64; threadIdx.x = s % 64;
-            k_finish<R, false>(P, B, 0, count, rec.data(), nacc.data(), X, ends.data());
+        for (long long s = 0; s < count; ++s) {
+            blockIdx.x = (unsigned)(s / 64); threadIdx.x = (unsigned)(s % 64);
+            k_finish<R, BATCH>(P, B, 0, (int)count, rec.data(), nacc.data(), X, ends.data());
         }
     }
     snprintf(p, sizeof p, "%s/emu_out_%d.bin", dir, precision);
     f = fopen(p, "wb");
-    fwrite(image.data(), sizeof(double), image.size(), f);
-    fwrite(aux.data(), sizeof(double), aux.size(), f);
+    for (int k = 0; k < n_img; ++k) {
+        fwrite(image[k].data(), sizeof(double), image[k].size(), f);
+        fwrite(aux[k].data(), sizeof(double), aux[k].size(), f);
+    }
+    if (AVG) fwrite(avg[0].data(), sizeof(double), avg[0].size(), f);
     fclose(f);
-    printf("emulated %dx%d image, precision %d, polarized %d, cap %d, extension requests %d, overflow rays %d\n",
-           n, n, precision, (int)POL, P.cap, ext_count, ovf_count);
+    printf("emulated %d image(s) of %dx%d, precision %d, polarized %d, cap %d, extension requests %d, "
+           "overflow rays %d\n", n_img, cam[0].n, cam[0].n, precision, (int)POL, P.cap, ext_count, ovf_count);
     bl_grid_destroy(grid);
     bl_destroy(ctx);
     free(prims); free(bounds);
 }
 template <bool POL, typename R>
-static void run_form(const char *dir, int precision, int cap, int ext, bool cuts, bool nth) {
-    if (cuts) run<POL, R, true, false>(dir, precision, cap, ext);
-    else if (nth) run<POL, R, false, true>(dir, precision, cap, ext);
-    else run<POL, R, false, false>(dir, precision, cap, ext);
-}
-int main(int argc, char **argv) {
-    const char *dir = argv[1];
-    int precision = atoi(argv[2]), pol = atoi(argv[3]);
-    int cap = argc > 4 ? atoi(argv[4]) : 0, ext = argc > 5 ? atoi(argv[5]) : 16;
-    const bool cuts = has_file(dir, "cuts.bin");
+static void run_form(const char *dir, int precision, int cap, int ext) {
     size_t sz;
     bl_plasma pl;
     void *b = readall(dir, "plasma.bin", &sz);
     memcpy(&pl, b, sizeof pl);
     free(b);
+    const bool cuts = has_file(dir, "cuts.bin"), batch = has_file(dir, "cam2.bin"), avg = has_file(dir, "avg.flag");
     const bool nth = pl.fractions[1] != 0.0 || pl.fractions[2] != 0.0;
+    if (batch) run<POL, R, false, false, true, false>(dir, precision, cap, ext);
+    else if (avg) run<POL, R, false, false, false, true>(dir, precision, cap, ext);
+    else if (cuts) run<POL, R, true, false, false, false>(dir, precision, cap, ext);
+    else if (nth) run<POL, R, false, true, false, false>(dir, precision, cap, ext);
+    else run<POL, R, false, false, false, false>(dir, precision, cap, ext);
+}
+int main(int argc, char **argv) {
+    const char *dir = argv[1];
+    int precision = atoi(argv[2]), pol = atoi(argv[3]);
+    int cap = argc > 4 ? atoi(argv[4]) : 0, ext = argc > 5 ? atoi(argv[5]) : 16;
+    // the mixed form's library build flushes FP32 values below 2^-126 to zero
+    // (inputs and results); on the host the same control word also flushes
+    // FP64, which the mixed form uses only for positions and step data
+    if (precision == 1) _mm_setcsr(_mm_getcsr() | 0x8040);   // flush-to-zero, denormals-are-zero
     if (precision == 0) {
-        if (pol) run_form<true, double>(dir, 0, cap, ext, cuts, nth);
-        else run_form<false, double>(dir, 0, cap, ext, cuts, nth);
+        if (pol) run_form<true, double>(dir, 0, cap, ext);
+        else run_form<false, double>(dir, 0, cap, ext);
     } else {
-        if (pol) run_form<true, float>(dir, 1, cap, ext, cuts, nth);
-        else run_form<false, float>(dir, 1, cap, ext, cuts, nth);
+        if (pol) run_form<true, float>(dir, 1, cap, ext);
+        else run_form<false, float>(dir, 1, cap, ext);
     }
     return 0;
 }

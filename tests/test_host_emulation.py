@@ -5,7 +5,8 @@ its binding never use this build).
 tests/hostemu/shim stands in for the HIP runtime header: kernels become plain
 functions, a wave has a single lane (a ballot is that lane's predicate),
 device memory is host memory, and the hardware reciprocal, reciprocal square
-root and transcendental estimates become their exact definitions.  The kernel
+root and transcendental estimates become their exact definitions, and mixed
+runs flush denormal numbers to zero as the library's build does.  The kernel
 sources are copied with their empty `asm volatile` scheduling barriers (no
 operation, only register constraints of the GPU) removed, and
 tests/hostemu/emu.cpp drives the render as the library does: camera frame,
@@ -19,9 +20,10 @@ place of the hardware estimates), with the oracle's step counts; and the
 same runs are clean under AddressSanitizer with UndefinedBehaviorSanitizer
 (float-to-integer overflow included) and under MemorySanitizer (no
 uninitialised value reaches a branch, an address or an output), for the
-polarized FP64 and mixed forms, the unpolarized FP64 form, the data-cut and
-nonthermal instantiations of the transfer, and with a record cap small
-enough to send rays through the extension slots and the overflow kernel.
+polarized FP64 and mixed forms, the unpolarized FP64 form, the data-cut,
+nonthermal, batched and averages instantiations of the transfer, and with a
+record cap small enough to send rays through the extension slots and the
+overflow kernel.
 What this cannot see: interactions between the 64 lanes of a wave and the
 GPU compiler's register allocation."""
 import ctypes as C
@@ -94,6 +96,15 @@ def _workload(name, n, d, extra):
         open(os.path.join(d, "cuts.bin"), "wb").write(C.string_at(C.addressof(c), C.sizeof(c)))
     elif extra == "thirds":
         w["plasma"]["fractions"] = (1 / 3, 1 / 3, 1 / 3)
+    elif extra == "avg":
+        open(os.path.join(d, "avg.flag"), "w").write("1\n")
+    elif extra == "batch":
+        # a second image in the same batch: another size, inclination and spin
+        cam2 = dict(w["camera"], n=7, theta=math.radians(45.0))
+        st2 = dict(w["spacetime"], a=0.5)
+        w["second"] = (cam2, st2)
+        for s, fn in ((blgpu.camera(cam2), "cam2.bin"), (blgpu.spacetime(st2), "st2.bin")):
+            open(os.path.join(d, fn), "wb").write(C.string_at(C.addressof(s), C.sizeof(s)))
     for s, fn in ((blgpu.camera(w["camera"]), "cam.bin"), (blgpu.spacetime(w["spacetime"]), "st.bin"),
                   (blgpu.integrator(w["integrator"]), "integ.bin"), (blgpu.plasma(w["plasma"]), "plasma.bin")):
         open(os.path.join(d, fn), "wb").write(C.string_at(C.addressof(s), C.sizeof(s)))
@@ -125,6 +136,10 @@ CASES = [  # workload, n, precision, polarized, record cap (0: default), extensi
     ("c2_256_pol", 10, 1, 1, 0, 16, "cuts"),
     ("c2_256_pol", 10, 0, 1, 0, 16, "thirds"),
     ("c2_256_pol", 10, 1, 1, 0, 16, "thirds"),
+    ("c2_256_pol", 9, 0, 1, 0, 16, "batch"),
+    ("c2_256_pol", 9, 1, 1, 0, 16, "batch"),
+    ("c2_256_pol", 10, 0, 1, 0, 16, "avg"),
+    ("c3_1024_smr", 10, 1, 1, 0, 16, "avg"),
 ]
 
 
@@ -146,14 +161,30 @@ def test_kernels_on_the_host_match_oracle_and_are_sanitizer_clean(emu, oracle, n
     # both builds compute the same image
     assert np.array_equal(outs["asan"], outs["msan"])
     v = outs["asan"]
-    img, aux = v[:4 * n * n].reshape(4, n, n), v[4 * n * n:].reshape(10, n, n)
-    io, ao = oracle.render(w["camera"], w["spacetime"], w["integrator"], g, w["plasma"])
-    if not pol:
-        img = img.copy()
-        img[1:] = 0.0
-    I = io[0]
-    den = np.maximum(np.abs(I), 1e-3 * np.abs(I).max())
-    e = float((np.abs(img - io) / den).max())
-    print(f"[host-emulation] {name} {n}^2 precision {precision} cap {cap} {extra or ''}: E_pix {e:.3e}", flush=True)
-    assert np.array_equal(aux[5:8], ao[5:8])
-    assert e <= (1e-10 if precision == 0 else 1e-4)
+    tol = 1e-10 if precision == 0 else 1e-4
+    images = [(w["camera"], w["spacetime"])] + ([w["second"]] if extra == "batch" else [])
+    at = 0
+    for cam, st in images:
+        m = int(cam["n"])
+        img, aux = v[at:at + 4 * m * m].reshape(4, m, m), v[at + 4 * m * m:at + 14 * m * m].reshape(10, m, m)
+        at += 14 * m * m
+        res = oracle.render(cam, st, w["integrator"], g, w["plasma"], averages=(extra == "avg"))
+        io, ao = res[0], res[1]
+        if not pol:
+            img = img.copy()
+            img[1:] = 0.0
+        I = io[0]
+        den = np.maximum(np.abs(I), 1e-3 * np.abs(I).max())
+        e = float((np.abs(img - io) / den).max())
+        print(f"[host-emulation] {name} {m}^2 precision {precision} cap {cap} {extra or ''}: E_pix {e:.3e}", flush=True)
+        assert np.array_equal(aux[5:8], ao[5:8])
+        assert e <= tol
+    if extra == "avg":
+        av, avo = v[at:].reshape(21, n, n), res[2]
+        worst = 0.0
+        for k in range(21):
+            scale = np.abs(avo[k]).max()
+            err = np.abs(av[k] - avo[k]).max()
+            assert (err == 0.0) if scale == 0.0 else (err <= tol * scale), (k, err, scale)
+            worst = max(worst, err / scale if scale > 0 else 0.0)
+        print(f"[host-emulation] averaged maps: worst {worst:.3e}", flush=True)
